@@ -1,0 +1,202 @@
+/*
+ * qaia.h -- C ABI of libqaia, simulated-bifurcation sampling of
+ * multi-objective MaxCut on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Multi-Objective Optimization by Quantum-Annealing-Inspired
+ * Algorithms" (arXiv 2604.26477).  Each entry point names the passage of the
+ * paper that defines what it computes.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every call returns an int32 status (QAIA_OK = 0 or one of the codes
+ *    below).  Argument errors are detected on the host before any device
+ *    work is enqueued.  qaia_last_error() returns a human-readable detail of
+ *    the calling thread's most recent failure.  No C++ exception crosses the
+ *    ABI.
+ *  - "HOST" pointers are ordinary CPU memory; "DEVICE" pointers are device
+ *    memory of the problem's device (for example torch tensors'
+ *    data_ptr()).  All buffers are owned by the caller unless stated.
+ *  - hip_stream is a hipStream_t (NULL = the legacy default stream).  Device
+ *    work is enqueued asynchronously on it; results are valid after the
+ *    caller synchronises that stream.  The library allocates no device
+ *    memory in qaia_sample, qaia_evaluate or qaia_pareto_filter: their
+ *    scratch space is the caller's workspace.
+ *  - Edge weights are int32 fixed point: the real weight is
+ *    W * 2^(-frac_bits).  Cut values are exact int64 in the same units.
+ *  - Spin vectors are packed: uint64 words[ceil(n/64)] per sample, bit i of
+ *    word i/64 set  <=>  s_i = -1.
+ */
+#ifndef QAIA_H
+#define QAIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QAIA_ABI_VERSION 1
+
+/* status codes */
+#define QAIA_OK 0
+#define QAIA_INVALID_ARGUMENT 1
+#define QAIA_UNSUPPORTED 2
+#define QAIA_OUT_OF_MEMORY 3
+#define QAIA_DEVICE_ERROR 4        /* a HIP call failed */
+#define QAIA_OVERFLOW 5            /* an exact integer range bound was exceeded */
+#define QAIA_WORKSPACE_TOO_SMALL 6
+
+/* SB variants, section "Simulated Bifurcation with Gaussian noise":
+ * phi(x) = x (ballistic) or sgn(x) (discrete). */
+#define QAIA_BSB 0
+#define QAIA_DSB 1
+
+/* arithmetic of the coupling product J.phi(x) */
+#define QAIA_FP32 0 /* float32 everywhere */
+#define QAIA_BF16 1 /* discrete SB, dense path: bf16 J (per-objective scaled) x exact +-1, fp32 accumulate */
+#define QAIA_FP8 2  /* discrete SB, dense path: fp8 e4m3 J (per-objective scaled) x exact +-1, fp32 accumulate */
+
+/* kernel family; AUTO lets the planner decide */
+#define QAIA_PATH_AUTO 0
+#define QAIA_PATH_SPARSE_REG 1 /* per-graph generated kernel, one replica per lane, state in registers */
+#define QAIA_PATH_SPARSE_LDS 2 /* generic kernel, one spin per lane, state and adjacency in LDS */
+#define QAIA_PATH_DENSE 3      /* stacked per-objective matrix product on the matrix cores */
+
+typedef struct qaia_problem qaia_problem;
+
+/* Integration schedule of Eq. (9) / Eq. (10).  The update per step t is
+ *   y <- y + dt * ( -(a0 - a_t) x - c0 J(c) phi(x) + noise_alpha * eta )
+ *   x <- x + dt * a0 * y
+ *   |x_i| > 1  ->  x_i = sgn(x_i), y_i = 0           (inelastic wall)
+ * with a_t = a0 * t / (steps - 1), J(c) = sum_k c_k J^(k) (Eq. 7) and
+ * c0 = 1 / max_i |sum_j J(c)_ij|.  x and y start ~ U(-init_amp, init_amp)
+ * from the counter-based stream (seed, replica index + replica_offset). */
+typedef struct qaia_schedule {
+    int32_t variant;     /* QAIA_BSB or QAIA_DSB */
+    int32_t precision;   /* QAIA_FP32, QAIA_BF16, QAIA_FP8 */
+    int32_t steps;       /* T >= 1 */
+    int32_t path;        /* QAIA_PATH_* */
+    float dt;            /* > 0 */
+    float a0;            /* > 0 */
+    float init_amp;      /* >= 0 */
+    float noise_alpha;   /* >= 0; 0 = plain SB, > 0 = noise-injected SB (Eq. 10) */
+    uint64_t seed;
+    uint64_t replica_offset;
+} qaia_schedule;
+
+/* ---------------------------------------------------------------- basics */
+
+int32_t qaia_abi_version(void);
+const char *qaia_status_string(int32_t status);
+/* Detail of the calling thread's last failure ("" if none).  The pointer
+ * stays valid until the thread's next qaia_* call. */
+const char *qaia_last_error(void);
+
+/* ---------------------------------------------------------------- problem */
+
+/* Build a multi-objective MaxCut instance: graph G = (V, E) with n nodes and
+ * m >= 1 edge-weight sets J^(k) (section "Hamiltonian formulation of
+ * multi-objective MaxCut", Eq. 1-3).
+ *   edge_u, edge_v : HOST int32[num_edges], 0 <= u < v < n, no repeated pair.
+ *   weights        : HOST int32[m][num_edges], fixed point.
+ *   frac_bits      : 0..30, fraction bits of the fixed point (informational;
+ *                    all arithmetic is scale-free or exact).
+ *   device         : HIP device ordinal on which the images live.
+ * The inputs are copied; the problem owns its device images and is
+ * immutable afterwards, so it may be used from several streams at once.
+ * Errors: INVALID_ARGUMENT (sizes, ranges, duplicates), OUT_OF_MEMORY,
+ * DEVICE_ERROR; *out is set only on success. */
+int32_t qaia_problem_create(int32_t n, int32_t m, int64_t num_edges, const int32_t *edge_u,
+                            const int32_t *edge_v, const int32_t *weights, int32_t frac_bits,
+                            int32_t device, qaia_problem **out);
+int32_t qaia_problem_destroy(qaia_problem *p);
+
+/* Sizes and properties of a problem: n, m, num_edges, and the per-objective
+ * totals T_k = sum_E W_k (HOST int64[m], may be NULL). */
+int32_t qaia_problem_info(const qaia_problem *p, int32_t *n, int32_t *m, int64_t *num_edges,
+                          int64_t *total_weight);
+
+/* ---------------------------------------------------------------- sampling */
+
+/* Bytes of device workspace qaia_sample needs for W weight vectors and R
+ * replicas each under schedule s. */
+int32_t qaia_sample_workspace_bytes(const qaia_problem *p, int64_t W, int32_t R,
+                                    const qaia_schedule *s, size_t *bytes);
+
+/* Simulated bifurcation for every (weight vector, replica), then the
+ * read-out s_i = sgn(x_i) (sgn 0 = +1) and the exact cut vector of every
+ * sample (Eq. 9, 10 and 1; weighted-sum scalarisation, Eq. 7-8).
+ *   weights : DEVICE float32[W][m], every row c_k >= 0, finite, sum > 0.
+ *             Rows are not renormalised (the dynamics are invariant to a
+ *             positive scale of c).
+ *   s       : HOST schedule.
+ *   spins   : DEVICE uint64[W*R][ceil(n/64)], row = w*R + r.
+ *   obj     : DEVICE int64[W*R][m], C_k of each row's spins.
+ *   workspace, ws_bytes : DEVICE scratch of at least
+ *             qaia_sample_workspace_bytes(); its contents are overwritten.
+ * Errors returned synchronously: INVALID_ARGUMENT, UNSUPPORTED (for example
+ * a reduced precision with ballistic SB), WORKSPACE_TOO_SMALL,
+ * DEVICE_ERROR.  Rows of `weights` that are negative, non-finite or
+ * all-zero cannot be checked on the host: the device marks them in the
+ * workspace, leaves their spins and cut values zero, and
+ * qaia_workspace_status() reports them after the stream is synchronised. */
+int32_t qaia_sample(const qaia_problem *p, const float *weights, int64_t W, int32_t R,
+                    const qaia_schedule *s, uint64_t *spins, int64_t *obj, void *workspace,
+                    size_t ws_bytes, void *hip_stream);
+
+/* Same as qaia_sample and additionally writes x after each of the first
+ * trace_steps steps: DEVICE float32[W*R][trace_steps][n].  Test hook for
+ * trajectory parity; any path that supports tracing may be forced with
+ * s->path. */
+int32_t qaia_sample_trace(const qaia_problem *p, const float *weights, int64_t W, int32_t R,
+                          const qaia_schedule *s, uint64_t *spins, int64_t *obj, void *workspace,
+                          size_t ws_bytes, float *x_trace, int32_t trace_steps, void *hip_stream);
+
+/* After synchronising the stream of a qaia_sample call: QAIA_OK if every
+ * weight row was valid, else QAIA_INVALID_ARGUMENT with *bad_row = the
+ * smallest offending row (HOST int64, may be NULL).  workspace is the
+ * DEVICE workspace of that call; this call synchronises on it. */
+int32_t qaia_workspace_status(const void *workspace, int64_t *bad_row);
+
+/* Exact cut values, Eq. (1): obj[i][k] = sum over edges with s_u != s_v of
+ * W_k.  spins DEVICE uint64[count][ceil(n/64)], obj DEVICE int64[count][m]. */
+int32_t qaia_evaluate(const qaia_problem *p, const uint64_t *spins, int64_t count, int64_t *obj,
+                      void *hip_stream);
+
+/* ---------------------------------------------------------------- filtering */
+
+int32_t qaia_pareto_filter_workspace_bytes(int64_t M, int32_t m, size_t *bytes);
+
+/* Non-dominated filtering of a sample pool, section "Pareto filtering":
+ * in cut (maximisation) space y' dominates y iff y'_k >= y_k for all k and
+ * y' != y (Eq. 4).  Equal objective vectors are merged and represented by
+ * their smallest sample index.
+ *   obj      : DEVICE int64[M][m], 1 <= m <= 8.
+ *   keep_idx : DEVICE int64[M] (capacity M), receives the representatives in
+ *              ascending order.
+ *   num_keep : DEVICE int64[1], receives their count.
+ *   workspace: DEVICE scratch of qaia_pareto_filter_workspace_bytes(M, m). */
+int32_t qaia_pareto_filter(const int64_t *obj, int64_t M, int32_t m, int64_t *keep_idx,
+                           int64_t *num_keep, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* ---------------------------------------------------------------- hypervolume */
+
+/* Exact hypervolume, Eq. (6) and Appendix A: the m-dimensional Lebesgue
+ * measure of the union of boxes [ref, y] over the points.  Points with some
+ * y_k <= ref_k add nothing (their box is clipped to zero width); dominated
+ * and repeated points are allowed.
+ *   pts : HOST int64[P][m], ref : HOST int64[m].
+ *   hv  : HOST uint64[4], the exact value as a 256-bit little-endian integer
+ *         in units of the product of the coordinate units.
+ *   hv_approx : HOST double, may be NULL.
+ * Errors: INVALID_ARGUMENT, OVERFLOW if the sum over objectives of the bit
+ * lengths of (max_k y_k - ref_k) exceeds 256. */
+int32_t qaia_hypervolume(const int64_t *pts, int64_t P, int32_t m, const int64_t *ref,
+                         uint64_t hv[4], double *hv_approx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAIA_H */

@@ -1,0 +1,285 @@
+"""Python binding of libqaia (simulated-bifurcation sampling of multi-objective
+MaxCut on AMD Instinct MI355X).
+
+Thin ctypes layer over the C ABI declared in ``include/qaia.h``: the functions
+carry the ABI's names and only marshal arguments.  PyTorch provides device
+memory (tensors) and streams; every step of the computation runs in the
+library's HIP kernels (or, for the exact hypervolume, its host C++).  Importing
+this module fails loudly when ``libqaia.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+import torch  # loaded first so that libqaia binds to the same HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqaia.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_26477_amd.build` "
+                      "(or __graft_entry__.build())")
+
+_lib = C.CDLL(LIB_PATH)
+
+QAIA_OK, QAIA_INVALID_ARGUMENT, QAIA_UNSUPPORTED, QAIA_OUT_OF_MEMORY = 0, 1, 2, 3
+QAIA_DEVICE_ERROR, QAIA_OVERFLOW, QAIA_WORKSPACE_TOO_SMALL = 4, 5, 6
+VARIANTS = {"bsb": 0, "dsb": 1}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+PATHS = {"auto": 0, "sparse_reg": 1, "sparse_lds": 2, "dense": 3}
+
+
+class qaia_schedule(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("precision", C.c_int32), ("steps", C.c_int32),
+                ("path", C.c_int32), ("dt", C.c_float), ("a0", C.c_float),
+                ("init_amp", C.c_float), ("noise_alpha", C.c_float),
+                ("seed", C.c_uint64), ("replica_offset", C.c_uint64)]
+
+
+_P, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+_SIGS = {
+    "qaia_abi_version": (_i32, []),
+    "qaia_status_string": (C.c_char_p, [_i32]),
+    "qaia_last_error": (C.c_char_p, []),
+    "qaia_problem_create": (_i32, [_i32, _i32, _i64, _P, _P, _P, _i32, _i32, C.POINTER(_P)]),
+    "qaia_problem_destroy": (_i32, [_P]),
+    "qaia_problem_info": (_i32, [_P, _P, _P, _P, _P]),
+    "qaia_sample_workspace_bytes": (_i32, [_P, _i64, _i32, C.POINTER(qaia_schedule), C.POINTER(_sz)]),
+    "qaia_sample": (_i32, [_P, _P, _i64, _i32, C.POINTER(qaia_schedule), _P, _P, _P, _sz, _P]),
+    "qaia_sample_trace": (_i32, [_P, _P, _i64, _i32, C.POINTER(qaia_schedule), _P, _P, _P, _sz, _P,
+                                 _i32, _P]),
+    "qaia_workspace_status": (_i32, [_P, C.POINTER(_i64)]),
+    "qaia_evaluate": (_i32, [_P, _P, _i64, _P, _P]),
+    "qaia_pareto_filter_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
+    "qaia_pareto_filter": (_i32, [_P, _i64, _i32, _P, _P, _P, _sz, _P]),
+    "qaia_hypervolume": (_i32, [_P, _i64, _i32, _P, _P, _P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class QaiaError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        super().__init__(f"{qaia_status_string(status)} ({status}): {detail}")
+
+
+def _check(rc: int):
+    if rc != QAIA_OK:
+        raise QaiaError(rc, qaia_last_error())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return C.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(C.c_void_p)
+    raise TypeError(type(t))
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_tensor(t, dtype, shape, device):
+    if t is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() < int(np.prod(shape)):
+        raise ValueError(f"expected a contiguous {dtype} tensor with at least {int(np.prod(shape))} elements")
+    return t
+
+
+# ------------------------------------------------------------------ basics
+
+def qaia_abi_version() -> int:
+    return int(_lib.qaia_abi_version())
+
+
+def qaia_status_string(status: int) -> str:
+    return _lib.qaia_status_string(status).decode()
+
+
+def qaia_last_error() -> str:
+    return _lib.qaia_last_error().decode()
+
+
+# ------------------------------------------------------------------ problem
+
+class Problem:
+    """Owning handle of a ``qaia_problem``."""
+
+    def __init__(self, handle, n, m, num_edges, device):
+        self.handle, self.n, self.m, self.num_edges, self.device = handle, n, m, num_edges, device
+        self.words = (n + 63) // 64
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and not sys.is_finalizing():  # at interpreter exit the process frees everything
+            _lib.qaia_problem_destroy(h)
+            self.handle = None
+
+    @property
+    def torch_device(self):
+        return torch.device("cuda", self.device)
+
+
+def qaia_problem_create(n, m, edge_u, edge_v, weights, frac_bits=16, device=0) -> Problem:
+    eu = np.ascontiguousarray(edge_u, np.int32)
+    ev = np.ascontiguousarray(edge_v, np.int32)
+    w = np.ascontiguousarray(weights, np.int32).ravel()
+    if eu.shape != ev.shape or w.size < max(m, 0) * eu.shape[0]:
+        raise ValueError("edge_u/edge_v lengths differ or weights hold fewer than m * num_edges values")
+    h = C.c_void_p()
+    _check(_lib.qaia_problem_create(n, m, eu.shape[0], _ptr(eu), _ptr(ev), _ptr(w), frac_bits,
+                                    device, C.byref(h)))
+    return Problem(h, n, m, eu.shape[0], device)
+
+
+def problem_from_instance(inst, device=0) -> Problem:
+    return qaia_problem_create(inst.n, inst.m, inst.edge_u, inst.edge_v, inst.weights,
+                               inst.frac_bits, device)
+
+
+def qaia_problem_destroy(p: Problem):
+    if p.handle:
+        _check(_lib.qaia_problem_destroy(p.handle))
+        p.handle = None
+
+
+def qaia_problem_info(p: Problem):
+    n, m, e = C.c_int32(), C.c_int32(), C.c_int64()
+    tot = np.zeros(p.m, np.int64)
+    _check(_lib.qaia_problem_info(p.handle, C.byref(n), C.byref(m), C.byref(e), _ptr(tot)))
+    return {"n": n.value, "m": m.value, "num_edges": e.value, "total_weight": tot}
+
+
+# ------------------------------------------------------------------ sampling
+
+def make_schedule(variant="bsb", precision="fp32", steps=1000, dt=0.5, a0=1.0, init_amp=0.1,
+                  noise_alpha=0.0, seed=0, replica_offset=0, path="auto") -> qaia_schedule:
+    return qaia_schedule(VARIANTS[variant], PRECISIONS[precision], steps, PATHS[path], dt, a0,
+                         init_amp, noise_alpha, seed & (2**64 - 1), replica_offset)
+
+
+def qaia_sample_workspace_bytes(p: Problem, W: int, R: int, s: qaia_schedule) -> int:
+    b = C.c_size_t()
+    _check(_lib.qaia_sample_workspace_bytes(p.handle, W, R, C.byref(s), C.byref(b)))
+    return b.value
+
+
+def qaia_sample(p: Problem, weights: torch.Tensor, R: int, s: qaia_schedule, spins=None, obj=None,
+                workspace=None, stream=None):
+    """Returns (spins uint64-as-int64 [W*R, words], obj int64 [W*R, m], workspace)."""
+    return _sample(p, weights, R, s, spins, obj, workspace, stream, None, 0)
+
+
+def qaia_sample_trace(p: Problem, weights: torch.Tensor, R: int, s: qaia_schedule, trace_steps: int,
+                      spins=None, obj=None, workspace=None, trace=None, stream=None):
+    """As qaia_sample, plus x after each of the first trace_steps steps [W*R, trace_steps, n]."""
+    W = weights.shape[0]
+    trace = _dev_tensor(trace, torch.float32, (W * R, trace_steps, p.n), p.torch_device)
+    out = _sample(p, weights, R, s, spins, obj, workspace, stream, trace, trace_steps)
+    return (*out, trace)
+
+
+def _sample(p, weights, R, s, spins, obj, workspace, stream, trace, trace_steps):
+    if weights.dtype != torch.float32 or not weights.is_cuda or not weights.is_contiguous():
+        raise ValueError("weights must be a contiguous float32 CUDA tensor [W, m]")
+    W = weights.shape[0]
+    dev = p.torch_device
+    spins = _dev_tensor(spins, torch.int64, (W * R, p.words), dev)
+    obj = _dev_tensor(obj, torch.int64, (W * R, p.m), dev)
+    need = qaia_sample_workspace_bytes(p, W, R, s)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    if trace is None:
+        rc = _lib.qaia_sample(p.handle, _ptr(weights), W, R, C.byref(s), _ptr(spins), _ptr(obj),
+                              _ptr(workspace), workspace.numel() * workspace.element_size(),
+                              _stream(stream))
+    else:
+        rc = _lib.qaia_sample_trace(p.handle, _ptr(weights), W, R, C.byref(s), _ptr(spins),
+                                    _ptr(obj), _ptr(workspace),
+                                    workspace.numel() * workspace.element_size(), _ptr(trace),
+                                    trace_steps, _stream(stream))
+    _check(rc)
+    return spins, obj, workspace
+
+
+def qaia_workspace_status(workspace: torch.Tensor):
+    """None if every weight row was valid, else the smallest invalid row."""
+    bad = C.c_int64(-1)
+    rc = _lib.qaia_workspace_status(_ptr(workspace), C.byref(bad))
+    if rc == QAIA_INVALID_ARGUMENT and bad.value >= 0:
+        return bad.value
+    _check(rc)
+    return None
+
+
+def qaia_evaluate(p: Problem, spins: torch.Tensor, obj=None, stream=None) -> torch.Tensor:
+    count = spins.shape[0]
+    obj = _dev_tensor(obj, torch.int64, (count, p.m), p.torch_device)
+    _check(_lib.qaia_evaluate(p.handle, _ptr(spins), count, _ptr(obj), _stream(stream)))
+    return obj
+
+
+# ------------------------------------------------------------------ filtering
+
+def qaia_pareto_filter_workspace_bytes(M: int, m: int) -> int:
+    b = C.c_size_t()
+    _check(_lib.qaia_pareto_filter_workspace_bytes(M, m, C.byref(b)))
+    return b.value
+
+
+def qaia_pareto_filter(obj: torch.Tensor, keep_idx=None, num_keep=None, workspace=None,
+                       stream=None):
+    """Returns (keep_idx int64 [M] device, num_keep int64 [1] device, workspace)."""
+    if obj.dtype != torch.int64 or not obj.is_contiguous() or obj.dim() != 2:
+        raise ValueError("obj must be a contiguous int64 tensor [M, m]")
+    M, m = obj.shape
+    dev = obj.device
+    keep_idx = _dev_tensor(keep_idx, torch.int64, (max(M, 1),), dev)
+    num_keep = _dev_tensor(num_keep, torch.int64, (1,), dev)
+    need = qaia_pareto_filter_workspace_bytes(M, m)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(_lib.qaia_pareto_filter(_ptr(obj), M, m, _ptr(keep_idx), _ptr(num_keep),
+                                   _ptr(workspace), workspace.numel(), _stream(stream)))
+    return keep_idx, num_keep, workspace
+
+
+def pareto_front(obj: torch.Tensor, stream=None) -> torch.Tensor:
+    """Representative sample indices of the non-dominated set (synchronises)."""
+    keep, num, _ = qaia_pareto_filter(obj, stream=stream)
+    return keep[: int(num.item())]
+
+
+# ------------------------------------------------------------------ hypervolume
+
+def qaia_hypervolume(points, ref) -> int:
+    """Exact hypervolume (Python int) of the union of boxes [ref, y] (host call)."""
+    pts = np.ascontiguousarray(points, np.int64)
+    ref = np.ascontiguousarray(ref, np.int64)
+    if pts.ndim == 1:
+        pts = pts.reshape(-1, ref.shape[0])
+    P, m = pts.shape if pts.size else (0, ref.shape[0])
+    hv = np.zeros(4, np.uint64)
+    approx = C.c_double()
+    _check(_lib.qaia_hypervolume(_ptr(pts) if P else None, P, m, _ptr(ref), _ptr(hv), C.byref(approx)))
+    return sum(int(hv[i]) << (64 * i) for i in range(4))
+
+
+def unpack_spins(spins: np.ndarray, n: int) -> np.ndarray:
+    """Packed rows (bit i set <=> s_i = -1) -> int8 +1/-1 rows [count, n]."""
+    words = np.ascontiguousarray(spins).view(np.uint64)
+    bits = ((words[:, :, None] >> np.arange(64, dtype=np.uint64)[None, None, :]) & np.uint64(1))
+    bits = bits.reshape(words.shape[0], -1)[:, :n].astype(np.int8)
+    return (1 - 2 * bits).astype(np.int8)

@@ -1,0 +1,241 @@
+// extern "C" entry points of libqaia: argument validation, path planning and
+// dispatch.  No C++ exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace qaia {
+Problem *build_problem(int32_t n, int32_t m, int64_t E, const int32_t *eu, const int32_t *ev,
+                       const int32_t *W, int32_t frac_bits, int32_t device);
+const char *last_error_cstr();
+
+namespace {
+
+template <typename F>
+int32_t guarded(F &&f) {
+    clear_error();
+    try {
+        return f();
+    } catch (const Error &e) {
+        return fail(e.status, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(QAIA_OUT_OF_MEMORY, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(QAIA_DEVICE_ERROR, e.what());
+    } catch (...) {
+        return fail(QAIA_DEVICE_ERROR, "unknown error");
+    }
+}
+
+void check_schedule(const Problem &p, const qaia_schedule *s) {
+    QAIA_CHECK(s != nullptr, QAIA_INVALID_ARGUMENT, "null schedule");
+    QAIA_CHECK(s->variant == QAIA_BSB || s->variant == QAIA_DSB, QAIA_INVALID_ARGUMENT,
+               "variant must be QAIA_BSB or QAIA_DSB");
+    QAIA_CHECK(s->precision == QAIA_FP32 || s->precision == QAIA_BF16 || s->precision == QAIA_FP8,
+               QAIA_INVALID_ARGUMENT, "unknown precision");
+    QAIA_CHECK(s->steps >= 1, QAIA_INVALID_ARGUMENT, "steps must be >= 1");
+    QAIA_CHECK(std::isfinite(s->dt) && s->dt > 0.0f, QAIA_INVALID_ARGUMENT, "dt must be finite and > 0");
+    QAIA_CHECK(std::isfinite(s->a0) && s->a0 > 0.0f, QAIA_INVALID_ARGUMENT, "a0 must be finite and > 0");
+    QAIA_CHECK(std::isfinite(s->init_amp) && s->init_amp >= 0.0f, QAIA_INVALID_ARGUMENT,
+               "init_amp must be finite and >= 0");
+    QAIA_CHECK(std::isfinite(s->noise_alpha) && s->noise_alpha >= 0.0f, QAIA_INVALID_ARGUMENT,
+               "noise_alpha must be finite and >= 0");
+    QAIA_CHECK(s->path >= QAIA_PATH_AUTO && s->path <= QAIA_PATH_DENSE, QAIA_INVALID_ARGUMENT,
+               "unknown path");
+    if (s->precision != QAIA_FP32)
+        QAIA_CHECK(s->variant == QAIA_DSB, QAIA_UNSUPPORTED,
+                   "reduced precision needs discrete SB (its phi(x) = sgn(x) is exact)");
+    (void)p;
+}
+
+// Picks the kernel family for a sampling call.
+int plan_path(const Problem &p, const qaia_schedule &s, bool tracing) {
+    (void)tracing;
+    if (s.path != QAIA_PATH_AUTO) return s.path;
+    if (s.precision != QAIA_FP32) return QAIA_PATH_DENSE;
+    if (p.jit[s.variant] != nullptr && s.noise_alpha == 0.0f) return QAIA_PATH_SPARSE_REG;
+    if (sparse_lds_supported(p, nullptr)) return QAIA_PATH_SPARSE_LDS;
+    return QAIA_PATH_DENSE;
+}
+
+int32_t sample_impl(const qaia_problem *pp, const float *weights, int64_t W, int32_t R,
+                    const qaia_schedule *s, uint64_t *spins, int64_t *obj, void *ws, size_t ws_bytes,
+                    float *trace, int32_t trace_steps, void *stream) {
+    QAIA_CHECK(pp != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
+    const Problem &p = *reinterpret_cast<const Problem *>(pp);
+    check_schedule(p, s);
+    QAIA_CHECK(W >= 0, QAIA_INVALID_ARGUMENT, "W must be >= 0");
+    QAIA_CHECK(R >= 1, QAIA_INVALID_ARGUMENT, "R must be >= 1");
+    QAIA_CHECK(W <= (int64_t(1) << 40) / R, QAIA_INVALID_ARGUMENT, "W * R too large");
+    const int64_t rows = W * (int64_t)R;
+    QAIA_CHECK(rows == 0 || (weights && spins && obj), QAIA_INVALID_ARGUMENT, "null weights, spins or obj");
+    QAIA_CHECK(trace_steps >= 0, QAIA_INVALID_ARGUMENT, "trace_steps must be >= 0");
+    QAIA_CHECK(trace_steps == 0 || trace != nullptr, QAIA_INVALID_ARGUMENT, "null trace buffer");
+    const WsLayout L = sample_ws_layout(p, W, R, *s);
+    QAIA_CHECK(ws != nullptr, QAIA_INVALID_ARGUMENT, "null workspace");
+    QAIA_CHECK(ws_bytes >= L.total, QAIA_WORKSPACE_TOO_SMALL,
+               "sample workspace needs " + std::to_string(L.total) + " bytes");
+    const int path = plan_path(p, *s, trace_steps > 0);
+    if (path == QAIA_PATH_DENSE)
+        throw Error{QAIA_UNSUPPORTED, "dense path not available for this call"};
+    hipStream_t st = (hipStream_t)stream;
+    DeviceGuard g(p.device);
+    launch_prep(p, weights, W, *s, ws, L, st);
+    if (rows == 0) return QAIA_OK;
+    if (path == QAIA_PATH_SPARSE_REG)
+        launch_sparse_reg(p, s->variant, W, R, *s, ws, L, spins, obj, trace_steps ? trace : nullptr,
+                          trace_steps, st);
+    else
+        launch_sparse_lds(p, W, R, *s, ws, L, spins, obj, trace_steps ? trace : nullptr,
+                          trace_steps, st);
+    return QAIA_OK;
+}
+
+}  // namespace
+}  // namespace qaia
+
+using namespace qaia;
+
+extern "C" {
+
+int32_t qaia_abi_version(void) { return QAIA_ABI_VERSION; }
+
+const char *qaia_status_string(int32_t status) {
+    switch (status) {
+        case QAIA_OK: return "ok";
+        case QAIA_INVALID_ARGUMENT: return "invalid argument";
+        case QAIA_UNSUPPORTED: return "unsupported";
+        case QAIA_OUT_OF_MEMORY: return "out of memory";
+        case QAIA_DEVICE_ERROR: return "device error";
+        case QAIA_OVERFLOW: return "overflow";
+        case QAIA_WORKSPACE_TOO_SMALL: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+const char *qaia_last_error(void) { return last_error_cstr(); }
+
+int32_t qaia_problem_create(int32_t n, int32_t m, int64_t num_edges, const int32_t *edge_u,
+                            const int32_t *edge_v, const int32_t *weights, int32_t frac_bits,
+                            int32_t device, qaia_problem **out) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(out != nullptr, QAIA_INVALID_ARGUMENT, "null output pointer");
+        Problem *p = build_problem(n, m, num_edges, edge_u, edge_v, weights, frac_bits, device);
+        *out = reinterpret_cast<qaia_problem *>(p);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_problem_destroy(qaia_problem *p) {
+    return guarded([&]() -> int32_t {
+        delete reinterpret_cast<Problem *>(p);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_problem_info(const qaia_problem *pp, int32_t *n, int32_t *m, int64_t *num_edges,
+                          int64_t *total_weight) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(pp != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
+        const Problem &p = *reinterpret_cast<const Problem *>(pp);
+        if (n) *n = p.n;
+        if (m) *m = p.m;
+        if (num_edges) *num_edges = p.E;
+        if (total_weight) std::memcpy(total_weight, p.total.data(), sizeof(int64_t) * p.m);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_sample_workspace_bytes(const qaia_problem *pp, int64_t W, int32_t R,
+                                    const qaia_schedule *s, size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(pp != nullptr && bytes != nullptr, QAIA_INVALID_ARGUMENT, "null argument");
+        const Problem &p = *reinterpret_cast<const Problem *>(pp);
+        check_schedule(p, s);
+        QAIA_CHECK(W >= 0 && R >= 1, QAIA_INVALID_ARGUMENT, "W must be >= 0 and R >= 1");
+        *bytes = sample_ws_layout(p, W, R, *s).total;
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_sample(const qaia_problem *p, const float *weights, int64_t W, int32_t R,
+                    const qaia_schedule *s, uint64_t *spins, int64_t *obj, void *workspace,
+                    size_t ws_bytes, void *hip_stream) {
+    return guarded([&]() {
+        return sample_impl(p, weights, W, R, s, spins, obj, workspace, ws_bytes, nullptr, 0,
+                           hip_stream);
+    });
+}
+
+int32_t qaia_sample_trace(const qaia_problem *p, const float *weights, int64_t W, int32_t R,
+                          const qaia_schedule *s, uint64_t *spins, int64_t *obj, void *workspace,
+                          size_t ws_bytes, float *x_trace, int32_t trace_steps, void *hip_stream) {
+    return guarded([&]() {
+        return sample_impl(p, weights, W, R, s, spins, obj, workspace, ws_bytes, x_trace,
+                           trace_steps, hip_stream);
+    });
+}
+
+int32_t qaia_workspace_status(const void *workspace, int64_t *bad_row) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(workspace != nullptr, QAIA_INVALID_ARGUMENT, "null workspace");
+        WsHeader h;
+        QAIA_HIP(hipMemcpy(&h, workspace, sizeof(h), hipMemcpyDeviceToHost));
+        QAIA_CHECK(h.magic == kWsMagic, QAIA_INVALID_ARGUMENT, "not a sampling workspace");
+        if (bad_row) *bad_row = h.bad_row == INT64_MAX ? -1 : h.bad_row;
+        if (h.bad_row != INT64_MAX)
+            return fail(QAIA_INVALID_ARGUMENT,
+                        "weight row " + std::to_string(h.bad_row) + " is negative, non-finite or all zero");
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_evaluate(const qaia_problem *pp, const uint64_t *spins, int64_t count, int64_t *obj,
+                      void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(pp != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
+        QAIA_CHECK(count >= 0, QAIA_INVALID_ARGUMENT, "count must be >= 0");
+        QAIA_CHECK(count == 0 || (spins && obj), QAIA_INVALID_ARGUMENT, "null spins or obj");
+        const Problem &p = *reinterpret_cast<const Problem *>(pp);
+        DeviceGuard g(p.device);
+        launch_evaluate(p, spins, count, obj, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_pareto_filter_workspace_bytes(int64_t M, int32_t m, size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(bytes != nullptr, QAIA_INVALID_ARGUMENT, "null argument");
+        QAIA_CHECK(M >= 0 && M < (int64_t(1) << 31), QAIA_INVALID_ARGUMENT, "M must be in [0, 2^31)");
+        QAIA_CHECK(m >= 1 && m <= 8, QAIA_INVALID_ARGUMENT, "m must be in [1, 8]");
+        *bytes = pareto_ws_bytes(M, m);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_pareto_filter(const int64_t *obj, int64_t M, int32_t m, int64_t *keep_idx,
+                           int64_t *num_keep, void *workspace, size_t ws_bytes, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(M >= 0 && M < (int64_t(1) << 31), QAIA_INVALID_ARGUMENT, "M must be in [0, 2^31)");
+        QAIA_CHECK(m >= 1 && m <= 8, QAIA_INVALID_ARGUMENT, "m must be in [1, 8]");
+        QAIA_CHECK(num_keep != nullptr, QAIA_INVALID_ARGUMENT, "null num_keep");
+        QAIA_CHECK(M == 0 || (obj && keep_idx && workspace), QAIA_INVALID_ARGUMENT,
+                   "null obj, keep_idx or workspace");
+        launch_pareto(obj, M, m, keep_idx, num_keep, workspace, ws_bytes, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_hypervolume(const int64_t *pts, int64_t P, int32_t m, const int64_t *ref,
+                         uint64_t hv[4], double *hv_approx) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(P >= 0, QAIA_INVALID_ARGUMENT, "P must be >= 0");
+        QAIA_CHECK(m >= 1 && m <= 64, QAIA_INVALID_ARGUMENT, "m must be in [1, 64]");
+        QAIA_CHECK(ref != nullptr && hv != nullptr, QAIA_INVALID_ARGUMENT, "null ref or hv");
+        QAIA_CHECK(P == 0 || pts != nullptr, QAIA_INVALID_ARGUMENT, "null points");
+        return hypervolume_exact(pts, P, m, ref, hv, hv_approx);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,276 @@
+// Exact hypervolume on the host, Eq. (6) and Appendix A.
+//
+// Points are translated to extents e = max(y - ref, 0) (clipping leaves the
+// union of boxes [ref, y] unchanged).  The volume is accumulated exactly in a
+// 256-bit unsigned integer:
+//   m = 1: the largest extent;
+//   m = 2: the staircase area;
+//   m = 3: a sweep in decreasing third coordinate that keeps the
+//          two-dimensional non-dominated staircase of the points seen so far
+//          in an ordered map and updates its area incrementally on insertion
+//          (the dimension-sweep idea of Fonseca, Paquete and Lopez-Ibanez,
+//          CEC 2006), O(P log P);
+//   m >= 4: the exclusive-volume recursion of the WFG algorithm (While,
+//          Bradstreet and Barone, IEEE TEVC 2012): with the points in
+//          increasing last coordinate, HV(S) = sum_i p_i,last *
+//          (prod_{k<last} p_i,k - HV_{m-1}(limit_i)), where limit_i holds
+//          min(q, p_i) over the later points q projected to the first m-1
+//          coordinates (their last coordinate is p_i,last for all of them).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace qaia {
+namespace {
+
+typedef unsigned __int128 u128;
+
+struct U256 {
+    uint64_t w[4] = {0, 0, 0, 0};
+};
+
+U256 from128(u128 v) {
+    U256 r;
+    r.w[0] = (uint64_t)v;
+    r.w[1] = (uint64_t)(v >> 64);
+    return r;
+}
+
+U256 add(const U256 &a, const U256 &b) {
+    U256 r;
+    u128 c = 0;
+    for (int i = 0; i < 4; ++i) {
+        u128 s = (u128)a.w[i] + b.w[i] + c;
+        r.w[i] = (uint64_t)s;
+        c = s >> 64;
+    }
+    return r;
+}
+
+// a - b with a >= b
+U256 sub(const U256 &a, const U256 &b) {
+    U256 r;
+    uint64_t borrow = 0;
+    for (int i = 0; i < 4; ++i) {
+        uint64_t bi = b.w[i] + borrow;
+        uint64_t nb = (bi < borrow) || (a.w[i] < bi) ? 1 : 0;
+        r.w[i] = a.w[i] - bi;
+        borrow = nb;
+    }
+    return r;
+}
+
+U256 mul64(const U256 &a, uint64_t b) {
+    U256 r;
+    u128 c = 0;
+    for (int i = 0; i < 4; ++i) {
+        u128 p = (u128)a.w[i] * b + c;
+        r.w[i] = (uint64_t)p;
+        c = p >> 64;
+    }
+    return r;
+}
+
+double to_double(const U256 &a) {
+    double r = 0.0;
+    for (int i = 3; i >= 0; --i) r = r * 18446744073709551616.0 + (double)a.w[i];
+    return r;
+}
+
+// 2-D staircase area of the points seen so far, updated on insertion.
+// Map key x (ascending), value y; kept non-dominated, so y descends with x.
+struct Staircase {
+    std::map<uint64_t, uint64_t> pts;
+    u128 area = 0;
+
+    // area of the segments of the points in [first, last) given the x of the
+    // point left of first (0 if none)
+    static u128 seg_sum(std::map<uint64_t, uint64_t>::iterator first,
+                        std::map<uint64_t, uint64_t>::iterator last, uint64_t left_x) {
+        u128 s = 0;
+        for (auto it = first; it != last; ++it) {
+            s += (u128)(it->first - left_x) * it->second;
+            left_x = it->first;
+        }
+        return s;
+    }
+
+    void insert(uint64_t x, uint64_t y) {
+        if (x == 0 || y == 0) return;
+        // dominated by (or equal to) a stored point: some stored px >= x with py >= y;
+        // among the points with px >= x the first one has the largest y.
+        auto ge = pts.lower_bound(x);
+        if (ge != pts.end() && ge->second >= y) return;
+        // every stored point with px >= x now has py < y.  Stored points
+        // dominated by (x, y) (px <= x and py <= y) form a contiguous run: the
+        // points left of `ge` with py <= y, plus `ge` itself when px == x.
+        auto right = ge;  // first surviving point to the right of x
+        if (right != pts.end() && right->first == x) ++right;
+        auto first = ge;
+        while (first != pts.begin()) {
+            auto prev = std::prev(first);
+            if (prev->second <= y)
+                first = prev;
+            else
+                break;
+        }
+        uint64_t left_x = first == pts.begin() ? 0 : std::prev(first)->first;
+        // segments whose area changes: the removed run and the right neighbour
+        auto stop = right == pts.end() ? right : std::next(right);
+        u128 before = seg_sum(first, stop, left_x);
+        u128 after = (u128)(x - left_x) * y;
+        if (right != pts.end()) after += (u128)(right->first - x) * right->second;
+        pts.erase(first, right);
+        pts.emplace(x, y);
+        area = area - before + after;
+    }
+};
+
+U256 hv2(std::vector<const uint64_t *> &P, int kx, int ky) {
+    std::sort(P.begin(), P.end(), [ky](const uint64_t *a, const uint64_t *b) { return a[ky] > b[ky]; });
+    U256 vol;
+    uint64_t best = 0;
+    for (size_t i = 0; i < P.size(); ++i) {
+        best = std::max(best, P[i][kx]);
+        uint64_t next = i + 1 < P.size() ? P[i + 1][ky] : 0;
+        uint64_t h = P[i][ky] - next;
+        if (h) vol = add(vol, from128((u128)best * h));
+    }
+    return vol;
+}
+
+// 3-D sweep over coordinates (0, 1, 2); dominated points are harmless.
+U256 hv3(std::vector<const uint64_t *> &P) {
+    std::sort(P.begin(), P.end(), [](const uint64_t *a, const uint64_t *b) { return a[2] > b[2]; });
+    Staircase st;
+    U256 vol;
+    for (size_t i = 0; i < P.size(); ++i) {
+        st.insert(P[i][0], P[i][1]);
+        uint64_t next = i + 1 < P.size() ? P[i + 1][2] : 0;
+        uint64_t h = P[i][2] - next;
+        if (h && st.area) {
+            U256 a = from128(st.area);
+            vol = add(vol, mul64(a, h));
+        }
+    }
+    return vol;
+}
+
+// Non-dominated subset in the first d coordinates (dominated and repeated
+// points removed), used to keep the WFG limit sets small.
+void nondominated(std::vector<uint64_t> &buf, int stride, int d, size_t &count) {
+    std::vector<size_t> order(count);
+    for (size_t i = 0; i < count; ++i) order[i] = i;
+    auto sum = [&](size_t i) {
+        long double s = 0;
+        for (int k = 0; k < d; ++k) s += (long double)buf[i * stride + k];
+        return s;
+    };
+    std::vector<long double> key(count);
+    for (size_t i = 0; i < count; ++i) key[i] = sum(i);
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return key[a] > key[b]; });
+    std::vector<size_t> keep;
+    for (size_t oi = 0; oi < count; ++oi) {
+        const uint64_t *q = &buf[order[oi] * stride];
+        bool any_zero = false;
+        for (int k = 0; k < d; ++k) any_zero |= q[k] == 0;
+        if (any_zero) continue;
+        bool dominated = false;
+        for (size_t kj : keep) {  // a dominator has a sum at least as large: it is kept already
+            const uint64_t *p = &buf[kj * stride];
+            bool ge = true;
+            for (int k = 0; k < d && ge; ++k) ge = p[k] >= q[k];
+            if (ge) {
+                dominated = true;
+                break;
+            }
+        }
+        if (!dominated) keep.push_back(order[oi]);
+    }
+    std::vector<uint64_t> out(keep.size() * stride);
+    for (size_t i = 0; i < keep.size(); ++i)
+        std::memcpy(&out[i * stride], &buf[keep[i] * stride], sizeof(uint64_t) * stride);
+    buf.swap(out);
+    count = keep.size();
+}
+
+// HV of `count` points (rows of `buf` with `stride`) in the first d >= 3 coordinates.
+U256 wfg(std::vector<uint64_t> buf, int stride, int d, size_t count) {
+    if (count == 0) return U256();
+    if (d == 3) {
+        std::vector<const uint64_t *> P(count);
+        for (size_t i = 0; i < count; ++i) P[i] = &buf[i * stride];
+        return hv3(P);
+    }
+    const int last = d - 1;
+    std::vector<size_t> order(count);
+    for (size_t i = 0; i < count; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(),
+              [&](size_t a, size_t b) { return buf[a * stride + last] < buf[b * stride + last]; });
+    U256 total;
+    std::vector<uint64_t> lim;
+    for (size_t oi = 0; oi < count; ++oi) {
+        const uint64_t *p = &buf[order[oi] * stride];
+        if (p[last] == 0) continue;
+        U256 box;
+        box.w[0] = 1;
+        for (int k = 0; k < last; ++k) box = mul64(box, p[k]);
+        size_t L = count - oi - 1;
+        lim.assign(L * stride, 0);
+        for (size_t j = 0; j < L; ++j) {
+            const uint64_t *q = &buf[order[oi + 1 + j] * stride];
+            for (int k = 0; k < last; ++k) lim[j * stride + k] = std::min(p[k], q[k]);
+        }
+        nondominated(lim, stride, last, L);
+        U256 covered = wfg(lim, stride, last, L);
+        total = add(total, mul64(sub(box, covered), p[last]));
+    }
+    return total;
+}
+
+}  // namespace
+
+int32_t hypervolume_exact(const int64_t *pts, int64_t P, int32_t m, const int64_t *ref,
+                          uint64_t hv[4], double *approx) {
+    for (int i = 0; i < 4; ++i) hv[i] = 0;
+    if (approx) *approx = 0.0;
+    if (P == 0) return QAIA_OK;
+    std::vector<uint64_t> ext((size_t)P * m);
+    int bits_total = 0;
+    for (int k = 0; k < m; ++k) {
+        uint64_t mx = 0;
+        for (int64_t i = 0; i < P; ++i) {
+            __int128 d = (__int128)pts[i * m + k] - (__int128)ref[k];
+            uint64_t v = d > 0 ? (uint64_t)d : 0;
+            ext[(size_t)i * m + k] = v;
+            mx = std::max(mx, v);
+        }
+        int b = 0;
+        while (b < 64 && (mx >> b) != 0) ++b;
+        bits_total += b;
+    }
+    if (bits_total > 256) return fail(QAIA_OVERFLOW, "hypervolume range exceeds 2^256");
+    U256 v;
+    if (m == 1) {
+        uint64_t mx = 0;
+        for (int64_t i = 0; i < P; ++i) mx = std::max(mx, ext[i]);
+        v.w[0] = mx;
+    } else if (m == 2) {
+        std::vector<const uint64_t *> Pp(P);
+        for (int64_t i = 0; i < P; ++i) Pp[i] = &ext[(size_t)i * 2];
+        v = hv2(Pp, 0, 1);
+    } else {
+        size_t count = (size_t)P;
+        nondominated(ext, m, m, count);
+        v = wfg(ext, m, m, count);
+    }
+    for (int i = 0; i < 4; ++i) hv[i] = v.w[i];
+    if (approx) *approx = to_double(v);
+    return QAIA_OK;
+}
+
+}  // namespace qaia

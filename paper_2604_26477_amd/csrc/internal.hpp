@@ -1,0 +1,115 @@
+// Internal declarations of libqaia (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/qaia.h"
+
+namespace qaia {
+
+// ----------------------------------------------------------------- errors
+struct Error {
+    int32_t status;
+    std::string msg;
+};
+
+void set_error(const std::string &msg);
+void clear_error();
+int32_t fail(int32_t status, const std::string &msg);  // records msg, returns status
+
+#define QAIA_HIP(call)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            throw ::qaia::Error{QAIA_DEVICE_ERROR, std::string(#call) + ": " +              \
+                                                       hipGetErrorString(e_)};              \
+    } while (0)
+
+#define QAIA_CHECK(cond, status, msg)                           \
+    do {                                                        \
+        if (!(cond)) throw ::qaia::Error{(status), (msg)};      \
+    } while (0)
+
+// Scoped device switch.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+};
+
+// ----------------------------------------------------------------- problem
+struct JitKernel;  // generated per-graph kernel (jit.cpp)
+
+struct Problem {
+    int32_t n = 0, m = 0, frac_bits = 0, device = 0;
+    int64_t E = 0;
+    int32_t words = 0;  // ceil(n / 64)
+    std::vector<int32_t> eu, ev, W;      // host copies, W is [m][E]
+    std::vector<int32_t> rowptr, col, eid;  // CSR over nodes (both directions)
+    std::vector<int64_t> total;          // T_k = sum_E W_k
+    int32_t max_degree = 0;
+    // device images
+    int32_t *d_eu = nullptr, *d_ev = nullptr, *d_W = nullptr;
+    int32_t *d_rowptr = nullptr, *d_col = nullptr, *d_eid = nullptr;
+    int64_t *d_rho = nullptr;  // [m][n] row sums sum_j W_k,ij (exact)
+    // generated register-resident kernels, index = variant (bSB, dSB)
+    JitKernel *jit[2] = {nullptr, nullptr};
+    std::string jit_error;
+    std::mutex mu;
+    ~Problem();
+};
+
+// ----------------------------------------------------------------- sampling workspace
+// Layout of the caller's workspace for qaia_sample (all offsets 256-aligned):
+//   header   : WsHeader
+//   kt       : float[T]          per-step coefficient -dt (a0 - a_t)
+//   c0s      : float[W]          dt*c0 per weight row; negative marks an invalid row
+//   jcp      : float[W][E]       folded edge coefficients -dt c0 J(c)_e (sparse paths)
+struct WsHeader {
+    uint64_t magic;
+    int64_t bad_row;  // smallest invalid weight row, INT64_MAX if none
+    int64_t W;
+    int64_t reserved;
+};
+constexpr uint64_t kWsMagic = 0x7161696177733031ull;  // "qaiaws01"
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct WsLayout {
+    size_t header = 0, kt = 0, c0s = 0, jcp = 0, total = 0;
+};
+WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s);
+
+// ----------------------------------------------------------------- kernels (host launchers)
+void launch_prep(const Problem &p, const float *weights, int64_t W, const qaia_schedule &s,
+                 void *ws, const WsLayout &L, hipStream_t st);
+void launch_sparse_lds(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws,
+                       const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
+                       int32_t trace_steps, hipStream_t st);
+bool sparse_lds_supported(const Problem &p, std::string *why);
+void launch_evaluate(const Problem &p, const uint64_t *spins, int64_t count, int64_t *obj,
+                     hipStream_t st);
+
+// generated kernels (jit.cpp)
+bool jit_eligible(const Problem &p, std::string *why);
+void jit_prepare(Problem &p);  // compiles both variants if eligible; records failures
+void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, const qaia_schedule &s,
+                       void *ws, const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
+                       int32_t trace_steps, hipStream_t st);
+void jit_release(JitKernel *k);
+
+// pareto filter (pareto.hip)
+size_t pareto_ws_bytes(int64_t M, int32_t m);
+void launch_pareto(const int64_t *obj, int64_t M, int32_t m, int64_t *keep, int64_t *num_keep,
+                   void *ws, size_t ws_bytes, hipStream_t st);
+
+// hypervolume (hypervolume.cpp)
+int32_t hypervolume_exact(const int64_t *pts, int64_t P, int32_t m, const int64_t *ref,
+                          uint64_t hv[4], double *approx);
+
+}  // namespace qaia

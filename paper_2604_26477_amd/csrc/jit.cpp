@@ -1,0 +1,310 @@
+// Per-graph generated sparse SB kernel.
+//
+// For a small sparse graph the fastest layout on CDNA is one replica per lane
+// with every soft spin x_i, momentum y_i and folded edge coefficient in
+// VGPRs: the graph (which x_j feeds which y_i) is fixed for the whole run, so
+// it is emitted as straight-line code and the T-step loop touches no memory
+// except one scalar load of the step coefficient.  A VGPR cannot be indexed by
+// a run-time neighbour id without extra instructions, hence the code is
+// generated per graph and compiled once, device-only, by the ROCm clang found
+// at ROCM_PATH (child process), then loaded as a module on the problem's
+// device.  The instance's integer weights are baked in as literals for the
+// fused exact cut evaluation.
+#include <fcntl.h>
+#include <spawn.h>
+#include <sys/stat.h>
+#include <sys/wait.h>
+#include <unistd.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "internal.hpp"
+
+extern char **environ;
+
+namespace qaia {
+
+struct JitKernel {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    int device = 0;
+};
+
+void jit_release(JitKernel *k) {
+    if (!k) return;
+    if (k->mod) {
+        DeviceGuard g(k->device);
+        (void)hipModuleUnload(k->mod);
+    }
+    delete k;
+}
+
+bool jit_eligible(const Problem &p, std::string *why) {
+    if (std::getenv("QAIA_DISABLE_JIT")) {
+        if (why) *why = "disabled by QAIA_DISABLE_JIT";
+        return false;
+    }
+    if (p.m > 8) {
+        if (why) *why = "more than 8 objectives";
+        return false;
+    }
+    // x, y and the edge coefficients live in VGPRs (plus ~20 temporaries);
+    // keep the kernel within 256 VGPRs (two waves per SIMD).
+    if (2 * (int64_t)p.n + p.E > 232) {
+        if (why) *why = "graph too large for register-resident state";
+        return false;
+    }
+    return true;
+}
+
+static const char *kPrelude = R"(#define __global__ __attribute__((global))
+#define __device__ __attribute__((device))
+#define __forceinline__ inline __attribute__((always_inline))
+typedef unsigned long long u64;
+typedef long long i64;
+typedef unsigned int u32;
+__device__ __forceinline__ u64 sm64(u64 seed, u64 idx) {
+  u64 z = seed + (idx + 1ull) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ float initv(u64 seed, u64 idx, float amp) {
+  u64 b = sm64(seed, idx);
+  float u = (float)(u32)(b >> 40) * 0x1p-24f;
+  return amp * (2.0f * u - 1.0f);
+}
+)";
+
+static std::string generate(const Problem &p, int variant) {
+    const int n = p.n, m = p.m;
+    const int64_t E = p.E;
+    const bool dsb = variant == QAIA_DSB;
+    std::ostringstream s;
+    s << kPrelude;
+    s << "extern \"C\" __global__ __attribute__((amdgpu_flat_work_group_size(1, 256)))\n"
+         "void qaia_sb_reg(const float* __restrict__ jcp, const float* __restrict__ c0s,\n"
+         "  const float* __restrict__ kt_tab, i64 rows, int R, int T, float dta0, u64 seed,\n"
+         "  u64 offset, float amp, u64* __restrict__ spins, i64* __restrict__ obj,\n"
+         "  float* __restrict__ trace, int trace_steps) {\n";
+    s << "  const i64 row = (i64)__builtin_amdgcn_workgroup_id_x() * 256 + "
+         "(i64)__builtin_amdgcn_workitem_id_x();\n";
+    s << "  if (row >= rows) return;\n";
+    s << "  const i64 w = row / R;\n";
+    s << "  const u64 g = (u64)row + offset;\n";
+    s << "  if (c0s[w] < 0.0f) {\n";
+    for (int wd = 0; wd < p.words; ++wd) s << "    spins[row * " << p.words << " + " << wd << "] = 0ull;\n";
+    for (int k = 0; k < m; ++k) s << "    obj[row * " << m << " + " << k << "] = 0ll;\n";
+    s << "    return;\n  }\n";
+    for (int i = 0; i < n; ++i)
+        s << "  float X" << i << " = initv(seed, ((g * " << n << "ull + " << i << "ull) << 1), amp), Y"
+          << i << " = initv(seed, ((g * " << n << "ull + " << i << "ull) << 1) | 1ull, amp);\n";
+    s << "  const float* jr = jcp + w * " << E << "ll;\n";
+    for (int64_t e = 0; e < E; ++e) s << "  const float J" << e << " = jr[" << e << "];\n";
+    s << "  for (int t = 0; t < T; ++t) {\n";
+    s << "    const float kt = kt_tab[t];\n";
+    if (dsb)
+        for (int i = 0; i < n; ++i)
+            s << "    const float S" << i << " = X" << i << " >= 0.0f ? 1.0f : -1.0f;\n";
+    // y_i += kt x_i + sum_j Jc'_ij phi(x_j), every phi from the pre-step x
+    for (int i = 0; i < n; ++i) {
+        s << "    Y" << i << " = __builtin_fmaf(kt, X" << i << ", Y" << i << ");";
+        for (int q = p.rowptr[i]; q < p.rowptr[i + 1]; ++q)
+            s << " Y" << i << " = __builtin_fmaf(J" << p.eid[q] << ", " << (dsb ? "S" : "X")
+              << p.col[q] << ", Y" << i << ");";
+        s << "\n";
+    }
+    // x_i += dt a0 y_i, then the inelastic wall
+    for (int i = 0; i < n; ++i) {
+        s << "    X" << i << " = __builtin_fmaf(dta0, Y" << i << ", X" << i << "); { const float c = "
+          << "__builtin_fminf(__builtin_fmaxf(X" << i << ", -1.0f), 1.0f); Y" << i << " = (c == X"
+          << i << ") ? Y" << i << " : 0.0f; X" << i << " = c; }\n";
+    }
+    s << "    if (trace != nullptr && t < trace_steps) {\n";
+    s << "      float* tr = trace + (row * trace_steps + t) * " << n << "ll;\n";
+    for (int i = 0; i < n; ++i) s << "      tr[" << i << "] = X" << i << ";\n";
+    s << "    }\n  }\n";
+    // read-out: bit i set <=> x_i < 0 (sgn 0 = +1)
+    for (int wd = 0; wd < p.words; ++wd) {
+        s << "  { u64 b = 0ull;";
+        for (int i = wd * 64; i < n && i < wd * 64 + 64; ++i)
+            s << " b |= (u64)(X" << i << " < 0.0f) << " << (i - wd * 64) << ";";
+        s << " spins[row * " << p.words << " + " << wd << "] = b; }\n";
+    }
+    // exact cut values, Eq. (1), weights as literals
+    for (int k = 0; k < m; ++k) {
+        int64_t absum = 0;
+        for (int64_t e = 0; e < E; ++e) absum += std::llabs((long long)p.W[(size_t)k * E + e]);
+        const bool narrow = absum < (int64_t(1) << 31);
+        s << "  { " << (narrow ? "int" : "i64") << " a = 0;";
+        for (int64_t e = 0; e < E; ++e) {
+            const int32_t wv = p.W[(size_t)k * E + e];
+            if (wv == 0) continue;
+            s << " a += ((X" << p.eu[e] << " < 0.0f) != (X" << p.ev[e] << " < 0.0f)) ? ("
+              << (narrow ? "int" : "i64") << ")(" << wv << ") : 0;";
+        }
+        s << " obj[row * " << m << " + " << k << "] = (i64)a; }\n";
+    }
+    s << "}\n";
+    return s.str();
+}
+
+static uint64_t fnv1a(const std::string &s) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+static std::string find_clang() {
+    if (const char *e = std::getenv("QAIA_CLANG")) return e;
+    std::string root = "/opt/rocm";
+    if (const char *r = std::getenv("ROCM_PATH")) root = r;
+    return root + "/llvm/bin/clang++";
+}
+
+// Compile one source to a raw gfx950 code object in a private temp dir.
+static std::vector<char> compile(const std::string &src) {
+    const char *tmpenv = std::getenv("TMPDIR");
+    std::string tmpl = std::string(tmpenv && *tmpenv ? tmpenv : "/tmp") + "/qaia_jit_XXXXXX";
+    std::vector<char> dirbuf(tmpl.begin(), tmpl.end());
+    dirbuf.push_back('\0');
+    QAIA_CHECK(mkdtemp(dirbuf.data()) != nullptr, QAIA_UNSUPPORTED,
+               "cannot create a temporary directory for kernel generation");
+    const std::string dir(dirbuf.data());
+    const std::string in = dir + "/k.hip", out = dir + "/k.hsaco", log = dir + "/k.log";
+    {
+        std::ofstream f(in);
+        f << src;
+    }
+    const std::string clang = find_clang();
+    std::vector<std::string> args = {clang,
+                                     "-x",
+                                     "hip",
+                                     "--offload-arch=gfx950",
+                                     "--offload-device-only",
+                                     "--no-gpu-bundle-output",
+                                     "-nogpuinc",
+                                     "-nogpulib",
+                                     "-O3",
+                                     "-mcode-object-version=5",
+                                     "-Xclang",
+                                     "-target-feature",
+                                     "-Xclang",
+                                     "-packed-fp32-ops",
+                                     "-c",
+                                     in,
+                                     "-o",
+                                     out};
+    std::vector<char *> argv;
+    for (auto &a : args) argv.push_back(const_cast<char *>(a.c_str()));
+    argv.push_back(nullptr);
+    posix_spawn_file_actions_t fa;
+    posix_spawn_file_actions_init(&fa);
+    posix_spawn_file_actions_addopen(&fa, 1, log.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0600);
+    posix_spawn_file_actions_adddup2(&fa, 1, 2);
+    pid_t pid;
+    int rc = posix_spawn(&pid, clang.c_str(), &fa, nullptr, argv.data(), environ);
+    posix_spawn_file_actions_destroy(&fa);
+    std::vector<char> code;
+    std::string err;
+    if (rc != 0) {
+        err = "cannot start " + clang + ": " + std::strerror(rc);
+    } else {
+        int status = 0;
+        waitpid(pid, &status, 0);
+        if (!WIFEXITED(status) || WEXITSTATUS(status) != 0) {
+            std::ifstream lf(log);
+            std::stringstream ls;
+            ls << lf.rdbuf();
+            err = "kernel generation failed: " + ls.str().substr(0, 2000);
+        } else {
+            std::ifstream f(out, std::ios::binary);
+            code.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+            if (code.empty()) err = "kernel generation produced no code object";
+        }
+    }
+    std::remove(in.c_str());
+    std::remove(out.c_str());
+    std::remove(log.c_str());
+    rmdir(dir.c_str());
+    QAIA_CHECK(err.empty(), QAIA_UNSUPPORTED, err);
+    return code;
+}
+
+static std::mutex g_cache_mu;
+static std::map<uint64_t, std::vector<char>> g_cache;  // source hash -> code object
+
+void jit_prepare(Problem &p) {
+    std::string why;
+    if (!jit_eligible(p, &why)) {
+        p.jit_error = why;
+        return;
+    }
+    for (int variant = 0; variant < 2; ++variant) {
+        try {
+            const std::string src = generate(p, variant);
+            const uint64_t h = fnv1a(src);
+            std::vector<char> code;
+            {
+                std::lock_guard<std::mutex> lk(g_cache_mu);
+                auto it = g_cache.find(h);
+                if (it != g_cache.end()) code = it->second;
+            }
+            if (code.empty()) {
+                code = compile(src);
+                std::lock_guard<std::mutex> lk(g_cache_mu);
+                g_cache[h] = code;
+            }
+            JitKernel *k = new JitKernel();
+            k->device = p.device;
+            DeviceGuard g(p.device);
+            hipError_t e = hipModuleLoadData(&k->mod, code.data());
+            if (e == hipSuccess) e = hipModuleGetFunction(&k->fn, k->mod, "qaia_sb_reg");
+            if (e != hipSuccess) {
+                std::string msg = std::string("loading the generated kernel: ") + hipGetErrorString(e);
+                jit_release(k);
+                throw Error{QAIA_DEVICE_ERROR, msg};
+            }
+            p.jit[variant] = k;
+        } catch (const Error &err) {
+            p.jit_error = err.msg;
+            return;
+        }
+    }
+}
+
+void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, const qaia_schedule &s,
+                       void *ws, const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
+                       int32_t trace_steps, hipStream_t st) {
+    const JitKernel *k = p.jit[variant];
+    QAIA_CHECK(k != nullptr, QAIA_UNSUPPORTED,
+               "register-resident path unavailable: " + (p.jit_error.empty() ? std::string("not built") : p.jit_error));
+    QAIA_CHECK(s.noise_alpha == 0.0f, QAIA_UNSUPPORTED,
+               "register-resident path runs plain SB only (noise_alpha must be 0)");
+    const int64_t rows = W * (int64_t)R;
+    if (rows == 0) return;
+    const int64_t blocks = (rows + 255) / 256;
+    QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many replicas for one launch");
+    char *b = (char *)ws;
+    const float *jcp = (const float *)(b + L.jcp), *c0s = (const float *)(b + L.c0s),
+                *kt = (const float *)(b + L.kt);
+    int T = s.steps;
+    float dta0 = s.dt * s.a0, amp = s.init_amp;
+    uint64_t seed = s.seed, off = s.replica_offset;
+    int64_t rows_ = rows;
+    int R_ = R, ts = trace_steps;
+    void *args[] = {(void *)&jcp, (void *)&c0s, (void *)&kt,   (void *)&rows_, (void *)&R_,
+                    (void *)&T,   (void *)&dta0, (void *)&seed, (void *)&off,  (void *)&amp,
+                    (void *)&spins, (void *)&obj, (void *)&trace, (void *)&ts};
+    QAIA_HIP(hipModuleLaunchKernel(k->fn, (unsigned)blocks, 1, 1, 256, 1, 1, 0, st, args, nullptr));
+}
+
+}  // namespace qaia

@@ -1,0 +1,248 @@
+// Non-dominated filtering of a sample pool (section "Pareto filtering",
+// dominance of Eq. 4 in cut / maximisation space) with duplicate merging.
+//
+// 1. Order all M objective vectors lexicographically descending with m
+//    stable radix passes (last objective first).  This order is a linear
+//    extension of dominance (y' dominates y  =>  y' >lex y), and equal
+//    vectors become adjacent with the smallest sample index first.
+// 2. Keep the first row of every run of equal vectors (the representative).
+// 3. Chunk pass: within chunks of 1024 consecutive unique vectors, a vector
+//    is dropped when an earlier one in its chunk is >= it componentwise.
+// 4. Global pass over the chunk survivors: a survivor is kept when no earlier
+//    survivor is >= it componentwise.  Any dominator of it in an earlier
+//    chunk is itself dominated-or-equal by a survivor of that chunk, so
+//    comparing survivors with survivors is complete.  Early exit per block.
+// 5. The kept sample indices are emitted in ascending order by a flagged
+//    selection over 0..M-1.
+// Every step runs on the caller's stream; counts stay on the device.
+#include <hipcub/hipcub.hpp>
+
+#include "internal.hpp"
+
+namespace qaia {
+
+namespace {
+
+constexpr int kB = 256;
+constexpr int kChunk = 1024;
+
+__global__ void iota_kernel(int32_t *idx, int64_t M) {
+    int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i < M) idx[i] = (int32_t)i;
+}
+
+__global__ void fill_u8_kernel(uint8_t *p, int64_t n, uint8_t v) {
+    int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void fill_i64_kernel(int64_t *p, int64_t n, int64_t v) {
+    int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void gather_key_kernel(const int64_t *__restrict__ obj, int m, int k,
+                                  const int32_t *__restrict__ idx, int64_t *__restrict__ key,
+                                  int64_t M) {
+    int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i < M) key[i] = obj[(int64_t)idx[i] * m + k];
+}
+
+__global__ void unique_flag_kernel(const int64_t *__restrict__ obj, int m,
+                                   const int32_t *__restrict__ idx, uint8_t *__restrict__ flag,
+                                   int64_t M) {
+    int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i >= M) return;
+    uint8_t f = 1;
+    if (i > 0) {
+        const int64_t *a = obj + (int64_t)idx[i] * m, *b = obj + (int64_t)idx[i - 1] * m;
+        f = 0;
+        for (int k = 0; k < m; ++k) f |= a[k] != b[k];
+    }
+    flag[i] = f;
+}
+
+// chunk-local pass over the unique vectors uidx[0..U)
+__global__ __launch_bounds__(kB) void chunk_nd_kernel(const int64_t *__restrict__ obj, int m,
+                                                      const int32_t *__restrict__ uidx,
+                                                      const int64_t *__restrict__ d_U,
+                                                      int64_t M, uint8_t *__restrict__ flag) {
+    __shared__ int64_t v[8][kChunk];
+    const int64_t U = *d_U;
+    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+    // positions U..M-1 still hold flags of the uniqueness pass: clear them so
+    // the following selection sees survivors only
+    for (int p = threadIdx.x; p < kChunk; p += kB) {
+        const int64_t pos = c0 + p;
+        if (pos >= U && pos < M) flag[pos] = 0;
+    }
+    if (c0 >= U) return;
+    const int len = (int)((U - c0) < kChunk ? (U - c0) : kChunk);
+    for (int p = threadIdx.x; p < len; p += kB) {
+        const int64_t *y = obj + (int64_t)uidx[c0 + p] * m;
+        for (int k = 0; k < m; ++k) v[k][p] = y[k];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < len; j += kB) {
+        int64_t yj[8];
+        for (int k = 0; k < m; ++k) yj[k] = v[k][j];
+        bool dom = false;
+        for (int i = 0; i < j && !dom; ++i) {
+            bool ge = true;
+            for (int k = 0; k < m; ++k) ge &= v[k][i] >= yj[k];
+            dom = ge;
+        }
+        flag[c0 + j] = dom ? 0 : 1;
+    }
+}
+
+// global pass over the chunk survivors sidx[0..S)
+__global__ __launch_bounds__(kB) void global_nd_kernel(const int64_t *__restrict__ obj, int m,
+                                                       const int32_t *__restrict__ sidx,
+                                                       const int64_t *__restrict__ d_S,
+                                                       uint8_t *__restrict__ keep) {
+    __shared__ int64_t v[8][kB];
+    const int64_t S = *d_S;
+    const int64_t j0 = (int64_t)blockIdx.x * kB;
+    if (j0 >= S) return;
+    const int64_t j = j0 + threadIdx.x;
+    const bool mine = j < S;
+    int64_t yj[8];
+    for (int k = 0; k < m; ++k) yj[k] = mine ? obj[(int64_t)sidx[j] * m + k] : 0;
+    bool alive = mine;
+    for (int64_t i0 = 0; i0 < j0 + kB && i0 < S; i0 += kB) {
+        const int64_t ii = i0 + threadIdx.x;
+        if (ii < S) {
+            const int64_t *y = obj + (int64_t)sidx[ii] * m;
+            for (int k = 0; k < m; ++k) v[k][threadIdx.x] = y[k];
+        }
+        __syncthreads();
+        if (alive) {
+            const int64_t lim = (j - i0) < kB ? (j - i0) : kB;  // earlier survivors only
+            for (int64_t t = 0; t < lim; ++t) {
+                bool ge = true;
+                for (int k = 0; k < m; ++k) ge &= v[k][t] >= yj[k];
+                if (ge) {
+                    alive = false;
+                    break;
+                }
+            }
+        }
+        if (!__syncthreads_or(alive ? 1 : 0)) break;
+    }
+    if (alive) keep[sidx[j]] = 1;
+}
+
+struct PLayout {
+    size_t idxA, idxB, keyA, keyB, flag, uidx, sidx, keep, counts, temp, temp_bytes, total;
+};
+
+size_t temp_bytes_needed(int64_t M) {
+    size_t sort_b = 0, sel_b = 0, sel2_b = 0;
+    hipcub::DeviceRadixSort::SortPairsDescending(nullptr, sort_b, (const int64_t *)nullptr,
+                                                 (int64_t *)nullptr, (const int32_t *)nullptr,
+                                                 (int32_t *)nullptr, (int)M, 0, 64, (hipStream_t)0);
+    hipcub::DeviceSelect::Flagged(nullptr, sel_b, (const int32_t *)nullptr,
+                                  (const uint8_t *)nullptr, (int32_t *)nullptr,
+                                  (int64_t *)nullptr, M, (hipStream_t)0);
+    hipcub::CountingInputIterator<int64_t> it(0);
+    hipcub::DeviceSelect::Flagged(nullptr, sel2_b, it, (const uint8_t *)nullptr,
+                                  (int64_t *)nullptr, (int64_t *)nullptr, M, (hipStream_t)0);
+    return std::max(sort_b, std::max(sel_b, sel2_b));
+}
+
+PLayout layout(int64_t M) {
+    PLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t Mz = (size_t)std::max<int64_t>(M, 1);
+    L.idxA = take(4 * Mz);
+    L.idxB = take(4 * Mz);
+    L.keyA = take(8 * Mz);
+    L.keyB = take(8 * Mz);
+    L.flag = take(Mz);
+    L.uidx = take(4 * Mz);
+    L.sidx = take(4 * Mz);
+    L.keep = take(Mz);
+    L.counts = take(8 * 4);
+    L.temp_bytes = temp_bytes_needed(std::max<int64_t>(M, 1));
+    L.temp = take(L.temp_bytes);
+    L.total = off;
+    return L;
+}
+
+unsigned grid_for(int64_t n, int per = kB) {
+    int64_t g = (n + per - 1) / per;
+    return (unsigned)std::max<int64_t>(g, 1);
+}
+
+}  // namespace
+
+size_t pareto_ws_bytes(int64_t M, int32_t m) {
+    (void)m;
+    return layout(M).total;
+}
+
+#define QAIA_CUB(call) QAIA_HIP(call)
+
+void launch_pareto(const int64_t *obj, int64_t M, int32_t m, int64_t *keep_idx, int64_t *num_keep,
+                   void *ws, size_t ws_bytes, hipStream_t st) {
+    if (M == 0) {
+        hipLaunchKernelGGL(fill_i64_kernel, dim3(1), dim3(kB), 0, st, num_keep, (int64_t)1,
+                           (int64_t)0);
+        QAIA_HIP(hipGetLastError());
+        return;
+    }
+    const PLayout L = layout(M);
+    QAIA_CHECK(ws_bytes >= L.total, QAIA_WORKSPACE_TOO_SMALL,
+               "pareto filter workspace needs " + std::to_string(L.total) + " bytes");
+    char *b = (char *)ws;
+    int32_t *idxA = (int32_t *)(b + L.idxA), *idxB = (int32_t *)(b + L.idxB);
+    int64_t *keyA = (int64_t *)(b + L.keyA), *keyB = (int64_t *)(b + L.keyB);
+    uint8_t *flag = (uint8_t *)(b + L.flag), *keep = (uint8_t *)(b + L.keep);
+    int32_t *uidx = (int32_t *)(b + L.uidx), *sidx = (int32_t *)(b + L.sidx);
+    int64_t *counts = (int64_t *)(b + L.counts);
+    void *temp = b + L.temp;
+    size_t tb = L.temp_bytes;
+
+    hipLaunchKernelGGL(iota_kernel, dim3(grid_for(M)), dim3(kB), 0, st, idxA, M);
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(M)), dim3(kB), 0, st, keep, M, (uint8_t)0);
+    QAIA_HIP(hipGetLastError());
+    int32_t *cur = idxA, *nxt = idxB;
+    for (int k = m - 1; k >= 0; --k) {
+        hipLaunchKernelGGL(gather_key_kernel, dim3(grid_for(M)), dim3(kB), 0, st, obj, m, k, cur,
+                           keyA, M);
+        QAIA_HIP(hipGetLastError());
+        size_t t = tb;
+        QAIA_CUB(hipcub::DeviceRadixSort::SortPairsDescending(temp, t, keyA, keyB, cur, nxt, (int)M,
+                                                              0, 64, st));
+        std::swap(cur, nxt);
+    }
+    hipLaunchKernelGGL(unique_flag_kernel, dim3(grid_for(M)), dim3(kB), 0, st, obj, m, cur, flag, M);
+    QAIA_HIP(hipGetLastError());
+    {
+        size_t t = tb;
+        QAIA_CUB(hipcub::DeviceSelect::Flagged(temp, t, cur, flag, uidx, counts + 0, M, st));
+    }
+    hipLaunchKernelGGL(chunk_nd_kernel, dim3(grid_for(M, kChunk)), dim3(kB), 0, st, obj, m, uidx,
+                       counts + 0, M, flag);
+    QAIA_HIP(hipGetLastError());
+    {
+        size_t t = tb;
+        QAIA_CUB(hipcub::DeviceSelect::Flagged(temp, t, uidx, flag, sidx, counts + 1, M, st));
+    }
+    hipLaunchKernelGGL(global_nd_kernel, dim3(grid_for(M)), dim3(kB), 0, st, obj, m, sidx,
+                       counts + 1, keep);
+    QAIA_HIP(hipGetLastError());
+    {
+        size_t t = tb;
+        hipcub::CountingInputIterator<int64_t> it(0);
+        QAIA_CUB(hipcub::DeviceSelect::Flagged(temp, t, it, keep, keep_idx, num_keep, M, st));
+    }
+}
+
+}  // namespace qaia

@@ -1,0 +1,454 @@
+// Weight preparation, the generic sparse SB kernel (one spin per lane, state
+// and adjacency in LDS) and exact cut evaluation.
+#include <climits>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace qaia {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Workspace header reset (a fill kernel rather than a memset so the sequence
+// stays valid inside a captured graph).
+__global__ void ws_header_init(WsHeader *h, int64_t W) {
+    if (threadIdx.x == 0) {
+        h->magic = kWsMagic;
+        h->bad_row = INT64_MAX;
+        h->W = W;
+        h->reserved = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight preparation, one block per weight row w (Eq. 7 and the coupling scale
+// of section "Simulated Bifurcation with Gaussian noise"):
+//   c0 = 1 / max_i |sum_k c_k rho_{k,i}|, rho_{k,i} = sum_j W_k,ij (exact ints);
+//   if that maximum is 0: c0 = 1 / max_i sum_j |J(c)_ij|; if 0 too: c0 = 0.
+//   jcp[w][e] = float(-dt * c0 * sum_k c_k W_k,e)  (float64 then one rounding)
+// Rows with a negative, non-finite or all-zero c are marked invalid
+// (c0s[w] = -1) and reported through the workspace header.
+// The first blocks also fill the per-step table kt[t] = -dt (a0 - a_t).
+__global__ __launch_bounds__(kBlock) void prep_kernel(
+    const float *__restrict__ weights, int64_t W, int m, int n, int64_t E,
+    const int64_t *__restrict__ rho, const int32_t *__restrict__ Wt,
+    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ eid, double dt, double a0,
+    int T, float *__restrict__ kt, float *__restrict__ c0s, float *__restrict__ jcp,
+    WsHeader *hdr) {
+    __shared__ double c_sh[8];
+    __shared__ double red[kBlock / 64];
+    __shared__ int valid_sh;
+    const int tid = threadIdx.x;
+    const int64_t w = blockIdx.x;
+
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + tid; t < T; t += (int64_t)gridDim.x * kBlock) {
+        double at = T > 1 ? a0 * (double)t / (double)(T - 1) : 0.0;
+        kt[t] = (float)(-dt * (a0 - at));
+    }
+    if (w >= W) return;
+
+    if (tid == 0) {
+        double s = 0.0;
+        int ok = 1;
+        for (int k = 0; k < m; ++k) {
+            float c = weights[w * m + k];
+            if (!(c >= 0.0f) || !isfinite(c)) ok = 0;  // catches NaN too
+            c_sh[k] = (double)c;
+            s += (double)c;
+        }
+        if (!(s > 0.0)) ok = 0;
+        valid_sh = ok;
+    }
+    __syncthreads();
+    if (!valid_sh) {
+        if (tid == 0) {
+            c0s[w] = -1.0f;
+            atomicMin((unsigned long long *)&hdr->bad_row, (unsigned long long)w);
+        }
+        if (jcp)
+            for (int64_t e = tid; e < E; e += kBlock) jcp[w * E + e] = 0.0f;
+        return;
+    }
+
+    auto block_max = [&](double v) -> double {
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        double r = red[0];
+        for (int i = 1; i < kBlock / 64; ++i) r = fmax(r, red[i]);
+        __syncthreads();
+        return r;
+    };
+
+    double mx = 0.0;
+    for (int i = tid; i < n; i += kBlock) {
+        double row = 0.0;
+        for (int k = 0; k < m; ++k) row += c_sh[k] * (double)rho[(int64_t)k * n + i];
+        mx = fmax(mx, fabs(row));
+    }
+    mx = block_max(mx);
+    double c0;
+    if (mx > 0.0) {
+        c0 = 1.0 / mx;
+    } else {
+        double mxa = 0.0;
+        for (int i = tid; i < n; i += kBlock) {
+            double a = 0.0;
+            for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+                double j = 0.0;
+                for (int k = 0; k < m; ++k) j += c_sh[k] * (double)Wt[(int64_t)k * E + eid[p]];
+                a += fabs(j);
+            }
+            mxa = fmax(mxa, a);
+        }
+        mxa = block_max(mxa);
+        c0 = mxa > 0.0 ? 1.0 / mxa : 0.0;
+    }
+    if (tid == 0) c0s[w] = (float)c0;
+    if (jcp) {
+        const double coef = -dt * c0;
+        for (int64_t e = tid; e < E; e += kBlock) {
+            double j = 0.0;
+            for (int k = 0; k < m; ++k) j += c_sh[k] * (double)Wt[(int64_t)k * E + e];
+            jcp[w * E + e] = (float)(coef * j);
+        }
+    }
+}
+
+WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s) {
+    (void)R;
+    WsLayout L;
+    size_t off = 0;
+    L.header = off;
+    off += align256(sizeof(WsHeader));
+    L.kt = off;
+    off += align256(sizeof(float) * (size_t)s.steps);
+    L.c0s = off;
+    off += align256(sizeof(float) * (size_t)W);
+    L.jcp = off;
+    off += align256(sizeof(float) * (size_t)W * (size_t)p.E);
+    L.total = off;
+    return L;
+}
+
+void launch_prep(const Problem &p, const float *weights, int64_t W, const qaia_schedule &s,
+                 void *ws, const WsLayout &L, hipStream_t st) {
+    char *b = (char *)ws;
+    WsHeader *hdr = (WsHeader *)(b + L.header);
+    hipLaunchKernelGGL(ws_header_init, dim3(1), dim3(64), 0, st, hdr, W);
+    QAIA_HIP(hipGetLastError());
+    int64_t grid = W > 0 ? W : 1;
+    int64_t need_kt = (s.steps + kBlock - 1) / kBlock;
+    if (grid < need_kt) grid = need_kt;
+    QAIA_CHECK(grid <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many weight rows");
+    hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(kBlock), 0, st, weights, W, p.m,
+                       p.n, p.E, p.d_rho, p.d_W, p.d_rowptr, p.d_eid, (double)s.dt, (double)s.a0,
+                       s.steps, (float *)(b + L.kt), (float *)(b + L.c0s),
+                       L.jcp != L.total ? (float *)(b + L.jcp) : nullptr, hdr);
+    QAIA_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Generic sparse SB kernel.  Lanes map to (replica, spin) pairs: with
+// rpb = max(1, 256 / n) replicas per block, slot L = q * 256 + tid (q < NPT)
+// covers spin L % n of local replica L / n.  x is double-buffered in LDS so
+// every force uses the pre-step x (Eq. 9); each lane keeps its own y, x and
+// its neighbour list (LDS offsets and folded coefficients) in registers.
+// After T steps the block reads out sgn(x) and evaluates the exact cut
+// vector of each replica with wave reductions.
+template <int MAXDEG, int NPT, bool DSB>
+__global__ __launch_bounds__(kBlock) void sparse_lds_kernel(
+    int n, int64_t E, int rpb, int64_t rows, int R, int T, const int32_t *__restrict__ rowptr,
+    const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
+    const float *__restrict__ jcp, const float *__restrict__ c0s,
+    const float *__restrict__ kt_tab, float dta0, float dt_alpha, uint64_t seed,
+    uint64_t offset, float amp, int m, const int32_t *__restrict__ Wt,
+    const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int words,
+    uint64_t *__restrict__ spins, int64_t *__restrict__ obj, float *__restrict__ trace,
+    int trace_steps) {
+    extern __shared__ float xs[];  // [2][rpb * n]
+    const int tid = threadIdx.x;
+    const int span = rpb * n;
+    const int64_t row0 = (int64_t)blockIdx.x * rpb;
+
+    float x[NPT], y[NPT], jv[NPT][MAXDEG];
+    int nb[NPT][MAXDEG], deg[NPT], node[NPT];
+    int64_t rowq[NPT];
+    bool act[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        const int L = q * kBlock + tid;
+        const int rl = L / n;
+        node[q] = L - rl * n;
+        rowq[q] = row0 + rl;
+        act[q] = L < span && rowq[q] < rows;
+        deg[q] = 0;
+        x[q] = y[q] = 0.0f;
+        if (act[q]) {
+            const int i = node[q];
+            const int64_t w = rowq[q] / R;
+            const uint64_t g = (uint64_t)rowq[q] + offset;
+            x[q] = init_value(seed, init_counter(g, n, i, 0), amp);
+            y[q] = init_value(seed, init_counter(g, n, i, 1), amp);
+            const int p0 = rowptr[i];
+            deg[q] = rowptr[i + 1] - p0;
+#pragma unroll
+            for (int d = 0; d < MAXDEG; ++d) {
+                if (d < deg[q]) {
+                    nb[q][d] = rl * n + col[p0 + d];
+                    jv[q][d] = jcp[w * E + eid[p0 + d]];
+                } else {
+                    nb[q][d] = 0;
+                    jv[q][d] = 0.0f;
+                }
+            }
+            xs[L] = x[q];
+        }
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int t = 0; t < T; ++t) {
+        const float kt = kt_tab[t];
+        const float *xc = xs + cur * span;
+        float *xn = xs + (cur ^ 1) * span;
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            if (!act[q]) continue;
+            float acc = fmaf(kt, x[q], y[q]);
+#pragma unroll
+            for (int d = 0; d < MAXDEG; ++d) {
+                if (d < deg[q]) {
+                    float v = xc[nb[q][d]];
+                    if (DSB) v = sgn1(v);
+                    acc = fmaf(jv[q][d], v, acc);
+                }
+            }
+            if (dt_alpha != 0.0f) {
+                const uint64_t g = (uint64_t)rowq[q] + offset;
+                const uint64_t nidx = (g * (uint64_t)T + (uint64_t)t) * (uint64_t)n + node[q];
+                acc = fmaf(dt_alpha, noise_value(seed, nidx), acc);
+            }
+            y[q] = acc;
+            x[q] = fmaf(dta0, y[q], x[q]);
+            wall(x[q], y[q]);
+            xn[q * kBlock + tid] = x[q];
+            if (trace != nullptr && t < trace_steps)
+                trace[(rowq[q] * trace_steps + t) * n + node[q]] = x[q];
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+
+    // read-out and exact cut evaluation, one wave per local replica
+    const float *xf = xs + cur * span;
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int rl = wave; rl < rpb; rl += kBlock / 64) {
+        const int64_t row = row0 + rl;
+        if (row >= rows) break;
+        const bool valid = c0s[row / R] >= 0.0f;
+        const float *xr = xf + rl * n;
+        for (int wd = lane; wd < words; wd += 64) {
+            uint64_t bits = 0;
+            if (valid)
+                for (int b = 0; b < 64 && wd * 64 + b < n; ++b)
+                    bits |= (uint64_t)(xr[wd * 64 + b] < 0.0f) << b;
+            spins[row * words + wd] = bits;
+        }
+        int64_t acc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = 0;
+        if (valid) {
+            for (int64_t e = lane; e < E; e += 64) {
+                const bool cut = (xr[eu[e]] < 0.0f) != (xr[ev[e]] < 0.0f);
+                if (cut) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (k < m) acc[k] += (int64_t)Wt[(int64_t)k * E + e];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k >= m) break;
+            int64_t v = acc[k];
+            for (int off = 32; off > 0; off >>= 1) {
+                int lo = __shfl_xor((int)(uint32_t)v, off);
+                int hi = __shfl_xor((int)(v >> 32), off);
+                v += (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+            }
+            if (lane == 0) obj[row * m + k] = v;
+        }
+    }
+}
+
+bool sparse_lds_supported(const Problem &p, std::string *why) {
+    if (p.max_degree > 32) {
+        if (why) *why = "maximum degree above 32 (use the dense path)";
+        return false;
+    }
+    if (p.n > 16 * kBlock) {
+        if (why) *why = "more than 4096 spins";
+        return false;
+    }
+    if (p.m > 8) {
+        if (why) *why = "more than 8 objectives";
+        return false;
+    }
+    return true;
+}
+
+template <int MAXDEG, int NPT>
+static void launch_lds_t(const Problem &p, bool dsb, dim3 grid, size_t shmem, hipStream_t st,
+                         int rpb, int64_t rows, int32_t R, const qaia_schedule &s, const float *jcp,
+                         const float *c0s, const float *kt, uint64_t *spins, int64_t *obj,
+                         float *trace, int trace_steps) {
+    const float dta0 = s.dt * s.a0;
+    const float dt_alpha = s.dt * s.noise_alpha;
+    if (dsb)
+        hipLaunchKernelGGL((sparse_lds_kernel<MAXDEG, NPT, true>), grid, dim3(kBlock), shmem, st,
+                           p.n, p.E, rpb, rows, R, s.steps, p.d_rowptr, p.d_col, p.d_eid, jcp,
+                           c0s, kt, dta0, dt_alpha, s.seed, s.replica_offset, s.init_amp, p.m,
+                           p.d_W, p.d_eu, p.d_ev, p.words, spins, obj, trace, trace_steps);
+    else
+        hipLaunchKernelGGL((sparse_lds_kernel<MAXDEG, NPT, false>), grid, dim3(kBlock), shmem, st,
+                           p.n, p.E, rpb, rows, R, s.steps, p.d_rowptr, p.d_col, p.d_eid, jcp,
+                           c0s, kt, dta0, dt_alpha, s.seed, s.replica_offset, s.init_amp, p.m,
+                           p.d_W, p.d_eu, p.d_ev, p.words, spins, obj, trace, trace_steps);
+}
+
+template <int MAXDEG>
+static void launch_lds_npt(int npt, const Problem &p, bool dsb, dim3 grid, size_t shmem,
+                           hipStream_t st, int rpb, int64_t rows, int32_t R,
+                           const qaia_schedule &s, const float *jcp, const float *c0s,
+                           const float *kt, uint64_t *spins, int64_t *obj, float *trace,
+                           int trace_steps) {
+#define QAIA_NPT(N)                                                                          \
+    case N:                                                                                  \
+        launch_lds_t<MAXDEG, N>(p, dsb, grid, shmem, st, rpb, rows, R, s, jcp, c0s, kt, spins, \
+                                obj, trace, trace_steps);                                    \
+        break;
+    switch (npt) {
+        QAIA_NPT(1)
+        QAIA_NPT(2)
+        QAIA_NPT(4)
+        QAIA_NPT(8)
+        QAIA_NPT(16)
+        default:
+            throw Error{QAIA_UNSUPPORTED, "spins per lane out of range"};
+    }
+#undef QAIA_NPT
+}
+
+void launch_sparse_lds(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws,
+                       const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
+                       int32_t trace_steps, hipStream_t st) {
+    std::string why;
+    QAIA_CHECK(sparse_lds_supported(p, &why), QAIA_UNSUPPORTED, "sparse LDS path: " + why);
+    const int64_t rows = W * (int64_t)R;
+    if (rows == 0) return;
+    const int rpb = p.n <= kBlock ? kBlock / p.n : 1;
+    const int span = rpb * p.n;
+    int npt = 1;
+    while (npt * kBlock < span) npt <<= 1;
+    const int64_t blocks = (rows + rpb - 1) / rpb;
+    QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many replicas for one launch");
+    const size_t shmem = sizeof(float) * 2 * (size_t)span;
+    char *b = (char *)ws;
+    const float *jcp = (const float *)(b + L.jcp), *c0s = (const float *)(b + L.c0s),
+                *kt = (const float *)(b + L.kt);
+    const bool dsb = s.variant == QAIA_DSB;
+    dim3 grid((unsigned)blocks);
+    if (p.max_degree <= 4)
+        launch_lds_npt<4>(npt, p, dsb, grid, shmem, st, rpb, rows, R, s, jcp, c0s, kt, spins, obj,
+                          trace, trace_steps);
+    else if (p.max_degree <= 8)
+        launch_lds_npt<8>(npt, p, dsb, grid, shmem, st, rpb, rows, R, s, jcp, c0s, kt, spins, obj,
+                          trace, trace_steps);
+    else if (p.max_degree <= 16)
+        launch_lds_npt<16>(npt, p, dsb, grid, shmem, st, rpb, rows, R, s, jcp, c0s, kt, spins,
+                           obj, trace, trace_steps);
+    else
+        launch_lds_npt<32>(npt, p, dsb, grid, shmem, st, rpb, rows, R, s, jcp, c0s, kt, spins,
+                           obj, trace, trace_steps);
+    QAIA_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Exact cut evaluation, Eq. (1), for given packed spins.
+// Few edges: one thread per sample.  Many edges: one block per sample with a
+// block reduction.
+__device__ __forceinline__ int spin_bit(const uint64_t *row, int i) {
+    return (int)((row[i >> 6] >> (i & 63)) & 1ull);
+}
+
+__global__ __launch_bounds__(kBlock) void eval_thread_kernel(
+    const uint64_t *__restrict__ spins, int64_t count, int words, int m, int64_t E,
+    const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
+    const int32_t *__restrict__ Wt, int64_t *__restrict__ obj) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= count) return;
+    const uint64_t *row = spins + s * words;
+    int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t e = 0; e < E; ++e) {
+        if (spin_bit(row, eu[e]) != spin_bit(row, ev[e])) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k < m) acc[k] += (int64_t)Wt[(int64_t)k * E + e];
+        }
+    }
+    for (int k = 0; k < m; ++k) obj[s * m + k] = acc[k];
+}
+
+__global__ __launch_bounds__(kBlock) void eval_block_kernel(
+    const uint64_t *__restrict__ spins, int64_t count, int words, int m, int64_t E,
+    const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
+    const int32_t *__restrict__ Wt, int64_t *__restrict__ obj) {
+    __shared__ int64_t red[8][kBlock / 64];
+    const int64_t s = blockIdx.x;
+    const uint64_t *row = spins + s * words;
+    int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t e = threadIdx.x; e < E; e += kBlock) {
+        if (spin_bit(row, eu[e]) != spin_bit(row, ev[e])) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k < m) acc[k] += (int64_t)Wt[(int64_t)k * E + e];
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int64_t v = acc[k];
+        for (int off = 32; off > 0; off >>= 1) {
+            int lo = __shfl_xor((int)(uint32_t)v, off);
+            int hi = __shfl_xor((int)(v >> 32), off);
+            v += (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+        }
+        if (lane == 0) red[k][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+        int64_t v = 0;
+        for (int i = 0; i < kBlock / 64; ++i) v += red[threadIdx.x][i];
+        obj[s * m + threadIdx.x] = v;
+    }
+}
+
+void launch_evaluate(const Problem &p, const uint64_t *spins, int64_t count, int64_t *obj,
+                     hipStream_t st) {
+    if (count == 0) return;
+    QAIA_CHECK(p.m <= 8, QAIA_UNSUPPORTED, "evaluation supports at most 8 objectives");
+    if (p.E <= 4096) {
+        int64_t blocks = (count + kBlock - 1) / kBlock;
+        QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many samples");
+        hipLaunchKernelGGL(eval_thread_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, spins,
+                           count, p.words, p.m, p.E, p.d_eu, p.d_ev, p.d_W, obj);
+    } else {
+        QAIA_CHECK(count <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many samples");
+        hipLaunchKernelGGL(eval_block_kernel, dim3((unsigned)count), dim3(kBlock), 0, st, spins,
+                           count, p.words, p.m, p.E, p.d_eu, p.d_ev, p.d_W, obj);
+    }
+    QAIA_HIP(hipGetLastError());
+}
+
+}  // namespace qaia

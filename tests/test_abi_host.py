@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI: symbols, status codes, argument validation
+and the library's exact hypervolume (pure host code) against the oracle's
+independent algorithm.  No GPU needed."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2604_26477_amd as q
+    return q
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "qaia.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qaia_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(q):
+    import ctypes
+    lib = ctypes.CDLL(q.LIB_PATH)
+    names = _declared_symbols()
+    assert "qaia_sample" in names and "qaia_hypervolume" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings(q):
+    assert q.qaia_abi_version() == 1
+    assert q.qaia_status_string(0) == "ok"
+    assert q.qaia_status_string(5) == "overflow"
+    assert q.qaia_status_string(99) == "unknown status"
+
+
+@pytest.mark.parametrize("eu,ev,msg", [
+    ([0, 1], [1, 1], "violates"),      # u == v
+    ([0, 2], [1, 1], "violates"),      # u > v
+    ([0, 0], [1, 1], "repeated"),      # duplicate pair
+    ([0, 0], [1, 9], "violates"),      # v >= n
+])
+def test_problem_create_rejects_bad_edges(q, eu, ev, msg):
+    with pytest.raises(q.QaiaError) as ei:
+        q.qaia_problem_create(4, 2, eu, ev, np.zeros((2, 2), np.int32))
+    assert ei.value.status == q.QAIA_INVALID_ARGUMENT and msg in str(ei.value)
+
+
+def test_problem_create_rejects_bad_sizes(q):
+    for n, m in ((0, 2), (4, 0), (4, 9)):
+        with pytest.raises(q.QaiaError) as ei:
+            q.qaia_problem_create(n, m, [0], [1], np.zeros((max(m, 1), 1), np.int32))
+        assert ei.value.status == q.QAIA_INVALID_ARGUMENT
+
+
+def test_hypervolume_worked_example(q):
+    assert q.qaia_hypervolume(np.array([[10, 5], [5, 10]]), [0, 0]) == 75
+    assert q.qaia_hypervolume(np.array([[10, 5], [5, 10], [8, 8]]), [0, 0]) == 84
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5])
+def test_hypervolume_matches_oracle(q, m):
+    rng = np.random.default_rng(100 + m)
+    for trial in range(25):
+        P = int(rng.integers(0, 60 if m < 5 else 25))
+        pts = rng.integers(-1000, 5000, size=(P, m))
+        ref = rng.integers(-500, 100, size=m)
+        assert q.qaia_hypervolume(pts, ref) == oracle.hypervolume(pts, ref)
+
+
+def test_hypervolume_ties_and_duplicates(q):
+    rng = np.random.default_rng(7)
+    for m in (2, 3, 4):
+        for trial in range(30):
+            pts = rng.integers(0, 5, size=(int(rng.integers(1, 40)), m))  # many equal coordinates
+            assert q.qaia_hypervolume(pts, np.zeros(m)) == oracle.hypervolume(pts, np.zeros(m))
+
+
+def test_hypervolume_on_sampled_front(q):
+    """A front of SB samples (oracle sampler) on a 4-objective instance."""
+    inst = wl.random_instance(16, 4, "deg3", seed=31, num_edges=20)
+    c = wl.dirichlet_weights(200, 4, 32)
+    spins = oracle.sb_sample(inst, c, R=4, T=200, seed=33)
+    obj = oracle.cut_values(inst, spins)
+    front = obj[oracle.pareto_filter(obj)]
+    ref = obj.min(axis=0)
+    assert len(front) > 5
+    assert q.qaia_hypervolume(front, ref) == oracle.hypervolume(front, ref)
+    assert q.qaia_hypervolume(obj, ref) == oracle.hypervolume(front, ref)  # dominated points add nothing
+
+
+def test_hypervolume_wide_range_and_overflow(q):
+    big = 2**62
+    pts = np.array([[big, big - 3, big - 5, big - 7], [big - 11, big, big, big - 1]], np.int64)
+    ref = np.zeros(4, np.int64)
+    assert q.qaia_hypervolume(pts, ref) == oracle.hypervolume(pts, ref)
+    # five objectives of 62 bits each need 310 bits: OVERFLOW
+    pts5 = np.full((1, 5), big, np.int64)
+    with pytest.raises(q.QaiaError) as ei:
+        q.qaia_hypervolume(pts5, np.zeros(5, np.int64))
+    assert ei.value.status == q.QAIA_OVERFLOW
+
+
+def test_hypervolume_empty_and_clipped(q):
+    assert q.qaia_hypervolume(np.zeros((0, 3), np.int64), [0, 0, 0]) == 0
+    # a point below the reference in one objective contributes nothing
+    assert q.qaia_hypervolume(np.array([[5, -1, 5], [2, 2, 2]]), [0, 0, 0]) == 8

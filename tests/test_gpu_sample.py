@@ -1,0 +1,195 @@
+"""GPU parity of the sampler (qaia_sample / qaia_sample_trace / qaia_evaluate)
+against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_helpers import pack_spins, rel_inf_error, unpack_spins
+
+pytestmark = pytest.mark.gpu
+
+SPARSE_PATHS = ["sparse_reg", "sparse_lds"]
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_26477_amd as q
+    return q
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _sample(q, prob, c, R, **kw):
+    s = q.make_schedule(**kw)
+    spins, obj, ws = q.qaia_sample(prob, _dev(c), R, s)
+    import torch
+    torch.cuda.synchronize()
+    return spins.cpu().numpy(), obj.cpu().numpy(), ws
+
+
+# ---------------------------------------------------------------- trajectories
+
+@pytest.mark.parametrize("path", SPARSE_PATHS)
+def test_trace_parity_bsb_first_100_steps(q, path):
+    """FP32 x stays within 1e-5 (relative infinity norm) of the FP64 oracle for 100 steps."""
+    inst = wl.random_instance(12, 3, "deg3", seed=41, num_edges=16)
+    c = wl.dirichlet_weights(6, 3, 42)
+    R, T, steps = 8, 1000, 100
+    prob = q.problem_from_instance(inst)
+    s = q.make_schedule("bsb", steps=T, dt=0.5, seed=43, path=path)
+    spins, obj, ws, tr = q.qaia_sample_trace(prob, _dev(c), R, s, steps)
+    tr = tr.cpu().numpy()
+    _, ref = oracle.sb_sample(inst, c, R, T, "bsb", dt=0.5, seed=43, trace_steps=steps)
+    err = rel_inf_error(tr, ref)
+    print(f"{path}: max rel err over {steps} steps = {err.max():.3e}")
+    assert err.max() <= 1e-5
+
+
+def _dsb_safe_seed(inst, c, R, T, steps):
+    """A seed whose oracle trajectories keep |x| >= 1e-4 over the traced steps, so
+    the sgn discontinuity of discrete SB is far from FP32 rounding."""
+    for seed in range(100, 160):
+        _, ref = oracle.sb_sample(inst, c, R, T, "dsb", dt=0.5, seed=seed, trace_steps=steps)
+        if np.abs(ref).min() >= 1e-4:
+            return seed, ref
+    pytest.skip("no seed without near-zero crossings")
+
+
+@pytest.mark.parametrize("path", SPARSE_PATHS)
+def test_trace_parity_dsb_first_100_steps(q, path):
+    inst = wl.random_instance(10, 2, "deg3", seed=51, num_edges=12)
+    c = wl.dirichlet_weights(2, 2, 52)
+    R, T, steps = 2, 1000, 100
+    seed, ref = _dsb_safe_seed(inst, c, R, T, steps)
+    prob = q.problem_from_instance(inst)
+    s = q.make_schedule("dsb", steps=T, dt=0.5, seed=seed, path=path)
+    _, _, _, tr = q.qaia_sample_trace(prob, _dev(c), R, s, steps)
+    err = rel_inf_error(tr.cpu().numpy(), ref)
+    print(f"{path}: dsb max rel err = {err.max():.3e}")
+    assert err.max() <= 1e-5
+
+
+# ---------------------------------------------------------------- exact cuts
+
+@pytest.mark.parametrize("path", SPARSE_PATHS)
+@pytest.mark.parametrize("variant", ["bsb", "dsb"])
+def test_c1_cut_values_bit_exact(q, path, variant):
+    """42-node, 48-edge, 3-objective workload at full size (200 x 16 x 1000):
+    every sampled cut vector equals the oracle's evaluation of the same spins."""
+    inst = wl.workload_instance("c1_bsb_n42_m3")
+    c = wl.workload_weights("c1_bsb_n42_m3")
+    prob = q.problem_from_instance(inst)
+    spins, obj, _ = _sample(q, prob, c, 16, variant=variant, steps=1000, dt=0.5, seed=1003, path=path)
+    s = unpack_spins(spins, inst.n)
+    assert np.array_equal(obj, oracle.cut_values(inst, s))
+    # the sampler found cuts well above random (mean cut of a random spin vector is T_k / 2)
+    scal = (obj.astype(np.float64) * np.repeat(c, 16, axis=0)).sum(axis=1)
+    rand = (inst.weights.sum(axis=1) / 2.0 * np.repeat(c, 16, axis=0)).sum(axis=1)
+    assert np.mean(scal > rand) > 0.95
+
+
+def test_evaluate_matches_oracle_sparse_and_dense(q):
+    import torch
+    rng = np.random.default_rng(3)
+    for inst in (wl.random_instance(42, 4, "deg3", seed=61, num_edges=48),
+                 wl.random_instance(100, 3, "p0.9", seed=62),          # > 4096 edges: block kernel
+                 wl.random_instance(130, 2, "p0.05", seed=63)):        # 3 words per row
+        prob = q.problem_from_instance(inst)
+        s = (1 - 2 * rng.integers(0, 2, size=(777, inst.n))).astype(np.int8)
+        got = q.qaia_evaluate(prob, _dev(pack_spins(s)))
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), oracle.cut_values(inst, s))
+        flipped = q.qaia_evaluate(prob, _dev(pack_spins(-s)))
+        assert np.array_equal(flipped.cpu().numpy(), got.cpu().numpy())
+
+
+# ---------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("path", SPARSE_PATHS)
+def test_scale_invariance_bitwise(q, path):
+    """c0 normalises J(c): c -> 4c or every weight -> 8W leaves the spins bit-identical."""
+    inst = wl.random_instance(20, 3, "deg3", seed=71, num_edges=26)
+    c = wl.dirichlet_weights(16, 3, 72)
+    prob = q.problem_from_instance(inst)
+    base, _, _ = _sample(q, prob, c, 8, steps=300, seed=73, path=path)
+    c4, _, _ = _sample(q, prob, (c * 4).astype(np.float32), 8, steps=300, seed=73, path=path)
+    inst8 = wl.Instance(inst.n, inst.m, inst.edge_u, inst.edge_v, inst.weights * 8)
+    w8, _, _ = _sample(q, q.problem_from_instance(inst8), c, 8, steps=300, seed=73, path=path)
+    assert np.array_equal(base, c4) and np.array_equal(base, w8)
+
+
+@pytest.mark.parametrize("path", SPARSE_PATHS)
+def test_determinism_and_replica_offset(q, path):
+    inst = wl.random_instance(30, 4, "deg3", seed=81, num_edges=40)
+    c = wl.dirichlet_weights(12, 4, 82)
+    prob = q.problem_from_instance(inst)
+    a, oa, _ = _sample(q, prob, c, 4, steps=200, seed=83, path=path)
+    b, ob, _ = _sample(q, prob, c, 4, steps=200, seed=83, path=path)
+    assert np.array_equal(a, b) and np.array_equal(oa, ob)
+    tail, otail, _ = _sample(q, prob, c[5:], 4, steps=200, seed=83, replica_offset=20, path=path)
+    assert np.array_equal(a[20:], tail) and np.array_equal(oa[20:], otail)
+
+
+def test_paths_agree_with_each_other_bitwise_on_cuts(q):
+    """The two sparse kernels produce cut vectors consistent with their own spins."""
+    inst = wl.workload_instance("c1_bsb_n42_m3")
+    c = wl.workload_weights("c1_bsb_n42_m3", count=20)
+    prob = q.problem_from_instance(inst)
+    for path in SPARSE_PATHS:
+        spins, obj, _ = _sample(q, prob, c, 16, steps=500, seed=5, path=path)
+        assert np.array_equal(obj, oracle.cut_values(inst, unpack_spins(spins, inst.n)))
+
+
+@pytest.mark.parametrize("path", SPARSE_PATHS)
+def test_invalid_weight_rows_are_reported(q, path):
+    inst = wl.random_instance(12, 3, "deg3", seed=91, num_edges=16)
+    c = wl.dirichlet_weights(5, 3, 92)
+    c[1] = [0.5, -0.1, 0.6]
+    c[3] = [0.0, 0.0, 0.0]
+    prob = q.problem_from_instance(inst)
+    spins, obj, ws = _sample(q, prob, c, 4, steps=100, seed=1, path=path)
+    assert q.qaia_workspace_status(ws) == 1
+    assert not spins[4:8].any() and not obj[4:8].any()
+    assert not spins[12:16].any() and not obj[12:16].any()
+    ok, _, ws2 = _sample(q, prob, wl.dirichlet_weights(5, 3, 92), 4, steps=100, seed=1, path=path)
+    assert q.qaia_workspace_status(ws2) is None
+
+
+def test_argument_errors(q):
+    import torch
+    inst = wl.random_instance(12, 3, "deg3", seed=91, num_edges=16)
+    prob = q.problem_from_instance(inst)
+    c = _dev(wl.dirichlet_weights(4, 3, 1))
+    for kw, status in ((dict(steps=0), q.QAIA_INVALID_ARGUMENT), (dict(dt=-1.0), q.QAIA_INVALID_ARGUMENT),
+                       (dict(variant="bsb", precision="bf16"), q.QAIA_UNSUPPORTED)):
+        with pytest.raises(q.QaiaError) as ei:
+            q.qaia_sample(prob, c, 4, q.make_schedule(**kw))
+        assert ei.value.status == status
+    s = q.make_schedule(steps=10)
+    need = q.qaia_sample_workspace_bytes(prob, 4, 4, s)
+    small = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(q.QaiaError) as ei:
+        q.qaia_sample(prob, c, 4, s, workspace=small)
+    assert ei.value.status == q.QAIA_WORKSPACE_TOO_SMALL
+
+
+def test_edge_cases_tiny_graphs(q):
+    # one spin, no edges: c0 = 0, cut values are 0
+    inst = wl.Instance(1, 2, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros((2, 0), np.int32))
+    prob = q.problem_from_instance(inst)
+    c = wl.dirichlet_weights(3, 2, 1)
+    for path in SPARSE_PATHS:
+        spins, obj, _ = _sample(q, prob, c, 2, steps=50, seed=1, path=path)
+        assert not obj.any() and spins.shape == (6, 1)
+    # W = 0 is a no-op
+    import torch
+    _, obj0, _ = q.qaia_sample(prob, torch.zeros((0, 2), dtype=torch.float32, device="cuda"), 2,
+                               q.make_schedule(steps=10))
+    assert obj0.numel() == 0
