@@ -164,6 +164,27 @@ int32_t qaia_workspace_status(const void *workspace, int64_t *bad_row);
 int32_t qaia_evaluate(const qaia_problem *p, const uint64_t *spins, int64_t count, int64_t *obj,
                       void *hip_stream);
 
+/* ---------------------------------------------------------------- precision form */
+
+/* Bytes of DEVICE workspace qaia_dense_field needs for `count` columns. */
+int32_t qaia_dense_field_workspace_bytes(const qaia_problem *p, int32_t precision, int64_t count,
+                                         size_t *bytes);
+
+/* The per-objective coupling products that the dense SB path computes every
+ * step (the force sum_j J^(k)_ij phi(x_j) of Eq. 9, per objective k of the
+ * scalarisation of Eq. 7), for given phi, in the requested arithmetic:
+ *   QAIA_FP32: fp32 J x fp32 phi; QAIA_BF16 / QAIA_FP8: J stored per objective
+ *   as bf16 / e4m3 of W * 2^-e_k, phi rounded to +-1 (entries 0 stay 0),
+ *   fp32 accumulation, result multiplied back by 2^e_k.
+ *   phi   : DEVICE float32[count][n].
+ *   field : DEVICE float32[count][m][n], in weight units (fixed point).
+ *   workspace : DEVICE scratch of qaia_dense_field_workspace_bytes().
+ * Test and reporting hook for the field error of reduced precision.  Errors:
+ * INVALID_ARGUMENT, UNSUPPORTED (no dense images or m > 4),
+ * WORKSPACE_TOO_SMALL, DEVICE_ERROR. */
+int32_t qaia_dense_field(const qaia_problem *p, int32_t precision, const float *phi, int64_t count,
+                         float *field, void *workspace, size_t ws_bytes, void *hip_stream);
+
 /* ---------------------------------------------------------------- filtering */
 
 int32_t qaia_pareto_filter_workspace_bytes(int64_t M, int32_t m, size_t *bytes);

@@ -43,9 +43,14 @@ void check_schedule(const Problem &p, const qaia_schedule *s) {
                "noise_alpha must be finite and >= 0");
     QAIA_CHECK(s->path >= QAIA_PATH_AUTO && s->path <= QAIA_PATH_DENSE, QAIA_INVALID_ARGUMENT,
                "unknown path");
-    if (s->precision != QAIA_FP32)
+    if (s->precision != QAIA_FP32) {
         QAIA_CHECK(s->variant == QAIA_DSB, QAIA_UNSUPPORTED,
                    "reduced precision needs discrete SB (its phi(x) = sgn(x) is exact)");
+        QAIA_CHECK(s->path == QAIA_PATH_AUTO || s->path == QAIA_PATH_DENSE, QAIA_UNSUPPORTED,
+                   "reduced precision runs on the dense path only");
+    }
+    if (s->path == QAIA_PATH_DENSE)
+        QAIA_CHECK(s->noise_alpha == 0.0f, QAIA_UNSUPPORTED, "the dense path runs plain SB only");
     (void)p;
 }
 
@@ -57,6 +62,16 @@ int plan_path(const Problem &p, const qaia_schedule &s, bool tracing) {
     if (p.jit[s.variant] != nullptr && s.noise_alpha == 0.0f) return QAIA_PATH_SPARSE_REG;
     if (sparse_lds_supported(p, nullptr)) return QAIA_PATH_SPARSE_LDS;
     return QAIA_PATH_DENSE;
+}
+
+WsLayout full_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, int path) {
+    WsLayout L = sample_ws_layout(p, W, R, s);
+    if (path == QAIA_PATH_DENSE) {
+        std::string why;
+        QAIA_CHECK(dense_supported(p, &why), QAIA_UNSUPPORTED, "dense path: " + why);
+        dense_ws_extend(p, W, R, s, L);
+    }
+    return L;
 }
 
 int32_t sample_impl(const qaia_problem *pp, const float *weights, int64_t W, int32_t R,
@@ -72,18 +87,19 @@ int32_t sample_impl(const qaia_problem *pp, const float *weights, int64_t W, int
     QAIA_CHECK(rows == 0 || (weights && spins && obj), QAIA_INVALID_ARGUMENT, "null weights, spins or obj");
     QAIA_CHECK(trace_steps >= 0, QAIA_INVALID_ARGUMENT, "trace_steps must be >= 0");
     QAIA_CHECK(trace_steps == 0 || trace != nullptr, QAIA_INVALID_ARGUMENT, "null trace buffer");
-    const WsLayout L = sample_ws_layout(p, W, R, *s);
+    const int path = plan_path(p, *s, trace_steps > 0);
+    const WsLayout L = full_layout(p, W, R, *s, path);
     QAIA_CHECK(ws != nullptr, QAIA_INVALID_ARGUMENT, "null workspace");
     QAIA_CHECK(ws_bytes >= L.total, QAIA_WORKSPACE_TOO_SMALL,
                "sample workspace needs " + std::to_string(L.total) + " bytes");
-    const int path = plan_path(p, *s, trace_steps > 0);
-    if (path == QAIA_PATH_DENSE)
-        throw Error{QAIA_UNSUPPORTED, "dense path not available for this call"};
     hipStream_t st = (hipStream_t)stream;
     DeviceGuard g(p.device);
     launch_prep(p, weights, W, *s, ws, L, st);
     if (rows == 0) return QAIA_OK;
-    if (path == QAIA_PATH_SPARSE_REG)
+    if (path == QAIA_PATH_DENSE)
+        launch_dense(p, weights, W, R, *s, ws, L, spins, obj, trace_steps ? trace : nullptr,
+                     trace_steps, st);
+    else if (path == QAIA_PATH_SPARSE_REG)
         launch_sparse_reg(p, s->variant, W, R, *s, ws, L, spins, obj, trace_steps ? trace : nullptr,
                           trace_steps, st);
     else
@@ -154,7 +170,7 @@ int32_t qaia_sample_workspace_bytes(const qaia_problem *pp, int64_t W, int32_t R
         const Problem &p = *reinterpret_cast<const Problem *>(pp);
         check_schedule(p, s);
         QAIA_CHECK(W >= 0 && R >= 1, QAIA_INVALID_ARGUMENT, "W must be >= 0 and R >= 1");
-        *bytes = sample_ws_layout(p, W, R, *s).total;
+        *bytes = full_layout(p, W, R, *s, plan_path(p, *s, false)).total;
         return QAIA_OK;
     });
 }
@@ -200,6 +216,34 @@ int32_t qaia_evaluate(const qaia_problem *pp, const uint64_t *spins, int64_t cou
         const Problem &p = *reinterpret_cast<const Problem *>(pp);
         DeviceGuard g(p.device);
         launch_evaluate(p, spins, count, obj, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_dense_field_workspace_bytes(const qaia_problem *pp, int32_t precision, int64_t count,
+                                         size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(pp != nullptr && bytes != nullptr, QAIA_INVALID_ARGUMENT, "null argument");
+        QAIA_CHECK(precision >= QAIA_FP32 && precision <= QAIA_FP8, QAIA_INVALID_ARGUMENT, "unknown precision");
+        QAIA_CHECK(count >= 0, QAIA_INVALID_ARGUMENT, "count must be >= 0");
+        const Problem &p = *reinterpret_cast<const Problem *>(pp);
+        std::string why;
+        QAIA_CHECK(dense_supported(p, &why), QAIA_UNSUPPORTED, "dense path: " + why);
+        *bytes = dense_field_ws_bytes(p, precision, count);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_dense_field(const qaia_problem *pp, int32_t precision, const float *phi, int64_t count,
+                         float *field, void *workspace, size_t ws_bytes, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(pp != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
+        QAIA_CHECK(precision >= QAIA_FP32 && precision <= QAIA_FP8, QAIA_INVALID_ARGUMENT, "unknown precision");
+        QAIA_CHECK(count >= 0 && count <= (int64_t(1) << 30), QAIA_INVALID_ARGUMENT, "count out of range");
+        QAIA_CHECK(count == 0 || (phi && field && workspace), QAIA_INVALID_ARGUMENT, "null buffer");
+        const Problem &p = *reinterpret_cast<const Problem *>(pp);
+        DeviceGuard g(p.device);
+        launch_dense_field(p, precision, phi, count, field, workspace, ws_bytes, (hipStream_t)hip_stream);
         return QAIA_OK;
     });
 }

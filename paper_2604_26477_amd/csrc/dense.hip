@@ -1,0 +1,574 @@
+// Dense SB path: the coupling product runs on the matrix cores.
+//
+// For every step, per objective k, H_k = J^(k) Phi with Phi = phi(x) for all
+// replicas at once ([Np x Np] . [Np x cols], the per-objective stacked form
+// of Eq. 7: the scalarised matrix J(c) differs per weight vector, so it is
+// never formed); the epilogue reduces h = sum_k coef_k(col) H_k with the
+// column's folded coefficient coef_k = -dt c0 c_k 2^e_k, applies the
+// symplectic update and the wall (Eq. 9), and writes phi(x) for the next step.
+//
+// Operand formats (J stored per objective, scaled by a power of two 2^-e_k):
+//   FP32: J fp32 (exact for |W| < 2^24), Phi fp32 (x for ballistic SB,
+//         sgn x for discrete SB), 32x32x2 fp32 MFMA;
+//   BF16: discrete SB only: J bf16, Phi = +-1 exact in bf16, 32x32x16 MFMA;
+//   FP8 : discrete SB only: J e4m3, Phi = +-1 exact in e4m3, 32x32x64 MFMA.
+// All accumulate in fp32.
+//
+// Layout (all device, zero padded to Np = ceil64(n) spins and colsP =
+// ceil128(W*R) columns): x, y fp32 [colsP][Np]; Phi [colsP][Np]; J [m][Np][Np]
+// (symmetric, so rows serve as the A operand directly).
+//
+// Tiling: a 256-thread block owns 64 spins x 128 columns; wave (wr, wc) owns
+// 32 spins x 64 columns (two 32x32 accumulators per objective).  For every
+// MFMA the A and B fragments of a lane come from the same k positions
+// (lane half h, slot j -> k0 + h*KG/2 + j), which pairs them correctly for
+// any internal k order of the instruction.
+#include <climits>
+#include <cmath>
+#include <cstring>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace qaia {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kDB = 256;      // threads per block
+constexpr int kTileM = 64;    // spins per block
+constexpr int kTileN = 128;   // columns per block
+
+// accumulator slot i of lane l holds row (i/4)*8 + (l/32)*4 + i%4, column l%32
+__device__ __forceinline__ int acc_row(int half, int i) { return (i >> 2) * 8 + half * 4 + (i & 3); }
+
+template <int PREC> struct PrecInfo;
+template <> struct PrecInfo<QAIA_FP32> { typedef float T; static constexpr int KG = 8; };
+template <> struct PrecInfo<QAIA_BF16> { typedef uint16_t T; static constexpr int KG = 16; };
+template <> struct PrecInfo<QAIA_FP8> { typedef uint8_t T; static constexpr int KG = 64; };
+
+__device__ __forceinline__ uint16_t bf16_pm1(float x) { return x >= 0.0f ? 0x3F80u : 0xBF80u; }
+__device__ __forceinline__ uint8_t fp8_pm1(float x) { return x >= 0.0f ? 0x38u : 0xB8u; }
+
+struct DenseStepArgs {
+    const void *J;         // [M][Np][Np]
+    const void *phi_in;    // [colsP][Np]
+    void *phi_out;         // [colsP][Np] (discrete SB)
+    const float *x_in;     // [colsP][Np]
+    float *x_out;
+    float *y;
+    const float *coef;     // [colsP][M]
+    const float *kt_tab;
+    float dta0;
+    int Np, N, cols, t;
+    float *trace;          // [cols][trace_steps][N] or null
+    int trace_steps;
+    float *field;          // field mode: [cols][M][N]
+    const float *jscale;   // field mode: [M]
+};
+
+template <int PREC, int M>
+__device__ __forceinline__ void mma_tile(const DenseStepArgs &a, int row_w, int col_w, int half,
+                                         int lr, f16v (&acc)[M][2]) {
+    typedef typename PrecInfo<PREC>::T T;
+    constexpr int KG = PrecInfo<PREC>::KG;
+    const T *J = (const T *)a.J;
+    const T *phi = (const T *)a.phi_in;
+    const size_t Np = (size_t)a.Np;
+    const T *arow[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) arow[k] = J + ((size_t)k * Np + row_w + lr) * Np + half * (KG / 2);
+    const T *bcol[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) bcol[cb] = phi + (size_t)(col_w + cb * 32 + lr) * Np + half * (KG / 2);
+
+    for (int k0 = 0; k0 < a.Np; k0 += KG) {
+        if constexpr (PREC == QAIA_FP32) {
+            float4 av[M], bv[2];
+#pragma unroll
+            for (int k = 0; k < M; ++k) av[k] = *(const float4 *)(arow[k] + k0);
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) bv[cb] = *(const float4 *)(bcol[cb] + k0);
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    acc[k][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k].x, bv[cb].x, acc[k][cb], 0, 0, 0);
+                    acc[k][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k].y, bv[cb].y, acc[k][cb], 0, 0, 0);
+                    acc[k][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k].z, bv[cb].z, acc[k][cb], 0, 0, 0);
+                    acc[k][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k].w, bv[cb].w, acc[k][cb], 0, 0, 0);
+                }
+        } else if constexpr (PREC == QAIA_BF16) {
+            bf16x8 av[M], bv[2];
+#pragma unroll
+            for (int k = 0; k < M; ++k) av[k] = *(const bf16x8 *)(arow[k] + k0);
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) bv[cb] = *(const bf16x8 *)(bcol[cb] + k0);
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[k][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[k], bv[cb], acc[k][cb], 0, 0, 0);
+        } else {
+            i32x8 av[M], bv[2];
+#pragma unroll
+            for (int k = 0; k < M; ++k) av[k] = *(const i32x8 *)(arow[k] + k0);
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) bv[cb] = *(const i32x8 *)(bcol[cb] + k0);
+            // format 0 = e4m3 for both operands, block scales 127 = 2^0
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[k][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        av[k], bv[cb], acc[k][cb], 0, 0, 0, 127, 0, 127);
+        }
+    }
+}
+
+template <int PREC, int M, bool DSB>
+__global__ __launch_bounds__(kDB) void dense_step_kernel(DenseStepArgs a) {
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int half = l >> 5, lr = l & 31;
+    const int row_w = blockIdx.y * kTileM + (wv & 1) * 32;
+    const int col_w = blockIdx.x * kTileN + (wv >> 1) * 64;
+    f16v acc[M][2];
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[k][cb][i] = 0.0f;
+    mma_tile<PREC, M>(a, row_w, col_w, half, lr, acc);
+
+    const float kt = a.kt_tab[a.t];
+    const size_t Np = (size_t)a.Np;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int col = col_w + cb * 32 + lr;
+        float cf[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) cf[k] = a.coef[(size_t)col * M + k];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int row = row_w + acc_row(half, g * 4);  // four consecutive spins row..row+3
+            const size_t off = (size_t)col * Np + row;
+            float4 xv = *(const float4 *)(a.x_in + off);
+            float4 yv = *(const float4 *)(a.y + off);
+            float xs[4] = {xv.x, xv.y, xv.z, xv.w}, ys[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) {
+                float h = 0.0f;
+#pragma unroll
+                for (int k = 0; k < M; ++k) h = fmaf(cf[k], acc[k][cb][g * 4 + ii], h);
+                float yn = fmaf(kt, xs[ii], ys[ii]) + h;
+                float xn = fmaf(a.dta0, yn, xs[ii]);
+                wall(xn, yn);
+                xs[ii] = xn;
+                ys[ii] = yn;
+            }
+            *(float4 *)(a.x_out + off) = make_float4(xs[0], xs[1], xs[2], xs[3]);
+            *(float4 *)(a.y + off) = make_float4(ys[0], ys[1], ys[2], ys[3]);
+            if (DSB) {
+                if constexpr (PREC == QAIA_FP32) {
+                    *(float4 *)((float *)a.phi_out + off) =
+                        make_float4(sgn1(xs[0]), sgn1(xs[1]), sgn1(xs[2]), sgn1(xs[3]));
+                } else if constexpr (PREC == QAIA_BF16) {
+                    uint2 v;
+                    v.x = (uint32_t)bf16_pm1(xs[0]) | ((uint32_t)bf16_pm1(xs[1]) << 16);
+                    v.y = (uint32_t)bf16_pm1(xs[2]) | ((uint32_t)bf16_pm1(xs[3]) << 16);
+                    *(uint2 *)((uint16_t *)a.phi_out + off) = v;
+                } else {
+                    uint32_t v = (uint32_t)fp8_pm1(xs[0]) | ((uint32_t)fp8_pm1(xs[1]) << 8) |
+                                 ((uint32_t)fp8_pm1(xs[2]) << 16) | ((uint32_t)fp8_pm1(xs[3]) << 24);
+                    *(uint32_t *)((uint8_t *)a.phi_out + off) = v;
+                }
+            }
+            if (a.trace != nullptr && a.t < a.trace_steps && col < a.cols) {
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii)
+                    if (row + ii < a.N)
+                        a.trace[((size_t)col * a.trace_steps + a.t) * a.N + row + ii] = xs[ii];
+            }
+        }
+    }
+}
+
+// Field mode (reduced-precision error reporting): field[col][k][i] = 2^e_k (J~_k Phi)_i.
+template <int PREC, int M>
+__global__ __launch_bounds__(kDB) void dense_field_kernel(DenseStepArgs a) {
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int half = l >> 5, lr = l & 31;
+    const int row_w = blockIdx.y * kTileM + (wv & 1) * 32;
+    const int col_w = blockIdx.x * kTileN + (wv >> 1) * 64;
+    f16v acc[M][2];
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[k][cb][i] = 0.0f;
+    mma_tile<PREC, M>(a, row_w, col_w, half, lr, acc);
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int col = col_w + cb * 32 + lr;
+        if (col >= a.cols) continue;
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int row = row_w + acc_row(half, i);
+                if (row < a.N)
+                    a.field[((size_t)col * M + k) * a.N + row] = acc[k][cb][i] * a.jscale[k];
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// set-up, coefficient and read-out kernels
+
+template <int PREC>
+__global__ void dense_init_kernel(float *x, float *y, void *phi, int Np, int N, int cols, int colsP,
+                                  uint64_t seed, uint64_t offset, float amp, bool dsb) {
+    const size_t idx = (size_t)blockIdx.x * kDB + threadIdx.x;
+    if (idx >= (size_t)colsP * Np) return;
+    const int col = (int)(idx / Np), i = (int)(idx % Np);
+    float xv = 0.0f, yv = 0.0f;
+    const bool live = col < cols && i < N;
+    if (live) {
+        const uint64_t g = (uint64_t)col + offset;
+        xv = init_value(seed, init_counter(g, N, i, 0), amp);
+        yv = init_value(seed, init_counter(g, N, i, 1), amp);
+    }
+    x[idx] = xv;
+    y[idx] = yv;
+    if (dsb) {
+        if constexpr (PREC == QAIA_FP32) ((float *)phi)[idx] = live ? sgn1(xv) : 0.0f;
+        else if constexpr (PREC == QAIA_BF16) ((uint16_t *)phi)[idx] = live ? bf16_pm1(xv) : 0;
+        else ((uint8_t *)phi)[idx] = live ? fp8_pm1(xv) : 0;
+    }
+}
+
+__global__ void dense_coef_kernel(const float *weights, const double *c0s, int m, int R, int cols,
+                                  int colsP, double dt, const float *jscale, float *coef) {
+    const int idx = blockIdx.x * kDB + threadIdx.x;
+    if (idx >= colsP * m) return;
+    const int col = idx / m, k = idx % m;
+    float v = 0.0f;
+    if (col < cols) {
+        const int w = col / R;
+        const double c0 = c0s[w];
+        if (c0 >= 0.0) v = (float)(-dt * c0 * (double)weights[(size_t)w * m + k] * (double)jscale[k]);
+    }
+    coef[idx] = v;
+}
+
+// Phi for the field hook: float input [count][N] -> padded operand [colsP][Np].
+template <int PREC>
+__global__ void dense_phi_kernel(const float *in, void *phi, int Np, int N, int count, int colsP) {
+    const size_t idx = (size_t)blockIdx.x * kDB + threadIdx.x;
+    if (idx >= (size_t)colsP * Np) return;
+    const int col = (int)(idx / Np), i = (int)(idx % Np);
+    const float v = (col < count && i < N) ? in[(size_t)col * N + i] : 0.0f;
+    if constexpr (PREC == QAIA_FP32) ((float *)phi)[idx] = v;
+    else if constexpr (PREC == QAIA_BF16) ((uint16_t *)phi)[idx] = v == 0.0f ? 0 : bf16_pm1(v);
+    else ((uint8_t *)phi)[idx] = v == 0.0f ? 0 : fp8_pm1(v);
+}
+
+// one wave per (column, 64-spin word): ballot of x < 0
+__global__ void dense_readout_kernel(const float *x, int Np, int N, int cols, int R, int words,
+                                     const double *c0s, uint64_t *spins) {
+    const int lane = threadIdx.x & 63;
+    const size_t item = (size_t)blockIdx.x * (kDB / 64) + (threadIdx.x >> 6);
+    if (item >= (size_t)cols * words) return;
+    const int col = (int)(item / words), wd = (int)(item % words);
+    const int i = wd * 64 + lane;
+    const bool neg = i < N && x[(size_t)col * Np + i] < 0.0f;
+    const uint64_t bits = __ballot(neg);
+    if (lane == 0) spins[(size_t)col * words + wd] = c0s[col / R] >= 0.0 ? bits : 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static uint16_t to_bf16(double v) {
+    float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round half to even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+
+// OCP e4m3 (bias 7, no infinities, max 448), round half to even, saturating.
+static uint8_t to_e4m3(double v) {
+    uint8_t s = v < 0 ? 0x80 : 0;
+    double a = std::fabs(v);
+    if (a == 0.0) return 0;
+    if (a >= 448.0) return s | 0x7E;
+    int e;
+    std::frexp(a, &e);  // a = f * 2^e, f in [0.5, 1)
+    e -= 1;             // a = (1 + m) 2^e
+    if (e < -6) {       // subnormal: quantum 2^-9
+        double q = std::nearbyint(a * 512.0);
+        if (q >= 8.0) return s | 0x08;
+        return s | (uint8_t)q;
+    }
+    double q = std::nearbyint((a / std::ldexp(1.0, e) - 1.0) * 8.0);
+    if (q >= 8.0) {
+        q = 0.0;
+        ++e;
+    }
+    if (e > 8 || (e == 8 && q > 6.0)) return s | 0x7E;
+    return s | (uint8_t)(((e + 7) << 3) | (int)q);
+}
+
+void dense_build(Problem &p) {
+    const int64_t Np = (p.n + 63) / 64 * 64;
+    const double bytes = (double)p.m * Np * Np * 7.0;
+    if (bytes > 4.0 * (1ull << 30)) {
+        p.dense.why = "dense images would exceed 4 GiB";
+        return;
+    }
+    DenseImages &d = p.dense;
+    d.Np = (int32_t)Np;
+    const size_t per = (size_t)Np * Np, all = per * p.m;
+    std::vector<float> j32(all, 0.0f);
+    std::vector<uint16_t> j16(all, 0);
+    std::vector<uint8_t> j8(all, 0);
+    for (int k = 0; k < p.m; ++k) {
+        int64_t mx = 0;
+        for (int64_t e = 0; e < p.E; ++e) mx = std::max<int64_t>(mx, std::llabs((long long)p.W[(size_t)k * p.E + e]));
+        // bf16: largest magnitude in [128, 256); e4m3: largest magnitude <= 448
+        int e16 = 0, e8 = 0;
+        if (mx > 0) {
+            e16 = (int)std::floor(std::log2((double)mx)) - 7;
+            e8 = (int)std::ceil(std::log2((double)mx / 448.0));
+            while ((double)mx * std::ldexp(1.0, -e8) > 448.0) ++e8;
+        }
+        d.scale16[k] = (float)std::ldexp(1.0, e16);
+        d.scale8[k] = (float)std::ldexp(1.0, e8);
+        for (int64_t e = 0; e < p.E; ++e) {
+            const double w = (double)p.W[(size_t)k * p.E + e];
+            const size_t a = per * k + (size_t)p.eu[e] * Np + p.ev[e];
+            const size_t b = per * k + (size_t)p.ev[e] * Np + p.eu[e];
+            j32[a] = j32[b] = (float)w;
+            j16[a] = j16[b] = to_bf16(w * std::ldexp(1.0, -e16));
+            j8[a] = j8[b] = to_e4m3(w * std::ldexp(1.0, -e8));
+        }
+    }
+    auto up = [](const void *src, size_t bytes) {
+        void *dst = nullptr;
+        hipError_t e = hipMalloc(&dst, bytes);
+        if (e == hipErrorOutOfMemory) throw Error{QAIA_OUT_OF_MEMORY, "device allocation failed"};
+        QAIA_HIP(e);
+        QAIA_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+        return dst;
+    };
+    DeviceGuard g(p.device);
+    d.J32 = (float *)up(j32.data(), all * 4);
+    d.J16 = (uint16_t *)up(j16.data(), all * 2);
+    d.J8 = (uint8_t *)up(j8.data(), all);
+    std::vector<float> sc(3 * 8, 1.0f);
+    for (int k = 0; k < p.m; ++k) {
+        sc[8 + k] = d.scale16[k];
+        sc[16 + k] = d.scale8[k];
+    }
+    d.scales = (float *)up(sc.data(), sc.size() * 4);
+    d.ok = true;
+}
+
+void dense_release(Problem &p) {
+    DeviceGuard g(p.device);
+    for (void *ptr : {(void *)p.dense.J32, (void *)p.dense.J16, (void *)p.dense.J8, (void *)p.dense.scales})
+        if (ptr) (void)hipFree(ptr);
+}
+
+static const void *dense_J(const Problem &p, int prec) {
+    return prec == QAIA_FP32 ? (const void *)p.dense.J32
+                             : (prec == QAIA_BF16 ? (const void *)p.dense.J16 : (const void *)p.dense.J8);
+}
+static size_t elem_bytes(int prec) { return prec == QAIA_FP32 ? 4 : (prec == QAIA_BF16 ? 2 : 1); }
+
+void dense_ws_extend(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, WsLayout &L) {
+    const size_t cols = (size_t)W * R;
+    const size_t colsP = (cols + kTileN - 1) / kTileN * kTileN;
+    const size_t Np = (size_t)p.dense.Np;
+    size_t off = L.total;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off += align256(b);
+        return o;
+    };
+    L.colsP = (int64_t)colsP;
+    L.xa = take(4 * colsP * Np);
+    L.xb = s.variant == QAIA_BSB ? take(4 * colsP * Np) : L.xa;
+    L.y = take(4 * colsP * Np);
+    const size_t pb = elem_bytes(s.precision) * colsP * Np;
+    L.pa = s.variant == QAIA_DSB ? take(pb) : L.xa;
+    L.pb = s.variant == QAIA_DSB ? take(pb) : L.xb;
+    L.coef = take(4 * colsP * (size_t)p.m);
+    L.total = off;
+}
+
+bool dense_supported(const Problem &p, std::string *why) {
+    if (!p.dense.ok) {
+        if (why) *why = p.dense.why.empty() ? "dense images not built" : p.dense.why;
+        return false;
+    }
+    return true;
+}
+
+template <int PREC, int M, bool DSB>
+static void step_launch(dim3 grid, hipStream_t st, const DenseStepArgs &a) {
+    hipLaunchKernelGGL((dense_step_kernel<PREC, M, DSB>), grid, dim3(kDB), 0, st, a);
+}
+
+template <int PREC, bool DSB>
+static void step_dispatch_m(int m, dim3 grid, hipStream_t st, const DenseStepArgs &a) {
+    switch (m) {
+        case 1: step_launch<PREC, 1, DSB>(grid, st, a); break;
+        case 2: step_launch<PREC, 2, DSB>(grid, st, a); break;
+        case 3: step_launch<PREC, 3, DSB>(grid, st, a); break;
+        case 4: step_launch<PREC, 4, DSB>(grid, st, a); break;
+        default: throw Error{QAIA_UNSUPPORTED, "dense path supports m <= 4"};
+    }
+}
+
+static void step_dispatch(int prec, bool dsb, int m, dim3 grid, hipStream_t st, const DenseStepArgs &a) {
+    if (prec == QAIA_FP32) {
+        if (dsb) step_dispatch_m<QAIA_FP32, true>(m, grid, st, a);
+        else step_dispatch_m<QAIA_FP32, false>(m, grid, st, a);
+    } else if (prec == QAIA_BF16) {
+        step_dispatch_m<QAIA_BF16, true>(m, grid, st, a);
+    } else {
+        step_dispatch_m<QAIA_FP8, true>(m, grid, st, a);
+    }
+}
+
+void launch_dense(const Problem &p, const float *weights, int64_t W, int32_t R,
+                  const qaia_schedule &s, void *ws, const WsLayout &L, uint64_t *spins, int64_t *obj,
+                  float *trace, int32_t trace_steps, hipStream_t st) {
+    std::string why;
+    QAIA_CHECK(dense_supported(p, &why), QAIA_UNSUPPORTED, "dense path: " + why);
+    QAIA_CHECK(p.m <= 4, QAIA_UNSUPPORTED, "dense path supports m <= 4");
+    const int64_t cols = W * (int64_t)R;
+    if (cols == 0) return;
+    QAIA_CHECK(L.colsP <= INT32_MAX / 2, QAIA_INVALID_ARGUMENT, "too many replicas for the dense path");
+    char *b = (char *)ws;
+    const int Np = p.dense.Np, colsP = (int)L.colsP, prec = s.precision;
+    const bool dsb = s.variant == QAIA_DSB;
+    const double *c0s = (const double *)(b + L.c0s);
+    float *xa = (float *)(b + L.xa), *xb = (float *)(b + L.xb), *y = (float *)(b + L.y);
+    void *pa = b + L.pa, *pbuf = b + L.pb;
+    float *coef = (float *)(b + L.coef);
+    const float *jscale = p.dense.scales + 8 * prec;
+
+    const size_t total = (size_t)colsP * Np;
+    const unsigned ib = (unsigned)((total + kDB - 1) / kDB);
+    if (prec == QAIA_FP32)
+        hipLaunchKernelGGL(dense_init_kernel<QAIA_FP32>, dim3(ib), dim3(kDB), 0, st, xa, y, pa, Np, p.n,
+                           (int)cols, colsP, s.seed, s.replica_offset, s.init_amp, dsb);
+    else if (prec == QAIA_BF16)
+        hipLaunchKernelGGL(dense_init_kernel<QAIA_BF16>, dim3(ib), dim3(kDB), 0, st, xa, y, pa, Np, p.n,
+                           (int)cols, colsP, s.seed, s.replica_offset, s.init_amp, dsb);
+    else
+        hipLaunchKernelGGL(dense_init_kernel<QAIA_FP8>, dim3(ib), dim3(kDB), 0, st, xa, y, pa, Np, p.n,
+                           (int)cols, colsP, s.seed, s.replica_offset, s.init_amp, dsb);
+    QAIA_HIP(hipGetLastError());
+    const unsigned cb = (unsigned)((colsP * p.m + kDB - 1) / kDB);
+    hipLaunchKernelGGL(dense_coef_kernel, dim3(cb), dim3(kDB), 0, st, weights, c0s, p.m, R, (int)cols,
+                       colsP, (double)s.dt, jscale, coef);
+    QAIA_HIP(hipGetLastError());
+
+    DenseStepArgs a{};
+    a.J = dense_J(p, prec);
+    a.coef = coef;
+    a.kt_tab = (const float *)(b + L.kt);
+    a.dta0 = s.dt * s.a0;
+    a.Np = Np;
+    a.N = p.n;
+    a.cols = (int)cols;
+    a.y = y;
+    a.trace = trace_steps > 0 ? trace : nullptr;
+    a.trace_steps = trace_steps;
+    const dim3 grid(colsP / kTileN, Np / kTileM);
+    float *xcur = xa, *xnext = xb;
+    void *pcur = pa, *pnext = pbuf;
+    for (int t = 0; t < s.steps; ++t) {
+        a.t = t;
+        a.x_in = xcur;
+        a.x_out = dsb ? xcur : xnext;  // discrete SB updates x in place (Phi is separate)
+        a.phi_in = dsb ? pcur : (const void *)xcur;
+        a.phi_out = dsb ? pnext : nullptr;
+        step_dispatch(prec, dsb, p.m, grid, st, a);
+        if (!dsb) std::swap(xcur, xnext);
+        else std::swap(pcur, pnext);
+    }
+    QAIA_HIP(hipGetLastError());
+    const size_t items = (size_t)cols * p.words;
+    hipLaunchKernelGGL(dense_readout_kernel, dim3((unsigned)((items + 3) / 4)), dim3(kDB), 0, st, xcur, Np,
+                       p.n, (int)cols, R, p.words, c0s, spins);
+    QAIA_HIP(hipGetLastError());
+    launch_evaluate(p, spins, cols, obj, st);
+}
+
+// ---------------------------------------------------------------------------
+// field hook
+
+size_t dense_field_ws_bytes(const Problem &p, int prec, int64_t count) {
+    const size_t colsP = (size_t)(count + kTileN - 1) / kTileN * kTileN;
+    return align256(elem_bytes(prec) * colsP * (size_t)std::max(p.dense.Np, 64));
+}
+
+template <int PREC, int M>
+static void field_launch(dim3 grid, hipStream_t st, const DenseStepArgs &a) {
+    hipLaunchKernelGGL((dense_field_kernel<PREC, M>), grid, dim3(kDB), 0, st, a);
+}
+
+template <int PREC>
+static void field_dispatch(int m, dim3 grid, hipStream_t st, const DenseStepArgs &a) {
+    switch (m) {
+        case 1: field_launch<PREC, 1>(grid, st, a); break;
+        case 2: field_launch<PREC, 2>(grid, st, a); break;
+        case 3: field_launch<PREC, 3>(grid, st, a); break;
+        case 4: field_launch<PREC, 4>(grid, st, a); break;
+        default: throw Error{QAIA_UNSUPPORTED, "dense path supports m <= 4"};
+    }
+}
+
+void launch_dense_field(const Problem &p, int prec, const float *phi, int64_t count, float *field,
+                        void *ws, size_t ws_bytes, hipStream_t st) {
+    std::string why;
+    QAIA_CHECK(dense_supported(p, &why), QAIA_UNSUPPORTED, "dense path: " + why);
+    QAIA_CHECK(p.m <= 4, QAIA_UNSUPPORTED, "dense path supports m <= 4");
+    QAIA_CHECK(ws_bytes >= dense_field_ws_bytes(p, prec, count), QAIA_WORKSPACE_TOO_SMALL,
+               "field workspace too small");
+    if (count == 0) return;
+    const int Np = p.dense.Np;
+    const int colsP = (int)((count + kTileN - 1) / kTileN * kTileN);
+    const size_t total = (size_t)colsP * Np;
+    const unsigned ib = (unsigned)((total + kDB - 1) / kDB);
+    if (prec == QAIA_FP32)
+        hipLaunchKernelGGL(dense_phi_kernel<QAIA_FP32>, dim3(ib), dim3(kDB), 0, st, phi, ws, Np, p.n, (int)count, colsP);
+    else if (prec == QAIA_BF16)
+        hipLaunchKernelGGL(dense_phi_kernel<QAIA_BF16>, dim3(ib), dim3(kDB), 0, st, phi, ws, Np, p.n, (int)count, colsP);
+    else
+        hipLaunchKernelGGL(dense_phi_kernel<QAIA_FP8>, dim3(ib), dim3(kDB), 0, st, phi, ws, Np, p.n, (int)count, colsP);
+    QAIA_HIP(hipGetLastError());
+    DenseStepArgs a{};
+    a.J = dense_J(p, prec);
+    a.phi_in = ws;
+    a.Np = Np;
+    a.N = p.n;
+    a.cols = (int)count;
+    a.field = field;
+    a.jscale = p.dense.scales + 8 * prec;
+    const dim3 grid(colsP / kTileN, Np / kTileM);
+    if (prec == QAIA_FP32) field_dispatch<QAIA_FP32>(p.m, grid, st, a);
+    else if (prec == QAIA_BF16) field_dispatch<QAIA_BF16>(p.m, grid, st, a);
+    else field_dispatch<QAIA_FP8>(p.m, grid, st, a);
+    QAIA_HIP(hipGetLastError());
+}
+
+}  // namespace qaia

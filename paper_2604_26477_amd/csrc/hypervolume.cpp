@@ -18,8 +18,10 @@
 //          coordinates (their last coordinate is p_i,last for all of them).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -198,8 +200,34 @@ void nondominated(std::vector<uint64_t> &buf, int stride, int d, size_t &count) 
     count = keep.size();
 }
 
-// HV of `count` points (rows of `buf` with `stride`) in the first d >= 3 coordinates.
-U256 wfg(std::vector<uint64_t> buf, int stride, int d, size_t count) {
+U256 wfg(std::vector<uint64_t> buf, int stride, int d, size_t count, int threads);
+
+// Exclusive volume of the point at order[oi] with respect to the points after
+// it (all of which have a last coordinate >= its own).
+U256 exclusive(const std::vector<uint64_t> &buf, const std::vector<size_t> &order, size_t oi,
+               int stride, int d, std::vector<uint64_t> &lim) {
+    const int last = d - 1;
+    const size_t count = order.size();
+    const uint64_t *p = &buf[order[oi] * stride];
+    if (p[last] == 0) return U256();
+    U256 box;
+    box.w[0] = 1;
+    for (int k = 0; k < last; ++k) box = mul64(box, p[k]);
+    size_t L = count - oi - 1;
+    lim.assign(L * stride, 0);
+    for (size_t j = 0; j < L; ++j) {
+        const uint64_t *q = &buf[order[oi + 1 + j] * stride];
+        for (int k = 0; k < last; ++k) lim[j * stride + k] = std::min(p[k], q[k]);
+    }
+    // the 3-D sweep tolerates dominated points; deeper recursion filters first
+    if (last > 3) nondominated(lim, stride, last, L);
+    U256 covered = wfg(lim, stride, last, L, 1);
+    return mul64(sub(box, covered), p[last]);
+}
+
+// HV of `count` points (rows of `buf` with `stride`) in the first d >= 3
+// coordinates; the top level splits its exclusive volumes over threads.
+U256 wfg(std::vector<uint64_t> buf, int stride, int d, size_t count, int threads) {
     if (count == 0) return U256();
     if (d == 3) {
         std::vector<const uint64_t *> P(count);
@@ -211,24 +239,23 @@ U256 wfg(std::vector<uint64_t> buf, int stride, int d, size_t count) {
     for (size_t i = 0; i < count; ++i) order[i] = i;
     std::sort(order.begin(), order.end(),
               [&](size_t a, size_t b) { return buf[a * stride + last] < buf[b * stride + last]; });
-    U256 total;
-    std::vector<uint64_t> lim;
-    for (size_t oi = 0; oi < count; ++oi) {
-        const uint64_t *p = &buf[order[oi] * stride];
-        if (p[last] == 0) continue;
-        U256 box;
-        box.w[0] = 1;
-        for (int k = 0; k < last; ++k) box = mul64(box, p[k]);
-        size_t L = count - oi - 1;
-        lim.assign(L * stride, 0);
-        for (size_t j = 0; j < L; ++j) {
-            const uint64_t *q = &buf[order[oi + 1 + j] * stride];
-            for (int k = 0; k < last; ++k) lim[j * stride + k] = std::min(p[k], q[k]);
-        }
-        nondominated(lim, stride, last, L);
-        U256 covered = wfg(lim, stride, last, L);
-        total = add(total, mul64(sub(box, covered), p[last]));
+    const int nt = (int)std::max<size_t>(1, std::min<size_t>((size_t)threads, count / 64));
+    std::vector<U256> part(nt);
+    auto work = [&](int t) {
+        std::vector<uint64_t> lim;
+        // interleaved assignment balances the decreasing cost along the order
+        for (size_t oi = (size_t)t; oi < count; oi += (size_t)nt)
+            part[t] = add(part[t], exclusive(buf, order, oi, stride, d, lim));
+    };
+    if (nt == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nt; ++t) pool.emplace_back(work, t);
+        for (auto &th : pool) th.join();
     }
+    U256 total;
+    for (const U256 &v : part) total = add(total, v);
     return total;
 }
 
@@ -266,7 +293,9 @@ int32_t hypervolume_exact(const int64_t *pts, int64_t P, int32_t m, const int64_
     } else {
         size_t count = (size_t)P;
         nondominated(ext, m, m, count);
-        v = wfg(ext, m, m, count);
+        int threads = (int)std::thread::hardware_concurrency();
+        if (const char *e = std::getenv("QAIA_HV_THREADS")) threads = std::atoi(e);
+        v = wfg(ext, m, m, count, std::max(1, threads));
     }
     for (int i = 0; i < 4; ++i) hv[i] = v.w[i];
     if (approx) *approx = to_double(v);

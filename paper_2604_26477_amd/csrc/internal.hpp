@@ -45,6 +45,19 @@ struct DeviceGuard {
 // ----------------------------------------------------------------- problem
 struct JitKernel;  // generated per-graph kernel (jit.cpp)
 
+// Dense per-objective images of J for the matrix-core path, zero padded to
+// Np = ceil64(n); bf16 / e4m3 copies hold W * 2^-e_k (value = stored * scale).
+struct DenseImages {
+    bool ok = false;
+    std::string why;  // reason when not built
+    int32_t Np = 0;
+    float *J32 = nullptr;     // [m][Np][Np]
+    uint16_t *J16 = nullptr;  // bf16 bits
+    uint8_t *J8 = nullptr;    // e4m3 bits
+    float scale16[8] = {}, scale8[8] = {};
+    float *scales = nullptr;  // device [3][8]: per precision, per objective
+};
+
 struct Problem {
     int32_t n = 0, m = 0, frac_bits = 0, device = 0;
     int64_t E = 0;
@@ -59,7 +72,9 @@ struct Problem {
     int64_t *d_rho = nullptr;  // [m][n] row sums sum_j W_k,ij (exact)
     // generated register-resident kernels, index = variant (bSB, dSB)
     JitKernel *jit[2] = {nullptr, nullptr};
+    JitKernel *jit_trace[2] = {nullptr, nullptr};  // tracing variants, built on first use
     std::string jit_error;
+    DenseImages dense;
     std::mutex mu;
     ~Problem();
 };
@@ -68,8 +83,10 @@ struct Problem {
 // Layout of the caller's workspace for qaia_sample (all offsets 256-aligned):
 //   header   : WsHeader
 //   kt       : float[T]          per-step coefficient -dt (a0 - a_t)
-//   c0s      : float[W]          dt*c0 per weight row; negative marks an invalid row
+//   c0s      : double[W]         c0 per weight row (weight units); negative marks an invalid row
 //   jcp      : float[W][E]       folded edge coefficients -dt c0 J(c)_e (sparse paths)
+// and for the dense path: x (two buffers for ballistic SB), y, Phi (two
+// buffers for discrete SB) and per-column coefficients.
 struct WsHeader {
     uint64_t magic;
     int64_t bad_row;  // smallest invalid weight row, INT64_MAX if none
@@ -82,8 +99,12 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct WsLayout {
     size_t header = 0, kt = 0, c0s = 0, jcp = 0, total = 0;
+    // dense path
+    int64_t colsP = 0;
+    size_t xa = 0, xb = 0, y = 0, pa = 0, pb = 0, coef = 0;
 };
 WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s);
+void dense_ws_extend(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, WsLayout &L);
 
 // ----------------------------------------------------------------- kernels (host launchers)
 void launch_prep(const Problem &p, const float *weights, int64_t W, const qaia_schedule &s,
@@ -102,6 +123,17 @@ void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, cons
                        void *ws, const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
                        int32_t trace_steps, hipStream_t st);
 void jit_release(JitKernel *k);
+
+// dense path (dense.hip)
+void dense_build(Problem &p);
+void dense_release(Problem &p);
+bool dense_supported(const Problem &p, std::string *why);
+void launch_dense(const Problem &p, const float *weights, int64_t W, int32_t R,
+                  const qaia_schedule &s, void *ws, const WsLayout &L, uint64_t *spins, int64_t *obj,
+                  float *trace, int32_t trace_steps, hipStream_t st);
+size_t dense_field_ws_bytes(const Problem &p, int prec, int64_t count);
+void launch_dense_field(const Problem &p, int prec, const float *phi, int64_t count, float *field,
+                        void *ws, size_t ws_bytes, hipStream_t st);
 
 // pareto filter (pareto.hip)
 size_t pareto_ws_bytes(int64_t M, int32_t m);

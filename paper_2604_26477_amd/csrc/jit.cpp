@@ -81,14 +81,14 @@ __device__ __forceinline__ float initv(u64 seed, u64 idx, float amp) {
 }
 )";
 
-static std::string generate(const Problem &p, int variant) {
+static std::string generate(const Problem &p, int variant, bool trace) {
     const int n = p.n, m = p.m;
     const int64_t E = p.E;
     const bool dsb = variant == QAIA_DSB;
     std::ostringstream s;
     s << kPrelude;
     s << "extern \"C\" __global__ __attribute__((amdgpu_flat_work_group_size(1, 256)))\n"
-         "void qaia_sb_reg(const float* __restrict__ jcp, const float* __restrict__ c0s,\n"
+         "void qaia_sb_reg(const float* __restrict__ jcp, const double* __restrict__ c0s,\n"
          "  const float* __restrict__ kt_tab, i64 rows, int R, int T, float dta0, u64 seed,\n"
          "  u64 offset, float amp, u64* __restrict__ spins, i64* __restrict__ obj,\n"
          "  float* __restrict__ trace, int trace_steps) {\n";
@@ -97,12 +97,14 @@ static std::string generate(const Problem &p, int variant) {
     s << "  if (row >= rows) return;\n";
     s << "  const i64 w = row / R;\n";
     s << "  const u64 g = (u64)row + offset;\n";
-    s << "  if (c0s[w] < 0.0f) {\n";
+    s << "  if (c0s[w] < 0.0) {\n";
     for (int wd = 0; wd < p.words; ++wd) s << "    spins[row * " << p.words << " + " << wd << "] = 0ull;\n";
     for (int k = 0; k < m; ++k) s << "    obj[row * " << m << " + " << k << "] = 0ll;\n";
     s << "    return;\n  }\n";
+    // "+ 0.0f" turns a -0 start (init_amp = 0) into +0, so x is never -0 and
+    // sgn(x) = copysign(1, x) agrees with sgn(0) = +1
     for (int i = 0; i < n; ++i)
-        s << "  float X" << i << " = initv(seed, ((g * " << n << "ull + " << i << "ull) << 1), amp), Y"
+        s << "  float X" << i << " = initv(seed, ((g * " << n << "ull + " << i << "ull) << 1), amp) + 0.0f, Y"
           << i << " = initv(seed, ((g * " << n << "ull + " << i << "ull) << 1) | 1ull, amp);\n";
     s << "  const float* jr = jcp + w * " << E << "ll;\n";
     for (int64_t e = 0; e < E; ++e) s << "  const float J" << e << " = jr[" << e << "];\n";
@@ -110,7 +112,7 @@ static std::string generate(const Problem &p, int variant) {
     s << "    const float kt = kt_tab[t];\n";
     if (dsb)
         for (int i = 0; i < n; ++i)
-            s << "    const float S" << i << " = X" << i << " >= 0.0f ? 1.0f : -1.0f;\n";
+            s << "    const float S" << i << " = __builtin_copysignf(1.0f, X" << i << ");\n";
     // y_i += kt x_i + sum_j Jc'_ij phi(x_j), every phi from the pre-step x
     for (int i = 0; i < n; ++i) {
         s << "    Y" << i << " = __builtin_fmaf(kt, X" << i << ", Y" << i << ");";
@@ -119,16 +121,19 @@ static std::string generate(const Problem &p, int variant) {
               << p.col[q] << ", Y" << i << ");";
         s << "\n";
     }
-    // x_i += dt a0 y_i, then the inelastic wall
+    // x_i += dt a0 y_i, then the inelastic wall: |x| > 1 zeroes y, clamps x
     for (int i = 0; i < n; ++i) {
-        s << "    X" << i << " = __builtin_fmaf(dta0, Y" << i << ", X" << i << "); { const float c = "
-          << "__builtin_fminf(__builtin_fmaxf(X" << i << ", -1.0f), 1.0f); Y" << i << " = (c == X"
-          << i << ") ? Y" << i << " : 0.0f; X" << i << " = c; }\n";
+        s << "    X" << i << " = __builtin_fmaf(dta0, Y" << i << ", X" << i << "); Y" << i
+          << " = __builtin_fabsf(X" << i << ") > 1.0f ? 0.0f : Y" << i << "; X" << i
+          << " = __builtin_fminf(__builtin_fmaxf(X" << i << ", -1.0f), 1.0f);\n";
     }
-    s << "    if (trace != nullptr && t < trace_steps) {\n";
-    s << "      float* tr = trace + (row * trace_steps + t) * " << n << "ll;\n";
-    for (int i = 0; i < n; ++i) s << "      tr[" << i << "] = X" << i << ";\n";
-    s << "    }\n  }\n";
+    if (trace) {  // test hook only: the plain kernel carries no trace code
+        s << "    if (t < trace_steps) {\n";
+        s << "      float* tr = trace + (row * trace_steps + t) * " << n << "ll;\n";
+        for (int i = 0; i < n; ++i) s << "      tr[" << i << "] = X" << i << ";\n";
+        s << "    }\n";
+    }
+    s << "  }\n";
     // read-out: bit i set <=> x_i < 0 (sgn 0 = +1)
     for (int wd = 0; wd < p.words; ++wd) {
         s << "  { u64 b = 0ull;";
@@ -242,6 +247,33 @@ static std::vector<char> compile(const std::string &src) {
 static std::mutex g_cache_mu;
 static std::map<uint64_t, std::vector<char>> g_cache;  // source hash -> code object
 
+static JitKernel *build_kernel(const Problem &p, int variant, bool trace) {
+    const std::string src = generate(p, variant, trace);
+    const uint64_t h = fnv1a(src);
+    std::vector<char> code;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find(h);
+        if (it != g_cache.end()) code = it->second;
+    }
+    if (code.empty()) {
+        code = compile(src);
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_cache[h] = code;
+    }
+    JitKernel *k = new JitKernel();
+    k->device = p.device;
+    DeviceGuard g(p.device);
+    hipError_t e = hipModuleLoadData(&k->mod, code.data());
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->fn, k->mod, "qaia_sb_reg");
+    if (e != hipSuccess) {
+        std::string msg = std::string("loading the generated kernel: ") + hipGetErrorString(e);
+        jit_release(k);
+        throw Error{QAIA_DEVICE_ERROR, msg};
+    }
+    return k;
+}
+
 void jit_prepare(Problem &p) {
     std::string why;
     if (!jit_eligible(p, &why)) {
@@ -250,30 +282,7 @@ void jit_prepare(Problem &p) {
     }
     for (int variant = 0; variant < 2; ++variant) {
         try {
-            const std::string src = generate(p, variant);
-            const uint64_t h = fnv1a(src);
-            std::vector<char> code;
-            {
-                std::lock_guard<std::mutex> lk(g_cache_mu);
-                auto it = g_cache.find(h);
-                if (it != g_cache.end()) code = it->second;
-            }
-            if (code.empty()) {
-                code = compile(src);
-                std::lock_guard<std::mutex> lk(g_cache_mu);
-                g_cache[h] = code;
-            }
-            JitKernel *k = new JitKernel();
-            k->device = p.device;
-            DeviceGuard g(p.device);
-            hipError_t e = hipModuleLoadData(&k->mod, code.data());
-            if (e == hipSuccess) e = hipModuleGetFunction(&k->fn, k->mod, "qaia_sb_reg");
-            if (e != hipSuccess) {
-                std::string msg = std::string("loading the generated kernel: ") + hipGetErrorString(e);
-                jit_release(k);
-                throw Error{QAIA_DEVICE_ERROR, msg};
-            }
-            p.jit[variant] = k;
+            p.jit[variant] = build_kernel(p, variant, false);
         } catch (const Error &err) {
             p.jit_error = err.msg;
             return;
@@ -281,12 +290,21 @@ void jit_prepare(Problem &p) {
     }
 }
 
+// The tracing variants exist for trajectory tests only; they are generated on
+// first use.
+static const JitKernel *trace_kernel(const Problem &p, int variant) {
+    Problem &mp = const_cast<Problem &>(p);
+    std::lock_guard<std::mutex> lk(mp.mu);
+    if (!mp.jit_trace[variant]) mp.jit_trace[variant] = build_kernel(p, variant, true);
+    return mp.jit_trace[variant];
+}
+
 void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, const qaia_schedule &s,
                        void *ws, const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
                        int32_t trace_steps, hipStream_t st) {
-    const JitKernel *k = p.jit[variant];
-    QAIA_CHECK(k != nullptr, QAIA_UNSUPPORTED,
+    QAIA_CHECK(p.jit[variant] != nullptr, QAIA_UNSUPPORTED,
                "register-resident path unavailable: " + (p.jit_error.empty() ? std::string("not built") : p.jit_error));
+    const JitKernel *k = trace != nullptr ? trace_kernel(p, variant) : p.jit[variant];
     QAIA_CHECK(s.noise_alpha == 0.0f, QAIA_UNSUPPORTED,
                "register-resident path runs plain SB only (noise_alpha must be 0)");
     const int64_t rows = W * (int64_t)R;
@@ -294,8 +312,8 @@ void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, cons
     const int64_t blocks = (rows + 255) / 256;
     QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many replicas for one launch");
     char *b = (char *)ws;
-    const float *jcp = (const float *)(b + L.jcp), *c0s = (const float *)(b + L.c0s),
-                *kt = (const float *)(b + L.kt);
+    const float *jcp = (const float *)(b + L.jcp), *kt = (const float *)(b + L.kt);
+    const double *c0s = (const double *)(b + L.c0s);
     int T = s.steps;
     float dta0 = s.dt * s.a0, amp = s.init_amp;
     uint64_t seed = s.seed, off = s.replica_offset;

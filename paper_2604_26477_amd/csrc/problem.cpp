@@ -32,6 +32,11 @@ Problem::~Problem() {
         jit_release(k);
         k = nullptr;
     }
+    for (auto &k : jit_trace) {
+        jit_release(k);
+        k = nullptr;
+    }
+    dense_release(*this);
     DeviceGuard g(device);
     for (void *ptr : {(void *)d_eu, (void *)d_ev, (void *)d_W, (void *)d_rowptr, (void *)d_col,
                       (void *)d_eid, (void *)d_rho})
@@ -92,7 +97,6 @@ Problem *build_problem(int32_t n, int32_t m, int64_t E, const int32_t *eu, const
         p->rowptr.assign(n + 1, 0);
         for (int i = 0; i < n; ++i) p->rowptr[i + 1] = p->rowptr[i] + deg[i];
         p->max_degree = n ? *std::max_element(deg.begin(), deg.end()) : 0;
-        std::vector<std::pair<int32_t, int32_t>> adj((size_t)2 * E);  // (node, neighbour) order
         std::vector<int32_t> fill(p->rowptr.begin(), p->rowptr.end() - 1);
         p->col.assign((size_t)2 * E, 0);
         p->eid.assign((size_t)2 * E, 0);
@@ -131,6 +135,7 @@ Problem *build_problem(int32_t n, int32_t m, int64_t E, const int32_t *eu, const
         p->d_col = upload(p->col);
         p->d_eid = upload(p->eid);
         p->d_rho = upload(rho);
+        dense_build(*p);
         jit_prepare(*p);
     } catch (...) {
         delete p;

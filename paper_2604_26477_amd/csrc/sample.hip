@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
     const float *__restrict__ weights, int64_t W, int m, int n, int64_t E,
     const int64_t *__restrict__ rho, const int32_t *__restrict__ Wt,
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ eid, double dt, double a0,
-    int T, float *__restrict__ kt, float *__restrict__ c0s, float *__restrict__ jcp,
+    int T, float *__restrict__ kt, double *__restrict__ c0s, float *__restrict__ jcp,
     WsHeader *hdr) {
     __shared__ double c_sh[8];
     __shared__ double red[kBlock / 64];
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
     __syncthreads();
     if (!valid_sh) {
         if (tid == 0) {
-            c0s[w] = -1.0f;
+            c0s[w] = -1.0;
             atomicMin((unsigned long long *)&hdr->bad_row, (unsigned long long)w);
         }
         if (jcp)
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
         mxa = block_max(mxa);
         c0 = mxa > 0.0 ? 1.0 / mxa : 0.0;
     }
-    if (tid == 0) c0s[w] = (float)c0;
+    if (tid == 0) c0s[w] = c0;
     if (jcp) {
         const double coef = -dt * c0;
         for (int64_t e = tid; e < E; e += kBlock) {
@@ -125,7 +125,7 @@ WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_sch
     L.kt = off;
     off += align256(sizeof(float) * (size_t)s.steps);
     L.c0s = off;
-    off += align256(sizeof(float) * (size_t)W);
+    off += align256(sizeof(double) * (size_t)W);
     L.jcp = off;
     off += align256(sizeof(float) * (size_t)W * (size_t)p.E);
     L.total = off;
@@ -144,7 +144,7 @@ void launch_prep(const Problem &p, const float *weights, int64_t W, const qaia_s
     QAIA_CHECK(grid <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many weight rows");
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(kBlock), 0, st, weights, W, p.m,
                        p.n, p.E, p.d_rho, p.d_W, p.d_rowptr, p.d_eid, (double)s.dt, (double)s.a0,
-                       s.steps, (float *)(b + L.kt), (float *)(b + L.c0s),
+                       s.steps, (float *)(b + L.kt), (double *)(b + L.c0s),
                        L.jcp != L.total ? (float *)(b + L.jcp) : nullptr, hdr);
     QAIA_HIP(hipGetLastError());
 }
@@ -161,7 +161,7 @@ template <int MAXDEG, int NPT, bool DSB>
 __global__ __launch_bounds__(kBlock) void sparse_lds_kernel(
     int n, int64_t E, int rpb, int64_t rows, int R, int T, const int32_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
-    const float *__restrict__ jcp, const float *__restrict__ c0s,
+    const float *__restrict__ jcp, const double *__restrict__ c0s,
     const float *__restrict__ kt_tab, float dta0, float dt_alpha, uint64_t seed,
     uint64_t offset, float amp, int m, const int32_t *__restrict__ Wt,
     const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int words,
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void sparse_lds_kernel(
     for (int rl = wave; rl < rpb; rl += kBlock / 64) {
         const int64_t row = row0 + rl;
         if (row >= rows) break;
-        const bool valid = c0s[row / R] >= 0.0f;
+        const bool valid = c0s[row / R] >= 0.0;
         const float *xr = xf + rl * n;
         for (int wd = lane; wd < words; wd += 64) {
             uint64_t bits = 0;
@@ -301,7 +301,7 @@ bool sparse_lds_supported(const Problem &p, std::string *why) {
 template <int MAXDEG, int NPT>
 static void launch_lds_t(const Problem &p, bool dsb, dim3 grid, size_t shmem, hipStream_t st,
                          int rpb, int64_t rows, int32_t R, const qaia_schedule &s, const float *jcp,
-                         const float *c0s, const float *kt, uint64_t *spins, int64_t *obj,
+                         const double *c0s, const float *kt, uint64_t *spins, int64_t *obj,
                          float *trace, int trace_steps) {
     const float dta0 = s.dt * s.a0;
     const float dt_alpha = s.dt * s.noise_alpha;
@@ -320,7 +320,7 @@ static void launch_lds_t(const Problem &p, bool dsb, dim3 grid, size_t shmem, hi
 template <int MAXDEG>
 static void launch_lds_npt(int npt, const Problem &p, bool dsb, dim3 grid, size_t shmem,
                            hipStream_t st, int rpb, int64_t rows, int32_t R,
-                           const qaia_schedule &s, const float *jcp, const float *c0s,
+                           const qaia_schedule &s, const float *jcp, const double *c0s,
                            const float *kt, uint64_t *spins, int64_t *obj, float *trace,
                            int trace_steps) {
 #define QAIA_NPT(N)                                                                          \
@@ -355,8 +355,8 @@ void launch_sparse_lds(const Problem &p, int64_t W, int32_t R, const qaia_schedu
     QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many replicas for one launch");
     const size_t shmem = sizeof(float) * 2 * (size_t)span;
     char *b = (char *)ws;
-    const float *jcp = (const float *)(b + L.jcp), *c0s = (const float *)(b + L.c0s),
-                *kt = (const float *)(b + L.kt);
+    const float *jcp = (const float *)(b + L.jcp), *kt = (const float *)(b + L.kt);
+    const double *c0s = (const double *)(b + L.c0s);
     const bool dsb = s.variant == QAIA_DSB;
     dim3 grid((unsigned)blocks);
     if (p.max_degree <= 4)
