@@ -216,6 +216,66 @@ int32_t qaia_pareto_filter(const int64_t *obj, int64_t M, int32_t m, int64_t *ke
 int32_t qaia_hypervolume(const int64_t *pts, int64_t P, int32_t m, const int64_t *ref,
                          uint64_t hv[4], double *hv_approx);
 
+/* ---------------------------------------------------------------- learned form */
+/* The paper scalarises with fixed weight vectors (Das-Dennis or Dirichlet,
+ * section "Scalarization via the weighted sum method"); the learned form
+ * proposes them instead: a multilayer perceptron in_dim -> 128 -> 128 -> 1
+ * (exact-erf GELU, bf16 weights, fp32 activations and accumulation) scores
+ * candidate vectors c from c and eight features of the current
+ * non-dominated archive, and is trained online by Adam on the mean binary
+ * cross-entropy of "c produced a new non-dominated point".
+ * Parameters (flat, in this order): W1 [128][in_dim], b1 [128], W2 [128][128],
+ * b2 [128], w3 [128], b3 [1]; in_dim in [1, 16].  All buffers DEVICE unless
+ * stated; calls are asynchronous on hip_stream. */
+
+int32_t qaia_mlp_param_count(int32_t in_dim, int64_t *count); /* count: HOST */
+int32_t qaia_mlp_forward_workspace_bytes(int64_t N, size_t *bytes);
+/* logits[N] of inputs X [N][in_dim]; params: bf16 bit patterns. */
+int32_t qaia_mlp_forward(const uint16_t *params, int32_t in_dim, const float *X, int64_t N,
+                         float *logits, void *workspace, size_t ws_bytes, void *hip_stream);
+int32_t qaia_mlp_backward_workspace_bytes(int32_t in_dim, int64_t B, size_t *bytes);
+/* grad [param count] of the mean binary cross-entropy of the logits of X
+ * [B][in_dim] against labels [B] (0 or 1); logits [B] written if not NULL. */
+int32_t qaia_mlp_backward(const uint16_t *params, int32_t in_dim, const float *X, const float *labels,
+                          int64_t B, float *grad, float *logits, void *workspace, size_t ws_bytes,
+                          void *hip_stream);
+/* One Adam step (step counts from 1) on fp32 master weights and moments;
+ * refreshes the bf16 params (round to nearest even). */
+int32_t qaia_mlp_adam(float *master, uint16_t *params, float *moment1, float *moment2,
+                      const float *grad, int64_t count, int32_t step, float lr, float beta1,
+                      float beta2, float eps, void *hip_stream);
+
+int32_t qaia_front_features_workspace_bytes(int64_t P, int32_t m, size_t *bytes);
+/* MLP input rows feat [N][m + 8] = (c, f1..f8): c followed by eight
+ * features of candidate c against the archive front
+ * (int64 [P][m], normalised per objective to [0,1] by its minimum and
+ * maximum; zero range maps to 1), with v_j = c . y^_j: max v; max minus the
+ * second; max minus the eighth (the smallest when P < 8); distance from the
+ * maximising point to its nearest other front point; fraction of the front
+ * within 0.05 of it; smallest angle to the `hits` rows [n_hits][m] and to the
+ * `misses` rows [n_misses][m] (pi/2 when empty); max_k |c_k - 1/m|. */
+int32_t qaia_front_features(const int64_t *front, int64_t P, int32_t m, const float *cands, int64_t N,
+                            const float *hits, int64_t n_hits, const float *misses, int64_t n_misses,
+                            float *feat, void *workspace, size_t ws_bytes, void *hip_stream);
+
+int32_t qaia_topk_workspace_bytes(int64_t N, size_t *bytes);
+/* Indices (int64 [k]) of the k largest scores [N], largest first; equal
+ * scores keep increasing index order. */
+int32_t qaia_topk(const float *scores, int64_t N, int64_t k, int64_t *idx, void *workspace,
+                  size_t ws_bytes, void *hip_stream);
+
+/* labels [W] = 1 where weight row w has a sample among the kept rows of a
+ * qaia_pareto_filter over [archive rows ; W*R new samples], else 0.  Because
+ * duplicates are represented by their smallest index, a kept new sample is a
+ * vector absent from the archive. */
+int32_t qaia_new_point_labels(const int64_t *keep_idx, const int64_t *num_keep, int64_t archive_rows,
+                              int32_t R, int64_t W, float *labels, void *hip_stream);
+
+/* Row gather: dst[r][:] = src[idx[r]][:] for r < min(*count, cap), rows of
+ * `width` 32-bit words (an int64 row of m values is 2m words). */
+int32_t qaia_gather_rows(const void *src, int32_t width, const int64_t *idx, const int64_t *count,
+                         int64_t cap, void *dst, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

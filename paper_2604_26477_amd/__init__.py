@@ -56,6 +56,21 @@ _SIGS = {
     "qaia_pareto_filter_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "qaia_pareto_filter": (_i32, [_P, _i64, _i32, _P, _P, _P, _sz, _P]),
     "qaia_hypervolume": (_i32, [_P, _i64, _i32, _P, _P, _P]),
+    "qaia_dense_field_workspace_bytes": (_i32, [_P, _i32, _i64, C.POINTER(_sz)]),
+    "qaia_dense_field": (_i32, [_P, _i32, _P, _i64, _P, _P, _sz, _P]),
+    "qaia_mlp_param_count": (_i32, [_i32, C.POINTER(_i64)]),
+    "qaia_mlp_forward_workspace_bytes": (_i32, [_i64, C.POINTER(_sz)]),
+    "qaia_mlp_forward": (_i32, [_P, _i32, _P, _i64, _P, _P, _sz, _P]),
+    "qaia_mlp_backward_workspace_bytes": (_i32, [_i32, _i64, C.POINTER(_sz)]),
+    "qaia_mlp_backward": (_i32, [_P, _i32, _P, _P, _i64, _P, _P, _P, _sz, _P]),
+    "qaia_mlp_adam": (_i32, [_P, _P, _P, _P, _P, _i64, _i32, C.c_float, C.c_float, C.c_float,
+                             C.c_float, _P]),
+    "qaia_front_features_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
+    "qaia_front_features": (_i32, [_P, _i64, _i32, _P, _i64, _P, _i64, _P, _i64, _P, _P, _sz, _P]),
+    "qaia_topk_workspace_bytes": (_i32, [_i64, C.POINTER(_sz)]),
+    "qaia_topk": (_i32, [_P, _i64, _i64, _P, _P, _sz, _P]),
+    "qaia_new_point_labels": (_i32, [_P, _P, _i64, _i32, _i64, _P, _P]),
+    "qaia_gather_rows": (_i32, [_P, _i32, _P, _P, _i64, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -283,3 +298,105 @@ def unpack_spins(spins: np.ndarray, n: int) -> np.ndarray:
     bits = ((words[:, :, None] >> np.arange(64, dtype=np.uint64)[None, None, :]) & np.uint64(1))
     bits = bits.reshape(words.shape[0], -1)[:, :n].astype(np.int8)
     return (1 - 2 * bits).astype(np.int8)
+
+
+# ------------------------------------------------------------------ precision form
+
+def qaia_dense_field(p: Problem, precision: str, phi: torch.Tensor, field=None, workspace=None, stream=None):
+    """Per-objective products sum_j J^(k)_ij phi_j (float32 [count, m, n]) in the given arithmetic."""
+    prec = PRECISIONS[precision]
+    count = phi.shape[0]
+    b = C.c_size_t()
+    _check(_lib.qaia_dense_field_workspace_bytes(p.handle, prec, count, C.byref(b)))
+    if workspace is None:
+        workspace = torch.empty(max(b.value, 1), dtype=torch.uint8, device=p.torch_device)
+    field = _dev_tensor(field, torch.float32, (count, p.m, p.n), p.torch_device)
+    _check(_lib.qaia_dense_field(p.handle, prec, _ptr(phi), count, _ptr(field), _ptr(workspace),
+                                 workspace.numel(), _stream(stream)))
+    return field
+
+
+# ------------------------------------------------------------------ learned form
+
+def qaia_mlp_param_count(in_dim: int) -> int:
+    n = C.c_int64()
+    _check(_lib.qaia_mlp_param_count(in_dim, C.byref(n)))
+    return n.value
+
+
+def qaia_mlp_forward(params: torch.Tensor, in_dim: int, X: torch.Tensor, logits=None, workspace=None,
+                     stream=None) -> torch.Tensor:
+    N = X.shape[0]
+    b = C.c_size_t()
+    _check(_lib.qaia_mlp_forward_workspace_bytes(N, C.byref(b)))
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(max(b.value, 1), dtype=torch.uint8, device=X.device)
+    logits = _dev_tensor(logits, torch.float32, (N,), X.device)
+    _check(_lib.qaia_mlp_forward(_ptr(params), in_dim, _ptr(X), N, _ptr(logits), _ptr(workspace),
+                                 workspace.numel(), _stream(stream)))
+    return logits
+
+
+def qaia_mlp_backward(params: torch.Tensor, in_dim: int, X: torch.Tensor, labels: torch.Tensor,
+                      grad=None, logits=None, workspace=None, stream=None):
+    B = X.shape[0]
+    b = C.c_size_t()
+    _check(_lib.qaia_mlp_backward_workspace_bytes(in_dim, B, C.byref(b)))
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(b.value, dtype=torch.uint8, device=X.device)
+    grad = _dev_tensor(grad, torch.float32, (qaia_mlp_param_count(in_dim),), X.device)
+    _check(_lib.qaia_mlp_backward(_ptr(params), in_dim, _ptr(X), _ptr(labels), B, _ptr(grad),
+                                  _ptr(logits), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return grad
+
+
+def qaia_mlp_adam(master, params, moment1, moment2, grad, step, lr=1e-3, beta1=0.9, beta2=0.999,
+                  eps=1e-8, stream=None):
+    _check(_lib.qaia_mlp_adam(_ptr(master), _ptr(params), _ptr(moment1), _ptr(moment2), _ptr(grad),
+                              master.numel(), step, lr, beta1, beta2, eps, _stream(stream)))
+
+
+def qaia_front_features(front: torch.Tensor, cands: torch.Tensor, hits: torch.Tensor, misses: torch.Tensor,
+                        out=None, workspace=None, stream=None) -> torch.Tensor:
+    """MLP input rows [N, m + 8] = (c, f1..f8) of candidates c against an int64 front [P, m]."""
+    P, m = front.shape[0], cands.shape[1]
+    N = cands.shape[0]
+    b = C.c_size_t()
+    _check(_lib.qaia_front_features_workspace_bytes(P, m, C.byref(b)))
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(b.value, dtype=torch.uint8, device=cands.device)
+    out = _dev_tensor(out, torch.float32, (N, m + 8), cands.device)
+    _check(_lib.qaia_front_features(_ptr(front) if P else None, P, m, _ptr(cands), N,
+                                    _ptr(hits) if hits.shape[0] else None, hits.shape[0],
+                                    _ptr(misses) if misses.shape[0] else None, misses.shape[0],
+                                    _ptr(out), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return out
+
+
+def qaia_topk(scores: torch.Tensor, k: int, idx=None, workspace=None, stream=None) -> torch.Tensor:
+    N = scores.shape[0]
+    b = C.c_size_t()
+    _check(_lib.qaia_topk_workspace_bytes(N, C.byref(b)))
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(b.value, dtype=torch.uint8, device=scores.device)
+    idx = _dev_tensor(idx, torch.int64, (max(k, 1),), scores.device)
+    _check(_lib.qaia_topk(_ptr(scores), N, k, _ptr(idx), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return idx[:k]
+
+
+def qaia_new_point_labels(keep_idx, num_keep, archive_rows: int, R: int, W: int, labels=None, stream=None):
+    labels = _dev_tensor(labels, torch.float32, (max(W, 1),), keep_idx.device)
+    _check(_lib.qaia_new_point_labels(_ptr(keep_idx), _ptr(num_keep), archive_rows, R, W, _ptr(labels),
+                                      _stream(stream)))
+    return labels[:W]
+
+
+def qaia_gather_rows(src: torch.Tensor, idx: torch.Tensor, count: torch.Tensor, dst: torch.Tensor, cap: int,
+                     stream=None):
+    """dst[r] = src[idx[r]] for r < min(count, cap); rows of any 4-byte-multiple width."""
+    row_bytes = src[0].numel() * src.element_size() if src.dim() > 1 else src.element_size()
+    if row_bytes % 4:
+        raise ValueError("row size must be a multiple of 4 bytes")
+    _check(_lib.qaia_gather_rows(_ptr(src), row_bytes // 4, _ptr(idx), _ptr(count), cap, _ptr(dst),
+                                 _stream(stream)))
+    return dst

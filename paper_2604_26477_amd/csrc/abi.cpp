@@ -282,4 +282,128 @@ int32_t qaia_hypervolume(const int64_t *pts, int64_t P, int32_t m, const int64_t
     });
 }
 
+// ---------------------------------------------------------------- learned proposer
+
+int32_t qaia_mlp_param_count(int32_t in_dim, int64_t *count) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(count != nullptr, QAIA_INVALID_ARGUMENT, "null count");
+        QAIA_CHECK(in_dim >= 1 && in_dim <= 16, QAIA_INVALID_ARGUMENT, "in_dim must be in [1, 16]");
+        *count = mlp_param_count(in_dim);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_mlp_forward_workspace_bytes(int64_t N, size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(bytes != nullptr && N >= 0, QAIA_INVALID_ARGUMENT, "bad argument");
+        *bytes = mlp_forward_ws_bytes(N);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_mlp_forward(const uint16_t *params, int32_t in_dim, const float *X, int64_t N, float *logits,
+                         void *workspace, size_t ws_bytes, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(N >= 0 && N <= (int64_t(1) << 26), QAIA_INVALID_ARGUMENT, "N out of range");
+        QAIA_CHECK(N == 0 || (params && X && logits && workspace), QAIA_INVALID_ARGUMENT, "null buffer");
+        QAIA_CHECK(ws_bytes >= mlp_forward_ws_bytes(N), QAIA_WORKSPACE_TOO_SMALL, "forward workspace too small");
+        launch_mlp_forward(params, in_dim, X, N, logits, workspace, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_mlp_backward_workspace_bytes(int32_t in_dim, int64_t B, size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(bytes != nullptr && B >= 1, QAIA_INVALID_ARGUMENT, "bad argument");
+        *bytes = mlp_backward_ws_bytes(in_dim, B);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_mlp_backward(const uint16_t *params, int32_t in_dim, const float *X, const float *labels,
+                          int64_t B, float *grad, float *logits, void *workspace, size_t ws_bytes,
+                          void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(B >= 1 && B <= (int64_t(1) << 24), QAIA_INVALID_ARGUMENT, "B out of range");
+        QAIA_CHECK(params && X && labels && grad && workspace, QAIA_INVALID_ARGUMENT, "null buffer");
+        QAIA_CHECK(ws_bytes >= mlp_backward_ws_bytes(in_dim, B), QAIA_WORKSPACE_TOO_SMALL,
+                   "backward workspace too small");
+        launch_mlp_backward(params, in_dim, X, labels, B, grad, logits, workspace, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_mlp_adam(float *master, uint16_t *params, float *moment1, float *moment2, const float *grad,
+                      int64_t count, int32_t step, float lr, float beta1, float beta2, float eps,
+                      void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(count >= 0, QAIA_INVALID_ARGUMENT, "count must be >= 0");
+        QAIA_CHECK(count == 0 || (master && params && moment1 && moment2 && grad), QAIA_INVALID_ARGUMENT,
+                   "null buffer");
+        QAIA_CHECK(lr > 0.0f && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f,
+                   QAIA_INVALID_ARGUMENT, "bad Adam hyper-parameters");
+        if (count) launch_adam(master, params, moment1, moment2, grad, count, step, lr, beta1, beta2, eps,
+                               (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_front_features_workspace_bytes(int64_t P, int32_t m, size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(bytes != nullptr && P >= 0 && m >= 1 && m <= 8, QAIA_INVALID_ARGUMENT, "bad argument");
+        *bytes = features_ws_bytes(P, m);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_front_features(const int64_t *front, int64_t P, int32_t m, const float *cands, int64_t N,
+                            const float *hits, int64_t n_hits, const float *misses, int64_t n_misses,
+                            float *feat, void *workspace, size_t ws_bytes, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(P >= 0 && N >= 0 && n_hits >= 0 && n_misses >= 0, QAIA_INVALID_ARGUMENT, "negative size");
+        QAIA_CHECK((P == 0 || front) && (N == 0 || (cands && feat)) && (n_hits == 0 || hits) &&
+                       (n_misses == 0 || misses) && workspace,
+                   QAIA_INVALID_ARGUMENT, "null buffer");
+        launch_features(front, P, m, cands, N, hits, n_hits, misses, n_misses, feat, workspace, ws_bytes,
+                        (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_topk_workspace_bytes(int64_t N, size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(bytes != nullptr && N >= 1 && N < (int64_t(1) << 31), QAIA_INVALID_ARGUMENT, "bad argument");
+        *bytes = topk_ws_bytes(N);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_topk(const float *scores, int64_t N, int64_t k, int64_t *idx, void *workspace, size_t ws_bytes,
+                  void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(scores && idx && workspace, QAIA_INVALID_ARGUMENT, "null buffer");
+        launch_topk(scores, N, k, idx, workspace, ws_bytes, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_new_point_labels(const int64_t *keep_idx, const int64_t *num_keep, int64_t archive_rows,
+                              int32_t R, int64_t W, float *labels, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(keep_idx && num_keep && (W == 0 || labels), QAIA_INVALID_ARGUMENT, "null buffer");
+        launch_labels(keep_idx, num_keep, archive_rows, R, W, labels, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_gather_rows(const void *src, int32_t width, const int64_t *idx, const int64_t *count,
+                         int64_t cap, void *dst, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(src && idx && count && dst, QAIA_INVALID_ARGUMENT, "null buffer");
+        launch_gather_rows((const uint32_t *)src, width, idx, count, cap, (uint32_t *)dst,
+                           (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
 }  // extern "C"

@@ -135,6 +135,28 @@ size_t dense_field_ws_bytes(const Problem &p, int prec, int64_t count);
 void launch_dense_field(const Problem &p, int prec, const float *phi, int64_t count, float *field,
                         void *ws, size_t ws_bytes, hipStream_t st);
 
+// learned proposer (mlp.hip)
+int64_t mlp_param_count(int D);
+size_t mlp_forward_ws_bytes(int64_t N);
+size_t mlp_backward_ws_bytes(int D, int64_t B);
+void launch_mlp_forward(const uint16_t *P, int D, const float *X, int64_t N, float *logits, void *ws,
+                        hipStream_t st);
+void launch_mlp_backward(const uint16_t *P, int D, const float *X, const float *y, int64_t B,
+                         float *grad, float *logits, void *ws, hipStream_t st);
+void launch_adam(float *master, uint16_t *P, float *m, float *v, const float *g, int64_t n, int step,
+                 float lr, float b1, float b2, float eps, hipStream_t st);
+size_t features_ws_bytes(int64_t Pn, int m);
+void launch_features(const int64_t *front, int64_t Pn, int m, const float *cands, int64_t N,
+                     const float *hits, int64_t Hn, const float *misses, int64_t Mn, float *feat,
+                     void *ws, size_t ws_bytes, hipStream_t st);
+size_t topk_ws_bytes(int64_t N);
+void launch_topk(const float *scores, int64_t N, int64_t k, int64_t *idx_out, void *ws, size_t ws_bytes,
+                 hipStream_t st);
+void launch_labels(const int64_t *keep, const int64_t *num_keep, int64_t archive, int R, int64_t W,
+                   float *labels, hipStream_t st);
+void launch_gather_rows(const uint32_t *src, int width, const int64_t *idx, const int64_t *count,
+                        int64_t cap, uint32_t *dst, hipStream_t st);
+
 // pareto filter (pareto.hip)
 size_t pareto_ws_bytes(int64_t M, int32_t m);
 void launch_pareto(const int64_t *obj, int64_t M, int32_t m, int64_t *keep, int64_t *num_keep,

@@ -1,0 +1,162 @@
+"""Online loop of the learned weight proposer (form F3) and its uniform baseline.
+
+Each round:
+  1. draw candidate weight vectors c ~ Dirichlet(1, ..., 1) (host, seeded);
+  2. learned: score them with the MLP on (c, eight front-gap features) and keep
+     the top (1 - explore) * n_sel plus explore * n_sel uniformly chosen
+     others; baseline: keep n_sel candidates uniformly;
+  3. sample every kept vector with R replicas (qaia_sample);
+  4. filter [archive ; new samples] (qaia_pareto_filter) and label each kept
+     vector 1 iff it produced a vector that enters the front and was not in
+     the archive (qaia_new_point_labels);
+  5. learned: one Adam step on the mean binary cross-entropy of those labels;
+  6. the new archive is the filtered set; its exact hypervolume (host) judges
+     progress.
+The driver only orchestrates library calls; tensors are device memory.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import (make_schedule, qaia_front_features, qaia_gather_rows, qaia_hypervolume, qaia_mlp_adam,
+               qaia_mlp_backward, qaia_mlp_forward, qaia_mlp_param_count, qaia_new_point_labels,
+               qaia_pareto_filter, qaia_pareto_filter_workspace_bytes, qaia_sample,
+               qaia_sample_workspace_bytes, qaia_topk)
+
+HIDDEN = 128
+
+
+def _init_params(D: int, rng: np.random.Generator) -> np.ndarray:
+    """He-style initialisation, flat layout W1, b1, W2, b2, w3, b3."""
+    parts = [rng.standard_normal(HIDDEN * D) * np.sqrt(2.0 / D), np.zeros(HIDDEN),
+             rng.standard_normal(HIDDEN * HIDDEN) * np.sqrt(2.0 / HIDDEN), np.zeros(HIDDEN),
+             rng.standard_normal(HIDDEN) * np.sqrt(1.0 / HIDDEN), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _to_bf16_bits(a: np.ndarray) -> np.ndarray:
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+class ProposerLoop:
+    def __init__(self, prob, R=256, steps=2000, variant="bsb", n_cand=65536, n_sel=1024,
+                 explore=0.1, lr=1e-3, learned=True, seed=0, archive_cap=1 << 20, ref=None,
+                 precision="fp32", path="auto"):
+        self.prob, self.m, self.R = prob, prob.m, R
+        self.n_cand, self.n_sel, self.explore, self.lr = n_cand, n_sel, explore, lr
+        self.learned = learned
+        self.rng = np.random.Generator(np.random.PCG64(seed))
+        self.sched_args = dict(variant=variant, precision=precision, steps=steps, dt=0.5, path=path)
+        self.seed = seed
+        self.dev = prob.torch_device
+        self.ref = np.zeros(self.m, np.int64) if ref is None else np.asarray(ref, np.int64)
+        self.D = self.m + 8
+        dev = self.dev
+        self.rows_new = n_sel * R
+        self.cap = archive_cap
+        self.pool_obj = torch.empty((archive_cap + self.rows_new, self.m), dtype=torch.int64, device=dev)
+        self.pool_spins = torch.empty((archive_cap + self.rows_new, prob.words), dtype=torch.int64, device=dev)
+        self.tmp_obj = torch.empty((archive_cap, self.m), dtype=torch.int64, device=dev)
+        self.tmp_spins = torch.empty((archive_cap, prob.words), dtype=torch.int64, device=dev)
+        self.A = 0
+        self.keep = torch.empty(archive_cap + self.rows_new, dtype=torch.int64, device=dev)
+        self.nkeep = torch.empty(1, dtype=torch.int64, device=dev)
+        self.ws_filter = torch.empty(qaia_pareto_filter_workspace_bytes(archive_cap + self.rows_new, self.m),
+                                     dtype=torch.uint8, device=dev)
+        s0 = make_schedule(seed=0, **self.sched_args)
+        self.ws_sample = torch.empty(qaia_sample_workspace_bytes(prob, n_sel, R, s0), dtype=torch.uint8,
+                                     device=dev)
+        npar = qaia_mlp_param_count(self.D)
+        theta = _init_params(self.D, np.random.Generator(np.random.PCG64(seed + 17)))
+        self.master = torch.from_numpy(theta).to(dev)
+        self.params = torch.from_numpy(_to_bf16_bits(theta).view(np.int16)).to(dev)
+        self.m1 = torch.zeros(npar, dtype=torch.float32, device=dev)
+        self.m2 = torch.zeros(npar, dtype=torch.float32, device=dev)
+        self.adam_step = 0
+        self.hits = torch.zeros((0, self.m), dtype=torch.float32, device=dev)
+        self.misses = torch.zeros((0, self.m), dtype=torch.float32, device=dev)
+        self.round_no = 0
+        self.replica_offset = 0
+        self.history = []
+
+    # -------------------------------------------------------------- selection
+    def _select(self):
+        cands_h = self.rng.dirichlet(np.ones(self.m), size=self.n_cand).astype(np.float32)
+        cands = torch.from_numpy(cands_h).to(self.dev)
+        if not self.learned:
+            pick = torch.from_numpy(np.arange(self.n_sel, dtype=np.int64)).to(self.dev)
+            X = None
+            return cands, pick, X
+        front = self.pool_obj[: self.A]
+        X = qaia_front_features(front, cands, self.hits, self.misses)
+        n_top = self.n_sel - int(round(self.explore * self.n_sel))
+        scores = qaia_mlp_forward(self.params, self.D, X)
+        top = qaia_topk(scores, n_top)
+        # exploration: uniformly chosen candidates outside the top set
+        top_h = top.cpu().numpy()
+        rest = np.setdiff1d(np.arange(self.n_cand), top_h, assume_unique=False)
+        extra = self.rng.choice(rest, size=self.n_sel - n_top, replace=False)
+        pick = torch.from_numpy(np.concatenate([top_h, np.sort(extra)]).astype(np.int64)).to(self.dev)
+        return cands, pick, X
+
+    # -------------------------------------------------------------- one round
+    def round(self):
+        t0 = time.perf_counter()
+        m, R, dev = self.m, self.R, self.dev
+        cands, pick, X = self._select()
+        count = torch.tensor([self.n_sel], dtype=torch.int64, device=dev)
+        w_sel = torch.empty((self.n_sel, m), dtype=torch.float32, device=dev)
+        qaia_gather_rows(cands, pick, count, w_sel, self.n_sel)
+        s = make_schedule(seed=self.seed, replica_offset=self.replica_offset, **self.sched_args)
+        self.replica_offset += self.rows_new
+        A = self.A
+        qaia_sample(self.prob, w_sel, R, s, spins=self.pool_spins[A:A + self.rows_new],
+                    obj=self.pool_obj[A:A + self.rows_new], workspace=self.ws_sample)
+        M = A + self.rows_new
+        qaia_pareto_filter(self.pool_obj[:M], keep_idx=self.keep, num_keep=self.nkeep, workspace=self.ws_filter)
+        labels = qaia_new_point_labels(self.keep, self.nkeep, A, R, self.n_sel)
+        qaia_gather_rows(self.pool_obj, self.keep, self.nkeep, self.tmp_obj, self.cap)
+        qaia_gather_rows(self.pool_spins, self.keep, self.nkeep, self.tmp_spins, self.cap)
+        P = int(self.nkeep.item())
+        if P > self.cap:
+            raise RuntimeError("archive capacity exceeded")
+        self.pool_obj[:P].copy_(self.tmp_obj[:P])
+        self.pool_spins[:P].copy_(self.tmp_spins[:P])
+        self.A = P
+        if self.learned:
+            xs = torch.empty((self.n_sel, self.D), dtype=torch.float32, device=dev)
+            qaia_gather_rows(X, pick, count, xs, self.n_sel)
+            grad = qaia_mlp_backward(self.params, self.D, xs, labels)
+            self.adam_step += 1
+            qaia_mlp_adam(self.master, self.params, self.m1, self.m2, grad, self.adam_step, lr=self.lr)
+            lab = labels.cpu().numpy() > 0.5
+            w_h = w_sel.cpu().numpy()
+            self.hits = torch.from_numpy(np.ascontiguousarray(w_h[lab])).to(dev)
+            self.misses = torch.from_numpy(np.ascontiguousarray(w_h[~lab])).to(dev)
+        new_points = int((labels > 0.5).sum().item())
+        front = self.pool_obj[:P].cpu().numpy()
+        hv = qaia_hypervolume(front, self.ref)
+        self.round_no += 1
+        rec = {"round": self.round_no, "front": P, "hv": hv, "hit_vectors": new_points,
+               "seconds": time.perf_counter() - t0}
+        self.history.append(rec)
+        return rec
+
+    def front(self):
+        return self.pool_obj[: self.A].cpu().numpy()
+
+
+def run_until(loop: ProposerLoop, target_hv: int, max_rounds: int):
+    """Rounds until the archive's hypervolume reaches target_hv; returns (rounds, seconds, reached)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(max_rounds):
+        rec = loop.round()
+        if rec["hv"] >= target_hv:
+            return r + 1, time.perf_counter() - t0, True
+    return max_rounds, time.perf_counter() - t0, False

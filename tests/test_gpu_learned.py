@@ -1,0 +1,165 @@
+"""GPU parity of the learned weight proposer's kernels against the float64
+oracle (oracle/mlp.py), and what the trained network gains."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_26477_amd as q
+    return q
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _bf16_round(a):
+    """float32 -> bf16 (round half to even) -> float64, and the bit patterns."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    bits = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    vals = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return vals, bits
+
+
+def _params(D, seed=0):
+    rng = np.random.default_rng(seed)
+    theta = (rng.standard_normal(omlp.n_params(D)) * 0.25).astype(np.float32)
+    vals, bits = _bf16_round(theta)
+    return theta, vals, bits
+
+
+def test_forward_matches_oracle(q):
+    D = 12
+    _, vals, bits = _params(D, 1)
+    X = np.random.default_rng(2).standard_normal((1000, D)).astype(np.float32)
+    got = q.qaia_mlp_forward(_dev(bits.view(np.int16)), D, _dev(X)).cpu().numpy()
+    want, _ = omlp.forward(vals, X.astype(np.float64), D)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"forward rel err {err:.2e}")
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("D,B", [(12, 1024), (11, 77)])
+def test_backward_matches_oracle(q, D, B):
+    _, vals, bits = _params(D, 3)
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((B, D)).astype(np.float32)
+    y = rng.integers(0, 2, size=B).astype(np.float32)
+    got = q.qaia_mlp_backward(_dev(bits.view(np.int16)), D, _dev(X), _dev(y)).cpu().numpy()
+    want = omlp.backward(vals, X.astype(np.float64), y.astype(np.float64), D)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"backward rel err (D={D}, B={B}) {err:.2e}")
+    assert err < 1e-3
+    # the output-bias gradient is mean(sigmoid(z) - y)
+    assert got[-1] == pytest.approx(want[-1], rel=1e-3, abs=1e-6)
+
+
+def test_adam_matches_oracle(q):
+    import torch
+    n = 5000
+    rng = np.random.default_rng(5)
+    theta = rng.standard_normal(n).astype(np.float32)
+    g = (rng.standard_normal(n) * 1e-2).astype(np.float32)
+    m1 = (rng.standard_normal(n) * 1e-3).astype(np.float32)
+    m2 = (np.abs(rng.standard_normal(n)) * 1e-5).astype(np.float32)
+    master, params = _dev(theta.copy()), torch.zeros(n, dtype=torch.int16, device="cuda")
+    dm1, dm2 = _dev(m1.copy()), _dev(m2.copy())
+    q.qaia_mlp_adam(master, params, dm1, dm2, _dev(g), step=3, lr=1e-3)
+    want, wm, wv = omlp.adam(theta.astype(np.float64), g.astype(np.float64), m1.astype(np.float64),
+                             m2.astype(np.float64), 3, lr=1e-3)
+    got = master.cpu().numpy()
+    np.testing.assert_allclose(got, want, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(dm1.cpu().numpy(), wm, rtol=1e-5, atol=1e-9)
+    # the bf16 copy is the round-to-nearest-even of the new master weights
+    assert np.array_equal(params.cpu().numpy().view(np.uint16), _bf16_round(got)[1])
+
+
+def test_features_match_oracle(q):
+    rng = np.random.default_rng(6)
+    m = 4
+    front = rng.integers(-10**6, 10**7, size=(300, m)).astype(np.int64)
+    cands = rng.dirichlet(np.ones(m), size=500).astype(np.float32)
+    hits = rng.dirichlet(np.ones(m), size=5).astype(np.float32)
+    misses = rng.dirichlet(np.ones(m), size=7).astype(np.float32)
+    got = q.qaia_front_features(_dev(front), _dev(cands), _dev(hits), _dev(misses)).cpu().numpy()
+    want = omlp.features(front, cands.astype(np.float64), hits.astype(np.float64), misses.astype(np.float64))
+    np.testing.assert_array_equal(got[:, :m], cands)
+    np.testing.assert_allclose(got[:, m:], want, rtol=0, atol=2e-5)
+    # empty archive and no hits / misses
+    got0 = q.qaia_front_features(_dev(front[:0]), _dev(cands), _dev(hits[:0]), _dev(misses[:0])).cpu().numpy()
+    want0 = omlp.features(front[:0], cands.astype(np.float64), hits[:0], misses[:0])
+    np.testing.assert_allclose(got0[:, m:], want0, rtol=0, atol=2e-6)
+
+
+def test_topk_gather_and_labels(q):
+    import torch
+    rng = np.random.default_rng(7)
+    scores = rng.standard_normal(65536).astype(np.float32)
+    idx = q.qaia_topk(_dev(scores), 1024).cpu().numpy()
+    assert np.array_equal(idx, np.argsort(-scores, kind="stable")[:1024])
+    ties = np.repeat(np.arange(10, dtype=np.float32), 7)
+    assert np.array_equal(q.qaia_topk(_dev(ties), 9).cpu().numpy(), np.argsort(-ties, kind="stable")[:9])
+    # gather of float rows
+    src = rng.standard_normal((100, 6)).astype(np.float32)
+    pick = np.array([5, 0, 99, 42], np.int64)
+    dst = torch.zeros((4, 6), dtype=torch.float32, device="cuda")
+    q.qaia_gather_rows(_dev(src), _dev(pick), _dev(np.array([4], np.int64)), dst, 4)
+    assert np.array_equal(dst.cpu().numpy(), src[pick])
+    # labels: archive of 10 rows, then W = 5 weight rows x R = 3 replicas
+    keep = np.array([2, 7, 10, 11, 18, 24], np.int64)  # new rows 10,11 -> w0; 18 -> w2; 24 -> w4
+    lab = q.qaia_new_point_labels(_dev(keep), _dev(np.array([6], np.int64)), 10, 3, 5).cpu().numpy()
+    assert np.array_equal(lab, [1, 0, 1, 0, 1])
+
+
+def _auc(scores, labels):
+    pos, neg = scores[labels > 0.5], scores[labels < 0.5]
+    if len(pos) == 0 or len(neg) == 0:
+        return float("nan")
+    order = np.argsort(np.concatenate([pos, neg]), kind="stable")
+    ranks = np.empty(len(order))
+    ranks[order] = np.arange(1, len(order) + 1)
+    return (ranks[: len(pos)].sum() - len(pos) * (len(pos) + 1) / 2) / (len(pos) * len(neg))
+
+
+def test_trained_network_predicts_new_points(q):
+    """What training gains: after online rounds on a 42-node, 4-objective
+    instance, the network's scores rank held-out weight vectors by whether they
+    produce a new non-dominated point (AUC above the 0.5 of an untrained or
+    uniform proposer).  Hypervolume curves of the learned and the uniform loops
+    are printed for the record."""
+    import torch
+    from paper_2604_26477_amd.learned import ProposerLoop
+    inst = wl.instance_42_node(4, seed=2000)
+    prob = q.problem_from_instance(inst)
+    kw = dict(R=32, steps=600, n_cand=8192, n_sel=256, seed=11)
+    learned = ProposerLoop(prob, learned=True, **kw)
+    uniform = ProposerLoop(prob, learned=False, **kw)
+    for r in range(14):
+        a, b = learned.round(), uniform.round()
+        print(f"round {r + 1:2d}: learned hv {a['hv']:.4e} front {a['front']:5d} hits {a['hit_vectors']:4d} | "
+              f"uniform hv {b['hv']:.4e} front {b['front']:5d} hits {b['hit_vectors']:4d}")
+    # held-out evaluation against the learned loop's archive
+    rng = np.random.default_rng(99)
+    cands = rng.dirichlet(np.ones(4), size=2048).astype(np.float32)
+    front = learned.pool_obj[: learned.A]
+    X = q.qaia_front_features(front, _dev(cands), learned.hits, learned.misses)
+    scores = q.qaia_mlp_forward(learned.params, learned.D, X).cpu().numpy()
+    s = q.make_schedule("bsb", steps=600, dt=0.5, seed=12345)
+    _, obj, _ = q.qaia_sample(prob, _dev(cands), 32, s)
+    pool = torch.cat([front, obj])
+    keep, num, _ = q.qaia_pareto_filter(pool)
+    labels = q.qaia_new_point_labels(keep, num, learned.A, 32, 2048).cpu().numpy()
+    auc = _auc(scores, labels)
+    print(f"held-out: {int(labels.sum())} of 2048 vectors find new points; AUC of the trained scores {auc:.3f}")
+    assert auc > 0.55
