@@ -65,7 +65,7 @@ int plan_path(const Problem &p, const qaia_schedule &s, bool tracing) {
 }
 
 WsLayout full_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, int path) {
-    WsLayout L = sample_ws_layout(p, W, R, s);
+    WsLayout L = sample_ws_layout(p, W, R, s, path != QAIA_PATH_DENSE);
     if (path == QAIA_PATH_DENSE) {
         std::string why;
         QAIA_CHECK(dense_supported(p, &why), QAIA_UNSUPPORTED, "dense path: " + why);

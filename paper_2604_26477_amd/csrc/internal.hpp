@@ -99,11 +99,13 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct WsLayout {
     size_t header = 0, kt = 0, c0s = 0, jcp = 0, total = 0;
+    bool has_jcp = false;  // per-edge coefficients reserved (sparse paths)
     // dense path
     int64_t colsP = 0;
     size_t xa = 0, xb = 0, y = 0, pa = 0, pb = 0, coef = 0;
 };
-WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s);
+// edge_coefs: reserve the folded per-edge coefficients (sparse paths only)
+WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, bool edge_coefs);
 void dense_ws_extend(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, WsLayout &L);
 
 // ----------------------------------------------------------------- kernels (host launchers)

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
     }
 }
 
-WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s) {
+WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, bool edge_coefs) {
     (void)R;
     WsLayout L;
     size_t off = 0;
@@ -127,7 +127,8 @@ WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_sch
     L.c0s = off;
     off += align256(sizeof(double) * (size_t)W);
     L.jcp = off;
-    off += align256(sizeof(float) * (size_t)W * (size_t)p.E);
+    L.has_jcp = edge_coefs && W > 0 && p.E > 0;
+    if (L.has_jcp) off += align256(sizeof(float) * (size_t)W * (size_t)p.E);
     L.total = off;
     return L;
 }
@@ -145,7 +146,7 @@ void launch_prep(const Problem &p, const float *weights, int64_t W, const qaia_s
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(kBlock), 0, st, weights, W, p.m,
                        p.n, p.E, p.d_rho, p.d_W, p.d_rowptr, p.d_eid, (double)s.dt, (double)s.a0,
                        s.steps, (float *)(b + L.kt), (double *)(b + L.c0s),
-                       L.jcp != L.total ? (float *)(b + L.jcp) : nullptr, hdr);
+                       L.has_jcp ? (float *)(b + L.jcp) : nullptr, hdr);
     QAIA_HIP(hipGetLastError());
 }
 
