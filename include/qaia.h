@@ -216,6 +216,45 @@ int32_t qaia_pareto_filter(const int64_t *obj, int64_t M, int32_t m, int64_t *ke
 int32_t qaia_hypervolume(const int64_t *pts, int64_t P, int32_t m, const int64_t *ref,
                          uint64_t hv[4], double *hv_approx);
 
+/* ---------------------------------------------------------------- batching form */
+/* A ragged batch: items of different problems (n, m, density), weight sets
+ * and replica counts sampled under one schedule.  Each item is sampled
+ * exactly as qaia_sample would sample it on the same path (same arithmetic,
+ * same counter streams), so the outputs are bit-identical to per-item calls. */
+typedef struct qaia_batch_item {
+    const qaia_problem *problem;
+    const float *weights; /* DEVICE [W][m] */
+    int64_t W;
+    int32_t R;
+    int32_t path;         /* QAIA_PATH_*; AUTO = the planner's default */
+    uint64_t *spins;      /* DEVICE [W*R][ceil(n/64)] */
+    int64_t *obj;         /* DEVICE [W*R][m] */
+} qaia_batch_item;
+
+int32_t qaia_sample_batch_workspace_bytes(const qaia_batch_item *items, int32_t count,
+                                          const qaia_schedule *s, size_t *bytes);
+/* Samples every item with one graph launch: per-item weight preparation, one
+ * launch of the batched generic sparse kernel for all items on that path
+ * (their whole step loops on chip), each item on a generated kernel as its
+ * own launch, and for the dense items one grouped step launch per step over
+ * all their tiles, the step loop captured in the graph.  items: HOST array,
+ * buffers DEVICE, all on one device.  Errors as qaia_sample; the call
+ * synchronises the host with the caller's stream once (descriptor upload). */
+int32_t qaia_sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedule *s,
+                          void *workspace, size_t ws_bytes, void *hip_stream);
+
+int32_t qaia_plan_autotune_workspace_bytes(const qaia_batch_item *items, int32_t count,
+                                           const qaia_schedule *s, int32_t probe_steps, size_t *bytes);
+/* Autotuner: for every item, times each kernel family available to it
+ * (generated one-replica-per-lane kernel, generic one-spin-per-lane kernel,
+ * matrix-core tiles) on probe_steps steps of its real shape, and writes the
+ * fastest into items[i].path (HOST, in place); est_seconds (HOST [count], may
+ * be NULL) receives the probe time scaled to s->steps.  The items' outputs
+ * are overwritten.  Synchronises the host with hip_stream. */
+int32_t qaia_plan_autotune(qaia_batch_item *items, int32_t count, const qaia_schedule *s,
+                           int32_t probe_steps, double *est_seconds, void *workspace, size_t ws_bytes,
+                           void *hip_stream);
+
 /* ---------------------------------------------------------------- learned form */
 /* The paper scalarises with fixed weight vectors (Das-Dennis or Dirichlet,
  * section "Scalarization via the weighted sum method"); the learned form

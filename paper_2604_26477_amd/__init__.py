@@ -39,6 +39,11 @@ class qaia_schedule(C.Structure):
                 ("seed", C.c_uint64), ("replica_offset", C.c_uint64)]
 
 
+class qaia_batch_item(C.Structure):
+    _fields_ = [("problem", C.c_void_p), ("weights", C.c_void_p), ("W", C.c_int64), ("R", C.c_int32),
+                ("path", C.c_int32), ("spins", C.c_void_p), ("obj", C.c_void_p)]
+
+
 _P, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
 _SIGS = {
     "qaia_abi_version": (_i32, []),
@@ -71,6 +76,10 @@ _SIGS = {
     "qaia_topk": (_i32, [_P, _i64, _i64, _P, _P, _sz, _P]),
     "qaia_new_point_labels": (_i32, [_P, _P, _i64, _i32, _i64, _P, _P]),
     "qaia_gather_rows": (_i32, [_P, _i32, _P, _P, _i64, _P, _P]),
+    "qaia_sample_batch_workspace_bytes": (_i32, [_P, _i32, C.POINTER(qaia_schedule), C.POINTER(_sz)]),
+    "qaia_sample_batch": (_i32, [_P, _i32, C.POINTER(qaia_schedule), _P, _sz, _P]),
+    "qaia_plan_autotune_workspace_bytes": (_i32, [_P, _i32, C.POINTER(qaia_schedule), _i32, C.POINTER(_sz)]),
+    "qaia_plan_autotune": (_i32, [_P, _i32, C.POINTER(qaia_schedule), _i32, _P, _P, _sz, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -400,3 +409,63 @@ def qaia_gather_rows(src: torch.Tensor, idx: torch.Tensor, count: torch.Tensor, 
     _check(_lib.qaia_gather_rows(_ptr(src), row_bytes // 4, _ptr(idx), _ptr(count), cap, _ptr(dst),
                                  _stream(stream)))
     return dst
+
+
+# ------------------------------------------------------------------ batching form
+
+class BatchItem:
+    """One item of a ragged batch: a problem, device weights [W, m], replicas R,
+    an optional forced path, and its outputs (allocated when not given)."""
+
+    def __init__(self, problem: Problem, weights: torch.Tensor, R: int, path: str = "auto", spins=None, obj=None):
+        W = weights.shape[0]
+        self.problem, self.weights, self.R, self.path = problem, weights, R, path
+        self.spins = _dev_tensor(spins, torch.int64, (W * R, problem.words), problem.torch_device)
+        self.obj = _dev_tensor(obj, torch.int64, (W * R, problem.m), problem.torch_device)
+
+    def c_struct(self):
+        return qaia_batch_item(self.problem.handle.value if isinstance(self.problem.handle, C.c_void_p)
+                               else self.problem.handle, self.weights.data_ptr(), self.weights.shape[0], self.R,
+                               PATHS[self.path], self.spins.data_ptr(), self.obj.data_ptr())
+
+
+def _items_array(items):
+    arr = (qaia_batch_item * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it.c_struct()
+    return arr
+
+
+def qaia_sample_batch_workspace_bytes(items, s: qaia_schedule) -> int:
+    arr = _items_array(items)
+    b = C.c_size_t()
+    _check(_lib.qaia_sample_batch_workspace_bytes(C.cast(arr, C.c_void_p), len(items), C.byref(s), C.byref(b)))
+    return b.value
+
+
+def qaia_sample_batch(items, s: qaia_schedule, workspace=None, stream=None):
+    """Samples every BatchItem with one graph launch; outputs land in item.spins / item.obj."""
+    arr = _items_array(items)
+    need = qaia_sample_batch_workspace_bytes(items, s)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=items[0].problem.torch_device)
+    _check(_lib.qaia_sample_batch(C.cast(arr, C.c_void_p), len(items), C.byref(s), _ptr(workspace),
+                                  workspace.numel(), _stream(stream)))
+    return workspace
+
+
+def qaia_plan_autotune(items, s: qaia_schedule, probe_steps: int = 20, stream=None):
+    """Times each kernel family per item; sets item.path to the fastest and
+    returns the estimated seconds per item at s.steps."""
+    arr = _items_array(items)
+    b = C.c_size_t()
+    _check(_lib.qaia_plan_autotune_workspace_bytes(C.cast(arr, C.c_void_p), len(items), C.byref(s), probe_steps,
+                                                   C.byref(b)))
+    ws = torch.empty(b.value, dtype=torch.uint8, device=items[0].problem.torch_device)
+    est = np.zeros(len(items), np.float64)
+    _check(_lib.qaia_plan_autotune(C.cast(arr, C.c_void_p), len(items), C.byref(s), probe_steps, _ptr(est),
+                                   _ptr(ws), ws.numel(), _stream(stream)))
+    inv = {v: k for k, v in PATHS.items()}
+    for i, it in enumerate(items):
+        it.path = inv[arr[i].path]
+    return est

@@ -406,4 +406,59 @@ int32_t qaia_gather_rows(const void *src, int32_t width, const int64_t *idx, con
     });
 }
 
+// ---------------------------------------------------------------- batching form
+
+int32_t qaia_sample_batch_workspace_bytes(const qaia_batch_item *items, int32_t count, const qaia_schedule *s,
+                                          size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(bytes != nullptr && count >= 0 && (count == 0 || items), QAIA_INVALID_ARGUMENT, "bad argument");
+        if (count == 0) {
+            *bytes = 256;
+            return QAIA_OK;
+        }
+        check_schedule(*reinterpret_cast<const Problem *>(items[0].problem), s);
+        *bytes = batch_ws_bytes(items, count, *s);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedule *s, void *workspace,
+                          size_t ws_bytes, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(count >= 0 && (count == 0 || items), QAIA_INVALID_ARGUMENT, "bad items");
+        if (count == 0) return QAIA_OK;
+        QAIA_CHECK(items[0].problem != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
+        check_schedule(*reinterpret_cast<const Problem *>(items[0].problem), s);
+        sample_batch(items, count, *s, workspace, ws_bytes, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_plan_autotune_workspace_bytes(const qaia_batch_item *items, int32_t count, const qaia_schedule *s,
+                                           int32_t probe_steps, size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(bytes != nullptr && count >= 0 && (count == 0 || items) && probe_steps >= 1,
+                   QAIA_INVALID_ARGUMENT, "bad argument");
+        if (count == 0) {
+            *bytes = 256;
+            return QAIA_OK;
+        }
+        check_schedule(*reinterpret_cast<const Problem *>(items[0].problem), s);
+        *bytes = autotune_ws_bytes(items, count, *s, probe_steps);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_plan_autotune(qaia_batch_item *items, int32_t count, const qaia_schedule *s, int32_t probe_steps,
+                           double *est_seconds, void *workspace, size_t ws_bytes, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(count >= 0 && (count == 0 || items) && workspace, QAIA_INVALID_ARGUMENT, "bad argument");
+        if (count == 0) return QAIA_OK;
+        QAIA_CHECK(items[0].problem != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
+        check_schedule(*reinterpret_cast<const Problem *>(items[0].problem), s);
+        autotune(items, count, *s, probe_steps, est_seconds, workspace, ws_bytes, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
 }  // extern "C"

@@ -1,0 +1,352 @@
+// Batching form: a ragged batch of (problem, weight vectors, replicas) items
+// sampled by one graph launch, and the autotuner that picks each item's
+// kernel family.
+//
+// Execution of qaia_sample_batch, captured once into a hipGraph on a private
+// stream and launched as one graph:
+//   - per item: workspace header reset and weight preparation;
+//   - branch A (forked stream): every item on the generic sparse kernel runs
+//     in ONE launch of the batched sparse kernel (blocks map to items through
+//     a prefix table; each item's whole T-step loop stays on chip), and items
+//     on the per-graph generated kernels run their own launches;
+//   - branch B: dense items are set up, then each of the T steps is ONE launch
+//     of the grouped dense step kernel over the tiles of all dense items, then
+//     each dense item is read out and evaluated;
+//   - the branches join and the caller's stream waits for the graph.
+// The kernel families differ in their tile shape and replicas per wave: one
+// replica per lane (64 replicas per wave, generated kernel), one spin per
+// lane (floor(256/n) replicas per 256-lane block, generic kernel), or 64-spin
+// x 128-replica matrix-core tiles (dense kernel).
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace qaia {
+
+namespace {
+
+struct ItemPlan {
+    const Problem *p;
+    int path;
+    WsLayout L;
+    size_t base;  // offset of the item's region in the batch workspace
+};
+
+int default_path(const Problem &p, const qaia_schedule &s) {
+    if (s.precision != QAIA_FP32) return QAIA_PATH_DENSE;
+    if (p.jit[s.variant] != nullptr && s.noise_alpha == 0.0f) return QAIA_PATH_SPARSE_REG;
+    if (sparse_lds_supported(p, nullptr)) return QAIA_PATH_SPARSE_LDS;
+    return QAIA_PATH_DENSE;
+}
+
+void check_path(const Problem &p, const qaia_schedule &s, int path) {
+    std::string why;
+    if (path == QAIA_PATH_SPARSE_REG) {
+        QAIA_CHECK(p.jit[s.variant] != nullptr, QAIA_UNSUPPORTED, "generated kernel unavailable: " + p.jit_error);
+        QAIA_CHECK(s.noise_alpha == 0.0f && s.precision == QAIA_FP32, QAIA_UNSUPPORTED,
+                   "generated kernel runs plain FP32 SB");
+    } else if (path == QAIA_PATH_SPARSE_LDS) {
+        QAIA_CHECK(sparse_lds_supported(p, &why), QAIA_UNSUPPORTED, "sparse LDS path: " + why);
+        QAIA_CHECK(s.precision == QAIA_FP32, QAIA_UNSUPPORTED, "sparse paths run FP32");
+    } else if (path == QAIA_PATH_DENSE) {
+        QAIA_CHECK(dense_supported(p, &why), QAIA_UNSUPPORTED, "dense path: " + why);
+        QAIA_CHECK(p.m <= 4, QAIA_UNSUPPORTED, "dense path supports m <= 4");
+        QAIA_CHECK(s.noise_alpha == 0.0f, QAIA_UNSUPPORTED, "dense path runs plain SB");
+    } else {
+        throw Error{QAIA_INVALID_ARGUMENT, "unknown path"};
+    }
+}
+
+struct BatchLayout {
+    std::vector<ItemPlan> items;
+    size_t jobs_off = 0, total = 0;
+    int n_sparse = 0, n_dense = 0;
+};
+
+BatchLayout batch_layout(const qaia_batch_item *items, int32_t count, const qaia_schedule &s) {
+    BatchLayout B;
+    size_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        const qaia_batch_item &it = items[i];
+        QAIA_CHECK(it.problem != nullptr, QAIA_INVALID_ARGUMENT, "item " + std::to_string(i) + ": null problem");
+        const Problem &p = *reinterpret_cast<const Problem *>(it.problem);
+        QAIA_CHECK(it.W >= 0 && it.R >= 1 && it.W <= (int64_t(1) << 40) / it.R, QAIA_INVALID_ARGUMENT,
+                   "item " + std::to_string(i) + ": bad W or R");
+        QAIA_CHECK(it.W * it.R == 0 || (it.weights && it.spins && it.obj), QAIA_INVALID_ARGUMENT,
+                   "item " + std::to_string(i) + ": null buffer");
+        const int path = it.path == QAIA_PATH_AUTO ? default_path(p, s) : it.path;
+        check_path(p, s, path);
+        ItemPlan ip{&p, path, sample_ws_layout(p, it.W, it.R, s, path != QAIA_PATH_DENSE), off};
+        if (path == QAIA_PATH_DENSE) {
+            dense_ws_extend(p, it.W, it.R, s, ip.L);
+            ++B.n_dense;
+        } else if (path == QAIA_PATH_SPARSE_LDS) {
+            ++B.n_sparse;
+        }
+        off += align256(ip.L.total);
+        B.items.push_back(ip);
+    }
+    B.jobs_off = off;
+    off += align256(sizeof(SparseJob) * (size_t)std::max(B.n_sparse, 1));
+    off += align256(sizeof(DenseJob) * (size_t)std::max(B.n_dense, 1));
+    off += 2 * align256(sizeof(int64_t) * (size_t)(count + 1));
+    B.total = off;
+    return B;
+}
+
+// Graphs launched by earlier calls, destroyed once their completion event has fired.
+struct PendingGraph {
+    hipGraphExec_t exec;
+    hipEvent_t done;
+};
+std::mutex g_pending_mu;
+std::vector<PendingGraph> g_pending;
+
+void reap_graphs() {
+    std::lock_guard<std::mutex> lk(g_pending_mu);
+    std::vector<PendingGraph> keep;
+    for (auto &g : g_pending) {
+        if (hipEventQuery(g.done) == hipSuccess) {
+            (void)hipGraphExecDestroy(g.exec);
+            (void)hipEventDestroy(g.done);
+        } else {
+            keep.push_back(g);
+        }
+    }
+    g_pending.swap(keep);
+}
+
+struct Streams {
+    hipStream_t a = nullptr, b = nullptr;
+};
+std::mutex g_streams_mu;
+std::vector<Streams> g_streams;  // per device, default priority, created on first use
+
+Streams private_streams(int device) {
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    if ((int)g_streams.size() <= device) g_streams.resize(device + 1);
+    Streams &s = g_streams[device];
+    if (!s.a) {
+        QAIA_HIP(hipStreamCreateWithFlags(&s.a, hipStreamNonBlocking));
+        QAIA_HIP(hipStreamCreateWithFlags(&s.b, hipStreamNonBlocking));
+    }
+    return s;
+}
+
+}  // namespace
+
+size_t batch_ws_bytes(const qaia_batch_item *items, int32_t count, const qaia_schedule &s) {
+    return batch_layout(items, count, s).total;
+}
+
+void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedule &s, void *ws, size_t ws_bytes,
+                  hipStream_t caller) {
+    QAIA_CHECK(count >= 0, QAIA_INVALID_ARGUMENT, "count must be >= 0");
+    QAIA_CHECK(count == 0 || items != nullptr, QAIA_INVALID_ARGUMENT, "null items");
+    if (count == 0) return;
+    const BatchLayout B = batch_layout(items, count, s);
+    QAIA_CHECK(ws != nullptr, QAIA_INVALID_ARGUMENT, "null workspace");
+    QAIA_CHECK(ws_bytes >= B.total, QAIA_WORKSPACE_TOO_SMALL,
+               "batch workspace needs " + std::to_string(B.total) + " bytes");
+    const int device = B.items[0].p->device;
+    for (const ItemPlan &ip : B.items)
+        QAIA_CHECK(ip.p->device == device, QAIA_INVALID_ARGUMENT, "all items must live on one device");
+    DeviceGuard g(device);
+    reap_graphs();
+    char *base = (char *)ws;
+    const bool dsb = s.variant == QAIA_DSB;
+
+    // descriptors of the batched launches
+    std::vector<SparseJob> sjobs;
+    std::vector<int64_t> sstart(1, 0);
+    int maxdeg = 4, npt = 1;
+    size_t shmem = 0;
+    std::vector<DenseJob> djobs;
+    std::vector<int64_t> dstart(1, 0);
+    for (int i = 0; i < count; ++i) {
+        const ItemPlan &ip = B.items[i];
+        const qaia_batch_item &it = items[i];
+        void *iws = base + ip.base;
+        if (it.W * it.R == 0) continue;
+        if (ip.path == QAIA_PATH_SPARSE_LDS) {
+            const SparseShape sh = sparse_lds_shape(*ip.p, it.W * (int64_t)it.R);
+            sjobs.push_back(sparse_job(*ip.p, it.W, it.R, s, iws, ip.L, it.spins, it.obj, nullptr, 0));
+            sstart.push_back(sstart.back() + sh.blocks);
+            maxdeg = std::max(maxdeg, sh.maxdeg);
+            npt = std::max(npt, sh.npt);
+            shmem = std::max(shmem, sh.shmem);
+        } else if (ip.path == QAIA_PATH_DENSE) {
+            DenseJob j = dense_job(*ip.p, it.W, it.R, s, iws, ip.L, nullptr, 0);
+            djobs.push_back(j);
+            dstart.push_back(dstart.back() + (int64_t)j.tiles_x * j.tiles_y);
+        }
+    }
+    char *jobs = base + B.jobs_off;
+    SparseJob *d_sjobs = (SparseJob *)jobs;
+    DenseJob *d_djobs = (DenseJob *)(jobs + align256(sizeof(SparseJob) * (size_t)std::max(B.n_sparse, 1)));
+    int64_t *d_sstart = (int64_t *)((char *)d_djobs + align256(sizeof(DenseJob) * (size_t)std::max(B.n_dense, 1)));
+    int64_t *d_dstart = (int64_t *)((char *)d_sstart + align256(sizeof(int64_t) * (size_t)(count + 1)));
+
+    Streams ps = private_streams(device);
+    hipEvent_t ev_start, ev_fork, ev_join, ev_done;
+    QAIA_HIP(hipEventCreateWithFlags(&ev_start, hipEventDisableTiming));
+    QAIA_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    QAIA_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    QAIA_HIP(hipEventCreateWithFlags(&ev_done, hipEventDisableTiming));
+    // the private stream follows the caller's prior work; descriptor uploads
+    // are ordered there too (outside the graph)
+    QAIA_HIP(hipEventRecord(ev_start, caller));
+    QAIA_HIP(hipStreamWaitEvent(ps.a, ev_start, 0));
+    if (!sjobs.empty()) {
+        QAIA_HIP(hipMemcpyAsync(d_sjobs, sjobs.data(), sizeof(SparseJob) * sjobs.size(), hipMemcpyHostToDevice, ps.a));
+        QAIA_HIP(hipMemcpyAsync(d_sstart, sstart.data(), sizeof(int64_t) * sstart.size(), hipMemcpyHostToDevice, ps.a));
+    }
+    if (!djobs.empty()) {
+        QAIA_HIP(hipMemcpyAsync(d_djobs, djobs.data(), sizeof(DenseJob) * djobs.size(), hipMemcpyHostToDevice, ps.a));
+        QAIA_HIP(hipMemcpyAsync(d_dstart, dstart.data(), sizeof(int64_t) * dstart.size(), hipMemcpyHostToDevice, ps.a));
+    }
+    // the host vectors above are released when this call returns
+    QAIA_HIP(hipStreamSynchronize(ps.a));
+
+    hipGraph_t graph = nullptr;
+    QAIA_HIP(hipStreamBeginCapture(ps.a, hipStreamCaptureModeThreadLocal));
+    try {
+        for (int i = 0; i < count; ++i) {
+            const ItemPlan &ip = B.items[i];
+            launch_prep(*ip.p, items[i].weights, items[i].W, s, base + ip.base, ip.L, ps.a);
+        }
+        QAIA_HIP(hipEventRecord(ev_fork, ps.a));
+        QAIA_HIP(hipStreamWaitEvent(ps.b, ev_fork, 0));
+        // branch A: sparse items
+        if (!sjobs.empty())
+            launch_sparse_lds_jobs(nullptr, d_sjobs, (int)sjobs.size(), d_sstart, sstart.back(), maxdeg, npt, shmem,
+                                   dsb, ps.b);
+        for (int i = 0; i < count; ++i) {
+            const ItemPlan &ip = B.items[i];
+            const qaia_batch_item &it = items[i];
+            if (ip.path == QAIA_PATH_SPARSE_REG && it.W * it.R > 0)
+                launch_sparse_reg(*ip.p, s.variant, it.W, it.R, s, base + ip.base, ip.L, it.spins, it.obj, nullptr, 0,
+                                  ps.b);
+        }
+        QAIA_HIP(hipEventRecord(ev_join, ps.b));
+        // branch B: dense items
+        if (!djobs.empty()) {
+            int di = 0;
+            for (int i = 0; i < count; ++i) {
+                const ItemPlan &ip = B.items[i];
+                const qaia_batch_item &it = items[i];
+                if (ip.path == QAIA_PATH_DENSE && it.W * it.R > 0)
+                    launch_dense_setup(*ip.p, it.weights, it.R, s, base + ip.base, ip.L, djobs[di++], ps.a);
+            }
+            for (int t = 0; t < s.steps; ++t)
+                launch_dense_batch_step(s.precision, dsb, d_djobs, (int)djobs.size(), d_dstart, dstart.back(), t, ps.a);
+            QAIA_HIP(hipGetLastError());
+            di = 0;
+            for (int i = 0; i < count; ++i) {
+                const ItemPlan &ip = B.items[i];
+                const qaia_batch_item &it = items[i];
+                if (ip.path == QAIA_PATH_DENSE && it.W * it.R > 0)
+                    launch_dense_finish(*ip.p, it.R, s, base + ip.base, ip.L, djobs[di++], it.spins, it.obj, ps.a);
+            }
+        }
+        QAIA_HIP(hipStreamWaitEvent(ps.a, ev_join, 0));
+    } catch (...) {
+        hipGraph_t dropped = nullptr;
+        (void)hipStreamEndCapture(ps.a, &dropped);
+        if (dropped) (void)hipGraphDestroy(dropped);
+        throw;
+    }
+    QAIA_HIP(hipStreamEndCapture(ps.a, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    QAIA_HIP(e);
+    QAIA_HIP(hipGraphLaunch(exec, ps.a));
+    QAIA_HIP(hipEventRecord(ev_done, ps.a));
+    QAIA_HIP(hipStreamWaitEvent(caller, ev_done, 0));
+    for (hipEvent_t ev : {ev_start, ev_fork, ev_join}) (void)hipEventDestroy(ev);
+    std::lock_guard<std::mutex> lk(g_pending_mu);
+    g_pending.push_back({exec, ev_done});
+}
+
+// Times every kernel family available to each item on `probe_steps` steps of
+// its real shape (its own outputs and workspace region serve as scratch) and
+// writes the fastest into items[i].path; est_seconds[i] scales the probe to
+// the schedule's steps.
+void autotune(qaia_batch_item *items, int32_t count, const qaia_schedule &s, int32_t probe_steps,
+              double *est_seconds, void *ws, size_t ws_bytes, hipStream_t st) {
+    QAIA_CHECK(probe_steps >= 1, QAIA_INVALID_ARGUMENT, "probe_steps must be >= 1");
+    for (int i = 0; i < count; ++i) items[i].path = QAIA_PATH_AUTO;
+    // a layout with every item on its default path bounds nothing: size each
+    // probe by its own single-item layout, placed at the workspace start
+    qaia_schedule ps = s;
+    ps.steps = probe_steps;
+    hipEvent_t e0, e1;
+    QAIA_HIP(hipEventCreate(&e0));
+    QAIA_HIP(hipEventCreate(&e1));
+    for (int i = 0; i < count; ++i) {
+        qaia_batch_item &it = items[i];
+        QAIA_CHECK(it.problem != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
+        const Problem &p = *reinterpret_cast<const Problem *>(it.problem);
+        DeviceGuard g(p.device);
+        double best = 1e300;
+        int best_path = default_path(p, s);
+        for (int path : {QAIA_PATH_SPARSE_REG, QAIA_PATH_SPARSE_LDS, QAIA_PATH_DENSE}) {
+            try {
+                check_path(p, s, path);
+            } catch (const Error &) {
+                continue;
+            }
+            WsLayout L = sample_ws_layout(p, it.W, it.R, ps, path != QAIA_PATH_DENSE);
+            if (path == QAIA_PATH_DENSE) dense_ws_extend(p, it.W, it.R, ps, L);
+            if (L.total > ws_bytes) continue;
+            if (it.W * it.R == 0) break;
+            QAIA_HIP(hipEventRecord(e0, st));
+            launch_prep(p, it.weights, it.W, ps, ws, L, st);
+            if (path == QAIA_PATH_DENSE)
+                launch_dense(p, it.weights, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0, st);
+            else if (path == QAIA_PATH_SPARSE_REG)
+                launch_sparse_reg(p, s.variant, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0, st);
+            else
+                launch_sparse_lds(p, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0, st);
+            QAIA_HIP(hipEventRecord(e1, st));
+            QAIA_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            QAIA_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const double est = ms * 1e-3 * (double)s.steps / (double)probe_steps;
+            if (est < best) {
+                best = est;
+                best_path = path;
+            }
+        }
+        it.path = best_path;
+        if (est_seconds) est_seconds[i] = best < 1e299 ? best : 0.0;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+size_t autotune_ws_bytes(const qaia_batch_item *items, int32_t count, const qaia_schedule &s, int32_t probe_steps) {
+    qaia_schedule ps = s;
+    ps.steps = probe_steps;
+    size_t need = 256;
+    for (int i = 0; i < count; ++i) {
+        QAIA_CHECK(items[i].problem != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
+        const Problem &p = *reinterpret_cast<const Problem *>(items[i].problem);
+        for (int path : {QAIA_PATH_SPARSE_REG, QAIA_PATH_SPARSE_LDS, QAIA_PATH_DENSE}) {
+            try {
+                check_path(p, s, path);
+            } catch (const Error &) {
+                continue;
+            }
+            WsLayout L = sample_ws_layout(p, items[i].W, items[i].R, ps, path != QAIA_PATH_DENSE);
+            if (path == QAIA_PATH_DENSE) dense_ws_extend(p, items[i].W, items[i].R, ps, L);
+            need = std::max(need, L.total);
+        }
+    }
+    return need;
+}
+
+}  // namespace qaia

@@ -51,49 +51,36 @@ template <> struct PrecInfo<QAIA_FP8> { typedef uint8_t T; static constexpr int 
 __device__ __forceinline__ uint16_t bf16_pm1(float x) { return x >= 0.0f ? 0x3F80u : 0xBF80u; }
 __device__ __forceinline__ uint8_t fp8_pm1(float x) { return x >= 0.0f ? 0x38u : 0xB8u; }
 
-struct DenseStepArgs {
-    const void *J;         // [M][Np][Np]
-    const void *phi_in;    // [colsP][Np]
-    void *phi_out;         // [colsP][Np] (discrete SB)
-    const float *x_in;     // [colsP][Np]
-    float *x_out;
-    float *y;
-    const float *coef;     // [colsP][M]
-    const float *kt_tab;
-    float dta0;
-    int Np, N, cols, t;
-    float *trace;          // [cols][trace_steps][N] or null
-    int trace_steps;
-    float *field;          // field mode: [cols][M][N]
-    const float *jscale;   // field mode: [M]
-};
-
-template <int PREC, int M>
-__device__ __forceinline__ void mma_tile(const DenseStepArgs &a, int row_w, int col_w, int half,
-                                         int lr, f16v (&acc)[M][2]) {
+// MT: compile-time objective count (accumulator tiles); objectives k >= m
+// (run time, m <= MT) are skipped uniformly across the block.
+template <int PREC, int MT>
+__device__ __forceinline__ void mma_tile(const void *Jv, const void *phiv, int Np_, int m, int row_w,
+                                         int col_w, int half, int lr, f16v (&acc)[MT][2]) {
     typedef typename PrecInfo<PREC>::T T;
     constexpr int KG = PrecInfo<PREC>::KG;
-    const T *J = (const T *)a.J;
-    const T *phi = (const T *)a.phi_in;
-    const size_t Np = (size_t)a.Np;
+    constexpr int M = MT;
+    const T *J = (const T *)Jv;
+    const T *phi = (const T *)phiv;
+    const size_t Np = (size_t)Np_;
     const T *arow[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) arow[k] = J + ((size_t)k * Np + row_w + lr) * Np + half * (KG / 2);
+    for (int k = 0; k < M; ++k) arow[k] = J + ((size_t)(k < m ? k : 0) * Np + row_w + lr) * Np + half * (KG / 2);
     const T *bcol[2];
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) bcol[cb] = phi + (size_t)(col_w + cb * 32 + lr) * Np + half * (KG / 2);
 
-    for (int k0 = 0; k0 < a.Np; k0 += KG) {
+    for (int k0 = 0; k0 < Np_; k0 += KG) {
         if constexpr (PREC == QAIA_FP32) {
             float4 av[M], bv[2];
 #pragma unroll
-            for (int k = 0; k < M; ++k) av[k] = *(const float4 *)(arow[k] + k0);
+            for (int k = 0; k < M; ++k) av[k] = k < m ? *(const float4 *)(arow[k] + k0) : make_float4(0, 0, 0, 0);
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) bv[cb] = *(const float4 *)(bcol[cb] + k0);
 #pragma unroll
             for (int k = 0; k < M; ++k)
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
+                    if (k >= m) continue;
                     acc[k][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k].x, bv[cb].x, acc[k][cb], 0, 0, 0);
                     acc[k][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k].y, bv[cb].y, acc[k][cb], 0, 0, 0);
                     acc[k][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k].z, bv[cb].z, acc[k][cb], 0, 0, 0);
@@ -102,18 +89,18 @@ __device__ __forceinline__ void mma_tile(const DenseStepArgs &a, int row_w, int 
         } else if constexpr (PREC == QAIA_BF16) {
             bf16x8 av[M], bv[2];
 #pragma unroll
-            for (int k = 0; k < M; ++k) av[k] = *(const bf16x8 *)(arow[k] + k0);
+            for (int k = 0; k < M; ++k) av[k] = *(const bf16x8 *)(arow[k] + k0);  // k >= m reads objective 0
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) bv[cb] = *(const bf16x8 *)(bcol[cb] + k0);
 #pragma unroll
             for (int k = 0; k < M; ++k)
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
-                    acc[k][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[k], bv[cb], acc[k][cb], 0, 0, 0);
+                    if (k < m) acc[k][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[k], bv[cb], acc[k][cb], 0, 0, 0);
         } else {
             i32x8 av[M], bv[2];
 #pragma unroll
-            for (int k = 0; k < M; ++k) av[k] = *(const i32x8 *)(arow[k] + k0);
+            for (int k = 0; k < M; ++k) av[k] = *(const i32x8 *)(arow[k] + k0);  // k >= m reads objective 0
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) bv[cb] = *(const i32x8 *)(bcol[cb] + k0);
             // format 0 = e4m3 for both operands, block scales 127 = 2^0
@@ -121,18 +108,28 @@ __device__ __forceinline__ void mma_tile(const DenseStepArgs &a, int row_w, int 
             for (int k = 0; k < M; ++k)
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
-                    acc[k][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        av[k], bv[cb], acc[k][cb], 0, 0, 0, 127, 0, 127);
+                    if (k < m)
+                        acc[k][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            av[k], bv[cb], acc[k][cb], 0, 0, 0, 127, 0, 127);
         }
     }
 }
 
-template <int PREC, int M, bool DSB>
-__global__ __launch_bounds__(kDB) void dense_step_kernel(DenseStepArgs a) {
+// One step for the tile (bx, by) of a job; MT accumulator tiles, j.m <= MT.
+template <int PREC, int MT, bool DSB>
+__device__ void dense_step_body(const DenseJob &j, int t, int bx, int by) {
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int half = l >> 5, lr = l & 31;
-    const int row_w = blockIdx.y * kTileM + (wv & 1) * 32;
-    const int col_w = blockIdx.x * kTileN + (wv >> 1) * 64;
+    const int row_w = by * kTileM + (wv & 1) * 32;
+    const int col_w = bx * kTileN + (wv >> 1) * 64;
+    constexpr int M = MT;
+    const int m = j.m;
+    // discrete SB: x in place, Phi double-buffered; ballistic SB: x double-buffered, Phi = x
+    const bool even = (t & 1) == 0;
+    const float *x_in = DSB ? j.xa : (even ? j.xa : j.xb);
+    float *x_out = DSB ? j.xa : (even ? j.xb : j.xa);
+    const void *phi_in = DSB ? (even ? j.pa : j.pb) : (const void *)x_in;
+    void *phi_out = DSB ? (even ? j.pb : j.pa) : nullptr;
     f16v acc[M][2];
 #pragma unroll
     for (int k = 0; k < M; ++k)
@@ -140,64 +137,91 @@ __global__ __launch_bounds__(kDB) void dense_step_kernel(DenseStepArgs a) {
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[k][cb][i] = 0.0f;
-    mma_tile<PREC, M>(a, row_w, col_w, half, lr, acc);
+    mma_tile<PREC, M>(j.J, phi_in, j.Np, m, row_w, col_w, half, lr, acc);
 
-    const float kt = a.kt_tab[a.t];
-    const size_t Np = (size_t)a.Np;
+    const float kt = j.kt_tab[t];
+    const size_t Np = (size_t)j.Np;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
         const int col = col_w + cb * 32 + lr;
         float cf[M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) cf[k] = a.coef[(size_t)col * M + k];
+        for (int k = 0; k < M; ++k) cf[k] = k < m ? j.coef[(size_t)col * m + k] : 0.0f;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const int row = row_w + acc_row(half, g * 4);  // four consecutive spins row..row+3
             const size_t off = (size_t)col * Np + row;
-            float4 xv = *(const float4 *)(a.x_in + off);
-            float4 yv = *(const float4 *)(a.y + off);
+            float4 xv = *(const float4 *)(x_in + off);
+            float4 yv = *(const float4 *)(j.y + off);
             float xs[4] = {xv.x, xv.y, xv.z, xv.w}, ys[4] = {yv.x, yv.y, yv.z, yv.w};
 #pragma unroll
             for (int ii = 0; ii < 4; ++ii) {
                 float h = 0.0f;
 #pragma unroll
-                for (int k = 0; k < M; ++k) h = fmaf(cf[k], acc[k][cb][g * 4 + ii], h);
+                for (int k = 0; k < M; ++k)
+                    if (k < m) h = fmaf(cf[k], acc[k][cb][g * 4 + ii], h);
                 float yn = fmaf(kt, xs[ii], ys[ii]) + h;
-                float xn = fmaf(a.dta0, yn, xs[ii]);
+                float xn = fmaf(j.dta0, yn, xs[ii]);
                 wall(xn, yn);
                 xs[ii] = xn;
                 ys[ii] = yn;
             }
-            *(float4 *)(a.x_out + off) = make_float4(xs[0], xs[1], xs[2], xs[3]);
-            *(float4 *)(a.y + off) = make_float4(ys[0], ys[1], ys[2], ys[3]);
+            *(float4 *)(x_out + off) = make_float4(xs[0], xs[1], xs[2], xs[3]);
+            *(float4 *)(j.y + off) = make_float4(ys[0], ys[1], ys[2], ys[3]);
             if (DSB) {
                 if constexpr (PREC == QAIA_FP32) {
-                    *(float4 *)((float *)a.phi_out + off) =
+                    *(float4 *)((float *)phi_out + off) =
                         make_float4(sgn1(xs[0]), sgn1(xs[1]), sgn1(xs[2]), sgn1(xs[3]));
                 } else if constexpr (PREC == QAIA_BF16) {
                     uint2 v;
                     v.x = (uint32_t)bf16_pm1(xs[0]) | ((uint32_t)bf16_pm1(xs[1]) << 16);
                     v.y = (uint32_t)bf16_pm1(xs[2]) | ((uint32_t)bf16_pm1(xs[3]) << 16);
-                    *(uint2 *)((uint16_t *)a.phi_out + off) = v;
+                    *(uint2 *)((uint16_t *)phi_out + off) = v;
                 } else {
                     uint32_t v = (uint32_t)fp8_pm1(xs[0]) | ((uint32_t)fp8_pm1(xs[1]) << 8) |
                                  ((uint32_t)fp8_pm1(xs[2]) << 16) | ((uint32_t)fp8_pm1(xs[3]) << 24);
-                    *(uint32_t *)((uint8_t *)a.phi_out + off) = v;
+                    *(uint32_t *)((uint8_t *)phi_out + off) = v;
                 }
             }
-            if (a.trace != nullptr && a.t < a.trace_steps && col < a.cols) {
+            if (j.trace != nullptr && t < j.trace_steps && col < j.cols) {
 #pragma unroll
                 for (int ii = 0; ii < 4; ++ii)
-                    if (row + ii < a.N)
-                        a.trace[((size_t)col * a.trace_steps + a.t) * a.N + row + ii] = xs[ii];
+                    if (row + ii < j.N)
+                        j.trace[((size_t)col * j.trace_steps + t) * j.N + row + ii] = xs[ii];
             }
         }
     }
 }
 
+template <int PREC, int M, bool DSB>
+__global__ __launch_bounds__(kDB) void dense_step_kernel(DenseJob j, int t) {
+    dense_step_body<PREC, M, DSB>(j, t, blockIdx.x, blockIdx.y);
+}
+
+// Grouped step over a ragged batch of dense jobs (each with its own n, m,
+// columns): block b runs tile b - block_start[i] of job i.
+template <int PREC, bool DSB>
+__global__ __launch_bounds__(kDB) void dense_batch_step_kernel(const DenseJob *__restrict__ jobs, int count,
+                                                               const int64_t *__restrict__ block_start, int t) {
+    const int64_t b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < count && block_start[i + 1] <= b) ++i;
+    const DenseJob j = jobs[i];
+    const int64_t local = b - block_start[i];
+    dense_step_body<PREC, 4, DSB>(j, t, (int)(local % j.tiles_x), (int)(local / j.tiles_x));
+}
+
 // Field mode (reduced-precision error reporting): field[col][k][i] = 2^e_k (J~_k Phi)_i.
+struct FieldArgs {
+    const void *J;
+    const void *phi;
+    int Np, N, cols;
+    float *field;
+    const float *jscale;
+};
+
 template <int PREC, int M>
-__global__ __launch_bounds__(kDB) void dense_field_kernel(DenseStepArgs a) {
+__global__ __launch_bounds__(kDB) void dense_field_kernel(FieldArgs a) {
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int half = l >> 5, lr = l & 31;
     const int row_w = blockIdx.y * kTileM + (wv & 1) * 32;
@@ -209,7 +233,7 @@ __global__ __launch_bounds__(kDB) void dense_field_kernel(DenseStepArgs a) {
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[k][cb][i] = 0.0f;
-    mma_tile<PREC, M>(a, row_w, col_w, half, lr, acc);
+    mma_tile<PREC, M>(a.J, a.phi, a.Np, M, row_w, col_w, half, lr, acc);
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
         const int col = col_w + cb * 32 + lr;
@@ -420,30 +444,108 @@ bool dense_supported(const Problem &p, std::string *why) {
 }
 
 template <int PREC, int M, bool DSB>
-static void step_launch(dim3 grid, hipStream_t st, const DenseStepArgs &a) {
-    hipLaunchKernelGGL((dense_step_kernel<PREC, M, DSB>), grid, dim3(kDB), 0, st, a);
+static void step_launch(dim3 grid, hipStream_t st, const DenseJob &j, int t) {
+    hipLaunchKernelGGL((dense_step_kernel<PREC, M, DSB>), grid, dim3(kDB), 0, st, j, t);
 }
 
 template <int PREC, bool DSB>
-static void step_dispatch_m(int m, dim3 grid, hipStream_t st, const DenseStepArgs &a) {
-    switch (m) {
-        case 1: step_launch<PREC, 1, DSB>(grid, st, a); break;
-        case 2: step_launch<PREC, 2, DSB>(grid, st, a); break;
-        case 3: step_launch<PREC, 3, DSB>(grid, st, a); break;
-        case 4: step_launch<PREC, 4, DSB>(grid, st, a); break;
+static void step_dispatch_m(dim3 grid, hipStream_t st, const DenseJob &j, int t) {
+    switch (j.m) {
+        case 1: step_launch<PREC, 1, DSB>(grid, st, j, t); break;
+        case 2: step_launch<PREC, 2, DSB>(grid, st, j, t); break;
+        case 3: step_launch<PREC, 3, DSB>(grid, st, j, t); break;
+        case 4: step_launch<PREC, 4, DSB>(grid, st, j, t); break;
         default: throw Error{QAIA_UNSUPPORTED, "dense path supports m <= 4"};
     }
 }
 
-static void step_dispatch(int prec, bool dsb, int m, dim3 grid, hipStream_t st, const DenseStepArgs &a) {
+static void step_dispatch(int prec, bool dsb, dim3 grid, hipStream_t st, const DenseJob &j, int t) {
     if (prec == QAIA_FP32) {
-        if (dsb) step_dispatch_m<QAIA_FP32, true>(m, grid, st, a);
-        else step_dispatch_m<QAIA_FP32, false>(m, grid, st, a);
+        if (dsb) step_dispatch_m<QAIA_FP32, true>(grid, st, j, t);
+        else step_dispatch_m<QAIA_FP32, false>(grid, st, j, t);
     } else if (prec == QAIA_BF16) {
-        step_dispatch_m<QAIA_BF16, true>(m, grid, st, a);
+        step_dispatch_m<QAIA_BF16, true>(grid, st, j, t);
     } else {
-        step_dispatch_m<QAIA_FP8, true>(m, grid, st, a);
+        step_dispatch_m<QAIA_FP8, true>(grid, st, j, t);
     }
+}
+
+void launch_dense_batch_step(int prec, bool dsb, const DenseJob *jobs, int count, const int64_t *starts,
+                             int64_t blocks, int t, hipStream_t st) {
+    QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many tiles for one launch");
+    if (blocks == 0) return;
+    const dim3 grid((unsigned)blocks);
+    if (prec == QAIA_FP32) {
+        if (dsb) hipLaunchKernelGGL((dense_batch_step_kernel<QAIA_FP32, true>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+        else hipLaunchKernelGGL((dense_batch_step_kernel<QAIA_FP32, false>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+    } else if (prec == QAIA_BF16) {
+        hipLaunchKernelGGL((dense_batch_step_kernel<QAIA_BF16, true>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+    } else {
+        hipLaunchKernelGGL((dense_batch_step_kernel<QAIA_FP8, true>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+    }
+}
+
+DenseJob dense_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws, const WsLayout &L,
+                   float *trace, int32_t trace_steps) {
+    char *b = (char *)ws;
+    DenseJob j{};
+    j.J = dense_J(p, s.precision);
+    j.xa = (float *)(b + L.xa);
+    j.xb = (float *)(b + L.xb);
+    j.y = (float *)(b + L.y);
+    j.pa = b + L.pa;
+    j.pb = b + L.pb;
+    j.coef = (const float *)(b + L.coef);
+    j.kt_tab = (const float *)(b + L.kt);
+    j.dta0 = s.dt * s.a0;
+    j.Np = p.dense.Np;
+    j.N = p.n;
+    j.m = p.m;
+    j.cols = (int)(W * (int64_t)R);
+    j.tiles_x = (int)(L.colsP / kTileN);
+    j.tiles_y = p.dense.Np / kTileM;
+    j.trace = trace_steps > 0 ? trace : nullptr;
+    j.trace_steps = trace_steps;
+    return j;
+}
+
+// x, y, Phi start values and the per-column coefficients
+void launch_dense_setup(const Problem &p, const float *weights, int32_t R, const qaia_schedule &s, void *ws,
+                        const WsLayout &L, const DenseJob &j, hipStream_t st) {
+    char *b = (char *)ws;
+    const int prec = s.precision;
+    const bool dsb = s.variant == QAIA_DSB;
+    const int colsP = (int)L.colsP, Np = j.Np;
+    const size_t total = (size_t)colsP * Np;
+    const unsigned ib = (unsigned)((total + kDB - 1) / kDB);
+    if (prec == QAIA_FP32)
+        hipLaunchKernelGGL(dense_init_kernel<QAIA_FP32>, dim3(ib), dim3(kDB), 0, st, j.xa, j.y, j.pa, Np, p.n,
+                           j.cols, colsP, s.seed, s.replica_offset, s.init_amp, dsb);
+    else if (prec == QAIA_BF16)
+        hipLaunchKernelGGL(dense_init_kernel<QAIA_BF16>, dim3(ib), dim3(kDB), 0, st, j.xa, j.y, j.pa, Np, p.n,
+                           j.cols, colsP, s.seed, s.replica_offset, s.init_amp, dsb);
+    else
+        hipLaunchKernelGGL(dense_init_kernel<QAIA_FP8>, dim3(ib), dim3(kDB), 0, st, j.xa, j.y, j.pa, Np, p.n,
+                           j.cols, colsP, s.seed, s.replica_offset, s.init_amp, dsb);
+    QAIA_HIP(hipGetLastError());
+    const unsigned cb = (unsigned)((colsP * p.m + kDB - 1) / kDB);
+    hipLaunchKernelGGL(dense_coef_kernel, dim3(cb), dim3(kDB), 0, st, weights, (const double *)(b + L.c0s), p.m,
+                       R, j.cols, colsP, (double)s.dt, p.dense.scales + 8 * prec, (float *)(b + L.coef));
+    QAIA_HIP(hipGetLastError());
+}
+
+// sgn read-out of the final x and exact cut values
+void launch_dense_finish(const Problem &p, int32_t R, const qaia_schedule &s, void *ws, const WsLayout &L,
+                         const DenseJob &j, uint64_t *spins, int64_t *obj, hipStream_t st) {
+    char *b = (char *)ws;
+    const bool dsb = s.variant == QAIA_DSB;
+    // after T steps the latest x is xa (discrete SB, in place) or the buffer step T-1 wrote
+    const float *xf = dsb ? j.xa : ((s.steps & 1) ? j.xb : j.xa);
+    const size_t items = (size_t)j.cols * p.words;
+    hipLaunchKernelGGL(dense_readout_kernel, dim3((unsigned)((items + 3) / 4)), dim3(kDB), 0, st, xf, j.Np, p.n,
+                       j.cols, R, p.words, (const double *)(b + L.c0s), spins);
+    QAIA_HIP(hipGetLastError());
+    launch_evaluate(p, spins, j.cols, obj, st);
 }
 
 void launch_dense(const Problem &p, const float *weights, int64_t W, int32_t R,
@@ -455,62 +557,12 @@ void launch_dense(const Problem &p, const float *weights, int64_t W, int32_t R,
     const int64_t cols = W * (int64_t)R;
     if (cols == 0) return;
     QAIA_CHECK(L.colsP <= INT32_MAX / 2, QAIA_INVALID_ARGUMENT, "too many replicas for the dense path");
-    char *b = (char *)ws;
-    const int Np = p.dense.Np, colsP = (int)L.colsP, prec = s.precision;
-    const bool dsb = s.variant == QAIA_DSB;
-    const double *c0s = (const double *)(b + L.c0s);
-    float *xa = (float *)(b + L.xa), *xb = (float *)(b + L.xb), *y = (float *)(b + L.y);
-    void *pa = b + L.pa, *pbuf = b + L.pb;
-    float *coef = (float *)(b + L.coef);
-    const float *jscale = p.dense.scales + 8 * prec;
-
-    const size_t total = (size_t)colsP * Np;
-    const unsigned ib = (unsigned)((total + kDB - 1) / kDB);
-    if (prec == QAIA_FP32)
-        hipLaunchKernelGGL(dense_init_kernel<QAIA_FP32>, dim3(ib), dim3(kDB), 0, st, xa, y, pa, Np, p.n,
-                           (int)cols, colsP, s.seed, s.replica_offset, s.init_amp, dsb);
-    else if (prec == QAIA_BF16)
-        hipLaunchKernelGGL(dense_init_kernel<QAIA_BF16>, dim3(ib), dim3(kDB), 0, st, xa, y, pa, Np, p.n,
-                           (int)cols, colsP, s.seed, s.replica_offset, s.init_amp, dsb);
-    else
-        hipLaunchKernelGGL(dense_init_kernel<QAIA_FP8>, dim3(ib), dim3(kDB), 0, st, xa, y, pa, Np, p.n,
-                           (int)cols, colsP, s.seed, s.replica_offset, s.init_amp, dsb);
+    const DenseJob j = dense_job(p, W, R, s, ws, L, trace, trace_steps);
+    launch_dense_setup(p, weights, R, s, ws, L, j, st);
+    const dim3 grid(j.tiles_x, j.tiles_y);
+    for (int t = 0; t < s.steps; ++t) step_dispatch(s.precision, s.variant == QAIA_DSB, grid, st, j, t);
     QAIA_HIP(hipGetLastError());
-    const unsigned cb = (unsigned)((colsP * p.m + kDB - 1) / kDB);
-    hipLaunchKernelGGL(dense_coef_kernel, dim3(cb), dim3(kDB), 0, st, weights, c0s, p.m, R, (int)cols,
-                       colsP, (double)s.dt, jscale, coef);
-    QAIA_HIP(hipGetLastError());
-
-    DenseStepArgs a{};
-    a.J = dense_J(p, prec);
-    a.coef = coef;
-    a.kt_tab = (const float *)(b + L.kt);
-    a.dta0 = s.dt * s.a0;
-    a.Np = Np;
-    a.N = p.n;
-    a.cols = (int)cols;
-    a.y = y;
-    a.trace = trace_steps > 0 ? trace : nullptr;
-    a.trace_steps = trace_steps;
-    const dim3 grid(colsP / kTileN, Np / kTileM);
-    float *xcur = xa, *xnext = xb;
-    void *pcur = pa, *pnext = pbuf;
-    for (int t = 0; t < s.steps; ++t) {
-        a.t = t;
-        a.x_in = xcur;
-        a.x_out = dsb ? xcur : xnext;  // discrete SB updates x in place (Phi is separate)
-        a.phi_in = dsb ? pcur : (const void *)xcur;
-        a.phi_out = dsb ? pnext : nullptr;
-        step_dispatch(prec, dsb, p.m, grid, st, a);
-        if (!dsb) std::swap(xcur, xnext);
-        else std::swap(pcur, pnext);
-    }
-    QAIA_HIP(hipGetLastError());
-    const size_t items = (size_t)cols * p.words;
-    hipLaunchKernelGGL(dense_readout_kernel, dim3((unsigned)((items + 3) / 4)), dim3(kDB), 0, st, xcur, Np,
-                       p.n, (int)cols, R, p.words, c0s, spins);
-    QAIA_HIP(hipGetLastError());
-    launch_evaluate(p, spins, cols, obj, st);
+    launch_dense_finish(p, R, s, ws, L, j, spins, obj, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -522,12 +574,12 @@ size_t dense_field_ws_bytes(const Problem &p, int prec, int64_t count) {
 }
 
 template <int PREC, int M>
-static void field_launch(dim3 grid, hipStream_t st, const DenseStepArgs &a) {
+static void field_launch(dim3 grid, hipStream_t st, const FieldArgs &a) {
     hipLaunchKernelGGL((dense_field_kernel<PREC, M>), grid, dim3(kDB), 0, st, a);
 }
 
 template <int PREC>
-static void field_dispatch(int m, dim3 grid, hipStream_t st, const DenseStepArgs &a) {
+static void field_dispatch(int m, dim3 grid, hipStream_t st, const FieldArgs &a) {
     switch (m) {
         case 1: field_launch<PREC, 1>(grid, st, a); break;
         case 2: field_launch<PREC, 2>(grid, st, a); break;
@@ -556,9 +608,9 @@ void launch_dense_field(const Problem &p, int prec, const float *phi, int64_t co
     else
         hipLaunchKernelGGL(dense_phi_kernel<QAIA_FP8>, dim3(ib), dim3(kDB), 0, st, phi, ws, Np, p.n, (int)count, colsP);
     QAIA_HIP(hipGetLastError());
-    DenseStepArgs a{};
+    FieldArgs a{};
     a.J = dense_J(p, prec);
-    a.phi_in = ws;
+    a.phi = ws;
     a.Np = Np;
     a.N = p.n;
     a.cols = (int)count;

@@ -108,6 +108,41 @@ struct WsLayout {
 WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, bool edge_coefs);
 void dense_ws_extend(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, WsLayout &L);
 
+// One problem's rows for the generic sparse kernel (passed by value, or as a
+// device array for a ragged batch).
+struct SparseJob {
+    int n, m, words, R, T, rpb;
+    int64_t E, rows;
+    const int32_t *rowptr, *col, *eid, *Wt, *eu, *ev;
+    const float *jcp;
+    const double *c0s;
+    const float *kt_tab;
+    float dta0, dt_alpha, amp;
+    uint64_t seed, offset;
+    uint64_t *spins;
+    int64_t *obj;
+    float *trace;
+    int trace_steps;
+};
+// One problem's dense SB state (both buffers of each double-buffered pair;
+// the step parity selects them).
+struct DenseJob {
+    const void *J;
+    float *xa, *xb, *y;
+    void *pa, *pb;
+    const float *coef;
+    const float *kt_tab;
+    float dta0;
+    int Np, N, m, cols, tiles_x, tiles_y;
+    float *trace;
+    int trace_steps;
+};
+struct SparseShape {
+    int rpb = 1, npt = 1, maxdeg = 4;
+    int64_t blocks = 0;
+    size_t shmem = 0;
+};
+
 // ----------------------------------------------------------------- kernels (host launchers)
 void launch_prep(const Problem &p, const float *weights, int64_t W, const qaia_schedule &s,
                  void *ws, const WsLayout &L, hipStream_t st);
@@ -115,6 +150,12 @@ void launch_sparse_lds(const Problem &p, int64_t W, int32_t R, const qaia_schedu
                        const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
                        int32_t trace_steps, hipStream_t st);
 bool sparse_lds_supported(const Problem &p, std::string *why);
+SparseShape sparse_lds_shape(const Problem &p, int64_t rows);
+SparseJob sparse_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws,
+                     const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace, int32_t trace_steps);
+// single: one job by value; otherwise `count` device jobs with block prefix `starts`
+void launch_sparse_lds_jobs(const SparseJob *single, const SparseJob *jobs, int count, const int64_t *starts,
+                            int64_t blocks, int maxdeg, int npt, size_t shmem, bool dsb, hipStream_t st);
 void launch_evaluate(const Problem &p, const uint64_t *spins, int64_t count, int64_t *obj,
                      hipStream_t st);
 
@@ -133,6 +174,14 @@ bool dense_supported(const Problem &p, std::string *why);
 void launch_dense(const Problem &p, const float *weights, int64_t W, int32_t R,
                   const qaia_schedule &s, void *ws, const WsLayout &L, uint64_t *spins, int64_t *obj,
                   float *trace, int32_t trace_steps, hipStream_t st);
+DenseJob dense_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws, const WsLayout &L,
+                   float *trace, int32_t trace_steps);
+void launch_dense_setup(const Problem &p, const float *weights, int32_t R, const qaia_schedule &s, void *ws,
+                        const WsLayout &L, const DenseJob &j, hipStream_t st);
+void launch_dense_finish(const Problem &p, int32_t R, const qaia_schedule &s, void *ws, const WsLayout &L,
+                         const DenseJob &j, uint64_t *spins, int64_t *obj, hipStream_t st);
+void launch_dense_batch_step(int prec, bool dsb, const DenseJob *jobs, int count, const int64_t *starts,
+                             int64_t blocks, int t, hipStream_t st);
 size_t dense_field_ws_bytes(const Problem &p, int prec, int64_t count);
 void launch_dense_field(const Problem &p, int prec, const float *phi, int64_t count, float *field,
                         void *ws, size_t ws_bytes, hipStream_t st);
@@ -158,6 +207,14 @@ void launch_labels(const int64_t *keep, const int64_t *num_keep, int64_t archive
                    float *labels, hipStream_t st);
 void launch_gather_rows(const uint32_t *src, int width, const int64_t *idx, const int64_t *count,
                         int64_t cap, uint32_t *dst, hipStream_t st);
+
+// batching form (batch.cpp)
+size_t batch_ws_bytes(const qaia_batch_item *items, int32_t count, const qaia_schedule &s);
+void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedule &s, void *ws, size_t ws_bytes,
+                  hipStream_t caller);
+void autotune(qaia_batch_item *items, int32_t count, const qaia_schedule &s, int32_t probe_steps,
+              double *est_seconds, void *ws, size_t ws_bytes, hipStream_t st);
+size_t autotune_ws_bytes(const qaia_batch_item *items, int32_t count, const qaia_schedule &s, int32_t probe_steps);
 
 // pareto filter (pareto.hip)
 size_t pareto_ws_bytes(int64_t M, int32_t m);

@@ -157,21 +157,15 @@ void launch_prep(const Problem &p, const float *weights, int64_t W, const qaia_s
 // every force uses the pre-step x (Eq. 9); each lane keeps its own y, x and
 // its neighbour list (LDS offsets and folded coefficients) in registers.
 // After T steps the block reads out sgn(x) and evaluates the exact cut
-// vector of each replica with wave reductions.
+// vector of each replica with wave reductions.  The body works on one
+// SparseJob (one problem's rows); the batched kernel maps blocks to jobs.
 template <int MAXDEG, int NPT, bool DSB>
-__global__ __launch_bounds__(kBlock) void sparse_lds_kernel(
-    int n, int64_t E, int rpb, int64_t rows, int R, int T, const int32_t *__restrict__ rowptr,
-    const int32_t *__restrict__ col, const int32_t *__restrict__ eid,
-    const float *__restrict__ jcp, const double *__restrict__ c0s,
-    const float *__restrict__ kt_tab, float dta0, float dt_alpha, uint64_t seed,
-    uint64_t offset, float amp, int m, const int32_t *__restrict__ Wt,
-    const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int words,
-    uint64_t *__restrict__ spins, int64_t *__restrict__ obj, float *__restrict__ trace,
-    int trace_steps) {
-    extern __shared__ float xs[];  // [2][rpb * n]
+__device__ void sparse_lds_body(const SparseJob &j, int64_t block, float *xs) {
+    const int n = j.n, rpb = j.rpb, R = j.R, T = j.T;
+    const int64_t E = j.E, rows = j.rows;
     const int tid = threadIdx.x;
     const int span = rpb * n;
-    const int64_t row0 = (int64_t)blockIdx.x * rpb;
+    const int64_t row0 = block * rpb;
 
     float x[NPT], y[NPT], jv[NPT][MAXDEG];
     int nb[NPT][MAXDEG], deg[NPT], node[NPT];
@@ -189,16 +183,16 @@ __global__ __launch_bounds__(kBlock) void sparse_lds_kernel(
         if (act[q]) {
             const int i = node[q];
             const int64_t w = rowq[q] / R;
-            const uint64_t g = (uint64_t)rowq[q] + offset;
-            x[q] = init_value(seed, init_counter(g, n, i, 0), amp);
-            y[q] = init_value(seed, init_counter(g, n, i, 1), amp);
-            const int p0 = rowptr[i];
-            deg[q] = rowptr[i + 1] - p0;
+            const uint64_t g = (uint64_t)rowq[q] + j.offset;
+            x[q] = init_value(j.seed, init_counter(g, n, i, 0), j.amp);
+            y[q] = init_value(j.seed, init_counter(g, n, i, 1), j.amp);
+            const int p0 = j.rowptr[i];
+            deg[q] = j.rowptr[i + 1] - p0;
 #pragma unroll
             for (int d = 0; d < MAXDEG; ++d) {
                 if (d < deg[q]) {
-                    nb[q][d] = rl * n + col[p0 + d];
-                    jv[q][d] = jcp[w * E + eid[p0 + d]];
+                    nb[q][d] = rl * n + j.col[p0 + d];
+                    jv[q][d] = j.jcp[w * E + j.eid[p0 + d]];
                 } else {
                     nb[q][d] = 0;
                     jv[q][d] = 0.0f;
@@ -210,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void sparse_lds_kernel(
     __syncthreads();
     int cur = 0;
     for (int t = 0; t < T; ++t) {
-        const float kt = kt_tab[t];
+        const float kt = j.kt_tab[t];
         const float *xc = xs + cur * span;
         float *xn = xs + (cur ^ 1) * span;
 #pragma unroll
@@ -225,17 +219,17 @@ __global__ __launch_bounds__(kBlock) void sparse_lds_kernel(
                     acc = fmaf(jv[q][d], v, acc);
                 }
             }
-            if (dt_alpha != 0.0f) {
-                const uint64_t g = (uint64_t)rowq[q] + offset;
+            if (j.dt_alpha != 0.0f) {
+                const uint64_t g = (uint64_t)rowq[q] + j.offset;
                 const uint64_t nidx = (g * (uint64_t)T + (uint64_t)t) * (uint64_t)n + node[q];
-                acc = fmaf(dt_alpha, noise_value(seed, nidx), acc);
+                acc = fmaf(j.dt_alpha, noise_value(j.seed, nidx), acc);
             }
             y[q] = acc;
-            x[q] = fmaf(dta0, y[q], x[q]);
+            x[q] = fmaf(j.dta0, y[q], x[q]);
             wall(x[q], y[q]);
             xn[q * kBlock + tid] = x[q];
-            if (trace != nullptr && t < trace_steps)
-                trace[(rowq[q] * trace_steps + t) * n + node[q]] = x[q];
+            if (j.trace != nullptr && t < j.trace_steps)
+                j.trace[(rowq[q] * j.trace_steps + t) * n + node[q]] = x[q];
         }
         __syncthreads();
         cur ^= 1;
@@ -244,28 +238,29 @@ __global__ __launch_bounds__(kBlock) void sparse_lds_kernel(
     // read-out and exact cut evaluation, one wave per local replica
     const float *xf = xs + cur * span;
     const int lane = tid & 63, wave = tid >> 6;
+    const int m = j.m, words = j.words;
     for (int rl = wave; rl < rpb; rl += kBlock / 64) {
         const int64_t row = row0 + rl;
         if (row >= rows) break;
-        const bool valid = c0s[row / R] >= 0.0;
+        const bool valid = j.c0s[row / R] >= 0.0;
         const float *xr = xf + rl * n;
         for (int wd = lane; wd < words; wd += 64) {
             uint64_t bits = 0;
             if (valid)
                 for (int b = 0; b < 64 && wd * 64 + b < n; ++b)
                     bits |= (uint64_t)(xr[wd * 64 + b] < 0.0f) << b;
-            spins[row * words + wd] = bits;
+            j.spins[row * words + wd] = bits;
         }
         int64_t acc[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[k] = 0;
         if (valid) {
             for (int64_t e = lane; e < E; e += 64) {
-                const bool cut = (xr[eu[e]] < 0.0f) != (xr[ev[e]] < 0.0f);
+                const bool cut = (xr[j.eu[e]] < 0.0f) != (xr[j.ev[e]] < 0.0f);
                 if (cut) {
 #pragma unroll
                     for (int k = 0; k < 8; ++k)
-                        if (k < m) acc[k] += (int64_t)Wt[(int64_t)k * E + e];
+                        if (k < m) acc[k] += (int64_t)j.Wt[(int64_t)k * E + e];
                 }
             }
         }
@@ -278,9 +273,28 @@ __global__ __launch_bounds__(kBlock) void sparse_lds_kernel(
                 int hi = __shfl_xor((int)(v >> 32), off);
                 v += (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
             }
-            if (lane == 0) obj[row * m + k] = v;
+            if (lane == 0) j.obj[row * m + k] = v;
         }
     }
+}
+
+template <int MAXDEG, int NPT, bool DSB>
+__global__ __launch_bounds__(kBlock) void sparse_lds_kernel(SparseJob j) {
+    extern __shared__ float xs[];  // [2][rpb * n]
+    sparse_lds_body<MAXDEG, NPT, DSB>(j, blockIdx.x, xs);
+}
+
+// Ragged batch: block b runs job i with block_start[i] <= b < block_start[i + 1].
+template <int MAXDEG, int NPT, bool DSB>
+__global__ __launch_bounds__(kBlock) void sparse_lds_batch_kernel(const SparseJob *__restrict__ jobs,
+                                                                  int count,
+                                                                  const int64_t *__restrict__ block_start) {
+    extern __shared__ float xs[];
+    const int64_t b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < count && block_start[i + 1] <= b) ++i;
+    const SparseJob j = jobs[i];
+    sparse_lds_body<MAXDEG, NPT, DSB>(j, b - block_start[i], xs);
 }
 
 bool sparse_lds_supported(const Problem &p, std::string *why) {
@@ -299,35 +313,69 @@ bool sparse_lds_supported(const Problem &p, std::string *why) {
     return true;
 }
 
-template <int MAXDEG, int NPT>
-static void launch_lds_t(const Problem &p, bool dsb, dim3 grid, size_t shmem, hipStream_t st,
-                         int rpb, int64_t rows, int32_t R, const qaia_schedule &s, const float *jcp,
-                         const double *c0s, const float *kt, uint64_t *spins, int64_t *obj,
-                         float *trace, int trace_steps) {
-    const float dta0 = s.dt * s.a0;
-    const float dt_alpha = s.dt * s.noise_alpha;
-    if (dsb)
-        hipLaunchKernelGGL((sparse_lds_kernel<MAXDEG, NPT, true>), grid, dim3(kBlock), shmem, st,
-                           p.n, p.E, rpb, rows, R, s.steps, p.d_rowptr, p.d_col, p.d_eid, jcp,
-                           c0s, kt, dta0, dt_alpha, s.seed, s.replica_offset, s.init_amp, p.m,
-                           p.d_W, p.d_eu, p.d_ev, p.words, spins, obj, trace, trace_steps);
+SparseShape sparse_lds_shape(const Problem &p, int64_t rows) {
+    SparseShape sh;
+    sh.rpb = p.n <= kBlock ? kBlock / p.n : 1;
+    const int span = sh.rpb * p.n;
+    sh.npt = 1;
+    while (sh.npt * kBlock < span) sh.npt <<= 1;
+    sh.maxdeg = p.max_degree <= 4 ? 4 : (p.max_degree <= 8 ? 8 : (p.max_degree <= 16 ? 16 : 32));
+    sh.blocks = (rows + sh.rpb - 1) / sh.rpb;
+    sh.shmem = sizeof(float) * 2 * (size_t)span;
+    return sh;
+}
+
+SparseJob sparse_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws,
+                     const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace, int32_t trace_steps) {
+    char *b = (char *)ws;
+    SparseJob j{};
+    j.n = p.n;
+    j.E = p.E;
+    j.m = p.m;
+    j.words = p.words;
+    j.R = R;
+    j.T = s.steps;
+    j.rows = W * (int64_t)R;
+    j.rpb = sparse_lds_shape(p, j.rows).rpb;
+    j.rowptr = p.d_rowptr;
+    j.col = p.d_col;
+    j.eid = p.d_eid;
+    j.Wt = p.d_W;
+    j.eu = p.d_eu;
+    j.ev = p.d_ev;
+    j.jcp = (const float *)(b + L.jcp);
+    j.c0s = (const double *)(b + L.c0s);
+    j.kt_tab = (const float *)(b + L.kt);
+    j.dta0 = s.dt * s.a0;
+    j.dt_alpha = s.dt * s.noise_alpha;
+    j.seed = s.seed;
+    j.offset = s.replica_offset;
+    j.amp = s.init_amp;
+    j.spins = spins;
+    j.obj = obj;
+    j.trace = trace;
+    j.trace_steps = trace_steps;
+    return j;
+}
+
+template <int MAXDEG, int NPT, bool DSB>
+static void launch_one(const SparseJob *single, const SparseJob *jobs, int count, const int64_t *starts,
+                       int64_t blocks, size_t shmem, hipStream_t st) {
+    if (single)
+        hipLaunchKernelGGL((sparse_lds_kernel<MAXDEG, NPT, DSB>), dim3((unsigned)blocks), dim3(kBlock), shmem,
+                           st, *single);
     else
-        hipLaunchKernelGGL((sparse_lds_kernel<MAXDEG, NPT, false>), grid, dim3(kBlock), shmem, st,
-                           p.n, p.E, rpb, rows, R, s.steps, p.d_rowptr, p.d_col, p.d_eid, jcp,
-                           c0s, kt, dta0, dt_alpha, s.seed, s.replica_offset, s.init_amp, p.m,
-                           p.d_W, p.d_eu, p.d_ev, p.words, spins, obj, trace, trace_steps);
+        hipLaunchKernelGGL((sparse_lds_batch_kernel<MAXDEG, NPT, DSB>), dim3((unsigned)blocks), dim3(kBlock),
+                           shmem, st, jobs, count, starts);
 }
 
 template <int MAXDEG>
-static void launch_lds_npt(int npt, const Problem &p, bool dsb, dim3 grid, size_t shmem,
-                           hipStream_t st, int rpb, int64_t rows, int32_t R,
-                           const qaia_schedule &s, const float *jcp, const double *c0s,
-                           const float *kt, uint64_t *spins, int64_t *obj, float *trace,
-                           int trace_steps) {
-#define QAIA_NPT(N)                                                                          \
-    case N:                                                                                  \
-        launch_lds_t<MAXDEG, N>(p, dsb, grid, shmem, st, rpb, rows, R, s, jcp, c0s, kt, spins, \
-                                obj, trace, trace_steps);                                    \
+static void dispatch_npt(int npt, bool dsb, const SparseJob *single, const SparseJob *jobs, int count,
+                         const int64_t *starts, int64_t blocks, size_t shmem, hipStream_t st) {
+#define QAIA_NPT(N)                                                                                   \
+    case N:                                                                                           \
+        if (dsb) launch_one<MAXDEG, N, true>(single, jobs, count, starts, blocks, shmem, st);         \
+        else launch_one<MAXDEG, N, false>(single, jobs, count, starts, blocks, shmem, st);            \
         break;
     switch (npt) {
         QAIA_NPT(1)
@@ -341,6 +389,19 @@ static void launch_lds_npt(int npt, const Problem &p, bool dsb, dim3 grid, size_
 #undef QAIA_NPT
 }
 
+void launch_sparse_lds_jobs(const SparseJob *single, const SparseJob *jobs, int count, const int64_t *starts,
+                            int64_t blocks, int maxdeg, int npt, size_t shmem, bool dsb, hipStream_t st) {
+    QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many replicas for one launch");
+    if (blocks == 0) return;
+    switch (maxdeg) {
+        case 4: dispatch_npt<4>(npt, dsb, single, jobs, count, starts, blocks, shmem, st); break;
+        case 8: dispatch_npt<8>(npt, dsb, single, jobs, count, starts, blocks, shmem, st); break;
+        case 16: dispatch_npt<16>(npt, dsb, single, jobs, count, starts, blocks, shmem, st); break;
+        default: dispatch_npt<32>(npt, dsb, single, jobs, count, starts, blocks, shmem, st); break;
+    }
+    QAIA_HIP(hipGetLastError());
+}
+
 void launch_sparse_lds(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws,
                        const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
                        int32_t trace_steps, hipStream_t st) {
@@ -348,31 +409,10 @@ void launch_sparse_lds(const Problem &p, int64_t W, int32_t R, const qaia_schedu
     QAIA_CHECK(sparse_lds_supported(p, &why), QAIA_UNSUPPORTED, "sparse LDS path: " + why);
     const int64_t rows = W * (int64_t)R;
     if (rows == 0) return;
-    const int rpb = p.n <= kBlock ? kBlock / p.n : 1;
-    const int span = rpb * p.n;
-    int npt = 1;
-    while (npt * kBlock < span) npt <<= 1;
-    const int64_t blocks = (rows + rpb - 1) / rpb;
-    QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many replicas for one launch");
-    const size_t shmem = sizeof(float) * 2 * (size_t)span;
-    char *b = (char *)ws;
-    const float *jcp = (const float *)(b + L.jcp), *kt = (const float *)(b + L.kt);
-    const double *c0s = (const double *)(b + L.c0s);
-    const bool dsb = s.variant == QAIA_DSB;
-    dim3 grid((unsigned)blocks);
-    if (p.max_degree <= 4)
-        launch_lds_npt<4>(npt, p, dsb, grid, shmem, st, rpb, rows, R, s, jcp, c0s, kt, spins, obj,
-                          trace, trace_steps);
-    else if (p.max_degree <= 8)
-        launch_lds_npt<8>(npt, p, dsb, grid, shmem, st, rpb, rows, R, s, jcp, c0s, kt, spins, obj,
-                          trace, trace_steps);
-    else if (p.max_degree <= 16)
-        launch_lds_npt<16>(npt, p, dsb, grid, shmem, st, rpb, rows, R, s, jcp, c0s, kt, spins,
-                           obj, trace, trace_steps);
-    else
-        launch_lds_npt<32>(npt, p, dsb, grid, shmem, st, rpb, rows, R, s, jcp, c0s, kt, spins,
-                           obj, trace, trace_steps);
-    QAIA_HIP(hipGetLastError());
+    const SparseShape sh = sparse_lds_shape(p, rows);
+    const SparseJob j = sparse_job(p, W, R, s, ws, L, spins, obj, trace, trace_steps);
+    launch_sparse_lds_jobs(&j, nullptr, 1, nullptr, sh.blocks, sh.maxdeg, sh.npt, sh.shmem,
+                           s.variant == QAIA_DSB, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,112 @@
+"""GPU tests of the batching form: a ragged batch sampled by one graph launch
+must reproduce per-item qaia_sample calls bit for bit, on every replay."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_helpers import unpack_spins
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_26477_amd as q
+    return q
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+SPECS = [  # (n, m, kind, W, R, path)
+    (42, 3, "deg3", 13, 5, "sparse_reg"),
+    (42, 4, "deg3", 7, 9, "sparse_lds"),
+    (200, 4, "deg3", 5, 32, "sparse_lds"),
+    (90, 3, "p0.1", 6, 11, "dense"),
+    (150, 4, "p0.5", 3, 40, "dense"),
+    (70, 3, "complete", 4, 8, "dense"),
+    (300, 3, "deg3", 2, 3, "sparse_lds"),
+]
+
+
+def _build(q, variant):
+    import torch
+    probs, items = [], []
+    for i, (n, m, kind, W, R, path) in enumerate(SPECS):
+        inst = wl.random_instance(n, m, kind, seed=700 + i)
+        p = q.problem_from_instance(inst)
+        c = _dev(wl.dirichlet_weights(W, m, 800 + i))
+        probs.append((inst, p, c, R, path))
+        items.append(q.BatchItem(p, c, R, path))
+    return probs, items
+
+
+@pytest.mark.parametrize("variant", ["bsb", "dsb"])
+def test_batch_matches_per_item_calls(q, variant):
+    import torch
+    probs, items = _build(q, variant)
+    s = q.make_schedule(variant, steps=300, dt=0.5, seed=91)
+    ref = []
+    for inst, p, c, R, path in probs:
+        sp, ob, _ = q.qaia_sample(p, c, R, q.make_schedule(variant, steps=300, dt=0.5, seed=91, path=path))
+        ref.append((sp.clone(), ob.clone()))
+    torch.cuda.synchronize()
+    ws = None
+    for replay in range(3):
+        for it in items:
+            it.spins.fill_(-1)
+            it.obj.fill_(-1)
+        ws = q.qaia_sample_batch(items, s, workspace=ws)
+        torch.cuda.synchronize()
+        for (inst, p, c, R, path), it, (sp, ob) in zip(probs, items, ref):
+            assert torch.equal(it.spins, sp), (replay, inst.name, path)
+            assert torch.equal(it.obj, ob), (replay, inst.name, path)
+        # eager work between replays
+        _ = q.qaia_sample(probs[0][1], probs[0][2], 2, q.make_schedule(variant, steps=10, seed=1))
+        torch.cuda.synchronize()
+    # and the cut values are exact for the returned spins
+    for (inst, p, c, R, path), it in zip(probs, items):
+        assert np.array_equal(it.obj.cpu().numpy(), oracle.cut_values(inst, unpack_spins(it.spins.cpu().numpy(), inst.n)))
+
+
+def test_batch_low_precision_dense(q):
+    import torch
+    specs = [(90, 3, "p0.1"), (150, 4, "p0.5"), (130, 3, "complete")]
+    items, refs = [], []
+    for i, (n, m, kind) in enumerate(specs):
+        inst = wl.random_instance(n, m, kind, seed=900 + i)
+        p = q.problem_from_instance(inst)
+        c = _dev(wl.dirichlet_weights(5, m, 950 + i))
+        items.append(q.BatchItem(p, c, 16, "dense"))
+        sp, ob, _ = q.qaia_sample(p, c, 16, q.make_schedule("dsb", precision="bf16", steps=200, seed=3))
+        refs.append((sp, ob))
+    q.qaia_sample_batch(items, q.make_schedule("dsb", precision="bf16", steps=200, seed=3))
+    torch.cuda.synchronize()
+    for it, (sp, ob) in zip(items, refs):
+        assert torch.equal(it.spins, sp) and torch.equal(it.obj, ob)
+
+
+def test_autotune_picks_valid_paths(q):
+    import torch
+    probs, items = _build(q, "bsb")
+    for it in items:
+        it.path = "auto"
+    s = q.make_schedule("bsb", steps=400, dt=0.5, seed=5)
+    est = q.qaia_plan_autotune(items, s, probe_steps=20)
+    print([(spec[:3], it.path, f"{e * 1e3:.2f} ms") for spec, it, e in zip(SPECS, items, est)])
+    assert all(e > 0 for e in est)
+    assert all(it.path in ("sparse_reg", "sparse_lds", "dense") for it in items)
+    # a small sparse graph never goes to the matrix cores, a 50%-dense one never to the LDS kernel
+    assert items[0].path in ("sparse_reg", "sparse_lds")
+    q.qaia_sample_batch(items, s)
+    torch.cuda.synchronize()
+    for (inst, p, c, R, path), it in zip(probs, items):
+        sp, ob, _ = q.qaia_sample(p, c, R, q.make_schedule("bsb", steps=400, dt=0.5, seed=5, path=it.path))
+        torch.cuda.synchronize()
+        assert torch.equal(it.spins, sp) and torch.equal(it.obj, ob)
