@@ -58,6 +58,111 @@ def cpu_baseline(inst, weights, R, T, budget_s=12.0):
                       f"{T} steps, fp64 dynamics + exact cuts ({el:.1f} s)"}
 
 
+def precision_form(q, wl, torch):
+    """Precision workload: dSB on a complete 2048-node, 3-objective graph, 512
+    Dirichlet weight vectors x 8 replicas (4096 matrix columns), 1000 steps,
+    FP32 vs BF16 vs FP8 coupling products (exact integer cut evaluation)."""
+    N, m, W, R, T = 2048, 3, 512, 8, 1000
+    inst = wl.random_instance(N, m, "complete", seed=3000)
+    prob = q.problem_from_instance(inst, 0)
+    c = torch.from_numpy(wl.dirichlet_weights(W, m, 3002)).cuda()
+    out = {"workload": f"complete N={N}, m={m}, {W} weight vectors x {R} replicas, T={T}, dSB dense"}
+    flops = 2 * m * N * N * W * R * T
+    for prec in ("fp32", "bf16", "fp8"):
+        s = q.make_schedule("dsb", precision=prec, steps=T, dt=0.5, seed=3003, path="dense")
+        spins, obj, ws = q.qaia_sample(prob, c, R, s)  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        q.qaia_sample(prob, c, R, s, spins=spins, obj=obj, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[prec] = {"ms": ms, "replica_steps_per_s": W * R * T / (ms * 1e-3),
+                     "matrix_TFLOPs": flops / (ms * 1e-3) / 1e12}
+    return out
+
+
+def learned_form(q, wl, torch, budget_rounds=40, ref_factor=10, max_seconds=240.0):
+    """Time to the reference hypervolume on the 42-node, 4-objective instance:
+    each round proposes 1024 weight vectors (from 65536 Dirichlet candidates),
+    samples 256 replicas x 2000 steps each (bSB, FP32), filters against the
+    archive and computes the exact hypervolume.  The reference is the
+    hypervolume of the union of fronts of uniform-Dirichlet plain runs at 10x
+    the budget."""
+    from paper_2604_26477_amd.learned import ProposerLoop, run_until
+    inst = wl.instance_42_node(4, seed=2000)
+    prob = q.problem_from_instance(inst, 0)
+    kw = dict(R=256, steps=2000, n_cand=65536, n_sel=1024)
+    t0 = time.perf_counter()
+    ref_loop = ProposerLoop(prob, learned=False, seed=777, **kw)
+    for _ in range(budget_rounds * ref_factor):
+        ref_loop.round()
+        if time.perf_counter() - t0 > max_seconds / 2:
+            break
+    ref_rounds = ref_loop.round_no
+    ref_hv = ref_loop.history[-1]["hv"]
+    out = {"workload": "42-node degree<=3, m=4; rounds of 1024 proposed weight vectors x 256 replicas "
+                       "x 2000 steps (bSB FP32) from 65536 Dirichlet candidates",
+           "reference": {"rounds": ref_rounds, "hv": str(ref_hv), "front": ref_loop.history[-1]["front"]},
+           "budget_rounds": budget_rounds}
+    for name, learned in (("plain_fp32_uniform", False), ("learned_proposer", True)):
+        loop = ProposerLoop(prob, learned=learned, seed=11, **kw)
+        rounds, secs, reached = run_until(loop, ref_hv, budget_rounds)
+        hist = loop.history
+        frac = [h["hv"] / ref_hv for h in hist]
+        def first(th):
+            for h, f in zip(hist, frac):
+                if f >= th:
+                    return h["round"]
+            return None
+        out[name] = {"reached_reference": reached, "rounds": rounds, "seconds": secs,
+                     "seconds_per_round": secs / max(rounds, 1), "final_hv_fraction": frac[-1],
+                     "rounds_to_99.9%": first(0.999), "rounds_to_99.99%": first(0.9999),
+                     "final_front": hist[-1]["front"]}
+    return out
+
+
+def batch_form(q, wl, torch, variant="bsb", precision="fp32", T=1500, W=1024, R=32, count=64):
+    """Batching workload: 64 ragged instances, each 1024 Dirichlet weight
+    vectors x 32 replicas x 1500 steps; one autotuned batched graph launch vs
+    64 per-instance qaia_sample calls on the same paths."""
+    specs = wl.ragged_batch(count)
+    items, probs = [], []
+    for n, m, kind, sd in specs:
+        inst = wl.random_instance(n, m, kind, seed=sd)
+        p = q.problem_from_instance(inst, 0)
+        c = torch.from_numpy(wl.dirichlet_weights(W, m, sd + 2)).cuda()
+        probs.append((p, c))
+        items.append(q.BatchItem(p, c, R, "auto"))
+    s = q.make_schedule(variant, precision=precision, steps=T, dt=0.5, seed=4444)
+    t0 = time.perf_counter()
+    est = q.qaia_plan_autotune(items, s, probe_steps=10)
+    tune_s = time.perf_counter() - t0
+    ws = torch.empty(q.qaia_sample_batch_workspace_bytes(items, s), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q.qaia_sample_batch(items, s, workspace=ws)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t0
+    del ws
+    t0 = time.perf_counter()
+    for (p, c), it in zip(probs, items):
+        s1 = q.make_schedule(variant, precision=precision, steps=T, dt=0.5, seed=4444, path=it.path)
+        q.qaia_sample(p, c, R, s1, spins=it.spins, obj=it.obj)
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - t0
+    paths = {}
+    for it in items:
+        paths[it.path] = paths.get(it.path, 0) + 1
+    total = count * W * R * T
+    return {"workload": f"{count} instances, N~U[42,1024], m~U{{3,4}}, class~U{{deg3,10%,50%}}, "
+                        f"{W} weight vectors x {R} replicas x {T} steps, {variant} {precision}",
+            "autotune_s": tune_s, "paths": paths, "estimated_s": float(est.sum()),
+            "batched_graph_s": batch_s, "per_instance_s": single_s,
+            "batched_replica_steps_per_s": total / batch_s, "per_instance_replica_steps_per_s": total / single_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +170,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path", default="auto")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision and learned form measurements")
+    ap.add_argument("--batch-form", action="store_true",
+                    help="also measure the 64-instance ragged batch (takes minutes in FP32)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sampler's work shards over weight vectors "
@@ -162,6 +270,16 @@ def main():
         "sampling_replica_steps_per_s": {v: rows * T / (stage[f"{v}_ms"] * 1e-3) for v in variants},
         "front_size": P, "hypervolume": str(hv),
     }
+    if not args.no_forms:
+        result["forms"] = {"precision": precision_form(q, wl, torch)}
+        lf = learned_form(q, wl, torch)
+        result["forms"]["learned"] = lf
+        if args.batch_form:
+            result["forms"]["batching"] = batch_form(q, wl, torch)
+        result["time_to_ref_hypervolume"] = {
+            "chosen_form_s": lf["learned_proposer"]["seconds"] if lf["learned_proposer"]["reached_reference"] else None,
+            "plain_fp32_s": lf["plain_fp32_uniform"]["seconds"] if lf["plain_fp32_uniform"]["reached_reference"] else None,
+        }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(inst, c_host, R, T)
     print(json.dumps(result), flush=True)

@@ -298,10 +298,14 @@ int32_t qaia_front_features(const int64_t *front, int64_t P, int32_t m, const fl
                             float *feat, void *workspace, size_t ws_bytes, void *hip_stream);
 
 int32_t qaia_topk_workspace_bytes(int64_t N, size_t *bytes);
-/* Indices (int64 [k]) of the k largest scores [N], largest first; equal
- * scores keep increasing index order. */
-int32_t qaia_topk(const float *scores, int64_t N, int64_t k, int64_t *idx, void *workspace,
-                  size_t ws_bytes, void *hip_stream);
+/* Indices (int64 [k]) of the k largest keys among N, largest first; equal
+ * keys keep increasing index order.  temperature = 0: the keys are the
+ * scores (deterministic top-k).  temperature > 0: the keys are
+ * score / temperature plus a standard Gumbel draw from the counter stream
+ * `seed`, i.e. k items sampled without replacement with probabilities
+ * proportional to exp(score / temperature). */
+int32_t qaia_topk(const float *scores, int64_t N, int64_t k, float temperature, uint64_t seed,
+                  int64_t *idx, void *workspace, size_t ws_bytes, void *hip_stream);
 
 /* labels [W] = 1 where weight row w has a sample among the kept rows of a
  * qaia_pareto_filter over [archive rows ; W*R new samples], else 0.  Because

@@ -73,7 +73,7 @@ _SIGS = {
     "qaia_front_features_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "qaia_front_features": (_i32, [_P, _i64, _i32, _P, _i64, _P, _i64, _P, _i64, _P, _P, _sz, _P]),
     "qaia_topk_workspace_bytes": (_i32, [_i64, C.POINTER(_sz)]),
-    "qaia_topk": (_i32, [_P, _i64, _i64, _P, _P, _sz, _P]),
+    "qaia_topk": (_i32, [_P, _i64, _i64, C.c_float, C.c_uint64, _P, _P, _sz, _P]),
     "qaia_new_point_labels": (_i32, [_P, _P, _i64, _i32, _i64, _P, _P]),
     "qaia_gather_rows": (_i32, [_P, _i32, _P, _P, _i64, _P, _P]),
     "qaia_sample_batch_workspace_bytes": (_i32, [_P, _i32, C.POINTER(qaia_schedule), C.POINTER(_sz)]),
@@ -382,14 +382,16 @@ def qaia_front_features(front: torch.Tensor, cands: torch.Tensor, hits: torch.Te
     return out
 
 
-def qaia_topk(scores: torch.Tensor, k: int, idx=None, workspace=None, stream=None) -> torch.Tensor:
+def qaia_topk(scores: torch.Tensor, k: int, temperature: float = 0.0, seed: int = 0, idx=None, workspace=None,
+              stream=None) -> torch.Tensor:
     N = scores.shape[0]
     b = C.c_size_t()
     _check(_lib.qaia_topk_workspace_bytes(N, C.byref(b)))
     if workspace is None or workspace.numel() < b.value:
         workspace = torch.empty(b.value, dtype=torch.uint8, device=scores.device)
     idx = _dev_tensor(idx, torch.int64, (max(k, 1),), scores.device)
-    _check(_lib.qaia_topk(_ptr(scores), N, k, _ptr(idx), _ptr(workspace), workspace.numel(), _stream(stream)))
+    _check(_lib.qaia_topk(_ptr(scores), N, k, temperature, seed & (2**64 - 1), _ptr(idx), _ptr(workspace),
+                          workspace.numel(), _stream(stream)))
     return idx[:k]
 
 

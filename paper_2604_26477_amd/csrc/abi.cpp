@@ -378,11 +378,11 @@ int32_t qaia_topk_workspace_bytes(int64_t N, size_t *bytes) {
     });
 }
 
-int32_t qaia_topk(const float *scores, int64_t N, int64_t k, int64_t *idx, void *workspace, size_t ws_bytes,
-                  void *hip_stream) {
+int32_t qaia_topk(const float *scores, int64_t N, int64_t k, float temperature, uint64_t seed, int64_t *idx,
+                  void *workspace, size_t ws_bytes, void *hip_stream) {
     return guarded([&]() -> int32_t {
         QAIA_CHECK(scores && idx && workspace, QAIA_INVALID_ARGUMENT, "null buffer");
-        launch_topk(scores, N, k, idx, workspace, ws_bytes, (hipStream_t)hip_stream);
+        launch_topk(scores, N, k, temperature, seed, idx, workspace, ws_bytes, (hipStream_t)hip_stream);
         return QAIA_OK;
     });
 }

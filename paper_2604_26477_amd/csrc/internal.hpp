@@ -201,8 +201,8 @@ void launch_features(const int64_t *front, int64_t Pn, int m, const float *cands
                      const float *hits, int64_t Hn, const float *misses, int64_t Mn, float *feat,
                      void *ws, size_t ws_bytes, hipStream_t st);
 size_t topk_ws_bytes(int64_t N);
-void launch_topk(const float *scores, int64_t N, int64_t k, int64_t *idx_out, void *ws, size_t ws_bytes,
-                 hipStream_t st);
+void launch_topk(const float *scores, int64_t N, int64_t k, float temperature, uint64_t seed, int64_t *idx_out,
+                 void *ws, size_t ws_bytes, hipStream_t st);
 void launch_labels(const int64_t *keep, const int64_t *num_keep, int64_t archive, int R, int64_t W,
                    float *labels, hipStream_t st);
 void launch_gather_rows(const uint32_t *src, int width, const int64_t *idx, const int64_t *count,

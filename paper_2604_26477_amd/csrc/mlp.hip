@@ -302,6 +302,21 @@ __global__ void features_kernel(const float *__restrict__ yh, int64_t Pn, int m,
 
 // ---------------------------------------------------------------- selection and labels
 
+// Gumbel-perturbed keys: the top k of score / tau + G (G standard Gumbel from
+// the counter stream) is a sample of k items without replacement with
+// probabilities proportional to exp(score / tau).
+__global__ void gumbel_keys_kernel(const float *__restrict__ scores, int64_t N, float inv_tau, uint64_t seed,
+                                   float *__restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i >= N) return;
+    uint64_t z = seed + ((uint64_t)i + 1ull) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    const float u = ((float)(uint32_t)(z >> 40) + 0.5f) * 0x1p-24f;  // (0, 1)
+    keys[i] = scores[i] * inv_tau - logf(-logf(u));
+}
+
 __global__ void iota64_kernel(int64_t *p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (i < n) p[i] = i;
@@ -428,17 +443,21 @@ void launch_features(const int64_t *front, int64_t Pn, int m, const float *cands
 
 size_t topk_ws_bytes(int64_t N) {
     const size_t n = (size_t)std::max<int64_t>(N, 1);
-    return align256(sizeof(float) * n) + 2 * align256(sizeof(int64_t) * n) + align256(topk_temp(N));
+    return 2 * align256(sizeof(float) * n) + 2 * align256(sizeof(int64_t) * n) + align256(topk_temp(N));
 }
 
-void launch_topk(const float *scores, int64_t N, int64_t k, int64_t *idx_out, void *ws, size_t ws_bytes,
-                 hipStream_t st) {
+void launch_topk(const float *scores, int64_t N, int64_t k, float temperature, uint64_t seed, int64_t *idx_out,
+                 void *ws, size_t ws_bytes, hipStream_t st) {
     QAIA_CHECK(N >= 1 && N < (int64_t(1) << 31), QAIA_INVALID_ARGUMENT, "N must be in [1, 2^31)");
     QAIA_CHECK(k >= 0 && k <= N, QAIA_INVALID_ARGUMENT, "k must be in [0, N]");
     QAIA_CHECK(ws_bytes >= topk_ws_bytes(N), QAIA_WORKSPACE_TOO_SMALL, "top-k workspace too small");
+    QAIA_CHECK(temperature >= 0.0f && std::isfinite(temperature), QAIA_INVALID_ARGUMENT,
+               "temperature must be finite and >= 0");
     char *b = (char *)ws;
     size_t off = 0;
     float *keys = (float *)(b + off);
+    off += align256(sizeof(float) * (size_t)N);
+    float *pert = (float *)(b + off);
     off += align256(sizeof(float) * (size_t)N);
     int64_t *iota = (int64_t *)(b + off);
     off += align256(sizeof(int64_t) * (size_t)N);
@@ -448,7 +467,13 @@ void launch_topk(const float *scores, int64_t N, int64_t k, int64_t *idx_out, vo
     hipLaunchKernelGGL(iota64_kernel, dim3(blocks_for(N)), dim3(kB), 0, st, iota, N);
     QAIA_HIP(hipGetLastError());
     // stable: equal scores keep increasing index order
-    QAIA_HIP(hipcub::DeviceRadixSort::SortPairsDescending(b + off, tb, scores, keys, iota, sorted, (int)N, 0,
+    const float *src = scores;
+    if (temperature > 0.0f) {
+        hipLaunchKernelGGL(gumbel_keys_kernel, dim3(blocks_for(N)), dim3(kB), 0, st, scores, N, 1.0f / temperature,
+                           seed, pert);
+        src = pert;
+    }
+    QAIA_HIP(hipcub::DeviceRadixSort::SortPairsDescending(b + off, tb, src, keys, iota, sorted, (int)N, 0,
                                                           32, st));
     if (k > 0) QAIA_HIP(hipMemcpyAsync(idx_out, sorted, sizeof(int64_t) * (size_t)k, hipMemcpyDeviceToDevice, st));
 }

@@ -2,14 +2,18 @@
 
 Each round:
   1. draw candidate weight vectors c ~ Dirichlet(1, ..., 1) (host, seeded);
-  2. learned: score them with the MLP on (c, eight front-gap features) and keep
-     the top (1 - explore) * n_sel plus explore * n_sel uniformly chosen
-     others; baseline: keep n_sel candidates uniformly;
+  2. learned: score them with the MLP on (c, eight front-gap features) and
+     draw (1 - explore) * n_sel of them without replacement with
+     probabilities proportional to exp(score / temperature) (Gumbel top-k),
+     plus explore * n_sel uniformly chosen others; baseline: keep n_sel
+     candidates uniformly;
   3. sample every kept vector with R replicas (qaia_sample);
   4. filter [archive ; new samples] (qaia_pareto_filter) and label each kept
      vector 1 iff it produced a vector that enters the front and was not in
      the archive (qaia_new_point_labels);
-  5. learned: one Adam step on the mean binary cross-entropy of those labels;
+  5. learned: the (input row, label) pairs join a ring buffer of the last
+     rounds, and a few Adam steps on minibatches drawn from it minimise the
+     mean binary cross-entropy;
   6. the new archive is the filtered set; its exact hypervolume (host) judges
      progress.
 The driver only orchestrates library calls; tensors are device memory.
@@ -46,7 +50,8 @@ def _to_bf16_bits(a: np.ndarray) -> np.ndarray:
 class ProposerLoop:
     def __init__(self, prob, R=256, steps=2000, variant="bsb", n_cand=65536, n_sel=1024,
                  explore=0.1, lr=1e-3, learned=True, seed=0, archive_cap=1 << 20, ref=None,
-                 precision="fp32", path="auto"):
+                 precision="fp32", path="auto", temperature=1.0, replay_rounds=8, train_steps=16,
+                 batch=1024):
         self.prob, self.m, self.R = prob, prob.m, R
         self.n_cand, self.n_sel, self.explore, self.lr = n_cand, n_sel, explore, lr
         self.learned = learned
@@ -78,6 +83,12 @@ class ProposerLoop:
         self.m1 = torch.zeros(npar, dtype=torch.float32, device=dev)
         self.m2 = torch.zeros(npar, dtype=torch.float32, device=dev)
         self.adam_step = 0
+        self.temperature, self.train_steps, self.batch = temperature, train_steps, batch
+        self.replay_cap = replay_rounds * n_sel
+        self.replay_X = torch.zeros((self.replay_cap, self.D), dtype=torch.float32, device=dev)
+        self.replay_y = torch.zeros(self.replay_cap, dtype=torch.float32, device=dev)
+        self.replay_n = 0
+        self.replay_slot = 0
         self.hits = torch.zeros((0, self.m), dtype=torch.float32, device=dev)
         self.misses = torch.zeros((0, self.m), dtype=torch.float32, device=dev)
         self.round_no = 0
@@ -96,7 +107,8 @@ class ProposerLoop:
         X = qaia_front_features(front, cands, self.hits, self.misses)
         n_top = self.n_sel - int(round(self.explore * self.n_sel))
         scores = qaia_mlp_forward(self.params, self.D, X)
-        top = qaia_topk(scores, n_top)
+        top = qaia_topk(scores, n_top, temperature=self.temperature,
+                        seed=self.seed * 1000003 + self.round_no)
         # exploration: uniformly chosen candidates outside the top set
         top_h = top.cpu().numpy()
         rest = np.setdiff1d(np.arange(self.n_cand), top_h, assume_unique=False)
@@ -129,11 +141,23 @@ class ProposerLoop:
         self.pool_spins[:P].copy_(self.tmp_spins[:P])
         self.A = P
         if self.learned:
-            xs = torch.empty((self.n_sel, self.D), dtype=torch.float32, device=dev)
-            qaia_gather_rows(X, pick, count, xs, self.n_sel)
-            grad = qaia_mlp_backward(self.params, self.D, xs, labels)
-            self.adam_step += 1
-            qaia_mlp_adam(self.master, self.params, self.m1, self.m2, grad, self.adam_step, lr=self.lr)
+            # this round's rows and labels enter the ring buffer
+            lo = self.replay_slot * self.n_sel
+            qaia_gather_rows(X, pick, count, self.replay_X[lo:lo + self.n_sel], self.n_sel)
+            self.replay_y[lo:lo + self.n_sel].copy_(labels)
+            self.replay_slot = (self.replay_slot + 1) % (self.replay_cap // self.n_sel)
+            self.replay_n = min(self.replay_n + self.n_sel, self.replay_cap)
+            B = min(self.batch, self.replay_n)
+            xb = torch.empty((B, self.D), dtype=torch.float32, device=dev)
+            yb = torch.empty(B, dtype=torch.float32, device=dev)
+            nb = torch.tensor([B], dtype=torch.int64, device=dev)
+            for _ in range(self.train_steps):
+                idx = torch.from_numpy(self.rng.choice(self.replay_n, size=B, replace=False).astype(np.int64)).to(dev)
+                qaia_gather_rows(self.replay_X, idx, nb, xb, B)
+                qaia_gather_rows(self.replay_y, idx, nb, yb, B)
+                grad = qaia_mlp_backward(self.params, self.D, xb, yb)
+                self.adam_step += 1
+                qaia_mlp_adam(self.master, self.params, self.m1, self.m2, grad, self.adam_step, lr=self.lr)
             lab = labels.cpu().numpy() > 0.5
             w_h = w_sel.cpu().numpy()
             self.hits = torch.from_numpy(np.ascontiguousarray(w_h[lab])).to(dev)

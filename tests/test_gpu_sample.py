@@ -193,3 +193,30 @@ def test_edge_cases_tiny_graphs(q):
     _, obj0, _ = q.qaia_sample(prob, torch.zeros((0, 2), dtype=torch.float32, device="cuda"), 2,
                                q.make_schedule(steps=10))
     assert obj0.numel() == 0
+
+
+# ---------------------------------------------------------------- noise injection (Eq. 10)
+
+def test_noise_injected_trace_parity(q):
+    """NI-SB on the generic kernel follows the FP64 oracle (same counter-based
+    Gaussian stream) within 1e-5 over the first 50 steps; alpha = 0 is plain SB."""
+    inst = wl.random_instance(12, 3, "deg3", seed=41, num_edges=16)
+    c = wl.dirichlet_weights(6, 3, 42)
+    prob = q.problem_from_instance(inst)
+    s = q.make_schedule("bsb", steps=1000, dt=0.5, seed=43, noise_alpha=0.15)
+    _, _, _, tr = q.qaia_sample_trace(prob, _dev(c), 8, s, 50)
+    _, ref = oracle.sb_sample(inst, c, 8, 1000, "bsb", dt=0.5, seed=43, alpha=0.15, trace_steps=50)
+    err = rel_inf_error(tr.cpu().numpy(), ref)
+    print(f"noise-injected: max rel err over 50 steps {err.max():.3e}")
+    assert err.max() <= 1e-5
+    plain = q.make_schedule("bsb", steps=1000, dt=0.5, seed=43)
+    _, _, _, tr0 = q.qaia_sample_trace(prob, _dev(c), 8, plain, 50)
+    assert not np.array_equal(tr0.cpu().numpy(), tr.cpu().numpy())
+
+
+def test_noise_injected_sampling_exact_cuts(q):
+    inst = wl.workload_instance("c1_bsb_n42_m3")
+    c = wl.workload_weights("c1_bsb_n42_m3", count=40)
+    prob = q.problem_from_instance(inst)
+    spins, obj, _ = _sample(q, prob, c, 16, steps=1000, seed=9, noise_alpha=0.15)
+    assert np.array_equal(obj, oracle.cut_values(inst, unpack_spins(spins, inst.n)))

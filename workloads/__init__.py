@@ -209,3 +209,18 @@ def workload_instance(name: str) -> Instance:
 def workload_weights(name: str, count: int | None = None) -> np.ndarray:
     cfg = WORKLOADS[name]
     return dirichlet_weights(cfg["W"] if count is None else count, cfg["m"], cfg["seed"] + 2)
+
+
+def ragged_batch(count: int = 64, seed: int = 4000):
+    """The batching workload: ``count`` instances with N uniform on [42, 1024],
+    m uniform on {3, 4} and the edge class uniform on {degree-3 sparse, 10 %,
+    50 % density}; instance i uses seed ``seed + 10 i`` (graph), ``+1``
+    (weights), ``+2`` (its 1024 Dirichlet weight vectors)."""
+    rng = _rng(seed)
+    specs = []
+    for i in range(count):
+        n = int(rng.integers(42, 1025))
+        m = int(rng.integers(3, 5))
+        kind = ("deg3", "p0.1", "p0.5")[int(rng.integers(0, 3))]
+        specs.append((n, m, kind, seed + 10 * i))
+    return specs
