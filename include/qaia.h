@@ -61,7 +61,8 @@ extern "C" {
 #define QAIA_PATH_AUTO 0
 #define QAIA_PATH_SPARSE_REG 1 /* per-graph generated kernel, one replica per lane, state in registers */
 #define QAIA_PATH_SPARSE_LDS 2 /* generic kernel, one spin per lane, state and adjacency in LDS */
-#define QAIA_PATH_DENSE 3      /* stacked per-objective matrix product on the matrix cores */
+#define QAIA_PATH_DENSE 3      /* stacked per-objective matrix product on the matrix cores, 64 x 128 tiles */
+#define QAIA_PATH_DENSE_STAGED 4 /* as QAIA_PATH_DENSE with 128 x 128 tiles staged through LDS */
 
 typedef struct qaia_problem qaia_problem;
 

@@ -41,15 +41,15 @@ void check_schedule(const Problem &p, const qaia_schedule *s) {
                "init_amp must be finite and >= 0");
     QAIA_CHECK(std::isfinite(s->noise_alpha) && s->noise_alpha >= 0.0f, QAIA_INVALID_ARGUMENT,
                "noise_alpha must be finite and >= 0");
-    QAIA_CHECK(s->path >= QAIA_PATH_AUTO && s->path <= QAIA_PATH_DENSE, QAIA_INVALID_ARGUMENT,
+    QAIA_CHECK(s->path >= QAIA_PATH_AUTO && s->path <= QAIA_PATH_DENSE_STAGED, QAIA_INVALID_ARGUMENT,
                "unknown path");
     if (s->precision != QAIA_FP32) {
         QAIA_CHECK(s->variant == QAIA_DSB, QAIA_UNSUPPORTED,
                    "reduced precision needs discrete SB (its phi(x) = sgn(x) is exact)");
-        QAIA_CHECK(s->path == QAIA_PATH_AUTO || s->path == QAIA_PATH_DENSE, QAIA_UNSUPPORTED,
+        QAIA_CHECK(s->path == QAIA_PATH_AUTO || is_dense_path(s->path), QAIA_UNSUPPORTED,
                    "reduced precision runs on the dense path only");
     }
-    if (s->path == QAIA_PATH_DENSE)
+    if (is_dense_path(s->path))
         QAIA_CHECK(s->noise_alpha == 0.0f, QAIA_UNSUPPORTED, "the dense path runs plain SB only");
     (void)p;
 }
@@ -58,15 +58,15 @@ void check_schedule(const Problem &p, const qaia_schedule *s) {
 int plan_path(const Problem &p, const qaia_schedule &s, bool tracing) {
     (void)tracing;
     if (s.path != QAIA_PATH_AUTO) return s.path;
-    if (s.precision != QAIA_FP32) return QAIA_PATH_DENSE;
+    if (s.precision != QAIA_FP32) return QAIA_PATH_DENSE_STAGED;
     if (p.jit[s.variant] != nullptr && s.noise_alpha == 0.0f) return QAIA_PATH_SPARSE_REG;
     if (sparse_lds_supported(p, nullptr)) return QAIA_PATH_SPARSE_LDS;
-    return QAIA_PATH_DENSE;
+    return QAIA_PATH_DENSE_STAGED;
 }
 
 WsLayout full_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, int path) {
-    WsLayout L = sample_ws_layout(p, W, R, s, path != QAIA_PATH_DENSE);
-    if (path == QAIA_PATH_DENSE) {
+    WsLayout L = sample_ws_layout(p, W, R, s, !is_dense_path(path));
+    if (is_dense_path(path)) {
         std::string why;
         QAIA_CHECK(dense_supported(p, &why), QAIA_UNSUPPORTED, "dense path: " + why);
         dense_ws_extend(p, W, R, s, L);
@@ -96,9 +96,9 @@ int32_t sample_impl(const qaia_problem *pp, const float *weights, int64_t W, int
     DeviceGuard g(p.device);
     launch_prep(p, weights, W, *s, ws, L, st);
     if (rows == 0) return QAIA_OK;
-    if (path == QAIA_PATH_DENSE)
+    if (is_dense_path(path))
         launch_dense(p, weights, W, R, *s, ws, L, spins, obj, trace_steps ? trace : nullptr,
-                     trace_steps, st);
+                     trace_steps, path == QAIA_PATH_DENSE_STAGED, st);
     else if (path == QAIA_PATH_SPARSE_REG)
         launch_sparse_reg(p, s->variant, W, R, *s, ws, L, spins, obj, trace_steps ? trace : nullptr,
                           trace_steps, st);

@@ -35,10 +35,10 @@ struct ItemPlan {
 };
 
 int default_path(const Problem &p, const qaia_schedule &s) {
-    if (s.precision != QAIA_FP32) return QAIA_PATH_DENSE;
+    if (s.precision != QAIA_FP32) return QAIA_PATH_DENSE_STAGED;
     if (p.jit[s.variant] != nullptr && s.noise_alpha == 0.0f) return QAIA_PATH_SPARSE_REG;
     if (sparse_lds_supported(p, nullptr)) return QAIA_PATH_SPARSE_LDS;
-    return QAIA_PATH_DENSE;
+    return QAIA_PATH_DENSE_STAGED;
 }
 
 void check_path(const Problem &p, const qaia_schedule &s, int path) {
@@ -50,7 +50,7 @@ void check_path(const Problem &p, const qaia_schedule &s, int path) {
     } else if (path == QAIA_PATH_SPARSE_LDS) {
         QAIA_CHECK(sparse_lds_supported(p, &why), QAIA_UNSUPPORTED, "sparse LDS path: " + why);
         QAIA_CHECK(s.precision == QAIA_FP32, QAIA_UNSUPPORTED, "sparse paths run FP32");
-    } else if (path == QAIA_PATH_DENSE) {
+    } else if (is_dense_path(path)) {
         QAIA_CHECK(dense_supported(p, &why), QAIA_UNSUPPORTED, "dense path: " + why);
         QAIA_CHECK(p.m <= 4, QAIA_UNSUPPORTED, "dense path supports m <= 4");
         QAIA_CHECK(s.noise_alpha == 0.0f, QAIA_UNSUPPORTED, "dense path runs plain SB");
@@ -78,8 +78,8 @@ BatchLayout batch_layout(const qaia_batch_item *items, int32_t count, const qaia
                    "item " + std::to_string(i) + ": null buffer");
         const int path = it.path == QAIA_PATH_AUTO ? default_path(p, s) : it.path;
         check_path(p, s, path);
-        ItemPlan ip{&p, path, sample_ws_layout(p, it.W, it.R, s, path != QAIA_PATH_DENSE), off};
-        if (path == QAIA_PATH_DENSE) {
+        ItemPlan ip{&p, path, sample_ws_layout(p, it.W, it.R, s, !is_dense_path(path)), off};
+        if (is_dense_path(path)) {
             dense_ws_extend(p, it.W, it.R, s, ip.L);
             ++B.n_dense;
         } else if (path == QAIA_PATH_SPARSE_LDS) {
@@ -91,7 +91,7 @@ BatchLayout batch_layout(const qaia_batch_item *items, int32_t count, const qaia
     B.jobs_off = off;
     off += align256(sizeof(SparseJob) * (size_t)std::max(B.n_sparse, 1));
     off += align256(sizeof(DenseJob) * (size_t)std::max(B.n_dense, 1));
-    off += 2 * align256(sizeof(int64_t) * (size_t)(count + 1));
+    off += 3 * align256(sizeof(int64_t) * (size_t)(count + 1));
     B.total = off;
     return B;
 }
@@ -163,8 +163,9 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
     std::vector<int64_t> sstart(1, 0);
     int maxdeg = 4, npt = 1;
     size_t shmem = 0;
-    std::vector<DenseJob> djobs;
-    std::vector<int64_t> dstart(1, 0);
+    // dense jobs grouped by tile kind: [0] 64 x 128 tiles, [1] staged 128 x 128 tiles
+    std::vector<DenseJob> djobs[2];
+    std::vector<int64_t> dstart[2] = {std::vector<int64_t>(1, 0), std::vector<int64_t>(1, 0)};
     for (int i = 0; i < count; ++i) {
         const ItemPlan &ip = B.items[i];
         const qaia_batch_item &it = items[i];
@@ -177,17 +178,21 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
             maxdeg = std::max(maxdeg, sh.maxdeg);
             npt = std::max(npt, sh.npt);
             shmem = std::max(shmem, sh.shmem);
-        } else if (ip.path == QAIA_PATH_DENSE) {
-            DenseJob j = dense_job(*ip.p, it.W, it.R, s, iws, ip.L, nullptr, 0);
-            djobs.push_back(j);
-            dstart.push_back(dstart.back() + (int64_t)j.tiles_x * j.tiles_y);
+        } else if (is_dense_path(ip.path)) {
+            const int g = ip.path == QAIA_PATH_DENSE_STAGED ? 1 : 0;
+            DenseJob j = dense_job(*ip.p, it.W, it.R, s, iws, ip.L, nullptr, 0, g == 1);
+            djobs[g].push_back(j);
+            dstart[g].push_back(dstart[g].back() + (int64_t)j.tiles_x * j.tiles_y);
         }
     }
     char *jobs = base + B.jobs_off;
     SparseJob *d_sjobs = (SparseJob *)jobs;
     DenseJob *d_djobs = (DenseJob *)(jobs + align256(sizeof(SparseJob) * (size_t)std::max(B.n_sparse, 1)));
     int64_t *d_sstart = (int64_t *)((char *)d_djobs + align256(sizeof(DenseJob) * (size_t)std::max(B.n_dense, 1)));
-    int64_t *d_dstart = (int64_t *)((char *)d_sstart + align256(sizeof(int64_t) * (size_t)(count + 1)));
+    DenseJob *d_djobs_g[2] = {d_djobs, d_djobs + djobs[0].size()};
+    int64_t *d_dstart_g[2];
+    d_dstart_g[0] = (int64_t *)((char *)d_sstart + align256(sizeof(int64_t) * (size_t)(count + 1)));
+    d_dstart_g[1] = (int64_t *)((char *)d_dstart_g[0] + align256(sizeof(int64_t) * (size_t)(count + 1)));
 
     Streams ps = private_streams(device);
     hipEvent_t ev_start, ev_fork, ev_join, ev_done;
@@ -203,10 +208,13 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
         QAIA_HIP(hipMemcpyAsync(d_sjobs, sjobs.data(), sizeof(SparseJob) * sjobs.size(), hipMemcpyHostToDevice, ps.a));
         QAIA_HIP(hipMemcpyAsync(d_sstart, sstart.data(), sizeof(int64_t) * sstart.size(), hipMemcpyHostToDevice, ps.a));
     }
-    if (!djobs.empty()) {
-        QAIA_HIP(hipMemcpyAsync(d_djobs, djobs.data(), sizeof(DenseJob) * djobs.size(), hipMemcpyHostToDevice, ps.a));
-        QAIA_HIP(hipMemcpyAsync(d_dstart, dstart.data(), sizeof(int64_t) * dstart.size(), hipMemcpyHostToDevice, ps.a));
-    }
+    for (int g = 0; g < 2; ++g)
+        if (!djobs[g].empty()) {
+            QAIA_HIP(hipMemcpyAsync(d_djobs_g[g], djobs[g].data(), sizeof(DenseJob) * djobs[g].size(),
+                                    hipMemcpyHostToDevice, ps.a));
+            QAIA_HIP(hipMemcpyAsync(d_dstart_g[g], dstart[g].data(), sizeof(int64_t) * dstart[g].size(),
+                                    hipMemcpyHostToDevice, ps.a));
+        }
     // the host vectors above are released when this call returns
     QAIA_HIP(hipStreamSynchronize(ps.a));
 
@@ -232,23 +240,31 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
         }
         QAIA_HIP(hipEventRecord(ev_join, ps.b));
         // branch B: dense items
-        if (!djobs.empty()) {
-            int di = 0;
+        if (!djobs[0].empty() || !djobs[1].empty()) {
+            int di[2] = {0, 0};
             for (int i = 0; i < count; ++i) {
                 const ItemPlan &ip = B.items[i];
                 const qaia_batch_item &it = items[i];
-                if (ip.path == QAIA_PATH_DENSE && it.W * it.R > 0)
-                    launch_dense_setup(*ip.p, it.weights, it.R, s, base + ip.base, ip.L, djobs[di++], ps.a);
+                if (is_dense_path(ip.path) && it.W * it.R > 0) {
+                    const int g = ip.path == QAIA_PATH_DENSE_STAGED ? 1 : 0;
+                    launch_dense_setup(*ip.p, it.weights, it.R, s, base + ip.base, ip.L, djobs[g][di[g]++], ps.a);
+                }
             }
             for (int t = 0; t < s.steps; ++t)
-                launch_dense_batch_step(s.precision, dsb, d_djobs, (int)djobs.size(), d_dstart, dstart.back(), t, ps.a);
+                for (int g = 0; g < 2; ++g)
+                    if (!djobs[g].empty())
+                        launch_dense_batch_step(s.precision, dsb, g == 1, d_djobs_g[g], (int)djobs[g].size(),
+                                                d_dstart_g[g], dstart[g].back(), t, ps.a);
             QAIA_HIP(hipGetLastError());
-            di = 0;
+            di[0] = di[1] = 0;
             for (int i = 0; i < count; ++i) {
                 const ItemPlan &ip = B.items[i];
                 const qaia_batch_item &it = items[i];
-                if (ip.path == QAIA_PATH_DENSE && it.W * it.R > 0)
-                    launch_dense_finish(*ip.p, it.R, s, base + ip.base, ip.L, djobs[di++], it.spins, it.obj, ps.a);
+                if (is_dense_path(ip.path) && it.W * it.R > 0) {
+                    const int g = ip.path == QAIA_PATH_DENSE_STAGED ? 1 : 0;
+                    launch_dense_finish(*ip.p, it.R, s, base + ip.base, ip.L, djobs[g][di[g]++], it.spins, it.obj,
+                                        ps.a);
+                }
             }
         }
         QAIA_HIP(hipStreamWaitEvent(ps.a, ev_join, 0));
@@ -293,20 +309,21 @@ void autotune(qaia_batch_item *items, int32_t count, const qaia_schedule &s, int
         DeviceGuard g(p.device);
         double best = 1e300;
         int best_path = default_path(p, s);
-        for (int path : {QAIA_PATH_SPARSE_REG, QAIA_PATH_SPARSE_LDS, QAIA_PATH_DENSE}) {
+        for (int path : {QAIA_PATH_SPARSE_REG, QAIA_PATH_SPARSE_LDS, QAIA_PATH_DENSE, QAIA_PATH_DENSE_STAGED}) {
             try {
                 check_path(p, s, path);
             } catch (const Error &) {
                 continue;
             }
-            WsLayout L = sample_ws_layout(p, it.W, it.R, ps, path != QAIA_PATH_DENSE);
-            if (path == QAIA_PATH_DENSE) dense_ws_extend(p, it.W, it.R, ps, L);
+            WsLayout L = sample_ws_layout(p, it.W, it.R, ps, !is_dense_path(path));
+            if (is_dense_path(path)) dense_ws_extend(p, it.W, it.R, ps, L);
             if (L.total > ws_bytes) continue;
             if (it.W * it.R == 0) break;
             QAIA_HIP(hipEventRecord(e0, st));
             launch_prep(p, it.weights, it.W, ps, ws, L, st);
-            if (path == QAIA_PATH_DENSE)
-                launch_dense(p, it.weights, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0, st);
+            if (is_dense_path(path))
+                launch_dense(p, it.weights, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0,
+                             path == QAIA_PATH_DENSE_STAGED, st);
             else if (path == QAIA_PATH_SPARSE_REG)
                 launch_sparse_reg(p, s.variant, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0, st);
             else
@@ -335,14 +352,14 @@ size_t autotune_ws_bytes(const qaia_batch_item *items, int32_t count, const qaia
     for (int i = 0; i < count; ++i) {
         QAIA_CHECK(items[i].problem != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
         const Problem &p = *reinterpret_cast<const Problem *>(items[i].problem);
-        for (int path : {QAIA_PATH_SPARSE_REG, QAIA_PATH_SPARSE_LDS, QAIA_PATH_DENSE}) {
+        for (int path : {QAIA_PATH_SPARSE_REG, QAIA_PATH_SPARSE_LDS, QAIA_PATH_DENSE, QAIA_PATH_DENSE_STAGED}) {
             try {
                 check_path(p, s, path);
             } catch (const Error &) {
                 continue;
             }
-            WsLayout L = sample_ws_layout(p, items[i].W, items[i].R, ps, path != QAIA_PATH_DENSE);
-            if (path == QAIA_PATH_DENSE) dense_ws_extend(p, items[i].W, items[i].R, ps, L);
+            WsLayout L = sample_ws_layout(p, items[i].W, items[i].R, ps, !is_dense_path(path));
+            if (is_dense_path(path)) dense_ws_extend(p, items[i].W, items[i].R, ps, L);
             need = std::max(need, L.total);
         }
     }

@@ -211,6 +211,242 @@ __global__ __launch_bounds__(kDB) void dense_batch_step_kernel(const DenseJob *_
     dense_step_body<PREC, 4, DSB>(j, t, (int)(local % j.tiles_x), (int)(local / j.tiles_x));
 }
 
+// ---------------------------------------------------------------------------
+// Staged tile: a 256-thread block owns 128 spins x 128 columns; wave (wr, wc)
+// owns 64 x 64 (2 x 2 accumulators per objective).  Each 64-byte k-chunk of
+// the block's J rows (all objectives) and Phi columns is copied to LDS once
+// and read by the two waves that share it; the next chunk's global loads are
+// in flight while the current chunk's MFMAs run.
+constexpr int kT2 = 128;          // tile height and width
+constexpr int kChunkB = 64;       // bytes of k per row per chunk
+constexpr int kPitchB = 80;       // LDS row pitch (bytes), padded against bank conflicts
+
+template <int PREC, int MT>
+__device__ __forceinline__ void mma_tile_staged(const void *Jv, const void *phiv, int Np_, int m, int row0,
+                                                int col0, int wr, int wc, int half, int lr,
+                                                f16v (&acc)[MT][2][2], char *lds) {
+    typedef typename PrecInfo<PREC>::T T;
+    constexpr int ES = sizeof(T);
+    constexpr int KCE = kChunkB / ES;  // k elements per chunk
+    constexpr int M = MT;
+    const size_t Np = (size_t)Np_;
+    const char *J = (const char *)Jv;
+    const char *phi = (const char *)phiv;
+    char *As = lds;                         // [M][128][pitch]
+    char *Bs = lds + M * kT2 * kPitchB;     // [128][pitch]
+    const int tid = threadIdx.x;
+    // 16-byte pieces: A has M*128 rows x 4 pieces, B 128 rows x 4 pieces
+    constexpr int A_PER = M * kT2 * 4 / kDB, B_PER = kT2 * 4 / kDB;
+    uint4 ra[A_PER], rb[B_PER];
+    auto load = [&](int k0) {  // k0 in elements
+#pragma unroll
+        for (int q = 0; q < A_PER; ++q) {
+            const int piece = q * kDB + tid, row = piece >> 2, part = piece & 3;
+            const int k = row / kT2, r = row % kT2;
+            ra[q] = k < m ? *(const uint4 *)(J + (((size_t)k * Np + row0 + r) * Np + k0) * ES + part * 16)
+                          : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < B_PER; ++q) {
+            const int piece = q * kDB + tid, row = piece >> 2, part = piece & 3;
+            rb[q] = *(const uint4 *)(phi + ((size_t)(col0 + row) * Np + k0) * ES + part * 16);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < A_PER; ++q) {
+            const int piece = q * kDB + tid, row = piece >> 2, part = piece & 3;
+            *(uint4 *)(As + row * kPitchB + part * 16) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < B_PER; ++q) {
+            const int piece = q * kDB + tid, row = piece >> 2, part = piece & 3;
+            *(uint4 *)(Bs + row * kPitchB + part * 16) = rb[q];
+        }
+    };
+    load(0);
+    store();
+    __syncthreads();
+    for (int k0 = 0; k0 < Np_; k0 += KCE) {
+        const bool more = k0 + KCE < Np_;
+        if (more) load(k0 + KCE);
+        if constexpr (PREC == QAIA_FP32) {
+#pragma unroll
+            for (int g = 0; g < KCE / 8; ++g) {  // k-groups of 8: lane half h holds k = 8g + 4h + 0..3
+                float4 av[M][2], bv[2];
+#pragma unroll
+                for (int k = 0; k < M; ++k)
+#pragma unroll
+                    for (int r2 = 0; r2 < 2; ++r2)
+                        av[k][r2] = *(const float4 *)(As + ((k * kT2) + wr * 64 + r2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+#pragma unroll
+                for (int c2 = 0; c2 < 2; ++c2)
+                    bv[c2] = *(const float4 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+#pragma unroll
+                for (int k = 0; k < M; ++k)
+#pragma unroll
+                    for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+                        for (int c2 = 0; c2 < 2; ++c2) {
+                            if (k >= m) continue;
+                            f16v &a = acc[k][r2][c2];
+                            a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].x, bv[c2].x, a, 0, 0, 0);
+                            a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].y, bv[c2].y, a, 0, 0, 0);
+                            a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].z, bv[c2].z, a, 0, 0, 0);
+                            a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].w, bv[c2].w, a, 0, 0, 0);
+                        }
+            }
+        } else if constexpr (PREC == QAIA_BF16) {
+#pragma unroll
+            for (int g = 0; g < KCE / 16; ++g) {  // lane half h holds k = 16g + 8h + 0..7
+                bf16x8 av[M][2], bv[2];
+#pragma unroll
+                for (int k = 0; k < M; ++k)
+#pragma unroll
+                    for (int r2 = 0; r2 < 2; ++r2)
+                        av[k][r2] = *(const bf16x8 *)(As + ((k * kT2) + wr * 64 + r2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+#pragma unroll
+                for (int c2 = 0; c2 < 2; ++c2)
+                    bv[c2] = *(const bf16x8 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+#pragma unroll
+                for (int k = 0; k < M; ++k)
+#pragma unroll
+                    for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+                        for (int c2 = 0; c2 < 2; ++c2)
+                            if (k < m)
+                                acc[k][r2][c2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[k][r2], bv[c2], acc[k][r2][c2], 0, 0, 0);
+            }
+        } else {
+            // one 32x32x64 step per chunk: lane half h holds k = 32h + 0..31
+            i32x8 av[M][2], bv[2];
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+                for (int r2 = 0; r2 < 2; ++r2)
+                    av[k][r2] = *(const i32x8 *)(As + ((k * kT2) + wr * 64 + r2 * 32 + lr) * kPitchB + half * 32);
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+                bv[c2] = *(const i32x8 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + half * 32);
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+                for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2)
+                        if (k < m)
+                            acc[k][r2][c2] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                av[k][r2], bv[c2], acc[k][r2][c2], 0, 0, 0, 127, 0, 127);
+        }
+        __syncthreads();
+        if (more) {
+            store();
+            __syncthreads();
+        }
+    }
+}
+
+template <int PREC, int MT, bool DSB>
+__device__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by, char *lds) {
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int half = l >> 5, lr = l & 31;
+    const int wr = wv & 1, wc = wv >> 1;
+    const int row0 = by * kT2, col0 = bx * kT2;
+    constexpr int M = MT;
+    const int m = j.m;
+    const bool even = (t & 1) == 0;
+    const float *x_in = DSB ? j.xa : (even ? j.xa : j.xb);
+    float *x_out = DSB ? j.xa : (even ? j.xb : j.xa);
+    const void *phi_in = DSB ? (even ? j.pa : j.pb) : (const void *)x_in;
+    void *phi_out = DSB ? (even ? j.pb : j.pa) : nullptr;
+    f16v acc[M][2][2];
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+#pragma unroll
+        for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[k][r2][c2][i] = 0.0f;
+    mma_tile_staged<PREC, M>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds);
+
+    const float kt = j.kt_tab[t];
+    const size_t Np = (size_t)j.Np;
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+        const int col = col0 + wc * 64 + c2 * 32 + lr;
+        float cf[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) cf[k] = k < m ? j.coef[(size_t)col * m + k] : 0.0f;
+#pragma unroll
+        for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int row = row0 + wr * 64 + r2 * 32 + acc_row(half, g * 4);
+                const size_t off = (size_t)col * Np + row;
+                float4 xv = *(const float4 *)(x_in + off);
+                float4 yv = *(const float4 *)(j.y + off);
+                float xs[4] = {xv.x, xv.y, xv.z, xv.w}, ys[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii) {
+                    float h = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < M; ++k)
+                        if (k < m) h = fmaf(cf[k], acc[k][r2][c2][g * 4 + ii], h);
+                    float yn = fmaf(kt, xs[ii], ys[ii]) + h;
+                    float xn = fmaf(j.dta0, yn, xs[ii]);
+                    wall(xn, yn);
+                    xs[ii] = xn;
+                    ys[ii] = yn;
+                }
+                *(float4 *)(x_out + off) = make_float4(xs[0], xs[1], xs[2], xs[3]);
+                *(float4 *)(j.y + off) = make_float4(ys[0], ys[1], ys[2], ys[3]);
+                if (DSB) {
+                    if constexpr (PREC == QAIA_FP32) {
+                        *(float4 *)((float *)phi_out + off) =
+                            make_float4(sgn1(xs[0]), sgn1(xs[1]), sgn1(xs[2]), sgn1(xs[3]));
+                    } else if constexpr (PREC == QAIA_BF16) {
+                        uint2 v;
+                        v.x = (uint32_t)bf16_pm1(xs[0]) | ((uint32_t)bf16_pm1(xs[1]) << 16);
+                        v.y = (uint32_t)bf16_pm1(xs[2]) | ((uint32_t)bf16_pm1(xs[3]) << 16);
+                        *(uint2 *)((uint16_t *)phi_out + off) = v;
+                    } else {
+                        uint32_t v = (uint32_t)fp8_pm1(xs[0]) | ((uint32_t)fp8_pm1(xs[1]) << 8) |
+                                     ((uint32_t)fp8_pm1(xs[2]) << 16) | ((uint32_t)fp8_pm1(xs[3]) << 24);
+                        *(uint32_t *)((uint8_t *)phi_out + off) = v;
+                    }
+                }
+                if (j.trace != nullptr && t < j.trace_steps && col < j.cols) {
+#pragma unroll
+                    for (int ii = 0; ii < 4; ++ii)
+                        if (row + ii < j.N)
+                            j.trace[((size_t)col * j.trace_steps + t) * j.N + row + ii] = xs[ii];
+                }
+            }
+    }
+}
+
+template <int MT>
+constexpr size_t staged_lds_bytes() { return (size_t)(MT + 1) * kT2 * kPitchB; }
+
+template <int PREC, int M, bool DSB>
+__global__ __launch_bounds__(kDB) void dense_step_staged_kernel(DenseJob j, int t) {
+    __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<M>()];
+    dense_step_staged_body<PREC, M, DSB>(j, t, blockIdx.x, blockIdx.y, lds);
+}
+
+template <int PREC, bool DSB>
+__global__ __launch_bounds__(kDB) void dense_batch_step_staged_kernel(const DenseJob *__restrict__ jobs, int count,
+                                                                      const int64_t *__restrict__ block_start, int t) {
+    __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<4>()];
+    const int64_t b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < count && block_start[i + 1] <= b) ++i;
+    const DenseJob j = jobs[i];
+    const int64_t local = b - block_start[i];
+    dense_step_staged_body<PREC, 4, DSB>(j, t, (int)(local % j.tiles_x), (int)(local / j.tiles_x), lds);
+}
+
 // Field mode (reduced-precision error reporting): field[col][k][i] = 2^e_k (J~_k Phi)_i.
 struct FieldArgs {
     const void *J;
@@ -348,7 +584,7 @@ static uint8_t to_e4m3(double v) {
 }
 
 void dense_build(Problem &p) {
-    const int64_t Np = (p.n + 63) / 64 * 64;
+    const int64_t Np = (p.n + 127) / 128 * 128;  // both tile heights (64, 128) divide it
     const double bytes = (double)p.m * Np * Np * 7.0;
     if (bytes > 4.0 * (1ull << 30)) {
         p.dense.why = "dense images would exceed 4 GiB";
@@ -459,7 +695,34 @@ static void step_dispatch_m(dim3 grid, hipStream_t st, const DenseJob &j, int t)
     }
 }
 
+template <int PREC, int M, bool DSB>
+static void staged_launch(dim3 grid, hipStream_t st, const DenseJob &j, int t) {
+    hipLaunchKernelGGL((dense_step_staged_kernel<PREC, M, DSB>), grid, dim3(kDB), 0, st, j, t);
+}
+
+template <int PREC, bool DSB>
+static void staged_dispatch_m(dim3 grid, hipStream_t st, const DenseJob &j, int t) {
+    switch (j.m) {
+        case 1: staged_launch<PREC, 1, DSB>(grid, st, j, t); break;
+        case 2: staged_launch<PREC, 2, DSB>(grid, st, j, t); break;
+        case 3: staged_launch<PREC, 3, DSB>(grid, st, j, t); break;
+        case 4: staged_launch<PREC, 4, DSB>(grid, st, j, t); break;
+        default: throw Error{QAIA_UNSUPPORTED, "dense path supports m <= 4"};
+    }
+}
+
 static void step_dispatch(int prec, bool dsb, dim3 grid, hipStream_t st, const DenseJob &j, int t) {
+    if (j.staged) {
+        if (prec == QAIA_FP32) {
+            if (dsb) staged_dispatch_m<QAIA_FP32, true>(grid, st, j, t);
+            else staged_dispatch_m<QAIA_FP32, false>(grid, st, j, t);
+        } else if (prec == QAIA_BF16) {
+            staged_dispatch_m<QAIA_BF16, true>(grid, st, j, t);
+        } else {
+            staged_dispatch_m<QAIA_FP8, true>(grid, st, j, t);
+        }
+        return;
+    }
     if (prec == QAIA_FP32) {
         if (dsb) step_dispatch_m<QAIA_FP32, true>(grid, st, j, t);
         else step_dispatch_m<QAIA_FP32, false>(grid, st, j, t);
@@ -470,11 +733,22 @@ static void step_dispatch(int prec, bool dsb, dim3 grid, hipStream_t st, const D
     }
 }
 
-void launch_dense_batch_step(int prec, bool dsb, const DenseJob *jobs, int count, const int64_t *starts,
-                             int64_t blocks, int t, hipStream_t st) {
+void launch_dense_batch_step(int prec, bool dsb, bool staged, const DenseJob *jobs, int count,
+                             const int64_t *starts, int64_t blocks, int t, hipStream_t st) {
     QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many tiles for one launch");
     if (blocks == 0) return;
     const dim3 grid((unsigned)blocks);
+    if (staged) {
+        if (prec == QAIA_FP32) {
+            if (dsb) hipLaunchKernelGGL((dense_batch_step_staged_kernel<QAIA_FP32, true>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+            else hipLaunchKernelGGL((dense_batch_step_staged_kernel<QAIA_FP32, false>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+        } else if (prec == QAIA_BF16) {
+            hipLaunchKernelGGL((dense_batch_step_staged_kernel<QAIA_BF16, true>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+        } else {
+            hipLaunchKernelGGL((dense_batch_step_staged_kernel<QAIA_FP8, true>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+        }
+        return;
+    }
     if (prec == QAIA_FP32) {
         if (dsb) hipLaunchKernelGGL((dense_batch_step_kernel<QAIA_FP32, true>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
         else hipLaunchKernelGGL((dense_batch_step_kernel<QAIA_FP32, false>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
@@ -486,7 +760,7 @@ void launch_dense_batch_step(int prec, bool dsb, const DenseJob *jobs, int count
 }
 
 DenseJob dense_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws, const WsLayout &L,
-                   float *trace, int32_t trace_steps) {
+                   float *trace, int32_t trace_steps, bool staged) {
     char *b = (char *)ws;
     DenseJob j{};
     j.J = dense_J(p, s.precision);
@@ -502,8 +776,9 @@ DenseJob dense_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule &
     j.N = p.n;
     j.m = p.m;
     j.cols = (int)(W * (int64_t)R);
-    j.tiles_x = (int)(L.colsP / kTileN);
-    j.tiles_y = p.dense.Np / kTileM;
+    j.staged = staged ? 1 : 0;
+    j.tiles_x = (int)(L.colsP / (staged ? kT2 : kTileN));
+    j.tiles_y = p.dense.Np / (staged ? kT2 : kTileM);
     j.trace = trace_steps > 0 ? trace : nullptr;
     j.trace_steps = trace_steps;
     return j;
@@ -550,14 +825,14 @@ void launch_dense_finish(const Problem &p, int32_t R, const qaia_schedule &s, vo
 
 void launch_dense(const Problem &p, const float *weights, int64_t W, int32_t R,
                   const qaia_schedule &s, void *ws, const WsLayout &L, uint64_t *spins, int64_t *obj,
-                  float *trace, int32_t trace_steps, hipStream_t st) {
+                  float *trace, int32_t trace_steps, bool staged, hipStream_t st) {
     std::string why;
     QAIA_CHECK(dense_supported(p, &why), QAIA_UNSUPPORTED, "dense path: " + why);
     QAIA_CHECK(p.m <= 4, QAIA_UNSUPPORTED, "dense path supports m <= 4");
     const int64_t cols = W * (int64_t)R;
     if (cols == 0) return;
     QAIA_CHECK(L.colsP <= INT32_MAX / 2, QAIA_INVALID_ARGUMENT, "too many replicas for the dense path");
-    const DenseJob j = dense_job(p, W, R, s, ws, L, trace, trace_steps);
+    const DenseJob j = dense_job(p, W, R, s, ws, L, trace, trace_steps, staged);
     launch_dense_setup(p, weights, R, s, ws, L, j, st);
     const dim3 grid(j.tiles_x, j.tiles_y);
     for (int t = 0; t < s.steps; ++t) step_dispatch(s.precision, s.variant == QAIA_DSB, grid, st, j, t);

@@ -136,6 +136,7 @@ struct DenseJob {
     int Np, N, m, cols, tiles_x, tiles_y;
     float *trace;
     int trace_steps;
+    int staged;  // 0: 64 x 128 tiles from global loads; 1: 128 x 128 tiles staged through LDS
 };
 struct SparseShape {
     int rpb = 1, npt = 1, maxdeg = 4;
@@ -173,15 +174,16 @@ void dense_release(Problem &p);
 bool dense_supported(const Problem &p, std::string *why);
 void launch_dense(const Problem &p, const float *weights, int64_t W, int32_t R,
                   const qaia_schedule &s, void *ws, const WsLayout &L, uint64_t *spins, int64_t *obj,
-                  float *trace, int32_t trace_steps, hipStream_t st);
+                  float *trace, int32_t trace_steps, bool staged, hipStream_t st);
 DenseJob dense_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws, const WsLayout &L,
-                   float *trace, int32_t trace_steps);
+                   float *trace, int32_t trace_steps, bool staged);
 void launch_dense_setup(const Problem &p, const float *weights, int32_t R, const qaia_schedule &s, void *ws,
                         const WsLayout &L, const DenseJob &j, hipStream_t st);
 void launch_dense_finish(const Problem &p, int32_t R, const qaia_schedule &s, void *ws, const WsLayout &L,
                          const DenseJob &j, uint64_t *spins, int64_t *obj, hipStream_t st);
-void launch_dense_batch_step(int prec, bool dsb, const DenseJob *jobs, int count, const int64_t *starts,
-                             int64_t blocks, int t, hipStream_t st);
+void launch_dense_batch_step(int prec, bool dsb, bool staged, const DenseJob *jobs, int count,
+                             const int64_t *starts, int64_t blocks, int t, hipStream_t st);
+inline bool is_dense_path(int path) { return path == QAIA_PATH_DENSE || path == QAIA_PATH_DENSE_STAGED; }
 size_t dense_field_ws_bytes(const Problem &p, int prec, int64_t count);
 void launch_dense_field(const Problem &p, int prec, const float *phi, int64_t count, float *field,
                         void *ws, size_t ws_bytes, hipStream_t st);

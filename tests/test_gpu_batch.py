@@ -29,8 +29,9 @@ SPECS = [  # (n, m, kind, W, R, path)
     (42, 4, "deg3", 7, 9, "sparse_lds"),
     (200, 4, "deg3", 5, 32, "sparse_lds"),
     (90, 3, "p0.1", 6, 11, "dense"),
-    (150, 4, "p0.5", 3, 40, "dense"),
+    (150, 4, "p0.5", 3, 40, "dense_staged"),
     (70, 3, "complete", 4, 8, "dense"),
+    (260, 3, "p0.3", 5, 30, "dense_staged"),
     (300, 3, "deg3", 2, 3, "sparse_lds"),
 ]
 
@@ -77,14 +78,15 @@ def test_batch_matches_per_item_calls(q, variant):
 
 def test_batch_low_precision_dense(q):
     import torch
-    specs = [(90, 3, "p0.1"), (150, 4, "p0.5"), (130, 3, "complete")]
+    specs = [(90, 3, "p0.1", "dense"), (150, 4, "p0.5", "dense_staged"), (130, 3, "complete", "dense"),
+             (200, 3, "complete", "dense_staged")]
     items, refs = [], []
-    for i, (n, m, kind) in enumerate(specs):
+    for i, (n, m, kind, path) in enumerate(specs):
         inst = wl.random_instance(n, m, kind, seed=900 + i)
         p = q.problem_from_instance(inst)
         c = _dev(wl.dirichlet_weights(5, m, 950 + i))
-        items.append(q.BatchItem(p, c, 16, "dense"))
-        sp, ob, _ = q.qaia_sample(p, c, 16, q.make_schedule("dsb", precision="bf16", steps=200, seed=3))
+        items.append(q.BatchItem(p, c, 16, path))
+        sp, ob, _ = q.qaia_sample(p, c, 16, q.make_schedule("dsb", precision="bf16", steps=200, seed=3, path=path))
         refs.append((sp, ob))
     q.qaia_sample_batch(items, q.make_schedule("dsb", precision="bf16", steps=200, seed=3))
     torch.cuda.synchronize()
@@ -101,7 +103,7 @@ def test_autotune_picks_valid_paths(q):
     est = q.qaia_plan_autotune(items, s, probe_steps=20)
     print([(spec[:3], it.path, f"{e * 1e3:.2f} ms") for spec, it, e in zip(SPECS, items, est)])
     assert all(e > 0 for e in est)
-    assert all(it.path in ("sparse_reg", "sparse_lds", "dense") for it in items)
+    assert all(it.path in ("sparse_reg", "sparse_lds", "dense", "dense_staged") for it in items)
     # a small sparse graph never goes to the matrix cores, a 50%-dense one never to the LDS kernel
     assert items[0].path in ("sparse_reg", "sparse_lds")
     q.qaia_sample_batch(items, s)

@@ -11,6 +11,9 @@ from gpu_helpers import rel_inf_error, unpack_spins
 
 pytestmark = pytest.mark.gpu
 
+# the two dense tile kernels: 64 x 128 register tiles, and 128 x 128 tiles staged through LDS
+DENSE_PATHS = ["dense", "dense_staged"]
+
 
 @pytest.fixture(scope="module")
 def q():
@@ -56,11 +59,12 @@ def _field(q, prob, prec, phi):
 
 # ---------------------------------------------------------------- trajectories
 
-def test_dense_fp32_trace_parity_bsb(q):
+@pytest.mark.parametrize("path", DENSE_PATHS)
+def test_dense_fp32_trace_parity_bsb(q, path):
     inst = wl.random_instance(12, 3, "deg3", seed=41, num_edges=16)
     c = wl.dirichlet_weights(6, 3, 42)
     prob = q.problem_from_instance(inst)
-    s = q.make_schedule("bsb", steps=1000, dt=0.5, seed=43, path="dense")
+    s = q.make_schedule("bsb", steps=1000, dt=0.5, seed=43, path=path)
     _, _, _, tr = q.qaia_sample_trace(prob, _dev(c), 8, s, 100)
     _, ref = oracle.sb_sample(inst, c, 8, 1000, "bsb", dt=0.5, seed=43, trace_steps=100)
     err = rel_inf_error(tr.cpu().numpy(), ref)
@@ -68,12 +72,13 @@ def test_dense_fp32_trace_parity_bsb(q):
     assert err.max() <= 1e-5
 
 
-def test_dense_fp32_trace_parity_complete_graph(q):
-    """A complete 70-node graph (two 64-spin tiles, ragged) for 100 steps."""
+@pytest.mark.parametrize("path", DENSE_PATHS)
+def test_dense_fp32_trace_parity_complete_graph(q, path):
+    """A complete 70-node graph (two 64-spin tiles, ragged; one ragged 128-spin tile) for 100 steps."""
     inst = wl.random_instance(70, 2, "complete", seed=44)
     c = wl.dirichlet_weights(3, 2, 45)
     prob = q.problem_from_instance(inst)
-    s = q.make_schedule("bsb", steps=1000, dt=0.5, seed=46, path="dense")
+    s = q.make_schedule("bsb", steps=1000, dt=0.5, seed=46, path=path)
     _, _, _, tr = q.qaia_sample_trace(prob, _dev(c), 5, s, 100)
     _, ref = oracle.sb_sample(inst, c, 5, 1000, "bsb", dt=0.5, seed=46, trace_steps=100)
     err = rel_inf_error(tr.cpu().numpy(), ref)
@@ -81,8 +86,9 @@ def test_dense_fp32_trace_parity_complete_graph(q):
     assert err.max() <= 1e-5
 
 
+@pytest.mark.parametrize("path", DENSE_PATHS)
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
-def test_dense_dsb_trace_parity(q, prec):
+def test_dense_dsb_trace_parity(q, prec, path):
     """Discrete SB with exactly representable weights: every precision follows the
     FP64 oracle within 1e-5 for 100 steps (seed pre-screened away from x = 0)."""
     inst = _small_int_instance(40, 3, seed=47)
@@ -96,14 +102,15 @@ def test_dense_dsb_trace_parity(q, prec):
     if seed is None:
         pytest.skip("no seed without near-zero crossings")
     prob = q.problem_from_instance(inst)
-    s = q.make_schedule("dsb", precision=prec, steps=1000, dt=0.5, seed=seed, path="dense")
+    s = q.make_schedule("dsb", precision=prec, steps=1000, dt=0.5, seed=seed, path=path)
     _, _, _, tr = q.qaia_sample_trace(prob, _dev(c), 2, s, 100)
     err = rel_inf_error(tr.cpu().numpy(), ref)
     print(f"dense dsb {prec}: max rel err {err.max():.3e}")
     assert err.max() <= 1e-5
 
 
-def test_low_precision_reproduces_fp32_bitwise_when_exact(q):
+@pytest.mark.parametrize("path", DENSE_PATHS)
+def test_low_precision_reproduces_fp32_bitwise_when_exact(q, path):
     """With weights exact in bf16 and e4m3 every product and partial sum is an
     exact integer in fp32, so the BF16 and FP8 forms of discrete SB must produce
     exactly the FP32 dense trajectory and spins."""
@@ -112,7 +119,7 @@ def test_low_precision_reproduces_fp32_bitwise_when_exact(q):
     prob = q.problem_from_instance(inst)
     outs = {}
     for prec in ("fp32", "bf16", "fp8"):
-        s = q.make_schedule("dsb", precision=prec, steps=400, dt=0.5, seed=51, path="dense")
+        s = q.make_schedule("dsb", precision=prec, steps=400, dt=0.5, seed=51, path=path)
         sp, ob, _, tr = q.qaia_sample_trace(prob, _dev(c), 16, s, 50)
         outs[prec] = (sp.cpu().numpy(), ob.cpu().numpy(), tr.cpu().numpy())
     for prec in ("bf16", "fp8"):
@@ -123,12 +130,13 @@ def test_low_precision_reproduces_fp32_bitwise_when_exact(q):
 
 # ---------------------------------------------------------------- exact cuts
 
+@pytest.mark.parametrize("path", DENSE_PATHS)
 @pytest.mark.parametrize("variant,prec", [("bsb", "fp32"), ("dsb", "fp32"), ("dsb", "bf16"), ("dsb", "fp8")])
-def test_dense_cut_values_bit_exact(q, variant, prec):
+def test_dense_cut_values_bit_exact(q, variant, prec, path):
     inst = wl.random_instance(150, 3, "complete", seed=52)
     c = wl.dirichlet_weights(16, 3, 53)
     prob = q.problem_from_instance(inst)
-    s = q.make_schedule(variant, precision=prec, steps=300, dt=0.5, seed=54, path="dense")
+    s = q.make_schedule(variant, precision=prec, steps=300, dt=0.5, seed=54, path=path)
     import torch
     spins, obj, ws = q.qaia_sample(prob, _dev(c), 8, s)
     torch.cuda.synchronize()
@@ -140,19 +148,38 @@ def test_dense_cut_values_bit_exact(q, variant, prec):
     assert q.qaia_workspace_status(ws) is None
 
 
-def test_dense_invalid_rows_and_determinism(q):
+@pytest.mark.parametrize("path", DENSE_PATHS)
+def test_dense_invalid_rows_and_determinism(q, path):
     import torch
     inst = wl.random_instance(90, 2, "p0.3", seed=55)
     c = wl.dirichlet_weights(5, 2, 56)
     c[2] = [np.nan, 1.0]
     prob = q.problem_from_instance(inst)
-    s = q.make_schedule("dsb", precision="bf16", steps=200, seed=57, path="dense")
+    s = q.make_schedule("dsb", precision="bf16", steps=200, seed=57, path=path)
     a, oa, ws = q.qaia_sample(prob, _dev(c), 4, s)
     b, ob, _ = q.qaia_sample(prob, _dev(c), 4, s)
     torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(oa, ob)
     assert q.qaia_workspace_status(ws) == 2
     assert not a[8:12].any() and not oa[8:12].any()
+
+
+@pytest.mark.parametrize("variant,prec", [("bsb", "fp32"), ("dsb", "bf16"), ("dsb", "fp8")])
+def test_staged_tiles_match_register_tiles_when_exact(q, variant, prec):
+    """Exact weights make every partial sum an exact integer, so the two tile
+    kernels must agree bit for bit whatever their k order: 300 spins (three
+    128-spin tiles, ragged) and 20 x 16 replicas (three 128-column tiles, ragged)."""
+    inst = _small_int_instance(300, 4, seed=60, kind="p0.6")
+    c = wl.dirichlet_weights(20, 4, 61)
+    prob = q.problem_from_instance(inst)
+    outs = []
+    for path in DENSE_PATHS:
+        s = q.make_schedule(variant, precision=prec, steps=300, dt=0.5, seed=62, path=path)
+        sp, ob, _, tr = q.qaia_sample_trace(prob, _dev(c), 16, s, 40)
+        outs.append((sp.cpu().numpy(), ob.cpu().numpy(), tr.cpu().numpy()))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(outs[0][1], oracle.cut_values(inst, unpack_spins(outs[0][0], inst.n)))
 
 
 # ---------------------------------------------------------------- field error (precision form)
