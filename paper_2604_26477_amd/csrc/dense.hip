@@ -14,7 +14,7 @@
 //   FP8 : discrete SB only: J e4m3, Phi = +-1 exact in e4m3, 32x32x64 MFMA.
 // All accumulate in fp32.
 //
-// Layout (all device, zero padded to Np = ceil64(n) spins and colsP =
+// Layout (all device, zero padded to Np = ceil128(n) spins and colsP =
 // ceil128(W*R) columns): x, y fp32 [colsP][Np]; Phi [colsP][Np]; J [m][Np][Np]
 // (symmetric, so rows serve as the A operand directly).
 //
@@ -22,7 +22,8 @@
 // 32 spins x 64 columns (two 32x32 accumulators per objective).  For every
 // MFMA the A and B fragments of a lane come from the same k positions
 // (lane half h, slot j -> k0 + h*KG/2 + j), which pairs them correctly for
-// any internal k order of the instruction.
+// any internal k order of the instruction.  The staged tile (below) doubles
+// the block to 128 x 128 and reads each operand chunk once through LDS.
 #include <climits>
 #include <cmath>
 #include <cstring>
