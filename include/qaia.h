@@ -72,7 +72,11 @@ typedef struct qaia_problem qaia_problem;
  *   |x_i| > 1  ->  x_i = sgn(x_i), y_i = 0           (inelastic wall)
  * with a_t = a0 * t / (steps - 1), J(c) = sum_k c_k J^(k) (Eq. 7) and
  * c0 = 1 / max_i |sum_j J(c)_ij|.  x and y start ~ U(-init_amp, init_amp)
- * from the counter-based stream (seed, replica index + replica_offset). */
+ * from the counter-based stream (seed, replica index + replica_offset).
+ * eta_i at step t of global replica g (= row + replica_offset) is a standard
+ * normal made by Box-Muller from draw (g * steps + t) * n + i of the same
+ * counter generator keyed with seed ^ 0xd1b54a32d192ed03; every path
+ * (generated, generic sparse, dense) draws this one stream. */
 typedef struct qaia_schedule {
     int32_t variant;     /* QAIA_BSB or QAIA_DSB */
     int32_t precision;   /* QAIA_FP32, QAIA_BF16, QAIA_FP8 */

@@ -49,8 +49,6 @@ void check_schedule(const Problem &p, const qaia_schedule *s) {
         QAIA_CHECK(s->path == QAIA_PATH_AUTO || is_dense_path(s->path), QAIA_UNSUPPORTED,
                    "reduced precision runs on the dense path only");
     }
-    if (is_dense_path(s->path))
-        QAIA_CHECK(s->noise_alpha == 0.0f, QAIA_UNSUPPORTED, "the dense path runs plain SB only");
     (void)p;
 }
 
@@ -59,7 +57,7 @@ int plan_path(const Problem &p, const qaia_schedule &s, bool tracing) {
     (void)tracing;
     if (s.path != QAIA_PATH_AUTO) return s.path;
     if (s.precision != QAIA_FP32) return QAIA_PATH_DENSE_STAGED;
-    if (p.jit[s.variant] != nullptr && s.noise_alpha == 0.0f) return QAIA_PATH_SPARSE_REG;
+    if (p.jit[s.variant] != nullptr) return QAIA_PATH_SPARSE_REG;
     if (sparse_lds_supported(p, nullptr)) return QAIA_PATH_SPARSE_LDS;
     return QAIA_PATH_DENSE_STAGED;
 }

@@ -24,6 +24,7 @@
 // (lane half h, slot j -> k0 + h*KG/2 + j), which pairs them correctly for
 // any internal k order of the instruction.  The staged tile (below) doubles
 // the block to 128 x 128 and reads each operand chunk once through LDS.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -36,6 +37,7 @@ namespace qaia {
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kDB = 256;      // threads per block
 constexpr int kTileM = 64;    // spins per block
@@ -162,6 +164,11 @@ __device__ void dense_step_body(const DenseJob &j, int t, int bx, int by) {
                 for (int k = 0; k < M; ++k)
                     if (k < m) h = fmaf(cf[k], acc[k][cb][g * 4 + ii], h);
                 float yn = fmaf(kt, xs[ii], ys[ii]) + h;
+                if (j.dt_alpha != 0.0f && col < j.cols && row + ii < j.N) {
+                    const uint64_t g = (uint64_t)col + j.offset;
+                    const uint64_t nidx = (g * (uint64_t)j.steps + (uint64_t)t) * (uint64_t)j.N + (uint64_t)(row + ii);
+                    yn = fmaf(j.dt_alpha, noise_value(j.seed, nidx), yn);
+                }
                 float xn = fmaf(j.dta0, yn, xs[ii]);
                 wall(xn, yn);
                 xs[ii] = xn;
@@ -214,147 +221,176 @@ __global__ __launch_bounds__(kDB) void dense_batch_step_kernel(const DenseJob *_
 
 // ---------------------------------------------------------------------------
 // Staged tile: a 256-thread block owns 128 spins x 128 columns; wave (wr, wc)
-// owns 64 x 64 (2 x 2 accumulators per objective).  Each 64-byte k-chunk of
-// the block's J rows (all objectives) and Phi columns is copied to LDS once
-// and read by the two waves that share it; the next chunk's global loads are
-// in flight while the current chunk's MFMAs run.
+// owns 64 x 64 (2 x 2 accumulators per objective).  The k dimension runs in
+// 64-byte chunks.  Each chunk of the block's J rows (all objectives) and Phi
+// columns is copied to LDS once and read there by the two waves that share
+// it.  Software pipeline: global loads run two chunks ahead into two static
+// register sets, LDS is double-buffered, and there is one barrier per chunk:
+//   iteration c: issue loads of chunk c+2 -> compute on LDS[c%2]
+//                -> write chunk c+1 (loaded during c-1) to LDS[(c+1)%2] -> barrier.
+// Loads of objectives k >= m (batched jobs with m < MT) read objective m-1;
+// their MFMAs are skipped by a uniform branch and their accumulators unused.
 constexpr int kT2 = 128;          // tile height and width
 constexpr int kChunkB = 64;       // bytes of k per row per chunk
 constexpr int kPitchB = 80;       // LDS row pitch (bytes), padded against bank conflicts
 
+template <int MT>
+constexpr int staged_buf_bytes() { return (MT + 1) * kT2 * kPitchB; }
+
+template <int MT>
+__device__ __forceinline__ void staged_load(u32x4 (&ra)[2 * MT], u32x4 (&rb)[2], const char *const (&pa)[2 * MT],
+                                            const char *const (&pb)[2], size_t koff) {
+#pragma unroll
+    for (int q = 0; q < 2 * MT; ++q) ra[q] = *(const u32x4 *)(pa[q] + koff);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) rb[q] = *(const u32x4 *)(pb[q] + koff);
+}
+
+// thread tid holds, for q < 2 MT, objective q/2, row (q%2)*64 + tid/4 of the
+// J tile and, for q < 2, column q*64 + tid/4 of the Phi tile; 16-byte part tid%4
+template <int MT>
+__device__ __forceinline__ void staged_store(char *buf, const u32x4 (&ra)[2 * MT], const u32x4 (&rb)[2], int tid) {
+    const int row = tid >> 2, part = tid & 3;
+#pragma unroll
+    for (int q = 0; q < 2 * MT; ++q)
+        *(u32x4 *)(buf + ((q >> 1) * kT2 + (q & 1) * 64 + row) * kPitchB + part * 16) = ra[q];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) *(u32x4 *)(buf + (MT * kT2 + q * 64 + row) * kPitchB + part * 16) = rb[q];
+}
+
+// MFMAs over one LDS chunk.  For every instruction the A and B fragments of a
+// lane come from the same k positions (lane half h, slot j), so any internal k
+// order of the instruction pairs them correctly.
+template <int PREC, int MT>
+__device__ __forceinline__ void staged_compute(const char *buf, int m, int wr, int wc, int half, int lr,
+                                               f16v (&acc)[MT][2][2]) {
+    const char *As = buf;
+    const char *Bs = buf + MT * kT2 * kPitchB;
+    if constexpr (PREC == QAIA_FP32) {
+#pragma unroll
+        for (int g = 0; g < kChunkB / 32; ++g) {  // k-groups of 8: lane half h holds k = 8g + 4h + 0..3
+            float4 av[MT][2], bv[2];
+#pragma unroll
+            for (int k = 0; k < MT; ++k)
+#pragma unroll
+                for (int r2 = 0; r2 < 2; ++r2)
+                    av[k][r2] = *(const float4 *)(As + (k * kT2 + wr * 64 + r2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+                bv[c2] = *(const float4 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+#pragma unroll
+            for (int k = 0; k < MT; ++k) {
+                if (k >= m) break;
+#pragma unroll
+                for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2) {
+                        f16v &a = acc[k][r2][c2];
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].x, bv[c2].x, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].y, bv[c2].y, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].z, bv[c2].z, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].w, bv[c2].w, a, 0, 0, 0);
+                    }
+            }
+        }
+    } else if constexpr (PREC == QAIA_BF16) {
+#pragma unroll
+        for (int g = 0; g < kChunkB / 32; ++g) {  // lane half h holds k = 16g + 8h + 0..7
+            bf16x8 av[MT][2], bv[2];
+#pragma unroll
+            for (int k = 0; k < MT; ++k)
+#pragma unroll
+                for (int r2 = 0; r2 < 2; ++r2)
+                    av[k][r2] = *(const bf16x8 *)(As + (k * kT2 + wr * 64 + r2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+                bv[c2] = *(const bf16x8 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+#pragma unroll
+            for (int k = 0; k < MT; ++k) {
+                if (k >= m) break;
+#pragma unroll
+                for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2)
+                        acc[k][r2][c2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[k][r2], bv[c2], acc[k][r2][c2], 0, 0, 0);
+            }
+        }
+    } else {
+        // one 32x32x64 step per chunk: lane half h holds k = 32h + 0..31
+        i32x8 av[MT][2], bv[2];
+#pragma unroll
+        for (int k = 0; k < MT; ++k)
+#pragma unroll
+            for (int r2 = 0; r2 < 2; ++r2)
+                av[k][r2] = *(const i32x8 *)(As + (k * kT2 + wr * 64 + r2 * 32 + lr) * kPitchB + half * 32);
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2)
+            bv[c2] = *(const i32x8 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + half * 32);
+#pragma unroll
+        for (int k = 0; k < MT; ++k) {
+            if (k >= m) break;
+#pragma unroll
+            for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+                for (int c2 = 0; c2 < 2; ++c2)
+                    acc[k][r2][c2] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        av[k][r2], bv[c2], acc[k][r2][c2], 0, 0, 0, 127, 0, 127);
+        }
+    }
+}
+
+// Np is a multiple of 128, so the chunk count Np * sizeof(T) / 64 is even and
+// >= 2.  The loop body is branch free: loads beyond the last chunk re-read the
+// last chunk and their LDS copy is never read.
 template <int PREC, int MT>
 __device__ __forceinline__ void mma_tile_staged(const void *Jv, const void *phiv, int Np_, int m, int row0,
                                                 int col0, int wr, int wc, int half, int lr,
                                                 f16v (&acc)[MT][2][2], char *lds) {
     typedef typename PrecInfo<PREC>::T T;
     constexpr int ES = sizeof(T);
-    constexpr int KCE = kChunkB / ES;  // k elements per chunk
-    constexpr int M = MT;
     const size_t Np = (size_t)Np_;
-    const char *J = (const char *)Jv;
-    const char *phi = (const char *)phiv;
-    char *As = lds;                         // [M][128][pitch]
-    char *Bs = lds + M * kT2 * kPitchB;     // [128][pitch]
     const int tid = threadIdx.x;
-    // 16-byte pieces: A has M*128 rows x 4 pieces, B 128 rows x 4 pieces
-    constexpr int A_PER = M * kT2 * 4 / kDB, B_PER = kT2 * 4 / kDB;
-    uint4 ra[A_PER], rb[B_PER];
-    auto load = [&](int k0) {  // k0 in elements
+    const char *pa[2 * MT];
+    const char *pb[2];
 #pragma unroll
-        for (int q = 0; q < A_PER; ++q) {
-            const int piece = q * kDB + tid, row = piece >> 2, part = piece & 3;
-            const int k = row / kT2, r = row % kT2;
-            ra[q] = k < m ? *(const uint4 *)(J + (((size_t)k * Np + row0 + r) * Np + k0) * ES + part * 16)
-                          : make_uint4(0, 0, 0, 0);
-        }
+    for (int q = 0; q < 2 * MT; ++q) {
+        const int k = (q >> 1) < m ? (q >> 1) : m - 1;
+        pa[q] = (const char *)Jv + (((size_t)k * Np + row0 + (q & 1) * 64 + (tid >> 2)) * Np) * ES + (tid & 3) * 16;
+    }
 #pragma unroll
-        for (int q = 0; q < B_PER; ++q) {
-            const int piece = q * kDB + tid, row = piece >> 2, part = piece & 3;
-            rb[q] = *(const uint4 *)(phi + ((size_t)(col0 + row) * Np + k0) * ES + part * 16);
-        }
-    };
-    auto store = [&]() {
-#pragma unroll
-        for (int q = 0; q < A_PER; ++q) {
-            const int piece = q * kDB + tid, row = piece >> 2, part = piece & 3;
-            *(uint4 *)(As + row * kPitchB + part * 16) = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < B_PER; ++q) {
-            const int piece = q * kDB + tid, row = piece >> 2, part = piece & 3;
-            *(uint4 *)(Bs + row * kPitchB + part * 16) = rb[q];
-        }
-    };
-    load(0);
-    store();
+    for (int q = 0; q < 2; ++q)
+        pb[q] = (const char *)phiv + ((size_t)(col0 + q * 64 + (tid >> 2)) * Np) * ES + (tid & 3) * 16;
+    char *buf0 = lds, *buf1 = lds + staged_buf_bytes<MT>();
+    const int nk = (int)(Np * ES / kChunkB);
+    const size_t last = (size_t)(nk - 1) * kChunkB;
+    u32x4 a0[2 * MT], b0[2], a1[2 * MT], b1[2];
+    staged_load<MT>(a0, b0, pa, pb, 0);
+    staged_load<MT>(a1, b1, pa, pb, kChunkB);
+    staged_store<MT>(buf0, a0, b0, tid);
     __syncthreads();
-    for (int k0 = 0; k0 < Np_; k0 += KCE) {
-        const bool more = k0 + KCE < Np_;
-        if (more) load(k0 + KCE);
-        if constexpr (PREC == QAIA_FP32) {
-#pragma unroll
-            for (int g = 0; g < KCE / 8; ++g) {  // k-groups of 8: lane half h holds k = 8g + 4h + 0..3
-                float4 av[M][2], bv[2];
-#pragma unroll
-                for (int k = 0; k < M; ++k)
-#pragma unroll
-                    for (int r2 = 0; r2 < 2; ++r2)
-                        av[k][r2] = *(const float4 *)(As + ((k * kT2) + wr * 64 + r2 * 32 + lr) * kPitchB + g * 32 + half * 16);
-#pragma unroll
-                for (int c2 = 0; c2 < 2; ++c2)
-                    bv[c2] = *(const float4 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + g * 32 + half * 16);
-#pragma unroll
-                for (int k = 0; k < M; ++k)
-#pragma unroll
-                    for (int r2 = 0; r2 < 2; ++r2)
-#pragma unroll
-                        for (int c2 = 0; c2 < 2; ++c2) {
-                            if (k >= m) continue;
-                            f16v &a = acc[k][r2][c2];
-                            a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].x, bv[c2].x, a, 0, 0, 0);
-                            a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].y, bv[c2].y, a, 0, 0, 0);
-                            a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].z, bv[c2].z, a, 0, 0, 0);
-                            a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].w, bv[c2].w, a, 0, 0, 0);
-                        }
-            }
-        } else if constexpr (PREC == QAIA_BF16) {
-#pragma unroll
-            for (int g = 0; g < KCE / 16; ++g) {  // lane half h holds k = 16g + 8h + 0..7
-                bf16x8 av[M][2], bv[2];
-#pragma unroll
-                for (int k = 0; k < M; ++k)
-#pragma unroll
-                    for (int r2 = 0; r2 < 2; ++r2)
-                        av[k][r2] = *(const bf16x8 *)(As + ((k * kT2) + wr * 64 + r2 * 32 + lr) * kPitchB + g * 32 + half * 16);
-#pragma unroll
-                for (int c2 = 0; c2 < 2; ++c2)
-                    bv[c2] = *(const bf16x8 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + g * 32 + half * 16);
-#pragma unroll
-                for (int k = 0; k < M; ++k)
-#pragma unroll
-                    for (int r2 = 0; r2 < 2; ++r2)
-#pragma unroll
-                        for (int c2 = 0; c2 < 2; ++c2)
-                            if (k < m)
-                                acc[k][r2][c2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[k][r2], bv[c2], acc[k][r2][c2], 0, 0, 0);
-            }
-        } else {
-            // one 32x32x64 step per chunk: lane half h holds k = 32h + 0..31
-            i32x8 av[M][2], bv[2];
-#pragma unroll
-            for (int k = 0; k < M; ++k)
-#pragma unroll
-                for (int r2 = 0; r2 < 2; ++r2)
-                    av[k][r2] = *(const i32x8 *)(As + ((k * kT2) + wr * 64 + r2 * 32 + lr) * kPitchB + half * 32);
-#pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2)
-                bv[c2] = *(const i32x8 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + half * 32);
-#pragma unroll
-            for (int k = 0; k < M; ++k)
-#pragma unroll
-                for (int r2 = 0; r2 < 2; ++r2)
-#pragma unroll
-                    for (int c2 = 0; c2 < 2; ++c2)
-                        if (k < m)
-                            acc[k][r2][c2] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                                av[k][r2], bv[c2], acc[k][r2][c2], 0, 0, 0, 127, 0, 127);
-        }
+    for (int c = 0; c < nk; c += 2) {
+        staged_load<MT>(a0, b0, pa, pb, std::min((size_t)(c + 2) * kChunkB, last));
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
+        staged_compute<PREC, MT>(buf0, m, wr, wc, half, lr, acc);
+        staged_store<MT>(buf1, a1, b1, tid);
         __syncthreads();
-        if (more) {
-            store();
-            __syncthreads();
-        }
+        staged_load<MT>(a1, b1, pa, pb, std::min((size_t)(c + 3) * kChunkB, last));
+        __builtin_amdgcn_sched_barrier(0);
+        staged_compute<PREC, MT>(buf1, m, wr, wc, half, lr, acc);
+        staged_store<MT>(buf0, a0, b0, tid);
+        __syncthreads();
     }
 }
 
-template <int PREC, int MT, bool DSB>
+// FIXED_M: the job's m equals MT (single-job launches), so objective guards fold away.
+template <int PREC, int MT, bool DSB, bool FIXED_M>
 __device__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by, char *lds) {
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int half = l >> 5, lr = l & 31;
     const int wr = wv & 1, wc = wv >> 1;
     const int row0 = by * kT2, col0 = bx * kT2;
     constexpr int M = MT;
-    const int m = j.m;
+    const int m = FIXED_M ? MT : j.m;
     const bool even = (t & 1) == 0;
     const float *x_in = DSB ? j.xa : (even ? j.xa : j.xb);
     float *x_out = DSB ? j.xa : (even ? j.xb : j.xa);
@@ -395,6 +431,12 @@ __device__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by,
                     for (int k = 0; k < M; ++k)
                         if (k < m) h = fmaf(cf[k], acc[k][r2][c2][g * 4 + ii], h);
                     float yn = fmaf(kt, xs[ii], ys[ii]) + h;
+                    if (j.dt_alpha != 0.0f && col < j.cols && row + ii < j.N) {
+                        const uint64_t g = (uint64_t)col + j.offset;
+                        const uint64_t nidx =
+                            (g * (uint64_t)j.steps + (uint64_t)t) * (uint64_t)j.N + (uint64_t)(row + ii);
+                        yn = fmaf(j.dt_alpha, noise_value(j.seed, nidx), yn);
+                    }
                     float xn = fmaf(j.dta0, yn, xs[ii]);
                     wall(xn, yn);
                     xs[ii] = xn;
@@ -428,12 +470,30 @@ __device__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by,
 }
 
 template <int MT>
-constexpr size_t staged_lds_bytes() { return (size_t)(MT + 1) * kT2 * kPitchB; }
+constexpr size_t staged_lds_bytes() { return 2 * (size_t)staged_buf_bytes<MT>(); }
+
+// XCD-aware tile order for a single job: blocks are dealt to the eight XCDs
+// round robin (block b runs on XCD b % 8), so when the row-tile count divides
+// by 8, XCD x is given row tiles [x*ty/8, (x+1)*ty/8) across all column tiles
+// and the J rows it reads stay in its own L2.
+__device__ __forceinline__ void xcd_tile(int tiles_x, int tiles_y, int &bx, int &by) {
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    if ((tiles_y & 7) != 0) {
+        bx = blockIdx.x;
+        by = blockIdx.y;
+        return;
+    }
+    const int xcd = b & 7, slot = b >> 3;
+    by = xcd * (tiles_y >> 3) + slot / tiles_x;
+    bx = slot % tiles_x;
+}
 
 template <int PREC, int M, bool DSB>
 __global__ __launch_bounds__(kDB) void dense_step_staged_kernel(DenseJob j, int t) {
     __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<M>()];
-    dense_step_staged_body<PREC, M, DSB>(j, t, blockIdx.x, blockIdx.y, lds);
+    int bx, by;
+    xcd_tile(j.tiles_x, j.tiles_y, bx, by);
+    dense_step_staged_body<PREC, M, DSB, true>(j, t, bx, by, lds);
 }
 
 template <int PREC, bool DSB>
@@ -445,7 +505,7 @@ __global__ __launch_bounds__(kDB) void dense_batch_step_staged_kernel(const Dens
     while (i + 1 < count && block_start[i + 1] <= b) ++i;
     const DenseJob j = jobs[i];
     const int64_t local = b - block_start[i];
-    dense_step_staged_body<PREC, 4, DSB>(j, t, (int)(local % j.tiles_x), (int)(local / j.tiles_x), lds);
+    dense_step_staged_body<PREC, 4, DSB, false>(j, t, (int)(local % j.tiles_x), (int)(local / j.tiles_x), lds);
 }
 
 // Field mode (reduced-precision error reporting): field[col][k][i] = 2^e_k (J~_k Phi)_i.
@@ -782,6 +842,10 @@ DenseJob dense_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule &
     j.tiles_y = p.dense.Np / (staged ? kT2 : kTileM);
     j.trace = trace_steps > 0 ? trace : nullptr;
     j.trace_steps = trace_steps;
+    j.dt_alpha = s.dt * s.noise_alpha;
+    j.steps = s.steps;
+    j.seed = s.seed;
+    j.offset = s.replica_offset;
     return j;
 }
 

@@ -73,6 +73,7 @@ struct Problem {
     // generated register-resident kernels, index = variant (bSB, dSB)
     JitKernel *jit[2] = {nullptr, nullptr};
     JitKernel *jit_trace[2] = {nullptr, nullptr};  // tracing variants, built on first use
+    JitKernel *jit_noise[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [variant][trace], noise-injected, built on first use
     std::string jit_error;
     DenseImages dense;
     std::mutex mu;
@@ -137,6 +138,10 @@ struct DenseJob {
     float *trace;
     int trace_steps;
     int staged;  // 0: 64 x 128 tiles from global loads; 1: 128 x 128 tiles staged through LDS
+    // noise injection (Eq. 10): y += dt alpha eta, eta from the keyed counter stream; off when 0
+    float dt_alpha;
+    int steps;
+    uint64_t seed, offset;
 };
 struct SparseShape {
     int rpb = 1, npt = 1, maxdeg = 4;

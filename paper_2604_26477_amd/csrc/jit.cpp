@@ -9,7 +9,9 @@
 // generated per graph and compiled once, device-only, by the ROCm clang found
 // at ROCM_PATH (child process), then loaded as a module on the problem's
 // device.  The instance's integer weights are baked in as literals for the
-// fused exact cut evaluation.
+// fused exact cut evaluation.  The noise-injected variant (Eq. 10) draws the
+// same counter-based Gaussian stream as the generic kernel, with the same
+// float operations, and links the ROCm device library for cosine.
 #include <fcntl.h>
 #include <spawn.h>
 #include <sys/stat.h>
@@ -81,17 +83,28 @@ __device__ __forceinline__ float initv(u64 seed, u64 idx, float amp) {
 }
 )";
 
-static std::string generate(const Problem &p, int variant, bool trace) {
+// Box-Muller on two 24-bit uniforms of one draw from the noise-keyed stream.
+static const char *kNoisePrelude = R"(extern "C" __device__ float __ocml_cos_f32(float);
+__device__ __forceinline__ float nzv(u64 seed, u64 idx) {
+  u64 b = sm64(seed ^ 0xd1b54a32d192ed03ull, idx);
+  float u1 = (float)((u32)(b >> 40) + 1u) * 0x1p-24f;
+  float u2 = (float)(u32)(b & 0xffffffull) * 0x1p-24f;
+  return __builtin_sqrtf(-2.0f * __builtin_logf(u1)) * __ocml_cos_f32(6.2831853071795864769f * u2);
+}
+)";
+
+static std::string generate(const Problem &p, int variant, bool trace, bool noise) {
     const int n = p.n, m = p.m;
     const int64_t E = p.E;
     const bool dsb = variant == QAIA_DSB;
     std::ostringstream s;
     s << kPrelude;
+    if (noise) s << kNoisePrelude;
     s << "extern \"C\" __global__ __attribute__((amdgpu_flat_work_group_size(1, 256)))\n"
          "void qaia_sb_reg(const float* __restrict__ jcp, const double* __restrict__ c0s,\n"
          "  const float* __restrict__ kt_tab, i64 rows, int R, int T, float dta0, u64 seed,\n"
          "  u64 offset, float amp, u64* __restrict__ spins, i64* __restrict__ obj,\n"
-         "  float* __restrict__ trace, int trace_steps) {\n";
+         "  float* __restrict__ trace, int trace_steps, float dt_alpha) {\n";
     s << "  const i64 row = (i64)__builtin_amdgcn_workgroup_id_x() * 256 + "
          "(i64)__builtin_amdgcn_workitem_id_x();\n";
     s << "  if (row >= rows) return;\n";
@@ -110,6 +123,7 @@ static std::string generate(const Problem &p, int variant, bool trace) {
     for (int64_t e = 0; e < E; ++e) s << "  const float J" << e << " = jr[" << e << "];\n";
     s << "  for (int t = 0; t < T; ++t) {\n";
     s << "    const float kt = kt_tab[t];\n";
+    if (noise) s << "    const u64 nb = (g * (u64)T + (u64)t) * " << n << "ull;\n";
     if (dsb)
         for (int i = 0; i < n; ++i)
             s << "    const float S" << i << " = __builtin_copysignf(1.0f, X" << i << ");\n";
@@ -119,6 +133,7 @@ static std::string generate(const Problem &p, int variant, bool trace) {
         for (int q = p.rowptr[i]; q < p.rowptr[i + 1]; ++q)
             s << " Y" << i << " = __builtin_fmaf(J" << p.eid[q] << ", " << (dsb ? "S" : "X")
               << p.col[q] << ", Y" << i << ");";
+        if (noise) s << " Y" << i << " = __builtin_fmaf(dt_alpha, nzv(seed, nb + " << i << "ull), Y" << i << ");";
         s << "\n";
     }
     // x_i += dt a0 y_i, then the inelastic wall: |x| > 1 zeroes y, clamps x
@@ -168,15 +183,19 @@ static uint64_t fnv1a(const std::string &s) {
     return h;
 }
 
-static std::string find_clang() {
-    if (const char *e = std::getenv("QAIA_CLANG")) return e;
-    std::string root = "/opt/rocm";
-    if (const char *r = std::getenv("ROCM_PATH")) root = r;
-    return root + "/llvm/bin/clang++";
+static std::string rocm_root() {
+    if (const char *r = std::getenv("ROCM_PATH")) return r;
+    return "/opt/rocm";
 }
 
-// Compile one source to a raw gfx950 code object in a private temp dir.
-static std::vector<char> compile(const std::string &src) {
+static std::string find_clang() {
+    if (const char *e = std::getenv("QAIA_CLANG")) return e;
+    return rocm_root() + "/llvm/bin/clang++";
+}
+
+// Compile one source to a raw gfx950 code object in a private temp dir;
+// device_libs links the ROCm device library (needed by the noise variant).
+static std::vector<char> compile(const std::string &src, bool device_libs) {
     const char *tmpenv = std::getenv("TMPDIR");
     std::string tmpl = std::string(tmpenv && *tmpenv ? tmpenv : "/tmp") + "/qaia_jit_XXXXXX";
     std::vector<char> dirbuf(tmpl.begin(), tmpl.end());
@@ -197,7 +216,7 @@ static std::vector<char> compile(const std::string &src) {
                                      "--offload-device-only",
                                      "--no-gpu-bundle-output",
                                      "-nogpuinc",
-                                     "-nogpulib",
+                                     device_libs ? "--rocm-path=" + rocm_root() : std::string("-nogpulib"),
                                      "-O3",
                                      "-mcode-object-version=5",
                                      "-Xclang",
@@ -247,8 +266,8 @@ static std::vector<char> compile(const std::string &src) {
 static std::mutex g_cache_mu;
 static std::map<uint64_t, std::vector<char>> g_cache;  // source hash -> code object
 
-static JitKernel *build_kernel(const Problem &p, int variant, bool trace) {
-    const std::string src = generate(p, variant, trace);
+static JitKernel *build_kernel(const Problem &p, int variant, bool trace, bool noise) {
+    const std::string src = generate(p, variant, trace, noise);
     const uint64_t h = fnv1a(src);
     std::vector<char> code;
     {
@@ -257,7 +276,7 @@ static JitKernel *build_kernel(const Problem &p, int variant, bool trace) {
         if (it != g_cache.end()) code = it->second;
     }
     if (code.empty()) {
-        code = compile(src);
+        code = compile(src, noise);
         std::lock_guard<std::mutex> lk(g_cache_mu);
         g_cache[h] = code;
     }
@@ -282,7 +301,7 @@ void jit_prepare(Problem &p) {
     }
     for (int variant = 0; variant < 2; ++variant) {
         try {
-            p.jit[variant] = build_kernel(p, variant, false);
+            p.jit[variant] = build_kernel(p, variant, false, false);
         } catch (const Error &err) {
             p.jit_error = err.msg;
             return;
@@ -290,13 +309,15 @@ void jit_prepare(Problem &p) {
     }
 }
 
-// The tracing variants exist for trajectory tests only; they are generated on
-// first use.
-static const JitKernel *trace_kernel(const Problem &p, int variant) {
+// The tracing variants (trajectory tests) and the noise-injected variants are
+// generated on first use.
+static const JitKernel *kernel_for(const Problem &p, int variant, bool trace, bool noise) {
+    if (!trace && !noise) return p.jit[variant];
     Problem &mp = const_cast<Problem &>(p);
     std::lock_guard<std::mutex> lk(mp.mu);
-    if (!mp.jit_trace[variant]) mp.jit_trace[variant] = build_kernel(p, variant, true);
-    return mp.jit_trace[variant];
+    JitKernel *&slot = noise ? mp.jit_noise[variant][trace ? 1 : 0] : mp.jit_trace[variant];
+    if (!slot) slot = build_kernel(p, variant, trace, noise);
+    return slot;
 }
 
 void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, const qaia_schedule &s,
@@ -304,9 +325,8 @@ void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, cons
                        int32_t trace_steps, hipStream_t st) {
     QAIA_CHECK(p.jit[variant] != nullptr, QAIA_UNSUPPORTED,
                "register-resident path unavailable: " + (p.jit_error.empty() ? std::string("not built") : p.jit_error));
-    const JitKernel *k = trace != nullptr ? trace_kernel(p, variant) : p.jit[variant];
-    QAIA_CHECK(s.noise_alpha == 0.0f, QAIA_UNSUPPORTED,
-               "register-resident path runs plain SB only (noise_alpha must be 0)");
+    float dt_alpha = s.dt * s.noise_alpha;
+    const JitKernel *k = kernel_for(p, variant, trace != nullptr, dt_alpha != 0.0f);
     const int64_t rows = W * (int64_t)R;
     if (rows == 0) return;
     const int64_t blocks = (rows + 255) / 256;
@@ -321,7 +341,7 @@ void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, cons
     int R_ = R, ts = trace_steps;
     void *args[] = {(void *)&jcp, (void *)&c0s, (void *)&kt,   (void *)&rows_, (void *)&R_,
                     (void *)&T,   (void *)&dta0, (void *)&seed, (void *)&off,  (void *)&amp,
-                    (void *)&spins, (void *)&obj, (void *)&trace, (void *)&ts};
+                    (void *)&spins, (void *)&obj, (void *)&trace, (void *)&ts, (void *)&dt_alpha};
     QAIA_HIP(hipModuleLaunchKernel(k->fn, (unsigned)blocks, 1, 1, 256, 1, 1, 0, st, args, nullptr));
 }
 
