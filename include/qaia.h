@@ -169,6 +169,25 @@ int32_t qaia_workspace_status(const void *workspace, int64_t *bad_row);
 int32_t qaia_evaluate(const qaia_problem *p, const uint64_t *spins, int64_t count, int64_t *obj,
                       void *hip_stream);
 
+/* Exact cut values of consecutive spin configurations, Eq. (1), for fronts
+ * by exhaustive enumeration (the brute-force reference fronts of section
+ * "Comparison to evolutionary algorithm-based heuristics").  Row r
+ * (0 <= r < count) is the configuration whose packed spin word (bit i set
+ * <=> s_i = -1) equals first + r; obj DEVICE int64[count][m].  Since
+ * C_k(s) = C_k(-s), codes 0 .. 2^(n-1) - 1 (spin n-1 fixed to +1) cover
+ * every cut once.  Needs n <= 63 and first + count <= 2^n, else
+ * QAIA_UNSUPPORTED / QAIA_INVALID_ARGUMENT. */
+int32_t qaia_enumerate_cuts(const qaia_problem *p, uint64_t first, int64_t count, int64_t *obj,
+                            void *hip_stream);
+
+/* Uniformly random spin configurations (the random-sampling baseline of the
+ * same section): row r gets n independent fair spins drawn from the
+ * counter-based stream keyed with seed ^ 0x6a09e667f3bcc909, draw
+ * (r + offset) * ceil(n/64) + word; bits >= n are zero.  spins DEVICE
+ * uint64[count][ceil(n/64)]. */
+int32_t qaia_random_spins(int32_t n, int64_t count, uint64_t seed, uint64_t offset, uint64_t *spins,
+                          void *hip_stream);
+
 /* ---------------------------------------------------------------- precision form */
 
 /* Bytes of DEVICE workspace qaia_dense_field needs for `count` columns. */

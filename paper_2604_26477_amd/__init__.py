@@ -58,6 +58,8 @@ _SIGS = {
                                  _i32, _P]),
     "qaia_workspace_status": (_i32, [_P, C.POINTER(_i64)]),
     "qaia_evaluate": (_i32, [_P, _P, _i64, _P, _P]),
+    "qaia_enumerate_cuts": (_i32, [_P, C.c_uint64, _i64, _P, _P]),
+    "qaia_random_spins": (_i32, [_i32, _i64, C.c_uint64, C.c_uint64, _P, _P]),
     "qaia_pareto_filter_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "qaia_pareto_filter": (_i32, [_P, _i64, _i32, _P, _P, _P, _sz, _P]),
     "qaia_hypervolume": (_i32, [_P, _i64, _i32, _P, _P, _P]),
@@ -253,6 +255,52 @@ def qaia_evaluate(p: Problem, spins: torch.Tensor, obj=None, stream=None) -> tor
     obj = _dev_tensor(obj, torch.int64, (count, p.m), p.torch_device)
     _check(_lib.qaia_evaluate(p.handle, _ptr(spins), count, _ptr(obj), _stream(stream)))
     return obj
+
+
+def qaia_enumerate_cuts(p: Problem, first: int, count: int, obj=None, stream=None) -> torch.Tensor:
+    """Cut values of the configurations with spin words first .. first + count - 1."""
+    obj = _dev_tensor(obj, torch.int64, (count, p.m), p.torch_device)
+    _check(_lib.qaia_enumerate_cuts(p.handle, first, count, _ptr(obj), _stream(stream)))
+    return obj
+
+
+def qaia_random_spins(n: int, count: int, seed: int, offset: int = 0, spins=None, device=None,
+                      stream=None) -> torch.Tensor:
+    """count uniformly random spin configurations, packed like qaia_sample's spins."""
+    words = (n + 63) // 64
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    spins = _dev_tensor(spins, torch.int64, (count, words), dev)
+    _check(_lib.qaia_random_spins(n, count, seed & (2**64 - 1), offset & (2**64 - 1), _ptr(spins),
+                                  _stream(stream)))
+    return spins
+
+
+def exact_front(p: Problem, chunk: int = 1 << 26):
+    """Pareto front by exhaustive enumeration of the 2^(n-1) cuts (n <= 36 here).
+
+    Enumerates in chunks, filters each chunk together with the running front,
+    and returns (codes int64 [P] host, obj int64 [P, m] host): the spin words
+    of one representative per non-dominated objective vector (the smallest
+    code) and their cut values, in ascending code order."""
+    if p.n > 36:
+        raise ValueError("exhaustive enumeration is limited to n <= 36")
+    total = 1 << (p.n - 1)
+    dev = p.torch_device
+    front_codes = torch.zeros(0, dtype=torch.int64, device=dev)
+    front_obj = torch.zeros((0, p.m), dtype=torch.int64, device=dev)
+    first = 0
+    while first < total:
+        cnt = min(chunk, total - first)
+        pool = torch.empty((front_obj.shape[0] + cnt, p.m), dtype=torch.int64, device=dev)
+        pool[: front_obj.shape[0]] = front_obj
+        qaia_enumerate_cuts(p, first, cnt, obj=pool[front_obj.shape[0]:])
+        keep = pareto_front(pool)
+        F = front_obj.shape[0]
+        codes = torch.where(keep < F, front_codes[keep.clamp(max=max(F - 1, 0))] if F else keep,
+                            keep - F + first)
+        front_codes, front_obj = codes, pool[keep]
+        first += cnt
+    return front_codes.cpu().numpy(), front_obj.cpu().numpy()
 
 
 # ------------------------------------------------------------------ filtering

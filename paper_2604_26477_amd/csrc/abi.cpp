@@ -218,6 +218,34 @@ int32_t qaia_evaluate(const qaia_problem *pp, const uint64_t *spins, int64_t cou
     });
 }
 
+int32_t qaia_enumerate_cuts(const qaia_problem *pp, uint64_t first, int64_t count, int64_t *obj,
+                            void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(pp != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
+        QAIA_CHECK(count >= 0, QAIA_INVALID_ARGUMENT, "count must be >= 0");
+        QAIA_CHECK(count == 0 || obj != nullptr, QAIA_INVALID_ARGUMENT, "null obj");
+        const Problem &p = *reinterpret_cast<const Problem *>(pp);
+        QAIA_CHECK(p.n <= 63, QAIA_UNSUPPORTED, "enumeration needs n <= 63");
+        const uint64_t limit = 1ull << p.n;
+        QAIA_CHECK(first <= limit && (uint64_t)count <= limit - first, QAIA_INVALID_ARGUMENT,
+                   "first + count exceeds 2^n");
+        DeviceGuard g(p.device);
+        launch_enumerate(p, first, count, obj, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_random_spins(int32_t n, int64_t count, uint64_t seed, uint64_t offset, uint64_t *spins,
+                          void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(n >= 1, QAIA_INVALID_ARGUMENT, "n must be >= 1");
+        QAIA_CHECK(count >= 0, QAIA_INVALID_ARGUMENT, "count must be >= 0");
+        QAIA_CHECK(count == 0 || spins != nullptr, QAIA_INVALID_ARGUMENT, "null spins");
+        launch_random_spins(n, count, seed, offset, spins, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
 int32_t qaia_dense_field_workspace_bytes(const qaia_problem *pp, int32_t precision, int64_t count,
                                          size_t *bytes) {
     return guarded([&]() -> int32_t {

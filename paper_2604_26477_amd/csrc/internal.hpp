@@ -162,6 +162,8 @@ SparseJob sparse_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule
 // single: one job by value; otherwise `count` device jobs with block prefix `starts`
 void launch_sparse_lds_jobs(const SparseJob *single, const SparseJob *jobs, int count, const int64_t *starts,
                             int64_t blocks, int maxdeg, int npt, size_t shmem, bool dsb, hipStream_t st);
+void launch_enumerate(const Problem &p, uint64_t first, int64_t count, int64_t *obj, hipStream_t st);
+void launch_random_spins(int n, int64_t count, uint64_t seed, uint64_t offset, uint64_t *spins, hipStream_t st);
 void launch_evaluate(const Problem &p, const uint64_t *spins, int64_t count, int64_t *obj,
                      hipStream_t st);
 

@@ -475,6 +475,61 @@ __global__ __launch_bounds__(kBlock) void eval_block_kernel(
     }
 }
 
+// Enumeration: thread r evaluates the configuration with spin word first + r.
+// The edge list and weights are read at wave-uniform addresses.
+__global__ __launch_bounds__(kBlock) void enumerate_kernel(uint64_t first, int64_t count, int m, int64_t E,
+                                                           const int32_t *__restrict__ eu,
+                                                           const int32_t *__restrict__ ev,
+                                                           const int32_t *__restrict__ Wt,
+                                                           int64_t *__restrict__ obj) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= count) return;
+    const uint64_t code = first + (uint64_t)r;
+    int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t e = 0; e < E; ++e) {
+        const int64_t mask = -(int64_t)(((code >> eu[e]) ^ (code >> ev[e])) & 1ull);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < m) acc[k] += (int64_t)Wt[(int64_t)k * E + e] & mask;
+    }
+    for (int k = 0; k < m; ++k) obj[r * m + k] = acc[k];
+}
+
+void launch_enumerate(const Problem &p, uint64_t first, int64_t count, int64_t *obj, hipStream_t st) {
+    if (count == 0) return;
+    QAIA_CHECK(p.m <= 8, QAIA_UNSUPPORTED, "enumeration supports at most 8 objectives");
+    const int64_t blocks = (count + kBlock - 1) / kBlock;
+    QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many configurations for one call");
+    hipLaunchKernelGGL(enumerate_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, first, count, p.m, p.E,
+                       p.d_eu, p.d_ev, p.d_W, obj);
+    QAIA_HIP(hipGetLastError());
+}
+
+constexpr uint64_t kRandomSpinKey = 0x6a09e667f3bcc909ull;
+
+__global__ __launch_bounds__(kBlock) void random_spins_kernel(int n, int words, int64_t total, uint64_t seed,
+                                                              uint64_t offset, uint64_t *__restrict__ spins) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // (row, word) flattened
+    if (idx >= total) return;
+    const int64_t row = idx / words;
+    const int wd = (int)(idx % words);
+    uint64_t b = splitmix64(seed ^ kRandomSpinKey, ((uint64_t)row + offset) * (uint64_t)words + (uint64_t)wd);
+    const int valid = n - wd * 64;
+    if (valid < 64) b &= (1ull << valid) - 1ull;
+    spins[idx] = b;
+}
+
+void launch_random_spins(int n, int64_t count, uint64_t seed, uint64_t offset, uint64_t *spins, hipStream_t st) {
+    const int words = (n + 63) / 64;
+    const int64_t total = count * words;
+    if (total == 0) return;
+    const int64_t blocks = (total + kBlock - 1) / kBlock;
+    QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many rows for one call");
+    hipLaunchKernelGGL(random_spins_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, words, total, seed,
+                       offset, spins);
+    QAIA_HIP(hipGetLastError());
+}
+
 void launch_evaluate(const Problem &p, const uint64_t *spins, int64_t count, int64_t *obj,
                      hipStream_t st) {
     if (count == 0) return;

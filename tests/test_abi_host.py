@@ -113,3 +113,18 @@ def test_hypervolume_empty_and_clipped(q):
     assert q.qaia_hypervolume(np.zeros((0, 3), np.int64), [0, 0, 0]) == 0
     # a point below the reference in one objective contributes nothing
     assert q.qaia_hypervolume(np.array([[5, -1, 5], [2, 2, 2]]), [0, 0, 0]) == 8
+
+
+def test_random_spins_and_enumeration_argument_errors(q):
+    for args in ((0, 4, 1, 0), (10, -1, 1, 0)):
+        with pytest.raises(q.QaiaError) as ei:
+            q._check(q._lib.qaia_random_spins(*args, None, None))
+        assert ei.value.status == q.QAIA_INVALID_ARGUMENT
+    with pytest.raises(q.QaiaError) as ei:
+        q._check(q._lib.qaia_random_spins(10, 4, 1, 0, None, None))
+    assert ei.value.status == q.QAIA_INVALID_ARGUMENT
+    with pytest.raises(q.QaiaError) as ei:
+        q._check(q._lib.qaia_enumerate_cuts(None, 0, 4, None, None))
+    assert ei.value.status == q.QAIA_INVALID_ARGUMENT
+    # an empty request is valid and touches no device
+    q._check(q._lib.qaia_random_spins(10, 0, 1, 0, None, None))
