@@ -163,6 +163,57 @@ def batch_form(q, wl, torch, variant="bsb", precision="fp32", T=1500, W=1024, R=
             "batched_replica_steps_per_s": total / batch_s, "per_instance_replica_steps_per_s": total / single_s}
 
 
+def table2_form(q, wl, torch, sizes=((25, 0.5), (25, 1.0), (100, 0.5), (100, 1.0), (200, 0.5), (200, 1.0))):
+    """Budgeted protocol on correlated three-objective instances shaped like
+    Appendix E: 190 Das-Dennis weight vectors x 3000 replicas per batch
+    (570 000 candidates), noise amplitude 0.1, 50 steps (n = 25) or 1000 steps,
+    5 s (n = 25) or 10 s budgets; random uniform spins as the sanity baseline.
+    n = 25 is scored against the exact front by GPU enumeration (reference
+    point: per-objective minimum cut); larger n against the composite front of
+    all methods (reference point: minimum over all samples)."""
+    from paper_2604_26477_amd.protocols import run_budget
+    weights = wl.das_dennis_interior(3, 21)
+    out = {"workload": "Appendix-E-shaped instances (A, B in [-25, 25], J1 = A + B, J2 = 0.2 A - 5 B, J3 "
+                       "independent, Bernoulli mask); 190 Das-Dennis vectors x 3000 replicas per batch, "
+                       "alpha 0.1, dt 1.0", "instances": []}
+    for idx, (n, d) in enumerate(sizes):
+        inst = wl.appendix_e_instance(n, d, seed=5000 + idx)
+        t0 = time.perf_counter()
+        prob = q.problem_from_instance(inst, 0)
+        torch.cuda.synchronize()
+        create_s = time.perf_counter() - t0
+        budget, T = (5.0, 50) if n <= 42 else (10.0, 1000)
+        rec = {"n": n, "density": d, "edges": inst.num_edges, "budget_s": budget, "steps": T,
+               "problem_create_s": create_s}
+        runs = {}
+        for mi, method in enumerate(("random", "bsb", "dsb")):
+            runs[method] = run_budget(prob, method, budget, weights=weights, R=3000, steps=T, dt=1.0,
+                                      alpha=0.1, seed=6000 + 10 * idx + mi)
+        if n <= 30:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, ref_front, lo = q.exact_front(prob, with_min=True)
+            rec["exact_front_seconds"] = time.perf_counter() - t0
+            rec["reference"] = "exact front by enumeration of 2^%d cuts" % (n - 1)
+        else:
+            allf = np.concatenate([r["front"] for r in runs.values()])
+            keep = q.pareto_front(torch.from_numpy(allf).cuda()).cpu().numpy()
+            ref_front = allf[keep]
+            lo = np.min(np.stack([r["min"] for r in runs.values()]), axis=0)
+            rec["reference"] = "composite front of the three methods"
+        ref_set = {tuple(v) for v in ref_front}
+        hv_ref = q.qaia_hypervolume(ref_front, lo)
+        rec["reference_front_size"] = len(ref_set)
+        for method, r in runs.items():
+            got = {tuple(v) for v in r["front"]}
+            rec[method] = {"front_points": len(got & ref_set), "archive": len(got),
+                           "hv_ratio": q.qaia_hypervolume(r["front"], lo) / hv_ref if hv_ref else None,
+                           "batches": r["batches"], "samples": r["samples"], "seconds": r["seconds"]}
+        out["instances"].append(rec)
+        print(json.dumps({"table2_row": rec}), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +224,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision and learned form measurements")
     ap.add_argument("--batch-form", action="store_true",
                     help="also measure the 64-instance ragged batch (takes minutes in FP32)")
+    ap.add_argument("--table2-form", action="store_true",
+                    help="also run the budgeted protocol on Appendix-E-shaped instances (about 2 minutes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sampler's work shards over weight vectors "
@@ -276,6 +329,8 @@ def main():
         result["forms"]["learned"] = lf
         if args.batch_form:
             result["forms"]["batching"] = batch_form(q, wl, torch)
+        if args.table2_form:
+            result["forms"]["table2"] = table2_form(q, wl, torch)
         result["time_to_ref_hypervolume"] = {
             "chosen_form_s": lf["learned_proposer"]["seconds"] if lf["learned_proposer"]["reached_reference"] else None,
             "plain_fp32_s": lf["plain_fp32_uniform"]["seconds"] if lf["plain_fp32_uniform"]["reached_reference"] else None,

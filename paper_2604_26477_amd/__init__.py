@@ -275,32 +275,40 @@ def qaia_random_spins(n: int, count: int, seed: int, offset: int = 0, spins=None
     return spins
 
 
-def exact_front(p: Problem, chunk: int = 1 << 26):
+def exact_front(p: Problem, chunk: int = 1 << 26, with_min: bool = False):
     """Pareto front by exhaustive enumeration of the 2^(n-1) cuts (n <= 36 here).
 
     Enumerates in chunks, filters each chunk together with the running front,
     and returns (codes int64 [P] host, obj int64 [P, m] host): the spin words
     of one representative per non-dominated objective vector (the smallest
-    code) and their cut values, in ascending code order."""
+    code) and their cut values, in ascending code order.  with_min also
+    returns the per-objective minimum cut value over all configurations."""
     if p.n > 36:
         raise ValueError("exhaustive enumeration is limited to n <= 36")
     total = 1 << (p.n - 1)
     dev = p.torch_device
     front_codes = torch.zeros(0, dtype=torch.int64, device=dev)
     front_obj = torch.zeros((0, p.m), dtype=torch.int64, device=dev)
+    lo = None
     first = 0
     while first < total:
         cnt = min(chunk, total - first)
-        pool = torch.empty((front_obj.shape[0] + cnt, p.m), dtype=torch.int64, device=dev)
-        pool[: front_obj.shape[0]] = front_obj
-        qaia_enumerate_cuts(p, first, cnt, obj=pool[front_obj.shape[0]:])
-        keep = pareto_front(pool)
         F = front_obj.shape[0]
-        codes = torch.where(keep < F, front_codes[keep.clamp(max=max(F - 1, 0))] if F else keep,
-                            keep - F + first)
+        pool = torch.empty((F + cnt, p.m), dtype=torch.int64, device=dev)
+        pool[:F] = front_obj
+        qaia_enumerate_cuts(p, first, cnt, obj=pool[F:])
+        if with_min:
+            cmin = pool[F:].amin(dim=0)
+            lo = cmin if lo is None else torch.minimum(lo, cmin)
+        keep = pareto_front(pool)
+        old = keep < F
+        codes = keep - F + first
+        if F:
+            codes = torch.where(old, front_codes[keep.clamp(max=F - 1)], codes)
         front_codes, front_obj = codes, pool[keep]
         first += cnt
-    return front_codes.cpu().numpy(), front_obj.cpu().numpy()
+    out = (front_codes.cpu().numpy(), front_obj.cpu().numpy())
+    return out + (lo.cpu().numpy(),) if with_min else out
 
 
 # ------------------------------------------------------------------ filtering

@@ -89,6 +89,7 @@ class ProposerLoop:
         self.replay_y = torch.zeros(self.replay_cap, dtype=torch.float32, device=dev)
         self.replay_n = 0
         self.replay_slot = 0
+        self.replay_zero = torch.zeros(self.replay_cap, dtype=torch.float32, device=dev)
         self.hits = torch.zeros((0, self.m), dtype=torch.float32, device=dev)
         self.misses = torch.zeros((0, self.m), dtype=torch.float32, device=dev)
         self.round_no = 0
@@ -152,7 +153,10 @@ class ProposerLoop:
             yb = torch.empty(B, dtype=torch.float32, device=dev)
             nb = torch.tensor([B], dtype=torch.int64, device=dev)
             for _ in range(self.train_steps):
-                idx = torch.from_numpy(self.rng.choice(self.replay_n, size=B, replace=False).astype(np.int64)).to(dev)
+                # a uniform minibatch without replacement, drawn on the device:
+                # Gumbel top-k over equal scores
+                idx = qaia_topk(self.replay_zero[: self.replay_n], B, temperature=1.0,
+                                seed=self.seed * 7919 + 104729 * (self.adam_step + 1))
                 qaia_gather_rows(self.replay_X, idx, nb, xb, B)
                 qaia_gather_rows(self.replay_y, idx, nb, yb, B)
                 grad = qaia_mlp_backward(self.params, self.D, xb, yb)
