@@ -1,0 +1,57 @@
+"""GPU checks of the budgeted sampling-filtering protocol (random baseline and
+noise-injected SB) against the exact front of a small Appendix-E-shaped
+instance computed by the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_26477_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def case(q):
+    n = 14
+    inst = wl.appendix_e_instance(n, 0.7, seed=1201)
+    codes = np.arange(1 << (n - 1), dtype=np.uint64)
+    bits = (codes[:, None] >> np.arange(n, dtype=np.uint64)[None, :]) & np.uint64(1)
+    all_obj = oracle.cut_values(inst, np.where(bits == 1, -1, 1).astype(np.int8))
+    front = all_obj[oracle.pareto_filter(all_obj)]
+    return inst, q.problem_from_instance(inst), all_obj, front
+
+
+@pytest.mark.parametrize("method", ["random", "bsb", "dsb"])
+def test_budget_archive_is_a_valid_front(q, case, method):
+    from paper_2604_26477_amd.protocols import run_budget
+    inst, prob, all_obj, front = case
+    w = wl.das_dennis_interior(3, 8)
+    r = run_budget(prob, method, 0.3, weights=w, R=64, steps=50, dt=1.0, alpha=0.1, seed=3)
+    arch = r["front"]
+    assert r["batches"] >= 1 and r["samples"] == r["batches"] * w.shape[0] * 64
+    # every archived vector is a cut vector of the instance, mutually non-dominated, unique
+    all_set = {tuple(v) for v in all_obj}
+    assert all(tuple(v) in all_set for v in arch)
+    assert len(oracle.pareto_filter(arch)) == len(arch)
+    assert len({tuple(v) for v in arch}) == len(arch)
+    assert np.all(r["min"] >= all_obj.min(axis=0))
+    if method != "random":
+        # Only 26 of the 144 front points of this instance are supported (optimal
+        # for some weight vector), so recall comes from diversity: the noise
+        # term (Eq. 10) must find more front points than plain SB on the same
+        # budget (the oracle finds 41 against 18 in six batches at alpha = 0.1).
+        fset = {tuple(v) for v in front}
+        got = {tuple(v) for v in arch} & fset
+        plain = run_budget(prob, method, 0.3, weights=w, R=64, steps=50, dt=1.0, alpha=0.0, seed=3)
+        got0 = {tuple(v) for v in plain["front"]} & fset
+        print(f"{method}: {len(got)} (noise) vs {len(got0)} (plain) of {len(front)} front points")
+        assert len(got) > len(got0)
