@@ -31,6 +31,17 @@ WORKLOAD = "c2_n42_m4"
 # datasheet's 157.3 counts packed FMA).
 PEAK_FP32_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
+# HBM bytes of one qaia_sb_reg launch on this workload, from two rocprofv3
+# --pmc passes over `bench.py --traffic-probe` (FETCH_SIZE, then WRITE_SIZE,
+# KiB per dispatch), each scaled by the same counter's reading for a plain
+# 1 GiB device copy in the same process (read 524308.9375 KiB, written
+# 1048576 KiB).  Set to None whenever the generated kernel changes, until the
+# counters are taken again.
+_KIB = 1024.0
+_FETCH_SCALE = 1048576.0 / 524308.9375
+_WRITE_SCALE = 1048576.0 / 1048576.0
+SB_REG_TRAFFIC_BYTES = (3699.6875 * _FETCH_SCALE + 200000.0 * _WRITE_SCALE) * _KIB
+
 
 def fma_flops_per_replica_step(n: int, E: int) -> int:
     """Algorithmic flops of one replica-step of the sparse kernel: 2|E| field
@@ -66,10 +77,11 @@ def precision_form(q, wl, torch):
     inst = wl.random_instance(N, m, "complete", seed=3000)
     prob = q.problem_from_instance(inst, 0)
     c = torch.from_numpy(wl.dirichlet_weights(W, m, 3002)).cuda()
-    out = {"workload": f"complete N={N}, m={m}, {W} weight vectors x {R} replicas, T={T}, dSB dense"}
+    out = {"workload": f"complete N={N}, m={m}, {W} weight vectors x {R} replicas, T={T}, dSB dense, "
+                       "128 x 128 LDS-staged matrix-core tiles"}
     flops = 2 * m * N * N * W * R * T
     for prec in ("fp32", "bf16", "fp8"):
-        s = q.make_schedule("dsb", precision=prec, steps=T, dt=0.5, seed=3003, path="dense")
+        s = q.make_schedule("dsb", precision=prec, steps=T, dt=0.5, seed=3003, path="dense_staged")
         spins, obj, ws = q.qaia_sample(prob, c, R, s)  # warm-up
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -251,6 +263,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision and learned form measurements")
     ap.add_argument("--batch-form", action="store_true",
                     help="also measure the 64-instance ragged batch (takes minutes in FP32)")
+    ap.add_argument("--only-form", choices=["precision", "learned", "batching", "table2"],
+                    help="run one form measurement alone and print its JSON (for profiling)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one bSB sampling launch of the workload and one 1 GiB device copy, for HBM "
                          "counter collection (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), then exit")
@@ -269,6 +283,11 @@ def main():
 
     if args.traffic_probe:
         traffic_probe(q, wl, torch)
+        return
+    if args.only_form:
+        fn = {"precision": precision_form, "learned": learned_form, "batching": batch_form,
+              "table2": table2_form}[args.only_form]
+        print(json.dumps({"form": args.only_form, "result": fn(q, wl, torch)}), flush=True)
         return
     cfg = wl.WORKLOADS[WORKLOAD]
     inst = wl.workload_instance(WORKLOAD)
@@ -335,6 +354,9 @@ def main():
     # roofline of the dominant kernel: the generated sparse SB kernel, whose
     # launches (one bSB, one dSB per step) do the same flops each
     flops_per_launch = fma_flops_per_replica_step(inst.n, inst.num_edges) * rows * T
+    # algorithmic HBM bytes of one launch: spins + cut vectors out, folded
+    # coefficients, c0 and the step table in
+    algo_bytes = rows * 8 * (prob.words + inst.m) + W * (4 * inst.num_edges + 8) + 4 * T
     avg_launch_ms = float(np.mean([stage[f"{v}_ms"] for v in variants]))
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     result = {
@@ -350,7 +372,8 @@ def main():
                    "path": args.path},
         "roofline": {"bound": "alu", "kernel": "qaia_sb_reg (bSB and dSB launches)",
                      "achieved": achieved, "peak": PEAK_FP32_FMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_FMA_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_FMA_TFLOPS, "traffic": SB_REG_TRAFFIC_BYTES,
+                     "traffic_unit": "bytes per launch (HBM, counters)", "algorithmic_bytes_per_launch": algo_bytes,
                      "avg_launch_ms": avg_launch_ms, "flops_per_launch": flops_per_launch},
         "stages_ms": stage,
         "sampling_replica_steps_per_s": {v: rows * T / (stage[f"{v}_ms"] * 1e-3) for v in variants},

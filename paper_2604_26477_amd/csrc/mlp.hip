@@ -117,33 +117,47 @@ __global__ void back1_kernel(const uint16_t *__restrict__ P, int D, const float 
     dz1[idx] = a * g1[idx];
 }
 
-// parameter gradients: one thread per parameter, sums over the batch
-__global__ void grads_kernel(int D, const float *__restrict__ X, const float *__restrict__ a1,
-                             const float *__restrict__ a2, const float *__restrict__ dz1,
-                             const float *__restrict__ dz2, const float *__restrict__ dz3, int64_t N,
-                             float *__restrict__ grad) {
+// parameter gradients in two passes: pass 1 gives each (parameter, slice of
+// kSlice samples) one thread, pass 2 sums the slices in order (deterministic)
+constexpr int kSlice = 64;
+
+__global__ void grads_partial_kernel(int D, const float *__restrict__ X, const float *__restrict__ a1,
+                                     const float *__restrict__ a2, const float *__restrict__ dz1,
+                                     const float *__restrict__ dz2, const float *__restrict__ dz3, int64_t N,
+                                     float *__restrict__ partial) {
     const ParamOffsets o = offsets(D);
     const int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (p >= o.total) return;
+    const int64_t s0 = (int64_t)blockIdx.y * kSlice;
+    const int64_t s1 = s0 + kSlice < N ? s0 + kSlice : N;
     float g = 0.0f;
     if (p < o.b1) {
         const int h = (int)(p / D), d = (int)(p % D);
-        for (int64_t s = 0; s < N; ++s) g = fmaf(dz1[s * kH + h], X[s * D + d], g);
+        for (int64_t s = s0; s < s1; ++s) g = fmaf(dz1[s * kH + h], X[s * D + d], g);
     } else if (p < o.W2) {
         const int h = (int)(p - o.b1);
-        for (int64_t s = 0; s < N; ++s) g += dz1[s * kH + h];
+        for (int64_t s = s0; s < s1; ++s) g += dz1[s * kH + h];
     } else if (p < o.b2) {
         const int u = (int)((p - o.W2) / kH), h = (int)((p - o.W2) % kH);
-        for (int64_t s = 0; s < N; ++s) g = fmaf(dz2[s * kH + u], a1[s * kH + h], g);
+        for (int64_t s = s0; s < s1; ++s) g = fmaf(dz2[s * kH + u], a1[s * kH + h], g);
     } else if (p < o.w3) {
         const int u = (int)(p - o.b2);
-        for (int64_t s = 0; s < N; ++s) g += dz2[s * kH + u];
+        for (int64_t s = s0; s < s1; ++s) g += dz2[s * kH + u];
     } else if (p < o.b3) {
         const int u = (int)(p - o.w3);
-        for (int64_t s = 0; s < N; ++s) g = fmaf(dz3[s], a2[s * kH + u], g);
+        for (int64_t s = s0; s < s1; ++s) g = fmaf(dz3[s], a2[s * kH + u], g);
     } else {
-        for (int64_t s = 0; s < N; ++s) g += dz3[s];
+        for (int64_t s = s0; s < s1; ++s) g += dz3[s];
     }
+    partial[(int64_t)blockIdx.y * o.total + p] = g;
+}
+
+__global__ void grads_reduce_kernel(const float *__restrict__ partial, int slices, int64_t total,
+                                    float *__restrict__ grad) {
+    const int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (p >= total) return;
+    float g = 0.0f;
+    for (int j = 0; j < slices; ++j) g += partial[(int64_t)j * total + p];
     grad[p] = g;
 }
 
@@ -363,10 +377,12 @@ size_t topk_temp(int64_t N) {
 
 int64_t mlp_param_count(int D) { return offsets(D).total; }
 
+static int64_t grad_slices(int64_t B) { return (B + kSlice - 1) / kSlice; }
+
 size_t mlp_backward_ws_bytes(int D, int64_t B) {
-    (void)D;
-    // a1, g1, a2, g2, dz1, dz2 [B][H] and dz3 [B]
-    return align256(sizeof(float) * (size_t)B * kH) * 6 + align256(sizeof(float) * (size_t)B);
+    // a1, g1, a2, g2, dz1, dz2 [B][H], dz3 [B], per-slice partial gradients [slices][params]
+    return align256(sizeof(float) * (size_t)B * kH) * 6 + align256(sizeof(float) * (size_t)B) +
+           align256(sizeof(float) * (size_t)grad_slices(B) * (size_t)offsets(std::max(D, 1)).total);
 }
 
 size_t mlp_forward_ws_bytes(int64_t N) { return align256(sizeof(float) * (size_t)N * kH) * 2; }
@@ -392,13 +408,18 @@ void launch_mlp_backward(const uint16_t *P, int D, const float *X, const float *
     const size_t S = align256(sizeof(float) * (size_t)B * kH);
     float *a1 = (float *)b, *g1 = (float *)(b + S), *a2 = (float *)(b + 2 * S), *g2 = (float *)(b + 3 * S);
     float *dz1 = (float *)(b + 4 * S), *dz2 = (float *)(b + 5 * S), *dz3 = (float *)(b + 6 * S);
+    float *partial = (float *)(b + 6 * S + align256(sizeof(float) * (size_t)B));
     hipLaunchKernelGGL(layer1_kernel, dim3(blocks_for(B * kH)), dim3(kB), 0, st, P, D, X, B, a1, g1);
     hipLaunchKernelGGL(layer2_kernel, dim3(blocks_for(B * kH)), dim3(kB), 0, st, P, D, a1, B, a2, g2);
     hipLaunchKernelGGL(head_kernel, dim3(blocks_for(B)), dim3(kB), 0, st, P, D, a2, g2, B, y, loss_logits,
                        dz3, dz2);
     hipLaunchKernelGGL(back1_kernel, dim3(blocks_for(B * kH)), dim3(kB), 0, st, P, D, dz2, g1, B, dz1);
-    hipLaunchKernelGGL(grads_kernel, dim3(blocks_for(offsets(D).total)), dim3(kB), 0, st, D, X, a1, a2, dz1,
-                       dz2, dz3, B, grad);
+    const int64_t total = offsets(D).total, slices = grad_slices(B);
+    QAIA_CHECK(slices <= 65535, QAIA_INVALID_ARGUMENT, "batch too large");
+    hipLaunchKernelGGL(grads_partial_kernel, dim3(blocks_for(total), (unsigned)slices), dim3(kB), 0, st, D, X, a1,
+                       a2, dz1, dz2, dz3, B, partial);
+    hipLaunchKernelGGL(grads_reduce_kernel, dim3(blocks_for(total)), dim3(kB), 0, st, partial, (int)slices, total,
+                       grad);
     QAIA_HIP(hipGetLastError());
 }
 

@@ -2,6 +2,8 @@
 // and adjacency in LDS) and exact cut evaluation.
 #include <climits>
 
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -530,15 +532,82 @@ void launch_random_spins(int n, int64_t count, uint64_t seed, uint64_t offset, u
     QAIA_HIP(hipGetLastError());
 }
 
+// Replica-tiled evaluation for large edge sets: a block stages the spins of 64
+// replicas in LDS (32-bit words, row pitch 2*words + 1 so the 64 lanes, one
+// replica each, read distinct banks) and its four waves walk four contiguous
+// parts of the block's edge range with the edge data at wave-uniform
+// addresses.  Partial sums are combined over the waves in LDS and added to the
+// zeroed output with 64-bit integer atomics (exact, order independent).
+constexpr int kEvalTile = 64;
+
+__global__ __launch_bounds__(kBlock) void eval_zero_kernel(int64_t *__restrict__ obj, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) obj[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void eval_tile_kernel(
+    const uint64_t *__restrict__ spins, int64_t count, int words, int m, int64_t E,
+    const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, const int32_t *__restrict__ Wt,
+    int64_t edges_per_block, int64_t *__restrict__ obj) {
+    extern __shared__ uint32_t sp[];
+    __shared__ int64_t red[kBlock / 64][kEvalTile][8];
+    const int pitch = 2 * words + 1;
+    const int64_t r0 = (int64_t)blockIdx.x * kEvalTile;
+    for (int i = threadIdx.x; i < kEvalTile * 2 * words; i += kBlock) {
+        const int r = i / (2 * words), wd = i % (2 * words);
+        sp[r * pitch + wd] = r0 + r < count ? ((const uint32_t *)(spins + (r0 + r) * words))[wd] : 0u;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t b0 = (int64_t)blockIdx.y * edges_per_block;
+    const int64_t b1 = b0 + edges_per_block < E ? b0 + edges_per_block : E;
+    const int64_t part = (b1 - b0 + 3) / 4;
+    const int64_t e0 = b0 + wave * part;
+    const int64_t e1 = e0 + part < b1 ? e0 + part : b1;
+    const uint32_t *my = sp + lane * pitch;
+    int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t e = e0; e < e1; ++e) {
+        const int u = eu[e], v = ev[e];
+        const uint32_t cut = ((my[u >> 5] >> (u & 31)) ^ (my[v >> 5] >> (v & 31))) & 1u;
+        const int64_t mask = -(int64_t)cut;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < m) acc[k] += (int64_t)Wt[(int64_t)k * E + e] & mask;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) red[wave][lane][k] = acc[k];
+    __syncthreads();
+    if (wave == 0 && r0 + lane < count) {
+        for (int k = 0; k < m; ++k) {
+            const int64_t v = red[0][lane][k] + red[1][lane][k] + red[2][lane][k] + red[3][lane][k];
+            atomicAdd((unsigned long long *)&obj[(r0 + lane) * m + k], (unsigned long long)v);
+        }
+    }
+}
+
 void launch_evaluate(const Problem &p, const uint64_t *spins, int64_t count, int64_t *obj,
                      hipStream_t st) {
     if (count == 0) return;
     QAIA_CHECK(p.m <= 8, QAIA_UNSUPPORTED, "evaluation supports at most 8 objectives");
+    const size_t tile_lds = sizeof(uint32_t) * (size_t)kEvalTile * (2 * (size_t)p.words + 1);
     if (p.E <= 4096) {
         int64_t blocks = (count + kBlock - 1) / kBlock;
         QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many samples");
         hipLaunchKernelGGL(eval_thread_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, spins,
                            count, p.words, p.m, p.E, p.d_eu, p.d_ev, p.d_W, obj);
+    } else if (tile_lds <= 48 * 1024) {
+        const int64_t tiles = (count + kEvalTile - 1) / kEvalTile;
+        QAIA_CHECK(tiles <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many samples");
+        // about 2048 blocks in all, at least 4096 edges per block
+        int64_t chunks = std::max<int64_t>(1, 2048 / tiles);
+        int64_t epb = std::max<int64_t>(4096, (p.E + chunks - 1) / chunks);
+        chunks = (p.E + epb - 1) / epb;
+        QAIA_CHECK(chunks <= 65535, QAIA_INVALID_ARGUMENT, "edge set too large");
+        const int64_t n = count * p.m;
+        hipLaunchKernelGGL(eval_zero_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           obj, n);
+        hipLaunchKernelGGL(eval_tile_kernel, dim3((unsigned)tiles, (unsigned)chunks), dim3(kBlock), tile_lds, st,
+                           spins, count, p.words, p.m, p.E, p.d_eu, p.d_ev, p.d_W, epb, obj);
     } else {
         QAIA_CHECK(count <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many samples");
         hipLaunchKernelGGL(eval_block_kernel, dim3((unsigned)count), dim3(kBlock), 0, st, spins,

@@ -100,3 +100,19 @@ def test_random_spins_properties(q):
     obj = q.qaia_evaluate(prob, torch.from_numpy(a[:500]).cuda())
     torch.cuda.synchronize()
     assert np.array_equal(obj.cpu().numpy(), oracle.cut_values(inst, s[:500]))
+
+
+@pytest.mark.parametrize("n,kind,count", [(700, "p0.05", 150), (300, "complete", 64), (6100, "deg3", 40)])
+def test_evaluate_large_edge_sets(q, n, kind, count):
+    """Exact cut values through the large-graph evaluators: the replica-tiled
+    kernel (ragged last tile of 64 replicas, several edge chunks) and, past its
+    LDS budget (n > 5952), the one-block-per-replica kernel."""
+    import torch
+    inst = wl.random_instance(n, 3, kind, seed=1107, num_edges=(n * 8) // 7 if kind == "deg3" else None)
+    assert inst.num_edges > 4096
+    prob = q.problem_from_instance(inst)
+    spins = q.qaia_random_spins(n, count, seed=9)
+    obj = q.qaia_evaluate(prob, spins)
+    torch.cuda.synchronize()
+    ref = oracle.cut_values(inst, unpack_spins(spins.cpu().numpy(), n))
+    assert np.array_equal(obj.cpu().numpy(), ref)
