@@ -247,17 +247,20 @@ __global__ void front_local_kernel(const float *__restrict__ yh, int64_t Pn, int
     frac[j] = (float)close / (float)Pn;
 }
 
-__device__ float angle(const float *a, const float *b, int m) {
+template <int M>
+__device__ float angle(const float (&a)[M], const float *b) {
     // 2 atan2(|a^ - b^|, |a^ + b^|): accurate for nearly parallel vectors
     float na = 0.0f, nb = 0.0f;
-    for (int k = 0; k < m; ++k) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
         na = fmaf(a[k], a[k], na);
         nb = fmaf(b[k], b[k], nb);
     }
     na = sqrtf(na);
     nb = sqrtf(nb);
     float dm = 0.0f, dp = 0.0f;
-    for (int k = 0; k < m; ++k) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
         const float u = a[k] / na, v = b[k] / nb;
         dm = fmaf(u - v, u - v, dm);
         dp = fmaf(u + v, u + v, dp);
@@ -265,53 +268,112 @@ __device__ float angle(const float *a, const float *b, int m) {
     return 2.0f * atan2f(sqrtf(dm), sqrtf(dp));
 }
 
-// one thread per candidate weight vector
-__global__ void features_kernel(const float *__restrict__ yh, int64_t Pn, int m,
-                                const float *__restrict__ nn, const float *__restrict__ frac,
-                                const float *__restrict__ cands, int64_t N,
-                                const float *__restrict__ hits, int64_t Hn,
-                                const float *__restrict__ misses, int64_t Mn,
-                                float *__restrict__ feat) {
-    const int64_t c = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (c >= N) return;
-    float w[8];
-    for (int k = 0; k < m; ++k) w[k] = cands[c * m + k];
-    float f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (Pn > 0) {
-        float top[8];
-        for (int i = 0; i < 8; ++i) top[i] = -INFINITY;
-        int64_t jstar = 0;
-        for (int64_t j = 0; j < Pn; ++j) {
-            float v = 0.0f;
-            for (int k = 0; k < m; ++k) v = fmaf(w[k], yh[j * m + k], v);
-            if (v > top[0]) jstar = j;  // first index on ties
-            if (v > top[7]) {
-                int i = 7;
-                while (i > 0 && top[i - 1] < v) {
-                    top[i] = top[i - 1];
-                    --i;
-                }
-                top[i] = v;
-            }
+// one thread per candidate weight vector; the front and the last round's hit
+// and miss vectors are staged through LDS in chunks shared by the block.  The
+// smallest angle to a set is taken at the set member with the largest cosine
+// (the angle decreases with the cosine) and then evaluated accurately once.
+constexpr int kFChunk = 1024;
+
+template <int M>
+__device__ __forceinline__ void best_cosine(const float (&u)[M], const float *__restrict__ vecs, int64_t count,
+                                            float *stage, bool active, int64_t &best) {
+    float bc = -INFINITY;
+    best = -1;
+    for (int64_t base = 0; base < count; base += kFChunk) {
+        const int cnt = (int)(count - base < kFChunk ? count - base : kFChunk);
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += kB) {
+            float nb = 0.0f;
+#pragma unroll
+            for (int k = 0; k < M; ++k) nb = fmaf(vecs[(base + i) * M + k], vecs[(base + i) * M + k], nb);
+            const float inv = nb > 0.0f ? 1.0f / sqrtf(nb) : 0.0f;
+#pragma unroll
+            for (int k = 0; k < M; ++k) stage[i * M + k] = vecs[(base + i) * M + k] * inv;
         }
+        __syncthreads();
+        if (active)
+            for (int i = 0; i < cnt; ++i) {
+                float d = 0.0f;
+#pragma unroll
+                for (int k = 0; k < M; ++k) d = fmaf(u[k], stage[i * M + k], d);
+                if (d > bc) {
+                    bc = d;
+                    best = base + i;
+                }
+            }
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(kB) void features_kernel(const float *__restrict__ yh, int64_t Pn,
+                                                      const float *__restrict__ nn, const float *__restrict__ frac,
+                                                      const float *__restrict__ cands, int64_t N,
+                                                      const float *__restrict__ hits, int64_t Hn,
+                                                      const float *__restrict__ misses, int64_t Mn,
+                                                      float *__restrict__ feat) {
+    __shared__ float stage[kFChunk * M];
+    const int64_t c = (int64_t)blockIdx.x * kB + threadIdx.x;
+    const bool active = c < N;
+    float w[M], u[M];
+    float nw = 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        w[k] = active ? cands[c * M + k] : 0.0f;
+        nw = fmaf(w[k], w[k], nw);
+    }
+    const float inv = nw > 0.0f ? 1.0f / sqrtf(nw) : 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) u[k] = w[k] * inv;
+    float f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // max, second and eighth largest of v_j = c . yh_j over the front, and the maximiser
+    float top[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) top[i] = -INFINITY;
+    int64_t jstar = 0;
+    for (int64_t base = 0; base < Pn; base += kFChunk) {
+        const int cnt = (int)(Pn - base < kFChunk ? Pn - base : kFChunk);
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt * M; i += kB) stage[i] = yh[base * M + i];
+        __syncthreads();
+        if (active)
+            for (int jj = 0; jj < cnt; ++jj) {
+                float v = 0.0f;
+#pragma unroll
+                for (int k = 0; k < M; ++k) v = fmaf(w[k], stage[jj * M + k], v);
+                if (v > top[0]) jstar = base + jj;  // first index on ties
+                if (v > top[7]) {
+                    int i = 7;
+                    while (i > 0 && top[i - 1] < v) {
+                        top[i] = top[i - 1];
+                        --i;
+                    }
+                    top[i] = v;
+                }
+            }
+    }
+    if (Pn > 0) {
         f[0] = top[0];
         f[1] = Pn > 1 ? top[0] - top[1] : 0.0f;
         f[2] = top[0] - top[Pn < 8 ? Pn - 1 : 7];
         f[3] = nn[jstar];
         f[4] = frac[jstar];
     }
-    float a6 = 1.57079632679489662f, a7 = 1.57079632679489662f;
-    for (int64_t h = 0; h < Hn; ++h) a6 = fminf(a6, angle(w, hits + h * m, m));
-    for (int64_t h = 0; h < Mn; ++h) a7 = fminf(a7, angle(w, misses + h * m, m));
-    f[5] = Hn > 0 ? a6 : 1.57079632679489662f;
-    f[6] = Mn > 0 ? a7 : 1.57079632679489662f;
+    int64_t bh, bm;
+    best_cosine<M>(u, hits, Hn, stage, active, bh);
+    best_cosine<M>(u, misses, Mn, stage, active, bm);
+    if (!active) return;
+    f[5] = bh >= 0 ? angle<M>(w, hits + bh * M) : 1.57079632679489662f;
+    f[6] = bm >= 0 ? angle<M>(w, misses + bm * M) : 1.57079632679489662f;
     float dev = 0.0f;
-    for (int k = 0; k < m; ++k) dev = fmaxf(dev, fabsf(w[k] - 1.0f / (float)m));
+#pragma unroll
+    for (int k = 0; k < M; ++k) dev = fmaxf(dev, fabsf(w[k] - 1.0f / (float)M));
     f[7] = dev;
     // one MLP input row: the candidate followed by its eight features
-    float *row = feat + c * (m + 8);
-    for (int k = 0; k < m; ++k) row[k] = w[k];
-    for (int i = 0; i < 8; ++i) row[m + i] = f[i];
+    float *row = feat + c * (M + 8);
+#pragma unroll
+    for (int k = 0; k < M; ++k) row[k] = w[k];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) row[M + i] = f[i];
 }
 
 // ---------------------------------------------------------------- selection and labels
@@ -457,8 +519,23 @@ void launch_features(const int64_t *front, int64_t Pn, int m, const float *cands
         hipLaunchKernelGGL(front_norm_kernel, dim3(blocks_for(Pn * m)), dim3(kB), 0, st, front, Pn, m, lohi, yh);
         hipLaunchKernelGGL(front_local_kernel, dim3(blocks_for(Pn)), dim3(kB), 0, st, yh, Pn, m, nn, frac);
     }
-    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(N)), dim3(kB), 0, st, yh, Pn, m, nn, frac, cands, N,
-                       hits, Hn, misses, Mn, feat);
+#define QAIA_FEATURES(MM)                                                                                     \
+    case MM:                                                                                                  \
+        hipLaunchKernelGGL(features_kernel<MM>, dim3(blocks_for(N)), dim3(kB), 0, st, yh, Pn, nn, frac, cands, N, \
+                           hits, Hn, misses, Mn, feat);                                                       \
+        break;
+    switch (m) {
+        QAIA_FEATURES(1)
+        QAIA_FEATURES(2)
+        QAIA_FEATURES(3)
+        QAIA_FEATURES(4)
+        QAIA_FEATURES(5)
+        QAIA_FEATURES(6)
+        QAIA_FEATURES(7)
+        QAIA_FEATURES(8)
+        default: throw Error{QAIA_UNSUPPORTED, "features support 1..8 objectives"};
+    }
+#undef QAIA_FEATURES
     QAIA_HIP(hipGetLastError());
 }
 

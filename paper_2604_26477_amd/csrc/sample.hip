@@ -558,7 +558,8 @@ __global__ __launch_bounds__(kBlock) void eval_tile_kernel(
         sp[r * pitch + wd] = r0 + r < count ? ((const uint32_t *)(spins + (r0 + r) * words))[wd] : 0u;
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index is uniform across the wave; saying so lets the edge loads use scalar loads
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t b0 = (int64_t)blockIdx.y * edges_per_block;
     const int64_t b1 = b0 + edges_per_block < E ? b0 + edges_per_block : E;
     const int64_t part = (b1 - b0 + 3) / 4;
@@ -566,7 +567,28 @@ __global__ __launch_bounds__(kBlock) void eval_tile_kernel(
     const int64_t e1 = e0 + part < b1 ? e0 + part : b1;
     const uint32_t *my = sp + lane * pitch;
     int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t e = e0; e < e1; ++e) {
+    // groups of 8 edges, so the uniform edge and weight loads batch into wide scalar loads
+    int64_t e = e0;
+    for (; e + 8 <= e1; e += 8) {
+        int uu[8], vv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            uu[q] = eu[e + q];
+            vv[q] = ev[e + q];
+        }
+        int64_t mask[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            mask[q] = -(int64_t)(((my[uu[q] >> 5] >> (uu[q] & 31)) ^ (my[vv[q] >> 5] >> (vv[q] & 31))) & 1u);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k >= m) break;
+            const int32_t *wk = Wt + (int64_t)k * E + e;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[k] += (int64_t)wk[q] & mask[q];
+        }
+    }
+    for (; e < e1; ++e) {
         const int u = eu[e], v = ev[e];
         const uint32_t cut = ((my[u >> 5] >> (u & 31)) ^ (my[v >> 5] >> (v & 31))) & 1u;
         const int64_t mask = -(int64_t)cut;

@@ -12,8 +12,8 @@ Each round:
      vector 1 iff it produced a vector that enters the front and was not in
      the archive (qaia_new_point_labels);
   5. learned: the (input row, label) pairs join a ring buffer of the last
-     rounds, and a few Adam steps on minibatches drawn from it minimise the
-     mean binary cross-entropy;
+     rounds, and a few Adam steps on minibatches (windows of random
+     permutations of the buffer) minimise the mean binary cross-entropy;
   6. the new archive is the filtered set; its exact hypervolume (host) judges
      progress.
 The driver only orchestrates library calls; tensors are device memory.
@@ -148,18 +148,23 @@ class ProposerLoop:
             self.replay_y[lo:lo + self.n_sel].copy_(labels)
             self.replay_slot = (self.replay_slot + 1) % (self.replay_cap // self.n_sel)
             self.replay_n = min(self.replay_n + self.n_sel, self.replay_cap)
-            B = min(self.batch, self.replay_n)
-            xb = torch.empty((B, self.D), dtype=torch.float32, device=dev)
-            yb = torch.empty(B, dtype=torch.float32, device=dev)
-            nb = torch.tensor([B], dtype=torch.int64, device=dev)
-            for _ in range(self.train_steps):
-                # a uniform minibatch without replacement, drawn on the device:
-                # Gumbel top-k over equal scores
-                idx = qaia_topk(self.replay_zero[: self.replay_n], B, temperature=1.0,
-                                seed=self.seed * 7919 + 104729 * (self.adam_step + 1))
-                qaia_gather_rows(self.replay_X, idx, nb, xb, B)
-                qaia_gather_rows(self.replay_y, idx, nb, yb, B)
-                grad = qaia_mlp_backward(self.params, self.D, xb, yb)
+            # minibatches are consecutive windows of random permutations of the
+            # ring buffer (one permutation per pass), drawn on the device with
+            # Gumbel top-k over equal scores
+            Rn = self.replay_n
+            B = min(self.batch, Rn)
+            per_pass = Rn // B
+            nrows = torch.tensor([Rn], dtype=torch.int64, device=dev)
+            xp = torch.empty((Rn, self.D), dtype=torch.float32, device=dev)
+            yp = torch.empty(Rn, dtype=torch.float32, device=dev)
+            for t in range(self.train_steps):
+                win = t % per_pass
+                if win == 0:
+                    perm = qaia_topk(self.replay_zero[:Rn], Rn, temperature=1.0,
+                                     seed=self.seed * 7919 + 104729 * (self.adam_step + 1))
+                    qaia_gather_rows(self.replay_X, perm, nrows, xp, Rn)
+                    qaia_gather_rows(self.replay_y, perm, nrows, yp, Rn)
+                grad = qaia_mlp_backward(self.params, self.D, xp[win * B:(win + 1) * B], yp[win * B:(win + 1) * B])
                 self.adam_step += 1
                 qaia_mlp_adam(self.master, self.params, self.m1, self.m2, grad, self.adam_step, lr=self.lr)
             lab = labels.cpu().numpy() > 0.5
