@@ -89,7 +89,7 @@ BatchLayout batch_layout(const qaia_batch_item *items, int32_t count, const qaia
     B.jobs_off = off;
     off += align256(sizeof(SparseJob) * (size_t)std::max(B.n_sparse, 1));
     off += align256(sizeof(DenseJob) * (size_t)std::max(B.n_dense, 1));
-    off += 3 * align256(sizeof(int64_t) * (size_t)(count + 1));
+    off += 6 * align256(sizeof(int64_t) * (size_t)(count + 1));  // sparse starts + 5 dense groups
     B.total = off;
     return B;
 }
@@ -161,9 +161,13 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
     std::vector<int64_t> sstart(1, 0);
     int maxdeg = 4, npt = 1;
     size_t shmem = 0;
-    // dense jobs grouped by tile kind: [0] 64 x 128 tiles, [1] staged 128 x 128 tiles
-    std::vector<DenseJob> djobs[2];
-    std::vector<int64_t> dstart[2] = {std::vector<int64_t>(1, 0), std::vector<int64_t>(1, 0)};
+    // dense jobs grouped by kernel: [0] 64 x 128 register tiles (any m <= 4),
+    // [g = 1..4] staged 128 x 128 tiles for m = g, with 8-aligned job starts
+    constexpr int kGroups = 5;
+    std::vector<DenseJob> djobs[kGroups];
+    std::vector<int64_t> dstart[kGroups];
+    for (auto &v : dstart) v.assign(1, 0);
+    auto group_of = [](const ItemPlan &ip) { return ip.path == QAIA_PATH_DENSE_STAGED ? ip.p->m : 0; };
     for (int i = 0; i < count; ++i) {
         const ItemPlan &ip = B.items[i];
         const qaia_batch_item &it = items[i];
@@ -177,20 +181,29 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
             npt = std::max(npt, sh.npt);
             shmem = std::max(shmem, sh.shmem);
         } else if (is_dense_path(ip.path)) {
-            const int g = ip.path == QAIA_PATH_DENSE_STAGED ? 1 : 0;
-            DenseJob j = dense_job(*ip.p, it.W, it.R, s, iws, ip.L, nullptr, 0, g == 1);
+            const int g = group_of(ip);
+            DenseJob j = dense_job(*ip.p, it.W, it.R, s, iws, ip.L, nullptr, 0, g != 0);
             djobs[g].push_back(j);
-            dstart[g].push_back(dstart[g].back() + (int64_t)j.tiles_x * j.tiles_y);
+            const int64_t tiles = (int64_t)j.tiles_x * j.tiles_y;
+            dstart[g].push_back(dstart[g].back() + (g != 0 ? (tiles + 7) / 8 * 8 : tiles));
         }
     }
     char *jobs = base + B.jobs_off;
     SparseJob *d_sjobs = (SparseJob *)jobs;
     DenseJob *d_djobs = (DenseJob *)(jobs + align256(sizeof(SparseJob) * (size_t)std::max(B.n_sparse, 1)));
     int64_t *d_sstart = (int64_t *)((char *)d_djobs + align256(sizeof(DenseJob) * (size_t)std::max(B.n_dense, 1)));
-    DenseJob *d_djobs_g[2] = {d_djobs, d_djobs + djobs[0].size()};
-    int64_t *d_dstart_g[2];
-    d_dstart_g[0] = (int64_t *)((char *)d_sstart + align256(sizeof(int64_t) * (size_t)(count + 1)));
-    d_dstart_g[1] = (int64_t *)((char *)d_dstart_g[0] + align256(sizeof(int64_t) * (size_t)(count + 1)));
+    DenseJob *d_djobs_g[kGroups];
+    int64_t *d_dstart_g[kGroups];
+    {
+        size_t jo = 0;
+        char *so = (char *)d_sstart + align256(sizeof(int64_t) * (size_t)(count + 1));
+        for (int g = 0; g < kGroups; ++g) {
+            d_djobs_g[g] = d_djobs + jo;
+            jo += djobs[g].size();
+            d_dstart_g[g] = (int64_t *)so;
+            so += align256(sizeof(int64_t) * (size_t)(count + 1));
+        }
+    }
 
     Streams ps = private_streams(device);
     hipEvent_t ev_start, ev_fork, ev_join, ev_done;
@@ -206,7 +219,7 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
         QAIA_HIP(hipMemcpyAsync(d_sjobs, sjobs.data(), sizeof(SparseJob) * sjobs.size(), hipMemcpyHostToDevice, ps.a));
         QAIA_HIP(hipMemcpyAsync(d_sstart, sstart.data(), sizeof(int64_t) * sstart.size(), hipMemcpyHostToDevice, ps.a));
     }
-    for (int g = 0; g < 2; ++g)
+    for (int g = 0; g < kGroups; ++g)
         if (!djobs[g].empty()) {
             QAIA_HIP(hipMemcpyAsync(d_djobs_g[g], djobs[g].data(), sizeof(DenseJob) * djobs[g].size(),
                                     hipMemcpyHostToDevice, ps.a));
@@ -238,28 +251,28 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
         }
         QAIA_HIP(hipEventRecord(ev_join, ps.b));
         // branch B: dense items
-        if (!djobs[0].empty() || !djobs[1].empty()) {
-            int di[2] = {0, 0};
+        if (B.n_dense > 0) {
+            int di[kGroups] = {0, 0, 0, 0, 0};
             for (int i = 0; i < count; ++i) {
                 const ItemPlan &ip = B.items[i];
                 const qaia_batch_item &it = items[i];
                 if (is_dense_path(ip.path) && it.W * it.R > 0) {
-                    const int g = ip.path == QAIA_PATH_DENSE_STAGED ? 1 : 0;
+                    const int g = group_of(ip);
                     launch_dense_setup(*ip.p, it.weights, it.R, s, base + ip.base, ip.L, djobs[g][di[g]++], ps.a);
                 }
             }
             for (int t = 0; t < s.steps; ++t)
-                for (int g = 0; g < 2; ++g)
+                for (int g = 0; g < kGroups; ++g)
                     if (!djobs[g].empty())
-                        launch_dense_batch_step(s.precision, dsb, g == 1, d_djobs_g[g], (int)djobs[g].size(),
+                        launch_dense_batch_step(s.precision, dsb, g != 0, g, d_djobs_g[g], (int)djobs[g].size(),
                                                 d_dstart_g[g], dstart[g].back(), t, ps.a);
             QAIA_HIP(hipGetLastError());
-            di[0] = di[1] = 0;
+            for (int &d : di) d = 0;
             for (int i = 0; i < count; ++i) {
                 const ItemPlan &ip = B.items[i];
                 const qaia_batch_item &it = items[i];
                 if (is_dense_path(ip.path) && it.W * it.R > 0) {
-                    const int g = ip.path == QAIA_PATH_DENSE_STAGED ? 1 : 0;
+                    const int g = group_of(ip);
                     launch_dense_finish(*ip.p, it.R, s, base + ip.base, ip.L, djobs[g][di[g]++], it.spins, it.obj,
                                         ps.a);
                 }

@@ -496,16 +496,46 @@ __global__ __launch_bounds__(kDB) void dense_step_staged_kernel(DenseJob j, int 
     dense_step_staged_body<PREC, M, DSB, true>(j, t, bx, by, lds);
 }
 
-template <int PREC, bool DSB>
+// XCD-aware order inside one job of a grouped launch (its first block index
+// is a multiple of 8, so local & 7 is the XCD): with 8 | tiles, each XCD takes
+// a contiguous eighth of the row tiles, or else of the column tiles.
+__device__ __forceinline__ void xcd_tile_local(int64_t local, int tiles_x, int tiles_y, int &bx, int &by) {
+    const int64_t T = (int64_t)tiles_x * tiles_y;
+    if ((T & 7) == 0) {
+        const int xcd = (int)(local & 7);
+        const int64_t slot = local >> 3;
+        if ((tiles_y & 7) == 0) {
+            by = xcd * (tiles_y >> 3) + (int)(slot / tiles_x);
+            bx = (int)(slot % tiles_x);
+            return;
+        }
+        if ((tiles_x & 7) == 0) {
+            const int cx = tiles_x >> 3;
+            bx = xcd * cx + (int)(slot % cx);
+            by = (int)(slot / cx);
+            return;
+        }
+    }
+    bx = (int)(local % tiles_x);
+    by = (int)(local / tiles_x);
+}
+
+// Grouped staged step over jobs that share m = MT; job i owns blocks
+// [block_start[i], block_start[i + 1]) (padded to a multiple of 8; blocks past
+// its tiles exit at once).
+template <int PREC, int MT, bool DSB>
 __global__ __launch_bounds__(kDB) void dense_batch_step_staged_kernel(const DenseJob *__restrict__ jobs, int count,
                                                                       const int64_t *__restrict__ block_start, int t) {
-    __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<4>()];
+    __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<MT>()];
     const int64_t b = blockIdx.x;
     int i = 0;
     while (i + 1 < count && block_start[i + 1] <= b) ++i;
     const DenseJob j = jobs[i];
     const int64_t local = b - block_start[i];
-    dense_step_staged_body<PREC, 4, DSB, false>(j, t, (int)(local % j.tiles_x), (int)(local / j.tiles_x), lds);
+    if (local >= (int64_t)j.tiles_x * j.tiles_y) return;
+    int bx, by;
+    xcd_tile_local(local, j.tiles_x, j.tiles_y, bx, by);
+    dense_step_staged_body<PREC, MT, DSB, true>(j, t, bx, by, lds);
 }
 
 // Field mode (reduced-precision error reporting): field[col][k][i] = 2^e_k (J~_k Phi)_i.
@@ -794,19 +824,31 @@ static void step_dispatch(int prec, bool dsb, dim3 grid, hipStream_t st, const D
     }
 }
 
-void launch_dense_batch_step(int prec, bool dsb, bool staged, const DenseJob *jobs, int count,
+template <int PREC, bool DSB>
+static void staged_batch_launch(int mt, dim3 grid, hipStream_t st, const DenseJob *jobs, int count,
+                                const int64_t *starts, int t) {
+    switch (mt) {
+        case 1: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 1, DSB>), grid, dim3(kDB), 0, st, jobs, count, starts, t); break;
+        case 2: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 2, DSB>), grid, dim3(kDB), 0, st, jobs, count, starts, t); break;
+        case 3: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 3, DSB>), grid, dim3(kDB), 0, st, jobs, count, starts, t); break;
+        case 4: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 4, DSB>), grid, dim3(kDB), 0, st, jobs, count, starts, t); break;
+        default: throw Error{QAIA_UNSUPPORTED, "dense path supports m <= 4"};
+    }
+}
+
+void launch_dense_batch_step(int prec, bool dsb, bool staged, int mt, const DenseJob *jobs, int count,
                              const int64_t *starts, int64_t blocks, int t, hipStream_t st) {
     QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many tiles for one launch");
     if (blocks == 0) return;
     const dim3 grid((unsigned)blocks);
     if (staged) {
         if (prec == QAIA_FP32) {
-            if (dsb) hipLaunchKernelGGL((dense_batch_step_staged_kernel<QAIA_FP32, true>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
-            else hipLaunchKernelGGL((dense_batch_step_staged_kernel<QAIA_FP32, false>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+            if (dsb) staged_batch_launch<QAIA_FP32, true>(mt, grid, st, jobs, count, starts, t);
+            else staged_batch_launch<QAIA_FP32, false>(mt, grid, st, jobs, count, starts, t);
         } else if (prec == QAIA_BF16) {
-            hipLaunchKernelGGL((dense_batch_step_staged_kernel<QAIA_BF16, true>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+            staged_batch_launch<QAIA_BF16, true>(mt, grid, st, jobs, count, starts, t);
         } else {
-            hipLaunchKernelGGL((dense_batch_step_staged_kernel<QAIA_FP8, true>), grid, dim3(kDB), 0, st, jobs, count, starts, t);
+            staged_batch_launch<QAIA_FP8, true>(mt, grid, st, jobs, count, starts, t);
         }
         return;
     }

@@ -188,7 +188,8 @@ void launch_dense_setup(const Problem &p, const float *weights, int32_t R, const
                         const WsLayout &L, const DenseJob &j, hipStream_t st);
 void launch_dense_finish(const Problem &p, int32_t R, const qaia_schedule &s, void *ws, const WsLayout &L,
                          const DenseJob &j, uint64_t *spins, int64_t *obj, hipStream_t st);
-void launch_dense_batch_step(int prec, bool dsb, bool staged, const DenseJob *jobs, int count,
+// grouped step over dense jobs; staged groups share m = mt and have 8-aligned block starts
+void launch_dense_batch_step(int prec, bool dsb, bool staged, int mt, const DenseJob *jobs, int count,
                              const int64_t *starts, int64_t blocks, int t, hipStream_t st);
 inline bool is_dense_path(int path) { return path == QAIA_PATH_DENSE || path == QAIA_PATH_DENSE_STAGED; }
 size_t dense_field_ws_bytes(const Problem &p, int prec, int64_t count);
