@@ -27,6 +27,18 @@ namespace qaia {
 
 namespace {
 
+// generic-sparse kernel shapes: maximum degree class {4, 8, 16, 32} x spins
+// per lane {1, 2, 4, 8, 16}; dense groups: register tiles, staged tiles m = 1..4
+constexpr int kSparseClasses = 20;
+constexpr int kDenseGroups = 5;
+
+int sparse_class(const SparseShape &sh) {
+    const int d = sh.maxdeg <= 4 ? 0 : sh.maxdeg <= 8 ? 1 : sh.maxdeg <= 16 ? 2 : 3;
+    int q = 0;
+    while ((1 << q) < sh.npt) ++q;
+    return d * 5 + q;
+}
+
 struct ItemPlan {
     const Problem *p;
     int path;
@@ -89,7 +101,8 @@ BatchLayout batch_layout(const qaia_batch_item *items, int32_t count, const qaia
     B.jobs_off = off;
     off += align256(sizeof(SparseJob) * (size_t)std::max(B.n_sparse, 1));
     off += align256(sizeof(DenseJob) * (size_t)std::max(B.n_dense, 1));
-    off += 6 * align256(sizeof(int64_t) * (size_t)(count + 1));  // sparse starts + 5 dense groups
+    // start tables: one per generic-sparse shape class and one per dense group
+    off += (kSparseClasses + kDenseGroups) * align256(sizeof(int64_t) * (size_t)(count + 1));
     B.total = off;
     return B;
 }
@@ -157,13 +170,17 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
     const bool dsb = s.variant == QAIA_DSB;
 
     // descriptors of the batched launches
-    std::vector<SparseJob> sjobs;
-    std::vector<int64_t> sstart(1, 0);
-    int maxdeg = 4, npt = 1;
-    size_t shmem = 0;
+    // generic-sparse jobs grouped by kernel shape (maximum degree class x spins
+    // per lane), so that no item runs with a larger unrolled neighbour loop or
+    // more spins per lane than its own graph needs
+    std::vector<SparseJob> sjobs[kSparseClasses];
+    std::vector<int64_t> sstart[kSparseClasses];
+    for (auto &v : sstart) v.assign(1, 0);
+    size_t shmem[kSparseClasses] = {};
+    int smaxdeg[kSparseClasses] = {}, snpt[kSparseClasses] = {};
     // dense jobs grouped by kernel: [0] 64 x 128 register tiles (any m <= 4),
     // [g = 1..4] staged 128 x 128 tiles for m = g, with 8-aligned job starts
-    constexpr int kGroups = 5;
+    constexpr int kGroups = kDenseGroups;
     std::vector<DenseJob> djobs[kGroups];
     std::vector<int64_t> dstart[kGroups];
     for (auto &v : dstart) v.assign(1, 0);
@@ -175,11 +192,12 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
         if (it.W * it.R == 0) continue;
         if (ip.path == QAIA_PATH_SPARSE_LDS) {
             const SparseShape sh = sparse_lds_shape(*ip.p, it.W * (int64_t)it.R);
-            sjobs.push_back(sparse_job(*ip.p, it.W, it.R, s, iws, ip.L, it.spins, it.obj, nullptr, 0));
-            sstart.push_back(sstart.back() + sh.blocks);
-            maxdeg = std::max(maxdeg, sh.maxdeg);
-            npt = std::max(npt, sh.npt);
-            shmem = std::max(shmem, sh.shmem);
+            const int c = sparse_class(sh);
+            sjobs[c].push_back(sparse_job(*ip.p, it.W, it.R, s, iws, ip.L, it.spins, it.obj, nullptr, 0));
+            sstart[c].push_back(sstart[c].back() + sh.blocks);
+            smaxdeg[c] = sh.maxdeg;
+            snpt[c] = sh.npt;
+            shmem[c] = std::max(shmem[c], sh.shmem);
         } else if (is_dense_path(ip.path)) {
             const int g = group_of(ip);
             DenseJob j = dense_job(*ip.p, it.W, it.R, s, iws, ip.L, nullptr, 0, g != 0);
@@ -191,12 +209,24 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
     char *jobs = base + B.jobs_off;
     SparseJob *d_sjobs = (SparseJob *)jobs;
     DenseJob *d_djobs = (DenseJob *)(jobs + align256(sizeof(SparseJob) * (size_t)std::max(B.n_sparse, 1)));
-    int64_t *d_sstart = (int64_t *)((char *)d_djobs + align256(sizeof(DenseJob) * (size_t)std::max(B.n_dense, 1)));
+    char *starts_base = (char *)d_djobs + align256(sizeof(DenseJob) * (size_t)std::max(B.n_dense, 1));
+    const size_t start_bytes = align256(sizeof(int64_t) * (size_t)(count + 1));
+    SparseJob *d_sjobs_c[kSparseClasses];
+    int64_t *d_sstart_c[kSparseClasses];
+    {
+        size_t jo = 0;
+        for (int c = 0; c < kSparseClasses; ++c) {
+            d_sjobs_c[c] = d_sjobs + jo;
+            jo += sjobs[c].size();
+            d_sstart_c[c] = (int64_t *)(starts_base + c * start_bytes);
+        }
+    }
+    int64_t *d_sstart = (int64_t *)(starts_base + (kSparseClasses - 1) * start_bytes);
     DenseJob *d_djobs_g[kGroups];
     int64_t *d_dstart_g[kGroups];
     {
         size_t jo = 0;
-        char *so = (char *)d_sstart + align256(sizeof(int64_t) * (size_t)(count + 1));
+        char *so = (char *)d_sstart + start_bytes;
         for (int g = 0; g < kGroups; ++g) {
             d_djobs_g[g] = d_djobs + jo;
             jo += djobs[g].size();
@@ -215,10 +245,13 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
     // are ordered there too (outside the graph)
     QAIA_HIP(hipEventRecord(ev_start, caller));
     QAIA_HIP(hipStreamWaitEvent(ps.a, ev_start, 0));
-    if (!sjobs.empty()) {
-        QAIA_HIP(hipMemcpyAsync(d_sjobs, sjobs.data(), sizeof(SparseJob) * sjobs.size(), hipMemcpyHostToDevice, ps.a));
-        QAIA_HIP(hipMemcpyAsync(d_sstart, sstart.data(), sizeof(int64_t) * sstart.size(), hipMemcpyHostToDevice, ps.a));
-    }
+    for (int c = 0; c < kSparseClasses; ++c)
+        if (!sjobs[c].empty()) {
+            QAIA_HIP(hipMemcpyAsync(d_sjobs_c[c], sjobs[c].data(), sizeof(SparseJob) * sjobs[c].size(),
+                                    hipMemcpyHostToDevice, ps.a));
+            QAIA_HIP(hipMemcpyAsync(d_sstart_c[c], sstart[c].data(), sizeof(int64_t) * sstart[c].size(),
+                                    hipMemcpyHostToDevice, ps.a));
+        }
     for (int g = 0; g < kGroups; ++g)
         if (!djobs[g].empty()) {
             QAIA_HIP(hipMemcpyAsync(d_djobs_g[g], djobs[g].data(), sizeof(DenseJob) * djobs[g].size(),
@@ -239,9 +272,10 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
         QAIA_HIP(hipEventRecord(ev_fork, ps.a));
         QAIA_HIP(hipStreamWaitEvent(ps.b, ev_fork, 0));
         // branch A: sparse items
-        if (!sjobs.empty())
-            launch_sparse_lds_jobs(nullptr, d_sjobs, (int)sjobs.size(), d_sstart, sstart.back(), maxdeg, npt, shmem,
-                                   dsb, ps.b);
+        for (int c = 0; c < kSparseClasses; ++c)
+            if (!sjobs[c].empty())
+                launch_sparse_lds_jobs(nullptr, d_sjobs_c[c], (int)sjobs[c].size(), d_sstart_c[c], sstart[c].back(),
+                                       smaxdeg[c], snpt[c], shmem[c], dsb, ps.b);
         for (int i = 0; i < count; ++i) {
             const ItemPlan &ip = B.items[i];
             const qaia_batch_item &it = items[i];
