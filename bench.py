@@ -146,10 +146,16 @@ def learned_form(q, wl, torch, budget_rounds=40, ref_factor=10, max_seconds=240.
     return out
 
 
-def batch_form(q, wl, torch, variant="bsb", precision="fp32", T=1500, W=1024, R=32, count=64):
+def batch_form(q, wl, torch):
     """Batching workload: 64 ragged instances, each 1024 Dirichlet weight
     vectors x 32 replicas x 1500 steps; one autotuned batched graph launch vs
-    64 per-instance qaia_sample calls on the same paths."""
+    64 per-instance qaia_sample calls on the same paths.  The same instances
+    with 32 weight vectors each show the regime batching is for: every
+    instance alone leaves most of the GPU idle."""
+    return {"full": batch_run(q, wl, torch, W=1024), "small_instances": batch_run(q, wl, torch, W=32)}
+
+
+def batch_run(q, wl, torch, variant="bsb", precision="fp32", T=1500, W=1024, R=32, count=64):
     specs = wl.ragged_batch(count)
     items, probs = [], []
     for n, m, kind, sd in specs:
