@@ -69,11 +69,11 @@ def cpu_baseline(inst, weights, R, T, budget_s=12.0):
                       f"{T} steps, fp64 dynamics + exact cuts ({el:.1f} s)"}
 
 
-def precision_form(q, wl, torch):
+def precision_form(q, wl, torch, T=1000):
     """Precision workload: dSB on a complete 2048-node, 3-objective graph, 512
     Dirichlet weight vectors x 8 replicas (4096 matrix columns), 1000 steps,
     FP32 vs BF16 vs FP8 coupling products (exact integer cut evaluation)."""
-    N, m, W, R, T = 2048, 3, 512, 8, 1000
+    N, m, W, R = 2048, 3, 512, 8
     inst = wl.random_instance(N, m, "complete", seed=3000)
     prob = q.problem_from_instance(inst, 0)
     c = torch.from_numpy(wl.dirichlet_weights(W, m, 3002)).cuda()
@@ -271,6 +271,8 @@ def main():
                     help="also measure the 64-instance ragged batch (takes minutes in FP32)")
     ap.add_argument("--only-form", choices=["precision", "learned", "batching", "table2"],
                     help="run one form measurement alone and print its JSON (for profiling)")
+    ap.add_argument("--precision-steps", type=int, default=1000,
+                    help="SB steps of the precision form (shorter runs for counter collection)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one bSB sampling launch of the workload and one 1 GiB device copy, for HBM "
                          "counter collection (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), then exit")
@@ -291,9 +293,11 @@ def main():
         traffic_probe(q, wl, torch)
         return
     if args.only_form:
-        fn = {"precision": precision_form, "learned": learned_form, "batching": batch_form,
-              "table2": table2_form}[args.only_form]
-        print(json.dumps({"form": args.only_form, "result": fn(q, wl, torch)}), flush=True)
+        if args.only_form == "precision":
+            res = precision_form(q, wl, torch, T=args.precision_steps)
+        else:
+            res = {"learned": learned_form, "batching": batch_form, "table2": table2_form}[args.only_form](q, wl, torch)
+        print(json.dumps({"form": args.only_form, "result": res}), flush=True)
         return
     cfg = wl.WORKLOADS[WORKLOAD]
     inst = wl.workload_instance(WORKLOAD)
