@@ -120,7 +120,7 @@ __device__ __forceinline__ void mma_tile(const void *Jv, const void *phiv, int N
 
 // One step for the tile (bx, by) of a job; MT accumulator tiles, j.m <= MT.
 template <int PREC, int MT, bool DSB>
-__device__ void dense_step_body(const DenseJob &j, int t, int bx, int by) {
+__device__ __forceinline__ void dense_step_body(const DenseJob &j, int t, int bx, int by) {
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int half = l >> 5, lr = l & 31;
     const int row_w = by * kTileM + (wv & 1) * 32;
@@ -232,7 +232,14 @@ __global__ __launch_bounds__(kDB) void dense_batch_step_kernel(const DenseJob *_
 // their MFMAs are skipped by a uniform branch and their accumulators unused.
 constexpr int kT2 = 128;          // tile height and width
 constexpr int kChunkB = 64;       // bytes of k per row per chunk
-constexpr int kPitchB = 80;       // LDS row pitch (bytes), padded against bank conflicts
+constexpr int kPitchB = 64;       // LDS row pitch (bytes): one chunk row, no padding
+constexpr int kHsPitch = kT2 + 4; // LDS pitch (floats) of the epilogue's h tile
+
+// LDS address of 16-byte part p (0..3) of chunk row r: the parts of a row are
+// XOR-swizzled with bits 2..3 of the row, so that both access patterns are
+// free of bank conflicts: a 16-lane write group (4 rows x 4 parts, 256
+// contiguous bytes) and a 16-lane fragment read (16 rows, one logical part).
+__device__ __forceinline__ int lds_off(int r, int p) { return r * kPitchB + ((p ^ ((r >> 2) & 3)) << 4); }
 
 template <int MT>
 constexpr int staged_buf_bytes() { return (MT + 1) * kT2 * kPitchB; }
@@ -250,12 +257,14 @@ __device__ __forceinline__ void staged_load(u32x4 (&ra)[2 * MT], u32x4 (&rb)[2],
 // J tile and, for q < 2, column q*64 + tid/4 of the Phi tile; 16-byte part tid%4
 template <int MT>
 __device__ __forceinline__ void staged_store(char *buf, const u32x4 (&ra)[2 * MT], const u32x4 (&rb)[2], int tid) {
-    const int row = tid >> 2, part = tid & 3;
+    // every row this thread writes has (row >> 2) & 3 == (tid >> 4) & 3, so the
+    // swizzled part offset is one per-thread constant
+    const int row = tid >> 2;
+    char *base = buf + row * kPitchB + (((tid & 3) ^ ((tid >> 4) & 3)) << 4);
 #pragma unroll
-    for (int q = 0; q < 2 * MT; ++q)
-        *(u32x4 *)(buf + ((q >> 1) * kT2 + (q & 1) * 64 + row) * kPitchB + part * 16) = ra[q];
+    for (int q = 0; q < 2 * MT; ++q) *(u32x4 *)(base + ((q >> 1) * kT2 + (q & 1) * 64) * kPitchB) = ra[q];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) *(u32x4 *)(buf + (MT * kT2 + q * 64 + row) * kPitchB + part * 16) = rb[q];
+    for (int q = 0; q < 2; ++q) *(u32x4 *)(base + (MT * kT2 + q * 64) * kPitchB) = rb[q];
 }
 
 // MFMAs over one LDS chunk.  For every instruction the A and B fragments of a
@@ -264,20 +273,28 @@ __device__ __forceinline__ void staged_store(char *buf, const u32x4 (&ra)[2 * MT
 template <int PREC, int MT>
 __device__ __forceinline__ void staged_compute(const char *buf, int m, int wr, int wc, int half, int lr,
                                                f16v (&acc)[MT][2][2]) {
-    const char *As = buf;
-    const char *Bs = buf + MT * kT2 * kPitchB;
+    // every row this lane reads has (row >> 2) & 3 == (lr >> 2) & 3
+    const int sw = (lr >> 2) & 3;
+    const char *As = buf + (wr * 64 + lr) * kPitchB;              // + (k * 128 + r2 * 32) rows
+    const char *Bs = buf + (MT * kT2 + wc * 64 + lr) * kPitchB;   // + c2 * 32 rows
+    auto part = [&](int p) { return (p ^ sw) << 4; };
+    // All fragments of the chunk are read first (one scheduling region), so
+    // the MFMAs of the first k-group run while the second group's reads land.
     if constexpr (PREC == QAIA_FP32) {
+        float4 av[2][MT][2], bv[2][2];
 #pragma unroll
         for (int g = 0; g < kChunkB / 32; ++g) {  // k-groups of 8: lane half h holds k = 8g + 4h + 0..3
-            float4 av[MT][2], bv[2];
+            const int po = part(2 * g + half);
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2) bv[g][c2] = *(const float4 *)(Bs + c2 * 32 * kPitchB + po);
 #pragma unroll
             for (int k = 0; k < MT; ++k)
 #pragma unroll
-                for (int r2 = 0; r2 < 2; ++r2)
-                    av[k][r2] = *(const float4 *)(As + (k * kT2 + wr * 64 + r2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+                for (int r2 = 0; r2 < 2; ++r2) av[g][k][r2] = *(const float4 *)(As + (k * kT2 + r2 * 32) * kPitchB + po);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2)
-                bv[c2] = *(const float4 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+        for (int g = 0; g < kChunkB / 32; ++g)
 #pragma unroll
             for (int k = 0; k < MT; ++k) {
                 if (k >= m) break;
@@ -286,25 +303,27 @@ __device__ __forceinline__ void staged_compute(const char *buf, int m, int wr, i
 #pragma unroll
                     for (int c2 = 0; c2 < 2; ++c2) {
                         f16v &a = acc[k][r2][c2];
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].x, bv[c2].x, a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].y, bv[c2].y, a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].z, bv[c2].z, a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k][r2].w, bv[c2].w, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[g][k][r2].x, bv[g][c2].x, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[g][k][r2].y, bv[g][c2].y, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[g][k][r2].z, bv[g][c2].z, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[g][k][r2].w, bv[g][c2].w, a, 0, 0, 0);
                     }
             }
-        }
     } else if constexpr (PREC == QAIA_BF16) {
+        bf16x8 av[2][MT][2], bv[2][2];
 #pragma unroll
         for (int g = 0; g < kChunkB / 32; ++g) {  // lane half h holds k = 16g + 8h + 0..7
-            bf16x8 av[MT][2], bv[2];
+            const int po = part(2 * g + half);
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2) bv[g][c2] = *(const bf16x8 *)(Bs + c2 * 32 * kPitchB + po);
 #pragma unroll
             for (int k = 0; k < MT; ++k)
 #pragma unroll
-                for (int r2 = 0; r2 < 2; ++r2)
-                    av[k][r2] = *(const bf16x8 *)(As + (k * kT2 + wr * 64 + r2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+                for (int r2 = 0; r2 < 2; ++r2) av[g][k][r2] = *(const bf16x8 *)(As + (k * kT2 + r2 * 32) * kPitchB + po);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2)
-                bv[c2] = *(const bf16x8 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + g * 32 + half * 16);
+        for (int g = 0; g < kChunkB / 32; ++g)
 #pragma unroll
             for (int k = 0; k < MT; ++k) {
                 if (k >= m) break;
@@ -312,20 +331,25 @@ __device__ __forceinline__ void staged_compute(const char *buf, int m, int wr, i
                 for (int r2 = 0; r2 < 2; ++r2)
 #pragma unroll
                     for (int c2 = 0; c2 < 2; ++c2)
-                        acc[k][r2][c2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[k][r2], bv[c2], acc[k][r2][c2], 0, 0, 0);
+                        acc[k][r2][c2] =
+                            __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[g][k][r2], bv[g][c2], acc[k][r2][c2], 0, 0, 0);
             }
-        }
     } else {
-        // one 32x32x64 step per chunk: lane half h holds k = 32h + 0..31
+        // one 32x32x64 step per chunk: lane half h holds k = 32h + 0..31 (parts 2h, 2h + 1)
+        const int plo = part(2 * half), phi_ = part(2 * half + 1);
+        auto frag = [&](const char *row) {
+            const u32x4 lo = *(const u32x4 *)(row + plo);
+            const u32x4 hi = *(const u32x4 *)(row + phi_);
+            return __builtin_bit_cast(i32x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+        };
         i32x8 av[MT][2], bv[2];
 #pragma unroll
         for (int k = 0; k < MT; ++k)
 #pragma unroll
-            for (int r2 = 0; r2 < 2; ++r2)
-                av[k][r2] = *(const i32x8 *)(As + (k * kT2 + wr * 64 + r2 * 32 + lr) * kPitchB + half * 32);
+            for (int r2 = 0; r2 < 2; ++r2) av[k][r2] = frag(As + (k * kT2 + r2 * 32) * kPitchB);
 #pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2)
-            bv[c2] = *(const i32x8 *)(Bs + (wc * 64 + c2 * 32 + lr) * kPitchB + half * 32);
+        for (int c2 = 0; c2 < 2; ++c2) bv[c2] = frag(Bs + c2 * 32 * kPitchB);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int k = 0; k < MT; ++k) {
             if (k >= m) break;
@@ -382,9 +406,83 @@ __device__ __forceinline__ void mma_tile_staged(const void *Jv, const void *phiv
     }
 }
 
+// Direct-to-LDS variant of the staged tile: every chunk is copied by
+// global_load_lds (16 bytes per lane straight into LDS, no registers), into a
+// ring of D stage buffers, D - 1 chunks ahead of the MFMAs.  Wave w copies
+// granules [(w * 2(MT+1) + i) * 64, +64) of a stage with its i-th copy; lane L
+// of that copy fetches the global 16 bytes that belong at granule g = base + L
+// of the swizzled layout (row g / 4, physical part g % 4).
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int MT>
+constexpr int dma_stages() { return MT <= 3 ? 4 : 3; }
+
+template <int MT>
+__device__ __forceinline__ void dma_chunk(char *stage, const char *const (&src)[2 * (MT + 1)], size_t koff,
+                                          int wave) {
+#pragma unroll
+    for (int i = 0; i < 2 * (MT + 1); ++i)
+        __builtin_amdgcn_global_load_lds((const void *)(src[i] + koff),
+                                         (lds_void_t *)(stage + (size_t)(wave * 2 * (MT + 1) + i) * 64 * 16), 16, 0,
+                                         0);
+}
+
+// this wave's copies of all but the newest `later` chunks have landed
+template <int PER>
+__device__ __forceinline__ void dma_wait(int later) {
+    if (later >= 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * PER) : "memory");
+    else if (later == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(PER) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+template <int PREC, int MT>
+__device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, int Np_, int m, int row0, int col0,
+                                             int wr, int wc, int half, int lr, f16v (&acc)[MT][2][2], char *s0,
+                                             char *s1, char *s2, char *s3) {
+    typedef typename PrecInfo<PREC>::T T;
+    constexpr int ES = sizeof(T);
+    constexpr int PER = 2 * (MT + 1);  // copies per wave per chunk
+    constexpr int D = dma_stages<MT>();
+    const size_t Np = (size_t)Np_;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const char *src[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int g = (wave * PER + i) * 64 + lane;
+        const int R = g >> 2, p = (g & 3) ^ ((R >> 2) & 3);
+        if (R < MT * kT2) {
+            const int k0 = R / kT2 < m ? R / kT2 : m - 1;
+            src[i] = (const char *)Jv + (((size_t)k0 * Np + row0 + (R % kT2)) * Np) * ES + p * 16;
+        } else {
+            src[i] = (const char *)phiv + ((size_t)(col0 + R - MT * kT2) * Np) * ES + p * 16;
+        }
+    }
+    char *S[4] = {s0, s1, s2, s3};
+    const int nk = (int)(Np * ES / kChunkB);
+#pragma unroll
+    for (int q = 0; q < D - 1; ++q)
+        if (q < nk) dma_chunk<MT>(S[q], src, (size_t)q * kChunkB, wave);
+    for (int c0 = 0; c0 < nk; c0 += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int c = c0 + u;
+            if (c < nk) {
+                const int later = (nk - 1 - c) < (D - 2) ? (nk - 1 - c) : (D - 2);
+                dma_wait<PER>(later);
+                lds_barrier();  // chunk c is in LDS for every wave; all waves are done with chunk c - 1
+                if (c + D - 1 < nk) dma_chunk<MT>(S[(u + D - 1) % D], src, (size_t)(c + D - 1) * kChunkB, wave);
+                staged_compute<PREC, MT>(S[u], m, wr, wc, half, lr, acc);
+            }
+        }
+    }
+    lds_barrier();
+}
+
 // FIXED_M: the job's m equals MT (single-job launches), so objective guards fold away.
 template <int PREC, int MT, bool DSB, bool FIXED_M>
-__device__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by, char *lds) {
+__device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by, char *lds) {
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int half = l >> 5, lr = l & 31;
     const int wr = wv & 1, wc = wv >> 1;
@@ -405,13 +503,22 @@ __device__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by,
             for (int c2 = 0; c2 < 2; ++c2)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) acc[k][r2][c2][i] = 0.0f;
-    mma_tile_staged<PREC, M>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds);
+    constexpr int SB = staged_buf_bytes<M>();
+    constexpr int D = dma_stages<M>();
+    mma_tile_dma<PREC, M>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds, lds + SB, lds + 2 * SB,
+                          lds + (D > 3 ? 3 * SB : 0));
 
-    const float kt = j.kt_tab[t];
-    const size_t Np = (size_t)j.Np;
+    // Epilogue in two phases.  (1) h = sum_k coef_k(col) H_k(row, col) from the
+    // accumulators (same k order as the register-tile kernel) into an LDS tile
+    // hs[col][row] (pitch 132 floats: conflict-free 16-byte writes).  (2) The
+    // update: thread t takes rows 4 (t mod 32) .. +3 of columns t / 32 + 8 i, so
+    // 32 lanes read and write one 512-byte segment of a column of x, y and phi.
+    float *hs = (float *)lds;
+    __syncthreads();
 #pragma unroll
     for (int c2 = 0; c2 < 2; ++c2) {
-        const int col = col0 + wc * 64 + c2 * 32 + lr;
+        const int cl = wc * 64 + c2 * 32 + lr;
+        const int col = col0 + cl;
         float cf[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) cf[k] = k < m ? j.coef[(size_t)col * m + k] : 0.0f;
@@ -419,58 +526,77 @@ __device__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by,
         for (int r2 = 0; r2 < 2; ++r2)
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const int row = row0 + wr * 64 + r2 * 32 + acc_row(half, g * 4);
-                const size_t off = (size_t)col * Np + row;
-                float4 xv = *(const float4 *)(x_in + off);
-                float4 yv = *(const float4 *)(j.y + off);
-                float xs[4] = {xv.x, xv.y, xv.z, xv.w}, ys[4] = {yv.x, yv.y, yv.z, yv.w};
+                float hv[4];
 #pragma unroll
                 for (int ii = 0; ii < 4; ++ii) {
                     float h = 0.0f;
 #pragma unroll
                     for (int k = 0; k < M; ++k)
                         if (k < m) h = fmaf(cf[k], acc[k][r2][c2][g * 4 + ii], h);
-                    float yn = fmaf(kt, xs[ii], ys[ii]) + h;
-                    if (j.dt_alpha != 0.0f && col < j.cols && row + ii < j.N) {
-                        const uint64_t g = (uint64_t)col + j.offset;
-                        const uint64_t nidx =
-                            (g * (uint64_t)j.steps + (uint64_t)t) * (uint64_t)j.N + (uint64_t)(row + ii);
-                        yn = fmaf(j.dt_alpha, noise_value(j.seed, nidx), yn);
-                    }
-                    float xn = fmaf(j.dta0, yn, xs[ii]);
-                    wall(xn, yn);
-                    xs[ii] = xn;
-                    ys[ii] = yn;
+                    hv[ii] = h;
                 }
-                *(float4 *)(x_out + off) = make_float4(xs[0], xs[1], xs[2], xs[3]);
-                *(float4 *)(j.y + off) = make_float4(ys[0], ys[1], ys[2], ys[3]);
-                if (DSB) {
-                    if constexpr (PREC == QAIA_FP32) {
-                        *(float4 *)((float *)phi_out + off) =
-                            make_float4(sgn1(xs[0]), sgn1(xs[1]), sgn1(xs[2]), sgn1(xs[3]));
-                    } else if constexpr (PREC == QAIA_BF16) {
-                        uint2 v;
-                        v.x = (uint32_t)bf16_pm1(xs[0]) | ((uint32_t)bf16_pm1(xs[1]) << 16);
-                        v.y = (uint32_t)bf16_pm1(xs[2]) | ((uint32_t)bf16_pm1(xs[3]) << 16);
-                        *(uint2 *)((uint16_t *)phi_out + off) = v;
-                    } else {
-                        uint32_t v = (uint32_t)fp8_pm1(xs[0]) | ((uint32_t)fp8_pm1(xs[1]) << 8) |
-                                     ((uint32_t)fp8_pm1(xs[2]) << 16) | ((uint32_t)fp8_pm1(xs[3]) << 24);
-                        *(uint32_t *)((uint8_t *)phi_out + off) = v;
-                    }
-                }
-                if (j.trace != nullptr && t < j.trace_steps && col < j.cols) {
-#pragma unroll
-                    for (int ii = 0; ii < 4; ++ii)
-                        if (row + ii < j.N)
-                            j.trace[((size_t)col * j.trace_steps + t) * j.N + row + ii] = xs[ii];
-                }
+                *(float4 *)(hs + cl * kHsPitch + wr * 64 + r2 * 32 + acc_row(half, g * 4)) =
+                    make_float4(hv[0], hv[1], hv[2], hv[3]);
             }
+    }
+    __syncthreads();
+
+    const float kt = j.kt_tab[t];
+    const size_t Np = (size_t)j.Np;
+    const int tr = (threadIdx.x & 31) * 4;
+    for (int it = 0; it < kT2 / 8; ++it) {
+        const int cl = it * 8 + (threadIdx.x >> 5);
+        const int col = col0 + cl, row = row0 + tr;
+        const size_t off = (size_t)col * Np + row;
+        const float4 hv4 = *(const float4 *)(hs + cl * kHsPitch + tr);
+        const float4 xv = *(const float4 *)(x_in + off);
+        const float4 yv = *(const float4 *)(j.y + off);
+        float hv[4] = {hv4.x, hv4.y, hv4.z, hv4.w};
+        float xs[4] = {xv.x, xv.y, xv.z, xv.w}, ys[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+            float yn = fmaf(kt, xs[ii], ys[ii]) + hv[ii];
+            if (j.dt_alpha != 0.0f && col < j.cols && row + ii < j.N) {
+                const uint64_t g = (uint64_t)col + j.offset;
+                const uint64_t nidx = (g * (uint64_t)j.steps + (uint64_t)t) * (uint64_t)j.N + (uint64_t)(row + ii);
+                yn = fmaf(j.dt_alpha, noise_value(j.seed, nidx), yn);
+            }
+            float xn = fmaf(j.dta0, yn, xs[ii]);
+            wall(xn, yn);
+            xs[ii] = xn;
+            ys[ii] = yn;
+        }
+        *(float4 *)(x_out + off) = make_float4(xs[0], xs[1], xs[2], xs[3]);
+        *(float4 *)(j.y + off) = make_float4(ys[0], ys[1], ys[2], ys[3]);
+        if (DSB) {
+            if constexpr (PREC == QAIA_FP32) {
+                *(float4 *)((float *)phi_out + off) = make_float4(sgn1(xs[0]), sgn1(xs[1]), sgn1(xs[2]), sgn1(xs[3]));
+            } else if constexpr (PREC == QAIA_BF16) {
+                uint2 v;
+                v.x = (uint32_t)bf16_pm1(xs[0]) | ((uint32_t)bf16_pm1(xs[1]) << 16);
+                v.y = (uint32_t)bf16_pm1(xs[2]) | ((uint32_t)bf16_pm1(xs[3]) << 16);
+                *(uint2 *)((uint16_t *)phi_out + off) = v;
+            } else {
+                uint32_t v = (uint32_t)fp8_pm1(xs[0]) | ((uint32_t)fp8_pm1(xs[1]) << 8) |
+                             ((uint32_t)fp8_pm1(xs[2]) << 16) | ((uint32_t)fp8_pm1(xs[3]) << 24);
+                *(uint32_t *)((uint8_t *)phi_out + off) = v;
+            }
+        }
+        if (j.trace != nullptr && t < j.trace_steps && col < j.cols) {
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii)
+                if (row + ii < j.N) j.trace[((size_t)col * j.trace_steps + t) * j.N + row + ii] = xs[ii];
+        }
     }
 }
 
+// the stage ring, reused after the k loop for the 128 x 132 float h tile
 template <int MT>
-constexpr size_t staged_lds_bytes() { return 2 * (size_t)staged_buf_bytes<MT>(); }
+constexpr size_t staged_lds_bytes() {
+    return (size_t)dma_stages<MT>() * staged_buf_bytes<MT>() > sizeof(float) * kT2 * kHsPitch
+               ? (size_t)dma_stages<MT>() * staged_buf_bytes<MT>()
+               : sizeof(float) * kT2 * kHsPitch;
+}
 
 // XCD-aware tile order for a single job: blocks are dealt to the eight XCDs
 // round robin (block b runs on XCD b % 8), so when the row-tile count divides
