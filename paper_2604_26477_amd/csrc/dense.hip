@@ -28,6 +28,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "internal.hpp"
@@ -235,174 +236,88 @@ constexpr int kChunkB = 64;       // bytes of k per row per chunk
 constexpr int kPitchB = 64;       // LDS row pitch (bytes): one chunk row, no padding
 constexpr int kHsPitch = kT2 + 4; // LDS pitch (floats) of the epilogue's h tile
 
-// LDS address of 16-byte part p (0..3) of chunk row r: the parts of a row are
-// XOR-swizzled with bits 2..3 of the row, so that both access patterns are
-// free of bank conflicts: a 16-lane write group (4 rows x 4 parts, 256
-// contiguous bytes) and a 16-lane fragment read (16 rows, one logical part).
-__device__ __forceinline__ int lds_off(int r, int p) { return r * kPitchB + ((p ^ ((r >> 2) & 3)) << 4); }
+// In LDS, 16-byte part p (0..3) of chunk row r sits at r * 64 + 16 (p ^ ((r >> 2) & 3)):
+// the parts are XOR-swizzled with bits 2..3 of the row, so that a 16-lane
+// fragment read (16 rows, one logical part) and a 64-lane chunk copy (16 rows
+// x 4 parts, 1024 contiguous bytes) are both free of bank conflicts.
 
 template <int MT>
 constexpr int staged_buf_bytes() { return (MT + 1) * kT2 * kPitchB; }
 
-template <int MT>
-__device__ __forceinline__ void staged_load(u32x4 (&ra)[2 * MT], u32x4 (&rb)[2], const char *const (&pa)[2 * MT],
-                                            const char *const (&pb)[2], size_t koff) {
-#pragma unroll
-    for (int q = 0; q < 2 * MT; ++q) ra[q] = *(const u32x4 *)(pa[q] + koff);
-#pragma unroll
-    for (int q = 0; q < 2; ++q) rb[q] = *(const u32x4 *)(pb[q] + koff);
+// Work on one LDS chunk is split into two units so that the fragment reads of
+// one unit overlap the MFMAs of the other: for FP32 and BF16 a unit is one of
+// the chunk's two k-groups, for FP8 (one 32x32x64 k-group per chunk) one of
+// the two 32-row halves of the wave's rows.  For every MFMA the A and B
+// fragments of a lane come from the same k positions (lane half h, slot j),
+// so any internal k order of the instruction pairs them correctly.
+template <int PREC, int MT> struct Frags;
+template <int MT> struct Frags<QAIA_FP32, MT> { float4 a[MT][2], b[2]; };
+template <int MT> struct Frags<QAIA_BF16, MT> { bf16x8 a[MT][2], b[2]; };
+template <int MT> struct Frags<QAIA_FP8, MT> { i32x8 a[MT], b[2]; };
+
+struct LaneLds {
+    const char *a, *b;  // this lane's first A row and first B row in a stage buffer
+    int sw;             // swizzle of every row this lane reads: (lr >> 2) & 3
+    int half;
+};
+
+__device__ __forceinline__ u32x4 lds16(const char *row, int part, int sw) {
+    return *(const u32x4 *)(row + ((part ^ sw) << 4));
 }
 
-// thread tid holds, for q < 2 MT, objective q/2, row (q%2)*64 + tid/4 of the
-// J tile and, for q < 2, column q*64 + tid/4 of the Phi tile; 16-byte part tid%4
-template <int MT>
-__device__ __forceinline__ void staged_store(char *buf, const u32x4 (&ra)[2 * MT], const u32x4 (&rb)[2], int tid) {
-    // every row this thread writes has (row >> 2) & 3 == (tid >> 4) & 3, so the
-    // swizzled part offset is one per-thread constant
-    const int row = tid >> 2;
-    char *base = buf + row * kPitchB + (((tid & 3) ^ ((tid >> 4) & 3)) << 4);
-#pragma unroll
-    for (int q = 0; q < 2 * MT; ++q) *(u32x4 *)(base + ((q >> 1) * kT2 + (q & 1) * 64) * kPitchB) = ra[q];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) *(u32x4 *)(base + (MT * kT2 + q * 64) * kPitchB) = rb[q];
-}
-
-// MFMAs over one LDS chunk.  For every instruction the A and B fragments of a
-// lane come from the same k positions (lane half h, slot j), so any internal k
-// order of the instruction pairs them correctly.
 template <int PREC, int MT>
-__device__ __forceinline__ void staged_compute(const char *buf, int m, int wr, int wc, int half, int lr,
-                                               f16v (&acc)[MT][2][2]) {
-    // every row this lane reads has (row >> 2) & 3 == (lr >> 2) & 3
-    const int sw = (lr >> 2) & 3;
-    const char *As = buf + (wr * 64 + lr) * kPitchB;              // + (k * 128 + r2 * 32) rows
-    const char *Bs = buf + (MT * kT2 + wc * 64 + lr) * kPitchB;   // + c2 * 32 rows
-    auto part = [&](int p) { return (p ^ sw) << 4; };
-    // All fragments of the chunk are read first (one scheduling region), so
-    // the MFMAs of the first k-group run while the second group's reads land.
-    if constexpr (PREC == QAIA_FP32) {
-        float4 av[2][MT][2], bv[2][2];
-#pragma unroll
-        for (int g = 0; g < kChunkB / 32; ++g) {  // k-groups of 8: lane half h holds k = 8g + 4h + 0..3
-            const int po = part(2 * g + half);
-#pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2) bv[g][c2] = *(const float4 *)(Bs + c2 * 32 * kPitchB + po);
-#pragma unroll
-            for (int k = 0; k < MT; ++k)
-#pragma unroll
-                for (int r2 = 0; r2 < 2; ++r2) av[g][k][r2] = *(const float4 *)(As + (k * kT2 + r2 * 32) * kPitchB + po);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int g = 0; g < kChunkB / 32; ++g)
-#pragma unroll
-            for (int k = 0; k < MT; ++k) {
-                if (k >= m) break;
-#pragma unroll
-                for (int r2 = 0; r2 < 2; ++r2)
-#pragma unroll
-                    for (int c2 = 0; c2 < 2; ++c2) {
-                        f16v &a = acc[k][r2][c2];
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[g][k][r2].x, bv[g][c2].x, a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[g][k][r2].y, bv[g][c2].y, a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[g][k][r2].z, bv[g][c2].z, a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av[g][k][r2].w, bv[g][c2].w, a, 0, 0, 0);
-                    }
-            }
-    } else if constexpr (PREC == QAIA_BF16) {
-        bf16x8 av[2][MT][2], bv[2][2];
-#pragma unroll
-        for (int g = 0; g < kChunkB / 32; ++g) {  // lane half h holds k = 16g + 8h + 0..7
-            const int po = part(2 * g + half);
-#pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2) bv[g][c2] = *(const bf16x8 *)(Bs + c2 * 32 * kPitchB + po);
-#pragma unroll
-            for (int k = 0; k < MT; ++k)
-#pragma unroll
-                for (int r2 = 0; r2 < 2; ++r2) av[g][k][r2] = *(const bf16x8 *)(As + (k * kT2 + r2 * 32) * kPitchB + po);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int g = 0; g < kChunkB / 32; ++g)
-#pragma unroll
-            for (int k = 0; k < MT; ++k) {
-                if (k >= m) break;
-#pragma unroll
-                for (int r2 = 0; r2 < 2; ++r2)
-#pragma unroll
-                    for (int c2 = 0; c2 < 2; ++c2)
-                        acc[k][r2][c2] =
-                            __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[g][k][r2], bv[g][c2], acc[k][r2][c2], 0, 0, 0);
-            }
-    } else {
-        // one 32x32x64 step per chunk: lane half h holds k = 32h + 0..31 (parts 2h, 2h + 1)
-        const int plo = part(2 * half), phi_ = part(2 * half + 1);
+__device__ __forceinline__ void frag_load(Frags<PREC, MT> &f, const LaneLds &L, int u) {
+    if constexpr (PREC == QAIA_FP8) {
+        // unit u = rows r2 = u; lane half h holds k = 32h + 0..31 (parts 2h, 2h + 1)
         auto frag = [&](const char *row) {
-            const u32x4 lo = *(const u32x4 *)(row + plo);
-            const u32x4 hi = *(const u32x4 *)(row + phi_);
+            const u32x4 lo = lds16(row, 2 * L.half, L.sw), hi = lds16(row, 2 * L.half + 1, L.sw);
             return __builtin_bit_cast(i32x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
         };
-        i32x8 av[MT][2], bv[2];
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) f.b[c2] = frag(L.b + c2 * 32 * kPitchB);
+#pragma unroll
+        for (int k = 0; k < MT; ++k) f.a[k] = frag(L.a + (k * kT2 + u * 32) * kPitchB);
+    } else {
+        // unit u = k-group u; lane half h holds its 16 bytes at logical part 2u + h
+        typedef decltype(f.b[0]) V;
+        typedef typename std::remove_reference<V>::type VT;
+        const int p = 2 * u + L.half;
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) f.b[c2] = __builtin_bit_cast(VT, lds16(L.b + c2 * 32 * kPitchB, p, L.sw));
 #pragma unroll
         for (int k = 0; k < MT; ++k)
 #pragma unroll
-            for (int r2 = 0; r2 < 2; ++r2) av[k][r2] = frag(As + (k * kT2 + r2 * 32) * kPitchB);
-#pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2) bv[c2] = frag(Bs + c2 * 32 * kPitchB);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int k = 0; k < MT; ++k) {
-            if (k >= m) break;
-#pragma unroll
             for (int r2 = 0; r2 < 2; ++r2)
-#pragma unroll
-                for (int c2 = 0; c2 < 2; ++c2)
-                    acc[k][r2][c2] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        av[k][r2], bv[c2], acc[k][r2][c2], 0, 0, 0, 127, 0, 127);
-        }
+                f.a[k][r2] = __builtin_bit_cast(VT, lds16(L.a + (k * kT2 + r2 * 32) * kPitchB, p, L.sw));
     }
 }
 
-// Np is a multiple of 128, so the chunk count Np * sizeof(T) / 64 is even and
-// >= 2.  The loop body is branch free: loads beyond the last chunk re-read the
-// last chunk and their LDS copy is never read.
 template <int PREC, int MT>
-__device__ __forceinline__ void mma_tile_staged(const void *Jv, const void *phiv, int Np_, int m, int row0,
-                                                int col0, int wr, int wc, int half, int lr,
-                                                f16v (&acc)[MT][2][2], char *lds) {
-    typedef typename PrecInfo<PREC>::T T;
-    constexpr int ES = sizeof(T);
-    const size_t Np = (size_t)Np_;
-    const int tid = threadIdx.x;
-    const char *pa[2 * MT];
-    const char *pb[2];
+__device__ __forceinline__ void frag_mma(const Frags<PREC, MT> &f, int m, int u, f16v (&acc)[MT][2][2]) {
 #pragma unroll
-    for (int q = 0; q < 2 * MT; ++q) {
-        const int k = (q >> 1) < m ? (q >> 1) : m - 1;
-        pa[q] = (const char *)Jv + (((size_t)k * Np + row0 + (q & 1) * 64 + (tid >> 2)) * Np) * ES + (tid & 3) * 16;
-    }
+    for (int k = 0; k < MT; ++k) {
+        if (k >= m) break;
+        if constexpr (PREC == QAIA_FP8) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-        pb[q] = (const char *)phiv + ((size_t)(col0 + q * 64 + (tid >> 2)) * Np) * ES + (tid & 3) * 16;
-    char *buf0 = lds, *buf1 = lds + staged_buf_bytes<MT>();
-    const int nk = (int)(Np * ES / kChunkB);
-    const size_t last = (size_t)(nk - 1) * kChunkB;
-    u32x4 a0[2 * MT], b0[2], a1[2 * MT], b1[2];
-    staged_load<MT>(a0, b0, pa, pb, 0);
-    staged_load<MT>(a1, b1, pa, pb, kChunkB);
-    staged_store<MT>(buf0, a0, b0, tid);
-    __syncthreads();
-    for (int c = 0; c < nk; c += 2) {
-        staged_load<MT>(a0, b0, pa, pb, std::min((size_t)(c + 2) * kChunkB, last));
-        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
-        staged_compute<PREC, MT>(buf0, m, wr, wc, half, lr, acc);
-        staged_store<MT>(buf1, a1, b1, tid);
-        __syncthreads();
-        staged_load<MT>(a1, b1, pa, pb, std::min((size_t)(c + 3) * kChunkB, last));
-        __builtin_amdgcn_sched_barrier(0);
-        staged_compute<PREC, MT>(buf1, m, wr, wc, half, lr, acc);
-        staged_store<MT>(buf0, a0, b0, tid);
-        __syncthreads();
+            for (int c2 = 0; c2 < 2; ++c2)
+                acc[k][u][c2] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.a[k], f.b[c2], acc[k][u][c2], 0, 0,
+                                                                               0, 127, 0, 127);
+        } else {
+#pragma unroll
+            for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+                for (int c2 = 0; c2 < 2; ++c2) {
+                    f16v &a = acc[k][r2][c2];
+                    if constexpr (PREC == QAIA_BF16) {
+                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[k][r2], f.b[c2], a, 0, 0, 0);
+                    } else {
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].x, f.b[c2].x, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].y, f.b[c2].y, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].z, f.b[c2].z, a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].w, f.b[c2].w, a, 0, 0, 0);
+                    }
+                }
+        }
     }
 }
 
@@ -461,9 +376,16 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
     }
     char *S[4] = {s0, s1, s2, s3};
     const int nk = (int)(Np * ES / kChunkB);
+    const int sw = (lr >> 2) & 3;
+    const int aoff = (wr * 64 + lr) * kPitchB, boff = (MT * kT2 + wc * 64 + lr) * kPitchB;
+    auto lane_lds = [&](int st) { return LaneLds{S[st] + aoff, S[st] + boff, sw, half}; };
 #pragma unroll
     for (int q = 0; q < D - 1; ++q)
         if (q < nk) dma_chunk<MT>(S[q], src, (size_t)q * kChunkB, wave);
+    // Rotation: after the barrier for chunk c, unit 0 of chunk c is read while
+    // unit 1 of chunk c - 1 (already in registers) runs, then unit 1 of chunk c
+    // is read while unit 0 of chunk c runs.
+    Frags<PREC, MT> f0, f1;
     for (int c0 = 0; c0 < nk; c0 += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) {
@@ -471,12 +393,22 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
             if (c < nk) {
                 const int later = (nk - 1 - c) < (D - 2) ? (nk - 1 - c) : (D - 2);
                 dma_wait<PER>(later);
-                lds_barrier();  // chunk c is in LDS for every wave; all waves are done with chunk c - 1
+                lds_barrier();  // chunk c is in LDS for every wave; all waves are done reading chunk c - 1
                 if (c + D - 1 < nk) dma_chunk<MT>(S[(u + D - 1) % D], src, (size_t)(c + D - 1) * kChunkB, wave);
-                staged_compute<PREC, MT>(S[u], m, wr, wc, half, lr, acc);
+                const LaneLds L = lane_lds(u);
+                // scheduling barriers keep each unit's reads ahead of the other unit's MFMAs
+                frag_load<PREC, MT>(f0, L, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (c > 0) frag_mma<PREC, MT>(f1, m, 1, acc);
+                __builtin_amdgcn_sched_barrier(0);
+                frag_load<PREC, MT>(f1, L, 1);
+                __builtin_amdgcn_sched_barrier(0);
+                frag_mma<PREC, MT>(f0, m, 0, acc);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
+    frag_mma<PREC, MT>(f1, m, 1, acc);
     lds_barrier();
 }
 
