@@ -8,6 +8,10 @@ exact hypervolume of the resulting front.  Inputs are seeded synthetic
 stand-ins for the paper's 42-node instances and are resident on the GPU before
 the timed region.
 
+Consecutive steps are pipelined: the exact hypervolume of step k runs on a
+host thread while the GPU samples step k + 1; every step's hypervolume
+completes inside the timed region.
+
 Prints one JSON line.  The optional CPU baseline runs the oracle (test
 infrastructure) on a bounded slice of the same workload.
 """
@@ -323,7 +327,18 @@ def main():
           for k in ("bsb", "dsb", "filter")}
     ref = np.zeros(inst.m, np.int64)
 
+    from concurrent.futures import ThreadPoolExecutor
+    host = ThreadPoolExecutor(max_workers=1)
+
+    def hypervolume(front):
+        t0 = time.perf_counter()
+        hv = q.qaia_hypervolume(front, ref)  # the ctypes call releases the GIL
+        return hv, (time.perf_counter() - t0) * 1e3
+
     def step(record):
+        """Sampling and filtering of one batch; the host hypervolume of the
+        resulting front is handed to a worker thread, so it overlaps the
+        device work of the next step.  Returns (front size, hv future, times)."""
         times = {}
         for i, v in enumerate(variants):
             if record:
@@ -339,26 +354,29 @@ def main():
             ev["filter"][1].record(stream)
         P = int(nkeep.item())  # synchronises the stream
         front = obj[keep[:P]].cpu().numpy()
-        t0 = time.perf_counter()
-        hv = q.qaia_hypervolume(front, ref)
-        times["hv_ms"] = (time.perf_counter() - t0) * 1e3
+        fut = host.submit(hypervolume, front)
         if record:
             for k in ev:
                 times[f"{k}_ms"] = ev[k][0].elapsed_time(ev[k][1])
-        return P, hv, times
+        return P, fut, times
 
     for _ in range(args.warmup):
-        step(False)
+        step(False)[1].result()
     torch.cuda.synchronize()
-    per = []
+    per, futs = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        P, hv, times = step(True)
+        P, fut, times = step(True)
         per.append(times)
+        futs.append(fut)
+    hvs = [f.result() for f in futs]  # every step's hypervolume is inside the timed region
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
     total_rs = 2 * rows * T
+    hv = hvs[-1][0]
+    for p_, (_, hv_ms) in zip(per, hvs):
+        p_["hv_ms"] = hv_ms
     stage = {k: float(np.mean([p[k] for p in per])) for k in per[0]}
 
     # roofline of the dominant kernel: the generated sparse SB kernel, whose
@@ -379,7 +397,8 @@ def main():
                                "2000 steps, dt=0.5; bSB and dSB FP32 sampling + exact cuts, "
                                "filter of the 10.24M-vector pool, exact hypervolume (origin)",
                    "W": W, "R": R, "T": T, "n": inst.n, "m": inst.m, "edges": inst.num_edges,
-                   "path": args.path},
+                   "path": args.path,
+                   "pipelining": "host hypervolume of step k overlaps the device work of step k+1"},
         "roofline": {"bound": "alu", "kernel": "qaia_sb_reg (bSB and dSB launches)",
                      "achieved": achieved, "peak": PEAK_FP32_FMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_FMA_TFLOPS, "traffic": SB_REG_TRAFFIC_BYTES,
