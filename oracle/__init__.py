@@ -46,6 +46,8 @@ def lib():
         L.orc_objective_fields.argtypes = [C.c_int, C.c_int, C.c_int64, P, P, P, C.c_int64, P, P]
         L.orc_pareto_filter.restype = C.c_int64
         L.orc_pareto_filter.argtypes = [P, C.c_int64, C.c_int, P]
+        L.orc_pareto_ranks.restype = C.c_int32
+        L.orc_pareto_ranks.argtypes = [P, C.c_int64, C.c_int, P]
         L.orc_hypervolume.restype = C.c_int
         L.orc_hypervolume.argtypes = [P, C.c_int64, C.c_int, P, P]
         _lib = L
@@ -131,6 +133,15 @@ def pareto_filter(obj: np.ndarray) -> np.ndarray:
     keep = np.zeros(max(M, 1), np.int64)
     P = lib().orc_pareto_filter(_p(obj), M, m, _p(keep))
     return keep[:P].copy()
+
+
+def pareto_ranks(obj: np.ndarray) -> np.ndarray:
+    """Non-dominated rank of every row (0 = non-dominated), int32 [M]."""
+    obj = _c(obj, np.int64)
+    M, m = obj.shape
+    rank = np.zeros(max(M, 1), np.int32)
+    lib().orc_pareto_ranks(_p(obj), M, m, _p(rank))
+    return rank[:M].copy()
 
 
 class HypervolumeOverflow(ArithmeticError):

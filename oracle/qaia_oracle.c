@@ -317,6 +317,47 @@ int64_t orc_pareto_filter(const int64_t *obj, int64_t M, int m, int64_t *keep_id
 }
 
 /* ------------------------------------------------------------------------ */
+/* Non-dominated ranks (non-dominated sorting; the fronts behind the         */
+/* section "Pareto filtering"): rank 0 is the non-dominated set of all rows, */
+/* rank r the non-dominated set of the rows left after removing ranks < r.   */
+/* Equal rows share their rank (neither dominates the other).  Plain peeling */
+/* over the unique vectors, O(R U^2 m).  Returns the number of ranks R.      */
+/* ------------------------------------------------------------------------ */
+int32_t orc_pareto_ranks(const int64_t *obj, int64_t M, int m, int32_t *rank)
+{
+    if (M <= 0) return 0;
+    for (int64_t i = 0; i < M; ++i) rank[i] = -1;
+    int32_t r = 0;
+    int64_t left = M;
+    char *front = (char *)malloc((size_t)M);
+    while (left > 0) {
+        /* rows still unranked that no other unranked row dominates */
+        for (int64_t a = 0; a < M; ++a) {
+            front[a] = 0;
+            if (rank[a] >= 0) continue;
+            const int64_t *ya = obj + a * m;
+            int dominated = 0;
+            for (int64_t b = 0; b < M && !dominated; ++b) {
+                if (rank[b] >= 0) continue;
+                const int64_t *yb = obj + b * m;
+                int ge = 1, gt = 0;
+                for (int k = 0; k < m; ++k) {
+                    if (yb[k] < ya[k]) { ge = 0; break; }
+                    if (yb[k] > ya[k]) gt = 1;
+                }
+                dominated = ge && gt;
+            }
+            front[a] = (char)!dominated;
+        }
+        for (int64_t a = 0; a < M; ++a)
+            if (front[a]) { rank[a] = r; --left; }
+        ++r;
+    }
+    free(front);
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exact hypervolume, Eq. (6) and Appendix A: the Lebesgue measure of the    */
 /* union of boxes [r, y].  Points are first clipped to max(y, r), which      */
 /* leaves the union unchanged.  Computed by slicing along the last          */

@@ -440,3 +440,55 @@ def test_appendix_e_correlation_closed_form():
     r13 = np.corrcoef(obj[:, 0], obj[:, 2])[0, 1]
     assert abs(r12 - (-4.8 / math.sqrt(2 * 25.04))) < 0.05
     assert abs(r13) < 0.1
+
+
+# --------------------------------------------------------------------------
+# Non-dominated ranks (non-dominated sorting of the sample pool)
+# --------------------------------------------------------------------------
+
+def _longest_chain_ranks(obj):
+    """Independent characterisation: rank(y) = 1 + max rank of the rows that
+    dominate y (0 if none), by dynamic programming in an order where every
+    dominator comes first (descending coordinate sum)."""
+    M = obj.shape[0]
+    order = np.argsort(-obj.sum(axis=1), kind="stable")
+    rank = np.zeros(M, np.int64)
+    for a_pos, a in enumerate(order):
+        best = -1
+        for b in order[:a_pos]:
+            if np.all(obj[b] >= obj[a]) and np.any(obj[b] > obj[a]):
+                best = max(best, rank[b])
+        rank[a] = best + 1
+    return rank
+
+
+@pytest.mark.parametrize("m,seed", [(2, 1), (3, 2), (4, 3)])
+def test_ranks_match_longest_dominance_chain(m, seed):
+    rng = np.random.default_rng(seed)
+    obj = rng.integers(0, 6, size=(120, m)).astype(np.int64)
+    ranks = oracle.pareto_ranks(obj)
+    assert np.array_equal(ranks, _longest_chain_ranks(obj))
+
+
+def test_ranks_front_duplicates_and_permutation():
+    rng = np.random.default_rng(4)
+    obj = rng.integers(-3, 4, size=(200, 3)).astype(np.int64)
+    ranks = oracle.pareto_ranks(obj)
+    # rank 0 is exactly the set of non-dominated vectors of the filter
+    front = {tuple(v) for v in obj[oracle.pareto_filter(obj)]}
+    assert {tuple(v) for v in obj[ranks == 0]} == front
+    # equal rows share a rank; ranks are contiguous from 0
+    for v in {tuple(r) for r in obj}:
+        assert len(set(ranks[(obj == v).all(axis=1)])) == 1
+    assert set(ranks) == set(range(ranks.max() + 1))
+    # a permutation of the rows permutes the ranks
+    perm = rng.permutation(len(obj))
+    assert np.array_equal(oracle.pareto_ranks(obj[perm]), ranks[perm])
+
+
+def test_ranks_chain_and_antichain():
+    chain = np.array([[i, i] for i in range(7)], np.int64)  # totally ordered: 7 ranks
+    assert list(oracle.pareto_ranks(chain)) == [6, 5, 4, 3, 2, 1, 0]
+    anti = np.array([[i, 6 - i] for i in range(7)], np.int64)  # mutually non-dominated
+    assert list(oracle.pareto_ranks(anti)) == [0] * 7
+    assert oracle.pareto_ranks(np.zeros((0, 3), np.int64)).size == 0
