@@ -225,6 +225,22 @@ int32_t qaia_pareto_filter_workspace_bytes(int64_t M, int32_t m, size_t *bytes);
 int32_t qaia_pareto_filter(const int64_t *obj, int64_t M, int32_t m, int64_t *keep_idx,
                            int64_t *num_keep, void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* Non-dominated ranks of all M rows (non-dominated sorting of the sample
+ * pool; the fronts behind section "Pareto filtering"): rank[i] = 0 for rows
+ * whose vector no other row dominates (Eq. 4), and r for rows that become
+ * non-dominated once the rows of ranks < r are removed; equal rows share a
+ * rank.  Ranks >= max_rank are reported as max_rank.
+ *   obj:       DEVICE int64[M][m], 1 <= m <= 8, M < 2^31
+ *   rank:      DEVICE int32[M]
+ *   num_ranks: HOST; number of ranks peeled (at most max_rank; rows left
+ *              over when it equals max_rank carry rank max_rank)
+ *   workspace: DEVICE scratch of qaia_pareto_ranks_workspace_bytes(M, m).
+ * Synchronises hip_stream once per rank (the number of fronts decides the
+ * work), so it cannot be captured in a graph. */
+int32_t qaia_pareto_ranks_workspace_bytes(int64_t M, int32_t m, size_t *bytes);
+int32_t qaia_pareto_ranks(const int64_t *obj, int64_t M, int32_t m, int32_t max_rank, int32_t *rank,
+                          int32_t *num_ranks, void *workspace, size_t ws_bytes, void *hip_stream);
+
 /* ---------------------------------------------------------------- hypervolume */
 
 /* Exact hypervolume, Eq. (6) and Appendix A: the m-dimensional Lebesgue

@@ -63,6 +63,8 @@ _SIGS = {
     "qaia_pareto_filter_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "qaia_pareto_filter": (_i32, [_P, _i64, _i32, _P, _P, _P, _sz, _P]),
     "qaia_hypervolume": (_i32, [_P, _i64, _i32, _P, _P, _P]),
+    "qaia_pareto_ranks_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
+    "qaia_pareto_ranks": (_i32, [_P, _i64, _i32, _i32, _P, C.POINTER(_i32), _P, _sz, _P]),
     "qaia_dense_field_workspace_bytes": (_i32, [_P, _i32, _i64, C.POINTER(_sz)]),
     "qaia_dense_field": (_i32, [_P, _i32, _P, _i64, _P, _P, _sz, _P]),
     "qaia_mlp_param_count": (_i32, [_i32, C.POINTER(_i64)]),
@@ -340,6 +342,22 @@ def pareto_front(obj: torch.Tensor, stream=None) -> torch.Tensor:
     """Representative sample indices of the non-dominated set (synchronises)."""
     keep, num, _ = qaia_pareto_filter(obj, stream=stream)
     return keep[: int(num.item())]
+
+
+def qaia_pareto_ranks(obj: torch.Tensor, max_rank: int = 2**31 - 1, rank=None, workspace=None, stream=None):
+    """Non-dominated rank of every row (int32 [M] device) and the number of ranks peeled."""
+    if obj.dtype != torch.int64 or not obj.is_contiguous() or obj.dim() != 2:
+        raise ValueError("obj must be a contiguous int64 tensor [M, m]")
+    M, m = obj.shape
+    b = C.c_size_t()
+    _check(_lib.qaia_pareto_ranks_workspace_bytes(M, m, C.byref(b)))
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(max(b.value, 1), dtype=torch.uint8, device=obj.device)
+    rank = _dev_tensor(rank, torch.int32, (max(M, 1),), obj.device)
+    n = C.c_int32()
+    _check(_lib.qaia_pareto_ranks(_ptr(obj), M, m, max_rank, _ptr(rank), C.byref(n), _ptr(workspace),
+                                  workspace.numel(), _stream(stream)))
+    return rank[:M], n.value
 
 
 # ------------------------------------------------------------------ hypervolume

@@ -297,6 +297,29 @@ int32_t qaia_pareto_filter(const int64_t *obj, int64_t M, int32_t m, int64_t *ke
     });
 }
 
+int32_t qaia_pareto_ranks_workspace_bytes(int64_t M, int32_t m, size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(bytes != nullptr, QAIA_INVALID_ARGUMENT, "null argument");
+        QAIA_CHECK(M >= 0 && M < (int64_t(1) << 31), QAIA_INVALID_ARGUMENT, "M must be in [0, 2^31)");
+        QAIA_CHECK(m >= 1 && m <= 8, QAIA_INVALID_ARGUMENT, "m must be in [1, 8]");
+        *bytes = pareto_ranks_ws_bytes(M, m);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_pareto_ranks(const int64_t *obj, int64_t M, int32_t m, int32_t max_rank, int32_t *rank,
+                          int32_t *num_ranks, void *workspace, size_t ws_bytes, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(M >= 0 && M < (int64_t(1) << 31), QAIA_INVALID_ARGUMENT, "M must be in [0, 2^31)");
+        QAIA_CHECK(m >= 1 && m <= 8, QAIA_INVALID_ARGUMENT, "m must be in [1, 8]");
+        QAIA_CHECK(max_rank >= 1, QAIA_INVALID_ARGUMENT, "max_rank must be >= 1");
+        QAIA_CHECK(num_ranks != nullptr, QAIA_INVALID_ARGUMENT, "null num_ranks");
+        QAIA_CHECK(M == 0 || (obj && rank && workspace), QAIA_INVALID_ARGUMENT, "null obj, rank or workspace");
+        *num_ranks = launch_pareto_ranks(obj, M, m, max_rank, rank, workspace, ws_bytes, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
 int32_t qaia_hypervolume(const int64_t *pts, int64_t P, int32_t m, const int64_t *ref,
                          uint64_t hv[4], double *hv_approx) {
     return guarded([&]() -> int32_t {

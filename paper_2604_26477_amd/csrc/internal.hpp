@@ -227,6 +227,9 @@ void autotune(qaia_batch_item *items, int32_t count, const qaia_schedule &s, int
 size_t autotune_ws_bytes(const qaia_batch_item *items, int32_t count, const qaia_schedule &s, int32_t probe_steps);
 
 // pareto filter (pareto.hip)
+size_t pareto_ranks_ws_bytes(int64_t M, int32_t m);
+int32_t launch_pareto_ranks(const int64_t *obj, int64_t M, int32_t m, int32_t max_rank, int32_t *rank, void *ws,
+                            size_t ws_bytes, hipStream_t st);
 size_t pareto_ws_bytes(int64_t M, int32_t m);
 void launch_pareto(const int64_t *obj, int64_t M, int32_t m, int64_t *keep, int64_t *num_keep,
                    void *ws, size_t ws_bytes, hipStream_t st);

@@ -133,8 +133,44 @@ __global__ __launch_bounds__(kB) void global_nd_kernel(const int64_t *__restrict
     if (alive) keep[sidx[j]] = 1;
 }
 
+// ranks: rows of the current list that entered rank r leave the list
+__global__ void rank_assign_kernel(const int32_t *__restrict__ list, const int64_t *__restrict__ d_n,
+                                   uint8_t *__restrict__ keep, int32_t r, int32_t *__restrict__ rank,
+                                   uint8_t *__restrict__ rem) {
+    const int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (p >= *d_n) return;
+    const int32_t s = list[p];
+    const bool in_front = keep[s] != 0;
+    if (in_front) {
+        rank[s] = r;
+        keep[s] = 0;
+    }
+    rem[p] = in_front ? 0 : 1;
+}
+
+__global__ void rank_fill_kernel(const int32_t *__restrict__ list, int64_t n, int32_t r, int32_t *__restrict__ rank) {
+    const int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (p < n) rank[list[p]] = r;
+}
+
+// every sorted position takes the rank of its run's representative
+__global__ void rank_spread_kernel(const int32_t *__restrict__ sorted, const int32_t *__restrict__ run,
+                                   const int32_t *__restrict__ uidx, int64_t M, int32_t *__restrict__ rank) {
+    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i >= M) return;
+    const int32_t rep = uidx[run[i] - 1];
+    const int32_t s = sorted[i];
+    if (s != rep) rank[s] = rank[rep];
+}
+
+__global__ void u8_to_i32_kernel(const uint8_t *__restrict__ f, int32_t *__restrict__ o, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i < n) o[i] = f[i];
+}
+
 struct PLayout {
     size_t idxA, idxB, keyA, keyB, flag, uidx, sidx, keep, counts, temp, temp_bytes, total;
+    size_t list2 = 0, rem = 0, run = 0;  // ranks only
 };
 
 size_t temp_bytes_needed(int64_t M) {
@@ -151,7 +187,7 @@ size_t temp_bytes_needed(int64_t M) {
     return std::max(sort_b, std::max(sel_b, sel2_b));
 }
 
-PLayout layout(int64_t M) {
+PLayout layout(int64_t M, bool ranks = false) {
     PLayout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -170,6 +206,15 @@ PLayout layout(int64_t M) {
     L.keep = take(Mz);
     L.counts = take(8 * 4);
     L.temp_bytes = temp_bytes_needed(std::max<int64_t>(M, 1));
+    if (ranks) {
+        L.list2 = take(4 * Mz);
+        L.rem = take(Mz);
+        L.run = take(4 * Mz);
+        size_t scan_b = 0;
+        hipcub::DeviceScan::InclusiveSum(nullptr, scan_b, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                         (int)std::max<int64_t>(M, 1), (hipStream_t)0);
+        L.temp_bytes = std::max(L.temp_bytes, scan_b);
+    }
     L.temp = take(L.temp_bytes);
     L.total = off;
     return L;
@@ -243,6 +288,92 @@ void launch_pareto(const int64_t *obj, int64_t M, int32_t m, int64_t *keep_idx, 
         hipcub::CountingInputIterator<int64_t> it(0);
         QAIA_CUB(hipcub::DeviceSelect::Flagged(temp, t, it, keep, keep_idx, num_keep, M, st));
     }
+}
+
+size_t pareto_ranks_ws_bytes(int64_t M, int32_t m) {
+    (void)m;
+    return layout(M, true).total;
+}
+
+// Non-dominated sorting by peeling: sort and de-duplicate as the filter does,
+// then repeatedly take the non-dominated set of the remaining unique vectors
+// (chunk pass + survivor pass, as above) as the next rank and remove it; the
+// list stays in lexicographic order, a linear extension of dominance, which
+// the two passes rely on.  Duplicates take their representative's rank.
+int32_t launch_pareto_ranks(const int64_t *obj, int64_t M, int32_t m, int32_t max_rank, int32_t *rank, void *ws,
+                            size_t ws_bytes, hipStream_t st) {
+    if (M == 0) return 0;
+    const PLayout L = layout(M, true);
+    QAIA_CHECK(ws_bytes >= L.total, QAIA_WORKSPACE_TOO_SMALL,
+               "pareto ranks workspace needs " + std::to_string(L.total) + " bytes");
+    QAIA_CHECK(M <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many rows");
+    char *b = (char *)ws;
+    int32_t *idxA = (int32_t *)(b + L.idxA), *idxB = (int32_t *)(b + L.idxB);
+    int64_t *keyA = (int64_t *)(b + L.keyA), *keyB = (int64_t *)(b + L.keyB);
+    uint8_t *flag = (uint8_t *)(b + L.flag), *keep = (uint8_t *)(b + L.keep), *rem = (uint8_t *)(b + L.rem);
+    int32_t *uidx = (int32_t *)(b + L.uidx), *sidx = (int32_t *)(b + L.sidx), *list2 = (int32_t *)(b + L.list2);
+    int32_t *run = (int32_t *)(b + L.run);
+    int64_t *counts = (int64_t *)(b + L.counts);
+    void *temp = b + L.temp;
+    const size_t tb = L.temp_bytes;
+
+    hipLaunchKernelGGL(iota_kernel, dim3(grid_for(M)), dim3(kB), 0, st, idxA, M);
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(M)), dim3(kB), 0, st, keep, M, (uint8_t)0);
+    QAIA_HIP(hipGetLastError());
+    int32_t *cur = idxA, *nxt = idxB;
+    for (int k = m - 1; k >= 0; --k) {
+        hipLaunchKernelGGL(gather_key_kernel, dim3(grid_for(M)), dim3(kB), 0, st, obj, m, k, cur, keyA, M);
+        QAIA_HIP(hipGetLastError());
+        size_t t = tb;
+        QAIA_CUB(hipcub::DeviceRadixSort::SortPairsDescending(temp, t, keyA, keyB, cur, nxt, (int)M, 0, 64, st));
+        std::swap(cur, nxt);
+    }
+    // cur: sorted sample indices; nxt is free from here on
+    hipLaunchKernelGGL(unique_flag_kernel, dim3(grid_for(M)), dim3(kB), 0, st, obj, m, cur, flag, M);
+    hipLaunchKernelGGL(u8_to_i32_kernel, dim3(grid_for(M)), dim3(kB), 0, st, flag, nxt, M);
+    QAIA_HIP(hipGetLastError());
+    {
+        size_t t = tb;
+        QAIA_CUB(hipcub::DeviceScan::InclusiveSum(temp, t, nxt, run, (int)M, st));
+        t = tb;
+        QAIA_CUB(hipcub::DeviceSelect::Flagged(temp, t, cur, flag, uidx, counts + 0, M, st));
+    }
+    // the working list starts as the unique representatives (a copy, uidx is kept for the spread)
+    int32_t *list = nxt, *other = list2;
+    QAIA_HIP(hipMemcpyAsync(list, uidx, sizeof(int32_t) * (size_t)M, hipMemcpyDeviceToDevice, st));
+    int64_t n = 0;
+    QAIA_HIP(hipMemcpyAsync(&n, counts + 0, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    QAIA_HIP(hipStreamSynchronize(st));
+    int32_t r = 0;
+    while (n > 0) {
+        if (r == max_rank) {
+            hipLaunchKernelGGL(rank_fill_kernel, dim3(grid_for(n)), dim3(kB), 0, st, list, n, r, rank);
+            QAIA_HIP(hipGetLastError());
+            break;
+        }
+        hipLaunchKernelGGL(chunk_nd_kernel, dim3(grid_for(n, kChunk)), dim3(kB), 0, st, obj, m, list, counts + 0,
+                           n, flag);
+        QAIA_HIP(hipGetLastError());
+        {
+            size_t t = tb;
+            QAIA_CUB(hipcub::DeviceSelect::Flagged(temp, t, list, flag, sidx, counts + 1, n, st));
+        }
+        hipLaunchKernelGGL(global_nd_kernel, dim3(grid_for(n)), dim3(kB), 0, st, obj, m, sidx, counts + 1, keep);
+        hipLaunchKernelGGL(rank_assign_kernel, dim3(grid_for(n)), dim3(kB), 0, st, list, counts + 0, keep, r, rank,
+                           rem);
+        QAIA_HIP(hipGetLastError());
+        {
+            size_t t = tb;
+            QAIA_CUB(hipcub::DeviceSelect::Flagged(temp, t, list, rem, other, counts + 0, n, st));
+        }
+        std::swap(list, other);
+        QAIA_HIP(hipMemcpyAsync(&n, counts + 0, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        QAIA_HIP(hipStreamSynchronize(st));
+        ++r;
+    }
+    hipLaunchKernelGGL(rank_spread_kernel, dim3(grid_for(M)), dim3(kB), 0, st, cur, run, uidx, M, rank);
+    QAIA_HIP(hipGetLastError());
+    return r;
 }
 
 }  // namespace qaia

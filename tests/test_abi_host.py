@@ -128,3 +128,16 @@ def test_random_spins_and_enumeration_argument_errors(q):
     assert ei.value.status == q.QAIA_INVALID_ARGUMENT
     # an empty request is valid and touches no device
     q._check(q._lib.qaia_random_spins(10, 0, 1, 0, None, None))
+
+
+def test_pareto_ranks_argument_errors(q):
+    import ctypes
+    n = ctypes.c_int32()
+    with pytest.raises(q.QaiaError) as ei:
+        q._check(q._lib.qaia_pareto_ranks(None, 4, 3, 0, None, ctypes.byref(n), None, 0, None))
+    assert ei.value.status == q.QAIA_INVALID_ARGUMENT  # max_rank < 1
+    with pytest.raises(q.QaiaError) as ei:
+        q._check(q._lib.qaia_pareto_ranks(None, 4, 9, 5, None, ctypes.byref(n), None, 0, None))
+    assert ei.value.status == q.QAIA_INVALID_ARGUMENT  # m > 8
+    q._check(q._lib.qaia_pareto_ranks(None, 0, 3, 5, None, ctypes.byref(n), None, 0, None))
+    assert n.value == 0

@@ -79,3 +79,54 @@ def test_filter_on_sampled_pool(q):
     # exact hypervolume of that front: library vs oracle
     ref = np.zeros(3, np.int64)
     assert q.qaia_hypervolume(o[got], ref) == oracle.hypervolume(o[got], ref)
+
+
+# ---------------------------------------------------------------- non-dominated ranks
+
+@pytest.mark.parametrize("m,M,hi", [(2, 3000, 40), (3, 5000, 12), (4, 4000, 6), (1, 500, 30)])
+def test_ranks_match_oracle(q, m, M, hi):
+    import torch
+    rng = np.random.default_rng(70 + m)
+    obj = rng.integers(-hi, hi, size=(M, m)).astype(np.int64)
+    rank, R = q.qaia_pareto_ranks(torch.from_numpy(obj).cuda())
+    torch.cuda.synchronize()
+    ref = oracle.pareto_ranks(obj)
+    assert np.array_equal(rank.cpu().numpy(), ref)
+    assert R == ref.max() + 1
+
+
+def test_ranks_truncation_and_edges(q):
+    import torch
+    rng = np.random.default_rng(80)
+    obj = rng.integers(0, 10, size=(2000, 3)).astype(np.int64)
+    ref = oracle.pareto_ranks(obj)
+    for cap in (1, 3, int(ref.max()), int(ref.max()) + 1):
+        rank, R = q.qaia_pareto_ranks(torch.from_numpy(obj).cuda(), max_rank=cap)
+        assert R == min(cap, ref.max() + 1)
+        assert np.array_equal(rank.cpu().numpy(), np.minimum(ref, cap))
+    r0, n0 = q.qaia_pareto_ranks(torch.zeros((0, 3), dtype=torch.int64, device="cuda"))
+    assert n0 == 0 and r0.numel() == 0
+    r1, n1 = q.qaia_pareto_ranks(torch.tensor([[4, 5]], dtype=torch.int64, device="cuda"))
+    assert n1 == 1 and r1.cpu().tolist() == [0]
+
+
+def test_ranks_large_pool_properties(q):
+    """200 000 rows, several chunks per rank: rank 0 is the filter's front, a
+    dominator always has a smaller rank, and every row of rank r > 0 has a
+    dominator of rank r - 1 (checked on a sample of rows)."""
+    import torch
+    rng = np.random.default_rng(81)
+    obj = rng.integers(0, 60, size=(200_000, 3)).astype(np.int64)
+    d = torch.from_numpy(obj).cuda()
+    rank, R = q.qaia_pareto_ranks(d)
+    keep = q.pareto_front(d).cpu().numpy()
+    rk = rank.cpu().numpy()
+    assert {tuple(v) for v in obj[rk == 0]} == {tuple(v) for v in obj[keep]}
+    print(f"{R} ranks")
+    for i in rng.choice(len(obj), size=300, replace=False):
+        ge = (obj >= obj[i]).all(axis=1) & (obj > obj[i]).any(axis=1)
+        if rk[i] == 0:
+            assert not ge.any()
+        else:
+            assert rk[ge].max() == rk[i] - 1
+            assert (rk[ge] < rk[i]).all()
