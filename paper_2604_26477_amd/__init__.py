@@ -149,9 +149,11 @@ class Problem:
         self.handle, self.n, self.m, self.num_edges, self.device = handle, n, m, num_edges, device
         self.words = (n + 63) // 64
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps sys.is_finalizing reachable while modules
+        # are torn down at interpreter exit, when the process frees everything
         h = getattr(self, "handle", None)
-        if h and not sys.is_finalizing():  # at interpreter exit the process frees everything
+        if h and not _finalizing():
             _lib.qaia_problem_destroy(h)
             self.handle = None
 
