@@ -285,7 +285,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sampler's work shards over weight vectors "
-              "with one front merge, which this build does not implement (run with --gpus 1)",
+              "with one front merge, which is not implemented here (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 
