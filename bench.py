@@ -8,10 +8,9 @@ exact hypervolume of the resulting front.  Inputs are seeded synthetic
 stand-ins for the paper's 42-node instances and are resident on the GPU before
 the timed region.
 
-Consecutive steps are pipelined: the sampling of step k + 1 (one stream)
-overlaps the filter of step k (a second stream, double-buffered pools), and
-the exact hypervolume of step k runs on a host thread; every step's
-hypervolume completes inside the timed region.
+Consecutive steps are pipelined: the exact hypervolume of step k runs on a
+host thread while the GPU samples step k + 1; every step's hypervolume
+completes inside the timed region.
 
 Prints one JSON line.  The optional CPU baseline runs the oracle (test
 infrastructure) on a bounded slice of the same workload.
@@ -315,18 +314,17 @@ def main():
     scheds = {v: q.make_schedule(v, steps=T, dt=0.5, seed=cfg["seed"] + 3 + i, path=args.path)
               for i, v in enumerate(variants)}
     rows = W * R
-    # two pools (double buffering): step k + 1 samples into one while the
-    # filter of step k reads the other on a second stream
-    spins = [torch.empty((2 * rows, prob.words), dtype=torch.int64, device=dev) for _ in range(2)]
-    obj = [torch.empty((2 * rows, inst.m), dtype=torch.int64, device=dev) for _ in range(2)]
+    spins = torch.empty((2 * rows, prob.words), dtype=torch.int64, device=dev)
+    obj = torch.empty((2 * rows, inst.m), dtype=torch.int64, device=dev)
     ws_s = torch.empty(max(q.qaia_sample_workspace_bytes(prob, W, R, s) for s in scheds.values()),
                        dtype=torch.uint8, device=dev)
-    keep = [torch.empty(2 * rows, dtype=torch.int64, device=dev) for _ in range(2)]
-    nkeep = [torch.empty(1, dtype=torch.int64, device=dev) for _ in range(2)]
+    keep = torch.empty(2 * rows, dtype=torch.int64, device=dev)
+    nkeep = torch.empty(1, dtype=torch.int64, device=dev)
     ws_f = torch.empty(q.qaia_pareto_filter_workspace_bytes(2 * rows, inst.m), dtype=torch.uint8,
                        device=dev)
-    s_sample = torch.cuda.current_stream()
-    s_filter = torch.cuda.Stream()  # default priority
+    stream = torch.cuda.current_stream()
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in ("bsb", "dsb", "filter")}
     ref = np.zeros(inst.m, np.int64)
 
     from concurrent.futures import ThreadPoolExecutor
@@ -337,71 +335,48 @@ def main():
         hv = q.qaia_hypervolume(front, ref)  # the ctypes call releases the GIL
         return hv, (time.perf_counter() - t0) * 1e3
 
-    def timing_events():
-        return {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                for k in ("bsb", "dsb", "filter")}
-
-    def enqueue_sampling(k, ev, after):
-        """Sampling of step k into pool k % 2, on the sampling stream, after the
-        filter that last read that pool (event `after`)."""
-        b = k % 2
-        if after is not None:
-            s_sample.wait_event(after)
+    def step(record):
+        """Sampling and filtering of one batch; the host hypervolume of the
+        resulting front is handed to a worker thread, so it overlaps the
+        device work of the next step.  Returns (front size, hv future, times)."""
+        times = {}
         for i, v in enumerate(variants):
-            ev[v][0].record(s_sample)
-            q.qaia_sample(prob, c, R, scheds[v], spins=spins[b][i * rows:(i + 1) * rows],
-                          obj=obj[b][i * rows:(i + 1) * rows], workspace=ws_s, stream=s_sample)
-            ev[v][1].record(s_sample)
-        done = torch.cuda.Event()
-        done.record(s_sample)
-        return done
+            if record:
+                ev[v][0].record(stream)
+            q.qaia_sample(prob, c, R, scheds[v], spins=spins[i * rows:(i + 1) * rows],
+                          obj=obj[i * rows:(i + 1) * rows], workspace=ws_s, stream=stream)
+            if record:
+                ev[v][1].record(stream)
+        if record:
+            ev["filter"][0].record(stream)
+        q.qaia_pareto_filter(obj, keep_idx=keep, num_keep=nkeep, workspace=ws_f, stream=stream)
+        if record:
+            ev["filter"][1].record(stream)
+        P = int(nkeep.item())  # synchronises the stream
+        front = obj[keep[:P]].cpu().numpy()
+        fut = host.submit(hypervolume, front)
+        if record:
+            for k in ev:
+                times[f"{k}_ms"] = ev[k][0].elapsed_time(ev[k][1])
+        return P, fut, times
 
-    def enqueue_filter(k, ev, sampled):
-        b = k % 2
-        s_filter.wait_event(sampled)
-        ev["filter"][0].record(s_filter)
-        q.qaia_pareto_filter(obj[b], keep_idx=keep[b], num_keep=nkeep[b], workspace=ws_f, stream=s_filter)
-        ev["filter"][1].record(s_filter)
-        done = torch.cuda.Event()
-        done.record(s_filter)
-        return done
-
-    def run(steps):
-        """Pipelined steps: sampling of step k + 1 is enqueued before the host
-        waits for the filter of step k, and the exact hypervolume of step k runs
-        on a host thread.  Returns per-step stage times, hypervolumes, front size."""
-        evs = [timing_events() for _ in range(steps)]
-        filt_done = [None] * steps
-        sampled = enqueue_sampling(0, evs[0], None)
-        filt_done[0] = enqueue_filter(0, evs[0], sampled)
-        futs, sizes = [], []
-        for k in range(steps):
-            if k + 1 < steps:
-                sampled = enqueue_sampling(k + 1, evs[k + 1], filt_done[k - 1] if k >= 1 else None)
-                filt_done[k + 1] = enqueue_filter(k + 1, evs[k + 1], sampled)
-            filt_done[k].synchronize()
-            b = k % 2
-            with torch.cuda.stream(s_filter):  # the read-back must not queue behind step k + 1's sampling
-                P = int(nkeep[b].item())
-                front = obj[b][keep[b][:P]].cpu().numpy()
-            futs.append(host.submit(hypervolume, front))
-            sizes.append(P)
-        hvs = [f.result() for f in futs]
-        torch.cuda.synchronize()
-        per = [{f"{name}_ms": e[0].elapsed_time(e[1]) for name, e in ev.items()} for ev in evs]
-        for p_, (_, hv_ms) in zip(per, hvs):
-            p_["hv_ms"] = hv_ms
-        return per, hvs, sizes
-
-    run(max(args.warmup, 1))
+    for _ in range(args.warmup):
+        step(False)[1].result()
     torch.cuda.synchronize()
+    per, futs = [], []
     t0 = time.perf_counter()
-    per, hvs, sizes = run(args.steps)  # every step's hypervolume completes inside the timed region
+    for _ in range(args.steps):
+        P, fut, times = step(True)
+        per.append(times)
+        futs.append(fut)
+    hvs = [f.result() for f in futs]  # every step's hypervolume is inside the timed region
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
     total_rs = 2 * rows * T
-    hv, P = hvs[-1][0], sizes[-1]
+    hv = hvs[-1][0]
+    for p_, (_, hv_ms) in zip(per, hvs):
+        p_["hv_ms"] = hv_ms
     stage = {k: float(np.mean([p[k] for p in per])) for k in per[0]}
 
     # roofline of the dominant kernel: the generated sparse SB kernel, whose
@@ -423,8 +398,7 @@ def main():
                                "filter of the 10.24M-vector pool, exact hypervolume (origin)",
                    "W": W, "R": R, "T": T, "n": inst.n, "m": inst.m, "edges": inst.num_edges,
                    "path": args.path,
-                   "pipelining": "sampling of step k+1 overlaps the filter of step k (second stream, "
-                                 "double-buffered pools) and the host hypervolume of step k"},
+                   "pipelining": "host hypervolume of step k overlaps the device work of step k+1"},
         "roofline": {"bound": "alu", "kernel": "qaia_sb_reg (bSB and dSB launches)",
                      "achieved": achieved, "peak": PEAK_FP32_FMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_FMA_TFLOPS, "traffic": SB_REG_TRAFFIC_BYTES,
