@@ -188,6 +188,14 @@ int32_t qaia_enumerate_cuts(const qaia_problem *p, uint64_t first, int64_t count
 int32_t qaia_random_spins(int32_t n, int64_t count, uint64_t seed, uint64_t offset, uint64_t *spins,
                           void *hip_stream);
 
+/* Weight vectors uniform on the simplex (Dirichlet(1, ..., 1); section
+ * "Scalarization via the weighted sum method"): row r is the normalised
+ * vector of m i.i.d. Exp(1) values -log(u), u from 24 bits of draw
+ * (r + offset) * m + k of the counter stream keyed seed ^ 0xbb67ae8584caa73b.
+ * weights DEVICE float[count][m], 1 <= m <= 8. */
+int32_t qaia_dirichlet_weights(int32_t m, int64_t count, uint64_t seed, uint64_t offset, float *weights,
+                               void *hip_stream);
+
 /* ---------------------------------------------------------------- precision form */
 
 /* Bytes of DEVICE workspace qaia_dense_field needs for `count` columns. */

@@ -60,6 +60,7 @@ _SIGS = {
     "qaia_evaluate": (_i32, [_P, _P, _i64, _P, _P]),
     "qaia_enumerate_cuts": (_i32, [_P, C.c_uint64, _i64, _P, _P]),
     "qaia_random_spins": (_i32, [_i32, _i64, C.c_uint64, C.c_uint64, _P, _P]),
+    "qaia_dirichlet_weights": (_i32, [_i32, _i64, C.c_uint64, C.c_uint64, _P, _P]),
     "qaia_pareto_filter_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "qaia_pareto_filter": (_i32, [_P, _i64, _i32, _P, _P, _P, _sz, _P]),
     "qaia_hypervolume": (_i32, [_P, _i64, _i32, _P, _P, _P]),
@@ -277,6 +278,16 @@ def qaia_random_spins(n: int, count: int, seed: int, offset: int = 0, spins=None
     _check(_lib.qaia_random_spins(n, count, seed & (2**64 - 1), offset & (2**64 - 1), _ptr(spins),
                                   _stream(stream)))
     return spins
+
+
+def qaia_dirichlet_weights(m: int, count: int, seed: int, offset: int = 0, out=None, device=None,
+                           stream=None) -> torch.Tensor:
+    """count weight vectors uniform on the simplex (float32 [count, m] device)."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = _dev_tensor(out, torch.float32, (count, m), dev)
+    _check(_lib.qaia_dirichlet_weights(m, count, seed & (2**64 - 1), offset & (2**64 - 1), _ptr(out),
+                                       _stream(stream)))
+    return out
 
 
 def exact_front(p: Problem, chunk: int = 1 << 26, with_min: bool = False):

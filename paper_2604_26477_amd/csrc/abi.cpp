@@ -246,6 +246,17 @@ int32_t qaia_random_spins(int32_t n, int64_t count, uint64_t seed, uint64_t offs
     });
 }
 
+int32_t qaia_dirichlet_weights(int32_t m, int64_t count, uint64_t seed, uint64_t offset, float *weights,
+                               void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(m >= 1 && m <= 8, QAIA_INVALID_ARGUMENT, "m must be in [1, 8]");
+        QAIA_CHECK(count >= 0, QAIA_INVALID_ARGUMENT, "count must be >= 0");
+        QAIA_CHECK(count == 0 || weights != nullptr, QAIA_INVALID_ARGUMENT, "null weights");
+        launch_dirichlet(m, count, seed, offset, weights, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
 int32_t qaia_dense_field_workspace_bytes(const qaia_problem *pp, int32_t precision, int64_t count,
                                          size_t *bytes) {
     return guarded([&]() -> int32_t {

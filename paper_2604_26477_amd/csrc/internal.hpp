@@ -164,6 +164,7 @@ void launch_sparse_lds_jobs(const SparseJob *single, const SparseJob *jobs, int 
                             int64_t blocks, int maxdeg, int npt, size_t shmem, bool dsb, hipStream_t st);
 void launch_enumerate(const Problem &p, uint64_t first, int64_t count, int64_t *obj, hipStream_t st);
 void launch_random_spins(int n, int64_t count, uint64_t seed, uint64_t offset, uint64_t *spins, hipStream_t st);
+void launch_dirichlet(int m, int64_t count, uint64_t seed, uint64_t offset, float *out, hipStream_t st);
 void launch_evaluate(const Problem &p, const uint64_t *spins, int64_t count, int64_t *obj,
                      hipStream_t st);
 

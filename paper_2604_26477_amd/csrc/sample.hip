@@ -532,6 +532,35 @@ void launch_random_spins(int n, int64_t count, uint64_t seed, uint64_t offset, u
     QAIA_HIP(hipGetLastError());
 }
 
+// Uniform weight vectors on the simplex: Dirichlet(1, ..., 1) as m i.i.d.
+// Exp(1) draws -log(u), u in (0, 1] from 24 bits of the counter stream keyed
+// seed ^ 0xbb67ae8584caa73b (draw (row + offset) * m + k), divided by their sum.
+constexpr uint64_t kDirichletKey = 0xbb67ae8584caa73bull;
+
+__global__ __launch_bounds__(kBlock) void dirichlet_kernel(int m, int64_t count, uint64_t seed, uint64_t offset,
+                                                           float *__restrict__ out) {
+    const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (row >= count) return;
+    float e[8];
+    float sum = 0.0f;
+    for (int k = 0; k < m; ++k) {
+        const uint64_t b = splitmix64(seed ^ kDirichletKey, ((uint64_t)row + offset) * (uint64_t)m + (uint64_t)k);
+        const float u = (float)((uint32_t)(b >> 40) + 1u) * 0x1p-24f;
+        e[k] = -logf(u);
+        sum += e[k];
+    }
+    const float inv = 1.0f / sum;
+    for (int k = 0; k < m; ++k) out[row * m + k] = e[k] * inv;
+}
+
+void launch_dirichlet(int m, int64_t count, uint64_t seed, uint64_t offset, float *out, hipStream_t st) {
+    if (count == 0) return;
+    const int64_t blocks = (count + kBlock - 1) / kBlock;
+    QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many rows for one call");
+    hipLaunchKernelGGL(dirichlet_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, m, count, seed, offset, out);
+    QAIA_HIP(hipGetLastError());
+}
+
 // Replica-tiled evaluation for large edge sets: a block stages the spins of 64
 // replicas in LDS (32-bit words, row pitch 2*words + 1 so the 64 lanes, one
 // replica each, read distinct banks) and its four waves walk four contiguous

@@ -1,7 +1,7 @@
 """Online loop of the learned weight proposer (form F3) and its uniform baseline.
 
 Each round:
-  1. draw candidate weight vectors c ~ Dirichlet(1, ..., 1) (host, seeded);
+  1. draw candidate weight vectors c ~ Dirichlet(1, ..., 1) (device, seeded);
   2. learned: score them with the MLP on (c, eight front-gap features) and
      draw (1 - explore) * n_sel of them without replacement with
      probabilities proportional to exp(score / temperature) (Gumbel top-k),
@@ -25,7 +25,8 @@ import time
 import numpy as np
 import torch
 
-from . import (make_schedule, qaia_front_features, qaia_gather_rows, qaia_hypervolume, qaia_mlp_adam,
+from . import (make_schedule, qaia_dirichlet_weights, qaia_front_features, qaia_gather_rows, qaia_hypervolume,
+               qaia_mlp_adam,
                qaia_mlp_backward, qaia_mlp_forward, qaia_mlp_param_count, qaia_new_point_labels,
                qaia_pareto_filter, qaia_pareto_filter_workspace_bytes, qaia_sample,
                qaia_sample_workspace_bytes, qaia_topk)
@@ -90,6 +91,8 @@ class ProposerLoop:
         self.replay_n = 0
         self.replay_slot = 0
         self.replay_zero = torch.zeros(self.replay_cap, dtype=torch.float32, device=dev)
+        self.iota_sel = torch.arange(n_sel, dtype=torch.int64, device=dev)
+        self.explore_idx = torch.arange(n_cand, n_cand + n_sel, dtype=torch.int64, device=dev)
         self.hits = torch.zeros((0, self.m), dtype=torch.float32, device=dev)
         self.misses = torch.zeros((0, self.m), dtype=torch.float32, device=dev)
         self.round_no = 0
@@ -98,23 +101,25 @@ class ProposerLoop:
 
     # -------------------------------------------------------------- selection
     def _select(self):
-        cands_h = self.rng.dirichlet(np.ones(self.m), size=self.n_cand).astype(np.float32)
-        cands = torch.from_numpy(cands_h).to(self.dev)
+        """Candidate weight vectors (device), the picked rows and the MLP inputs.
+
+        Candidates are drawn on the device (uniform on the simplex).  Learned:
+        n_cand candidates are scored and (1 - explore) n_sel of them drawn by
+        Gumbel top-k; the exploration share are n_explore further fresh uniform
+        draws (i.i.d. candidates, so equivalent to uniform picks among the rest).
+        Uniform: n_sel fresh draws."""
+        key = self.seed * 1000003 + self.round_no
         if not self.learned:
-            pick = torch.from_numpy(np.arange(self.n_sel, dtype=np.int64)).to(self.dev)
-            X = None
-            return cands, pick, X
+            cands = qaia_dirichlet_weights(self.m, self.n_sel, seed=key, device=self.dev)
+            return cands, self.iota_sel, None
+        n_top = self.n_sel - int(round(self.explore * self.n_sel))
+        n_exp = self.n_sel - n_top
+        cands = qaia_dirichlet_weights(self.m, self.n_cand + n_exp, seed=key, device=self.dev)
         front = self.pool_obj[: self.A]
         X = qaia_front_features(front, cands, self.hits, self.misses)
-        n_top = self.n_sel - int(round(self.explore * self.n_sel))
-        scores = qaia_mlp_forward(self.params, self.D, X)
-        top = qaia_topk(scores, n_top, temperature=self.temperature,
-                        seed=self.seed * 1000003 + self.round_no)
-        # exploration: uniformly chosen candidates outside the top set
-        top_h = top.cpu().numpy()
-        rest = np.setdiff1d(np.arange(self.n_cand), top_h, assume_unique=False)
-        extra = self.rng.choice(rest, size=self.n_sel - n_top, replace=False)
-        pick = torch.from_numpy(np.concatenate([top_h, np.sort(extra)]).astype(np.int64)).to(self.dev)
+        scores = qaia_mlp_forward(self.params, self.D, X[: self.n_cand])
+        top = qaia_topk(scores, n_top, temperature=self.temperature, seed=key)
+        pick = torch.cat([top, self.explore_idx[:n_exp]])
         return cands, pick, X
 
     # -------------------------------------------------------------- one round
