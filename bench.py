@@ -100,12 +100,16 @@ def precision_form(q, wl, torch, T=1000):
 
 
 def learned_form(q, wl, torch, budget_rounds=40, ref_factor=10, max_seconds=240.0):
-    """Time to the reference hypervolume on the 42-node, 4-objective instance:
-    each round proposes 1024 weight vectors (from 65536 Dirichlet candidates),
-    samples 256 replicas x 2000 steps each (bSB, FP32), filters against the
-    archive and computes the exact hypervolume.  The reference is the
-    hypervolume of the union of fronts of uniform-Dirichlet plain runs at 10x
-    the budget."""
+    """Time to a reference hypervolume on the 42-node, 4-objective instance.
+    Every loop runs rounds of 1024 weight vectors x 256 replicas, filters
+    against its archive and computes the exact hypervolume.  Contenders:
+    plain FP32 bSB, 2000 steps, uniform Dirichlet vectors (the baseline); the
+    learned proposer (1024 of 65536 scored candidates, same sampler); and
+    noise-injected bSB with the paper's short schedule (50 steps, dt 1,
+    alpha 0.1, Eq. 10), uniform vectors.  The plain loop runs budget_rounds
+    rounds; the others run for the same wall time.  References: the plain
+    loop's final hypervolume (time_to_ref), and the union hypervolume of a
+    plain loop at ref_factor times the budget (fractions)."""
     from paper_2604_26477_amd.learned import ProposerLoop, run_until
     inst = wl.instance_42_node(4, seed=2000)
     prob = q.problem_from_instance(inst, 0)
@@ -118,28 +122,33 @@ def learned_form(q, wl, torch, budget_rounds=40, ref_factor=10, max_seconds=240.
             break
     ref_rounds = ref_loop.round_no
     ref_hv = ref_loop.history[-1]["hv"]
-    out = {"workload": "42-node degree<=3, m=4; rounds of 1024 proposed weight vectors x 256 replicas "
-                       "x 2000 steps (bSB FP32) from 65536 Dirichlet candidates",
+    out = {"workload": "42-node degree<=3, m=4; rounds of 1024 weight vectors x 256 replicas; plain: bSB FP32 "
+                       "2000 steps dt 0.5, uniform Dirichlet; learned: 1024 of 65536 scored candidates; "
+                       "ni_bsb_short: bSB 50 steps dt 1.0 alpha 0.1, uniform Dirichlet",
            "reference": {"rounds": ref_rounds, "hv": str(ref_hv), "front": ref_loop.history[-1]["front"]},
            "budget_rounds": budget_rounds}
-    for name, learned in (("plain_fp32_uniform", False), ("learned_proposer", True)):
-        loop = ProposerLoop(prob, learned=learned, seed=11, **kw)
-        rounds, secs, reached = run_until(loop, ref_hv, budget_rounds)
+    contenders = (("plain_fp32_uniform", dict(learned=False)),
+                  ("learned_proposer", dict(learned=True)),
+                  ("ni_bsb_short", dict(learned=False, steps=50, dt=1.0, noise_alpha=0.1)))
+    budget_s = None
+    for name, extra in contenders:
+        args = dict(kw)
+        args.update(extra)
+        loop = ProposerLoop(prob, seed=11, **args)
+        if budget_s is None:
+            rounds, secs, reached = run_until(loop, ref_hv, budget_rounds)
+            budget_s = secs
+        else:
+            rounds, secs, reached = run_until(loop, ref_hv, 100000, max_seconds=budget_s)
         hist = loop.history
         frac = [h["hv"] / ref_hv for h in hist]
-        def first(th):
-            for h, f in zip(hist, frac):
-                if f >= th:
-                    return h["round"]
-            return None
         out[name] = {"reached_reference": reached, "rounds": rounds, "seconds": secs,
                      "seconds_per_round": secs / max(rounds, 1), "final_hv_fraction": frac[-1],
-                     "rounds_to_99.9%": first(0.999), "rounds_to_99.99%": first(0.9999),
                      "final_front": hist[-1]["front"], "hv_by_round": [str(h["hv"]) for h in hist],
                      "elapsed_by_round": list(np.cumsum([h["seconds"] for h in hist]))}
-    # time to the plain run's final hypervolume (the target both can reach)
+    # time to the plain run's final hypervolume (the target all can reach)
     target = int(out["plain_fp32_uniform"]["hv_by_round"][-1])
-    for name in ("plain_fp32_uniform", "learned_proposer"):
+    for name, _ in contenders:
         r = out[name]
         t = None
         for hv, el in zip(r["hv_by_round"], r["elapsed_by_round"]):
@@ -416,11 +425,15 @@ def main():
             result["forms"]["batching"] = batch_form(q, wl, torch)
         if args.table2_form:
             result["forms"]["table2"] = table2_form(q, wl, torch)
+        forms = {k: lf[k]["seconds_to_plain_final_hv"] for k in ("learned_proposer", "ni_bsb_short")}
+        reached = {k: v for k, v in forms.items() if v is not None}
+        chosen = min(reached, key=reached.get) if reached else None
         result["time_to_ref_hypervolume"] = {
             "reference": "hypervolume the plain FP32 uniform-Dirichlet run reaches at the end of its "
                          f"{lf['budget_rounds']}-round budget",
-            "chosen_form": "learned proposer",
-            "chosen_form_s": lf["learned_proposer"]["seconds_to_plain_final_hv"],
+            "forms_s": forms,
+            "chosen_form": chosen,
+            "chosen_form_s": forms[chosen] if chosen else None,
             "plain_fp32_s": lf["plain_fp32_uniform"]["seconds_to_plain_final_hv"],
         }
     if not args.no_cpu_baseline:

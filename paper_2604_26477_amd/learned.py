@@ -52,12 +52,13 @@ class ProposerLoop:
     def __init__(self, prob, R=256, steps=2000, variant="bsb", n_cand=65536, n_sel=1024,
                  explore=0.1, lr=1e-3, learned=True, seed=0, archive_cap=1 << 20, ref=None,
                  precision="fp32", path="auto", temperature=1.0, replay_rounds=8, train_steps=16,
-                 batch=1024):
+                 batch=1024, dt=0.5, noise_alpha=0.0):
         self.prob, self.m, self.R = prob, prob.m, R
         self.n_cand, self.n_sel, self.explore, self.lr = n_cand, n_sel, explore, lr
         self.learned = learned
         self.rng = np.random.Generator(np.random.PCG64(seed))
-        self.sched_args = dict(variant=variant, precision=precision, steps=steps, dt=0.5, path=path)
+        self.sched_args = dict(variant=variant, precision=precision, steps=steps, dt=dt, noise_alpha=noise_alpha,
+                               path=path)
         self.seed = seed
         self.dev = prob.torch_device
         self.ref = np.zeros(self.m, np.int64) if ref is None else np.asarray(ref, np.int64)
@@ -189,12 +190,15 @@ class ProposerLoop:
         return self.pool_obj[: self.A].cpu().numpy()
 
 
-def run_until(loop: ProposerLoop, target_hv: int, max_rounds: int):
-    """Rounds until the archive's hypervolume reaches target_hv; returns (rounds, seconds, reached)."""
+def run_until(loop: ProposerLoop, target_hv: int, max_rounds: int, max_seconds: float = float("inf")):
+    """Rounds until the archive's hypervolume reaches target_hv, or max_rounds
+    rounds or max_seconds have passed; returns (rounds, seconds, reached)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in range(max_rounds):
         rec = loop.round()
         if rec["hv"] >= target_hv:
             return r + 1, time.perf_counter() - t0, True
+        if time.perf_counter() - t0 >= max_seconds:
+            return r + 1, time.perf_counter() - t0, False
     return max_rounds, time.perf_counter() - t0, False
