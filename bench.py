@@ -134,6 +134,7 @@ def learned_form(q, wl, torch, budget_rounds=40, ref_factor=10, max_seconds=240.
     for name, extra in contenders:
         args = dict(kw)
         args.update(extra)
+        ProposerLoop(prob, seed=5, **args).round()  # warm-up: kernels built on first use, caches
         loop = ProposerLoop(prob, seed=11, **args)
         if budget_s is None:
             rounds, secs, reached = run_until(loop, ref_hv, budget_rounds)
