@@ -321,6 +321,62 @@ __device__ __forceinline__ void frag_mma(const Frags<PREC, MT> &f, int m, int u,
     }
 }
 
+// frag_mma with NC copies of the next chunk interleaved: copy j is issued
+// after MFMA (j * NM) / NC of the unit (NM MFMAs when m == MT), so a copy that
+// waits for room in the memory queue stalls behind queued matrix work instead
+// of in front of an idle matrix pipe.  Copies not yet issued (m < MT) follow.
+template <int PREC, int MT, int NC, typename Copy>
+__device__ __forceinline__ void frag_mma_cp(const Frags<PREC, MT> &f, int m, int u, f16v (&acc)[MT][2][2],
+                                            Copy &&copy) {
+    constexpr int NM = PREC == QAIA_FP8 ? MT * 2 : (PREC == QAIA_BF16 ? MT * 4 : MT * 16);
+    int i = 0, j = 0;
+    auto after = [&]() {
+        if constexpr (NC > 0) {
+            if (j < NC && i == (j * NM) / NC) {
+                __builtin_amdgcn_sched_barrier(0);
+                copy(j);
+                __builtin_amdgcn_sched_barrier(0);
+                ++j;
+            }
+        }
+        ++i;
+    };
+#pragma unroll
+    for (int k = 0; k < MT; ++k) {
+        if (k >= m) break;
+        if constexpr (PREC == QAIA_FP8) {
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2) {
+                acc[k][u][c2] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.a[k], f.b[c2], acc[k][u][c2], 0, 0,
+                                                                               0, 127, 0, 127);
+                after();
+            }
+        } else {
+#pragma unroll
+            for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+                for (int c2 = 0; c2 < 2; ++c2) {
+                    f16v &a = acc[k][r2][c2];
+                    if constexpr (PREC == QAIA_BF16) {
+                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[k][r2], f.b[c2], a, 0, 0, 0);
+                        after();
+                    } else {
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].x, f.b[c2].x, a, 0, 0, 0);
+                        after();
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].y, f.b[c2].y, a, 0, 0, 0);
+                        after();
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].z, f.b[c2].z, a, 0, 0, 0);
+                        after();
+                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].w, f.b[c2].w, a, 0, 0, 0);
+                        after();
+                    }
+                }
+        }
+    }
+#pragma unroll
+    for (; j < NC; ++j) copy(j);
+}
+
 // Direct-to-LDS variant of the staged tile: every chunk is copied by
 // global_load_lds (16 bytes per lane straight into LDS, no registers), into a
 // ring of D stage buffers, D - 1 chunks ahead of the MFMAs.  Wave w copies
@@ -330,36 +386,69 @@ __device__ __forceinline__ void frag_mma(const Frags<PREC, MT> &f, int m, int u,
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 template <int MT>
-constexpr int dma_stages() { return MT <= 3 ? 4 : 3; }
+constexpr int dma_stages() {
+    // four stage buffers (three for m = 4: 3 x 40 KB); filling all 160 KB of
+    // LDS with five measured slower
+    return MT <= 3 ? 4 : 3;
+}
+
+// The copy is issued from inline assembly (M0 = the wave's LDS destination,
+// one wait state, then global_load_lds_dwordx4) so that the compiler's wait
+// insertion does not see an LDS-writing memory operation: with one pending it
+// treats the LDS counter as out of order and drains it completely before every
+// MFMA group, serialising the fragment reads with the MFMAs.  The copies are
+// ordered by hand (dma_wait, lds_barrier); M0 is written nowhere else here.
+template <int MT>
+__device__ __forceinline__ void dma_copy(char *stage, const char *src, size_t koff, int wave, int i) {
+    const uint32_t base = (uint32_t)(uintptr_t)(lds_void_t *)stage;
+    const uint32_t dst = __builtin_amdgcn_readfirstlane(base + (uint32_t)(wave * 2 * (MT + 1) + i) * 64 * 16);
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src + koff), "s"(dst)
+                 : "memory");
+}
 
 template <int MT>
 __device__ __forceinline__ void dma_chunk(char *stage, const char *const (&src)[2 * (MT + 1)], size_t koff,
                                           int wave) {
 #pragma unroll
-    for (int i = 0; i < 2 * (MT + 1); ++i)
-        __builtin_amdgcn_global_load_lds((const void *)(src[i] + koff),
-                                         (lds_void_t *)(stage + (size_t)(wave * 2 * (MT + 1) + i) * 64 * 16), 16, 0,
-                                         0);
+    for (int i = 0; i < 2 * (MT + 1); ++i) dma_copy<MT>(stage, src[i], koff, wave, i);
 }
 
 // this wave's copies of all but the newest `later` chunks have landed
+// (later <= 6; later * PER stays within the 6-bit vmcnt field)
 template <int PER>
 __device__ __forceinline__ void dma_wait(int later) {
-    if (later >= 2) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * PER) : "memory");
-    else if (later == 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(PER) : "memory");
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    static_assert(6 * PER <= 63, "vmcnt range");
+    switch (later) {
+        case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+        case 1: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(PER) : "memory"); break;
+        case 2: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * PER) : "memory"); break;
+        case 3: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(3 * PER) : "memory"); break;
+        case 4: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(4 * PER) : "memory"); break;
+        case 5: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(5 * PER) : "memory"); break;
+        default: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(6 * PER) : "memory"); break;
+    }
 }
 
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
+// This wave's LDS reads have returned (so a stage it read may be refilled once
+// every wave is past the barrier), then the block barrier.  The wait is a
+// compiler-visible s_waitcnt (lgkmcnt 0, vmcnt and expcnt left at their
+// maxima, gfx9 encoding): it also retires any scalar load the compiler hoisted
+// above the loop, which would otherwise force a full LDS drain before every
+// MFMA group instead of a wait for the older fragment unit only.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    asm volatile("s_barrier" ::: "memory");
+}
 
 template <int PREC, int MT>
 __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, int Np_, int m, int row0, int col0,
-                                             int wr, int wc, int half, int lr, f16v (&acc)[MT][2][2], char *s0,
-                                             char *s1, char *s2, char *s3) {
+                                             int wr, int wc, int half, int lr, f16v (&acc)[MT][2][2],
+                                             char *lds) {
     typedef typename PrecInfo<PREC>::T T;
     constexpr int ES = sizeof(T);
     constexpr int PER = 2 * (MT + 1);  // copies per wave per chunk
     constexpr int D = dma_stages<MT>();
+    static_assert(D >= 2 && D - 2 <= 6, "stage ring depth");
     const size_t Np = (size_t)Np_;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const char *src[PER];
@@ -374,7 +463,10 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
             src[i] = (const char *)phiv + ((size_t)(col0 + R - MT * kT2) * Np) * ES + p * 16;
         }
     }
-    char *S[4] = {s0, s1, s2, s3};
+    constexpr int SB = staged_buf_bytes<MT>();
+    char *S[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) S[i] = lds + i * SB;
     const int nk = (int)(Np * ES / kChunkB);
     const int sw = (lr >> 2) & 3;
     const int aoff = (wr * 64 + lr) * kPitchB, boff = (MT * kT2 + wc * 64 + lr) * kPitchB;
@@ -394,16 +486,35 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
                 const int later = (nk - 1 - c) < (D - 2) ? (nk - 1 - c) : (D - 2);
                 dma_wait<PER>(later);
                 lds_barrier();  // chunk c is in LDS for every wave; all waves are done reading chunk c - 1
-                if (c + D - 1 < nk) dma_chunk<MT>(S[(u + D - 1) % D], src, (size_t)(c + D - 1) * kChunkB, wave);
+                // the copies of chunk c + D - 1 (into the stage chunk c - 1 used):
+                // BF16 / FP32 spread them over this iteration's two MFMA groups,
+                // FP8 (six MFMAs per group for m = 3, measured slower spread)
+                // issues them all here
+                constexpr bool kSpread = PREC != QAIA_FP8;
+                const bool issue = c + D - 1 < nk;
+                char *const nst = S[(u + D - 1) % D];
+                const size_t koff = (size_t)(c + D - 1) * kChunkB;
+                if (!kSpread && issue) dma_chunk<MT>(nst, src, koff, wave);
+                auto copy0 = [&](int i) {
+                    if (kSpread && issue) dma_copy<MT>(nst, src[i], koff, wave, i);
+                };
+                auto copy1 = [&](int i) {
+                    if (kSpread && issue) dma_copy<MT>(nst, src[PER / 2 + i], koff, wave, PER / 2 + i);
+                };
                 const LaneLds L = lane_lds(u);
                 // scheduling barriers keep each unit's reads ahead of the other unit's MFMAs
                 frag_load<PREC, MT>(f0, L, 0);
                 __builtin_amdgcn_sched_barrier(0);
-                if (c > 0) frag_mma<PREC, MT>(f1, m, 1, acc);
+                if (c > 0) {
+                    frag_mma_cp<PREC, MT, kSpread ? PER / 2 : 0>(f1, m, 1, acc, copy0);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < PER / 2; ++i) copy0(i);
+                }
                 __builtin_amdgcn_sched_barrier(0);
                 frag_load<PREC, MT>(f1, L, 1);
                 __builtin_amdgcn_sched_barrier(0);
-                frag_mma<PREC, MT>(f0, m, 0, acc);
+                frag_mma_cp<PREC, MT, kSpread ? PER / 2 : 0>(f0, m, 0, acc, copy1);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -435,10 +546,7 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
             for (int c2 = 0; c2 < 2; ++c2)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) acc[k][r2][c2][i] = 0.0f;
-    constexpr int SB = staged_buf_bytes<M>();
-    constexpr int D = dma_stages<M>();
-    mma_tile_dma<PREC, M>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds, lds + SB, lds + 2 * SB,
-                          lds + (D > 3 ? 3 * SB : 0));
+    mma_tile_dma<PREC, M>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds);
 
     // Epilogue in two phases.  (1) h = sum_k coef_k(col) H_k(row, col) from the
     // accumulators (same k order as the register-tile kernel) into an LDS tile
