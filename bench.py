@@ -99,6 +99,44 @@ def precision_form(q, wl, torch, T=1000):
     return out
 
 
+def measured_peaks(q, torch, reps=3):
+    """This GPU's own ceilings, from the library's measurement kernels (best
+    of `reps` timed launches after one untimed): fp32 FMA issue (eight
+    independent chains per lane, 16 waves per CU), the matrix-core rate per
+    operand format (four independent 32x32 accumulators per wave, 16 waves
+    per CU) and an HBM-to-HBM copy of 1 GiB."""
+    dev = torch.device("cuda", 0)
+
+    def best_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return min(times)
+
+    out = torch.empty(4096 * 256, dtype=torch.float32, device=dev)
+    fma_iters = 1 << 15
+    ms = best_ms(lambda: q.qaia_peak_fma(4096, fma_iters, 1.0, 1.0, out=out))
+    res = {"fp32_fma_TFLOPs": 4096 * 256 * fma_iters * 16 / (ms * 1e-3) / 1e12}
+    for prec, K, iters in (("fp32", 2, 8192), ("bf16", 16, 16384), ("fp8", 64, 16384)):
+        ms = best_ms(lambda: q.qaia_peak_mfma(prec, 1024, iters, out=out))
+        res[f"{prec}_mfma_TFLOPs"] = 1024 * 4 * iters * 4 * 2 * 32 * 32 * K / (ms * 1e-3) / 1e12
+    src = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(3)
+    dst = torch.empty_like(src)
+    ms = best_ms(lambda: q.qaia_peak_copy(src, dst))
+    res["hbm_copy_GBps"] = 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
+    del src, dst
+    res["method"] = ("library measurement kernels: 4096 x 256 lanes of 8 FMA chains; 1024 x 4 waves of 4 "
+                     "independent 32x32 MFMAs (operands 1.0); 1 GiB device copy; best of 3")
+    return res
+
+
 def learned_form(q, wl, torch, budget_rounds=40, ref_factor=10, max_seconds=240.0):
     """Time to a reference hypervolume on the 42-node, 4-objective instance.
     Every loop runs rounds of 1024 weight vectors x 256 replicas, filters
@@ -226,6 +264,7 @@ def table2_form(q, wl, torch, sizes=((25, 0.5), (25, 1.0), (100, 0.5), (100, 1.0
                        "alpha 0.1, dt 1.0", "instances": []}
     for idx, (n, d) in enumerate(sizes):
         inst = wl.appendix_e_instance(n, d, seed=5000 + idx)
+        torch.cuda.synchronize()  # earlier work must not land in the construction time
         t0 = time.perf_counter()
         prob = q.problem_from_instance(inst, 0)
         torch.cuda.synchronize()
@@ -288,7 +327,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision and learned form measurements")
     ap.add_argument("--batch-form", action="store_true",
                     help="also measure the 64-instance ragged batch (takes minutes in FP32)")
-    ap.add_argument("--only-form", choices=["precision", "learned", "batching", "table2"],
+    ap.add_argument("--only-form", choices=["precision", "learned", "batching", "table2", "peaks"],
                     help="run one form measurement alone and print its JSON (for profiling)")
     ap.add_argument("--precision-steps", type=int, default=1000,
                     help="SB steps of the precision form (shorter runs for counter collection)")
@@ -314,6 +353,8 @@ def main():
     if args.only_form:
         if args.only_form == "precision":
             res = precision_form(q, wl, torch, T=args.precision_steps)
+        elif args.only_form == "peaks":
+            res = measured_peaks(q, torch)
         else:
             res = {"learned": learned_form, "batching": batch_form, "table2": table2_form}[args.only_form](q, wl, torch)
         print(json.dumps({"form": args.only_form, "result": res}), flush=True)
@@ -423,8 +464,15 @@ def main():
         "sampling_replica_steps_per_s": {v: rows * T / (stage[f"{v}_ms"] * 1e-3) for v in variants},
         "front_size": P, "hypervolume": str(hv),
     }
+    peaks = measured_peaks(q, torch)
+    result["measured_peaks"] = peaks
+    result["roofline"]["measured_peak"] = peaks["fp32_fma_TFLOPs"]
+    result["roofline"]["frac_of_measured_peak"] = achieved / peaks["fp32_fma_TFLOPs"]
     if not args.no_forms:
         result["forms"] = {"precision": precision_form(q, wl, torch)}
+        for prec in ("fp32", "bf16", "fp8"):
+            pf = result["forms"]["precision"][prec]
+            pf["frac_of_measured_peak"] = pf["matrix_TFLOPs"] / peaks[f"{prec}_mfma_TFLOPs"]
         lf = learned_form(q, wl, torch)
         result["forms"]["learned"] = lf
         if args.batch_form:

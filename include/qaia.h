@@ -367,6 +367,34 @@ int32_t qaia_new_point_labels(const int64_t *keep_idx, const int64_t *num_keep, 
 int32_t qaia_gather_rows(const void *src, int32_t width, const int64_t *idx, const int64_t *count,
                          int64_t cap, void *dst, void *hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Measurement kernels.  Not part of the method: they measure this GPU's own
+ * ceilings (VALU FMA issue, matrix-core rate per operand format, HBM copy)
+ * so that a kernel's roofline fraction can be stated against a measured peak
+ * as well as the datasheet one.  Each result has a closed form (checked by
+ * the tests); time the launch with events on `hip_stream`.  Asynchronous;
+ * argument errors return before anything is enqueued.
+ */
+
+/* blocks x 256 lanes, each running eight independent fp32 FMA chains
+ * x <- x * a + b for `iters` iterations from x0 = (t + c) mod 8 (lane t,
+ * chain c); out[t] (DEVICE float [blocks * 256]) = sum of the eight final
+ * values.  Work: blocks * 256 * iters * 8 FMAs = 16 flop per lane-iteration.
+ * blocks in [1, 2^31), iters >= 1. */
+int32_t qaia_peak_fma(int64_t blocks, int32_t iters, float a, float b, float *out, void *hip_stream);
+
+/* blocks x 4 waves, each wave issuing `iters` rounds of four independent
+ * 32x32 MFMAs with every operand 1.0: precision QAIA_FP32 (32x32x2),
+ * QAIA_BF16 (32x32x16) or QAIA_FP8 (e4m3, 32x32x64).  out[t] (DEVICE float
+ * [blocks * 256]) = 4 * K * iters with K = 2, 16, 64.  Work per launch:
+ * blocks * 4 * iters * 4 * 2 * 32 * 32 * K flop.  blocks in [1, 2^31),
+ * iters >= 1 and 4 * K * iters < 2^24 (exact accumulation). */
+int32_t qaia_peak_mfma(int32_t precision, int64_t blocks, int32_t iters, float *out, void *hip_stream);
+
+/* dst = src, `bytes` (a multiple of 16) between two DEVICE buffers that are
+ * 16-byte aligned and do not overlap; 2 * bytes of HBM traffic. */
+int32_t qaia_peak_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -85,6 +85,9 @@ _SIGS = {
     "qaia_sample_batch": (_i32, [_P, _i32, C.POINTER(qaia_schedule), _P, _sz, _P]),
     "qaia_plan_autotune_workspace_bytes": (_i32, [_P, _i32, C.POINTER(qaia_schedule), _i32, C.POINTER(_sz)]),
     "qaia_plan_autotune": (_i32, [_P, _i32, C.POINTER(qaia_schedule), _i32, _P, _P, _sz, _P]),
+    "qaia_peak_fma": (_i32, [_i64, _i32, C.c_float, C.c_float, _P, _P]),
+    "qaia_peak_mfma": (_i32, [_i32, _i64, _i32, _P, _P]),
+    "qaia_peak_copy": (_i32, [_P, _P, _sz, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -497,6 +500,35 @@ def qaia_gather_rows(src: torch.Tensor, idx: torch.Tensor, count: torch.Tensor, 
         raise ValueError("row size must be a multiple of 4 bytes")
     _check(_lib.qaia_gather_rows(_ptr(src), row_bytes // 4, _ptr(idx), _ptr(count), cap, _ptr(dst),
                                  _stream(stream)))
+    return dst
+
+
+# ------------------------------------------------------------------ measurement kernels
+
+def qaia_peak_fma(blocks: int, iters: int, a: float = 1.0, b: float = 1.0, out=None, device=None,
+                  stream=None) -> torch.Tensor:
+    """Eight fp32 FMA chains per lane (x <- x a + b); out[t] = sum of the final values."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = _dev_tensor(out, torch.float32, (blocks * 256,), dev)
+    _check(_lib.qaia_peak_fma(blocks, iters, a, b, _ptr(out), _stream(stream)))
+    return out
+
+
+def qaia_peak_mfma(precision, blocks: int, iters: int, out=None, device=None, stream=None) -> torch.Tensor:
+    """Four independent 32x32 MFMAs per wave per iteration, operands 1.0; out[t] = 4 K iters."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = _dev_tensor(out, torch.float32, (blocks * 256,), dev)
+    _check(_lib.qaia_peak_mfma(prec, blocks, iters, _ptr(out), _stream(stream)))
+    return out
+
+
+def qaia_peak_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> torch.Tensor:
+    """dst = src for two equal-sized device buffers (16-byte multiple)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst sizes differ")
+    _check(_lib.qaia_peak_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)))
     return dst
 
 

@@ -466,6 +466,46 @@ int32_t qaia_gather_rows(const void *src, int32_t width, const int64_t *idx, con
     });
 }
 
+// ---------------------------------------------------------------- measurement kernels
+
+int32_t qaia_peak_fma(int64_t blocks, int32_t iters, float a, float b, float *out, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(blocks >= 1 && blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "blocks must be in [1, 2^31)");
+        QAIA_CHECK(iters >= 1, QAIA_INVALID_ARGUMENT, "iters must be >= 1");
+        QAIA_CHECK(out != nullptr, QAIA_INVALID_ARGUMENT, "null out");
+        launch_peak_fma(blocks, iters, a, b, out, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_peak_mfma(int32_t precision, int64_t blocks, int32_t iters, float *out, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(precision == QAIA_FP32 || precision == QAIA_BF16 || precision == QAIA_FP8,
+                   QAIA_INVALID_ARGUMENT, "unknown precision");
+        QAIA_CHECK(blocks >= 1 && blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "blocks must be in [1, 2^31)");
+        const int64_t K = precision == QAIA_FP32 ? 2 : (precision == QAIA_BF16 ? 16 : 64);
+        QAIA_CHECK(iters >= 1 && 4 * K * (int64_t)iters < (int64_t(1) << 24), QAIA_INVALID_ARGUMENT,
+                   "iters must be >= 1 with 4 K iters < 2^24");
+        QAIA_CHECK(out != nullptr, QAIA_INVALID_ARGUMENT, "null out");
+        launch_peak_mfma(precision, blocks, iters, out, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_peak_copy(const void *src, void *dst, size_t bytes, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(bytes % 16 == 0, QAIA_INVALID_ARGUMENT, "bytes must be a multiple of 16");
+        QAIA_CHECK(bytes == 0 || (src && dst), QAIA_INVALID_ARGUMENT, "null buffer");
+        QAIA_CHECK(((uintptr_t)src | (uintptr_t)dst) % 16 == 0, QAIA_INVALID_ARGUMENT,
+                   "buffers must be 16-byte aligned");
+        const uintptr_t s0 = (uintptr_t)src, d0 = (uintptr_t)dst;
+        QAIA_CHECK(bytes == 0 || s0 + bytes <= d0 || d0 + bytes <= s0, QAIA_INVALID_ARGUMENT,
+                   "buffers overlap");
+        launch_peak_copy(src, dst, bytes, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
 // ---------------------------------------------------------------- batching form
 
 int32_t qaia_sample_batch_workspace_bytes(const qaia_batch_item *items, int32_t count, const qaia_schedule *s,

@@ -218,6 +218,10 @@ void launch_labels(const int64_t *keep, const int64_t *num_keep, int64_t archive
                    float *labels, hipStream_t st);
 void launch_gather_rows(const uint32_t *src, int width, const int64_t *idx, const int64_t *count,
                         int64_t cap, uint32_t *dst, hipStream_t st);
+// measurement kernels (peaks.hip)
+void launch_peak_fma(int64_t blocks, int32_t iters, float a, float b, float *out, hipStream_t st);
+void launch_peak_mfma(int32_t precision, int64_t blocks, int32_t iters, float *out, hipStream_t st);
+void launch_peak_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 
 // batching form (batch.cpp)
 size_t batch_ws_bytes(const qaia_batch_item *items, int32_t count, const qaia_schedule &s);

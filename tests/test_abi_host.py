@@ -141,3 +141,21 @@ def test_pareto_ranks_argument_errors(q):
     assert ei.value.status == q.QAIA_INVALID_ARGUMENT  # m > 8
     q._check(q._lib.qaia_pareto_ranks(None, 0, 3, 5, None, ctypes.byref(n), None, 0, None))
     assert n.value == 0
+
+
+def test_peak_kernels_argument_errors(q):
+    bad = [
+        lambda: q._lib.qaia_peak_fma(0, 10, 1.0, 1.0, 16, None),            # blocks < 1
+        lambda: q._lib.qaia_peak_fma(4, 0, 1.0, 1.0, 16, None),             # iters < 1
+        lambda: q._lib.qaia_peak_fma(4, 10, 1.0, 1.0, None, None),          # null out
+        lambda: q._lib.qaia_peak_mfma(3, 4, 10, 16, None),                  # unknown precision
+        lambda: q._lib.qaia_peak_mfma(q.PRECISIONS["fp8"], 4, 1 << 16, 16, None),  # 4 * 64 * iters >= 2^24
+        lambda: q._lib.qaia_peak_copy(16, 4096, 40, None),                  # not a multiple of 16
+        lambda: q._lib.qaia_peak_copy(16, 32, 64, None),                    # overlapping buffers
+        lambda: q._lib.qaia_peak_copy(8, 4096, 64, None),                   # misaligned
+    ]
+    for call in bad:
+        with pytest.raises(q.QaiaError) as ei:
+            q._check(call())
+        assert ei.value.status == q.QAIA_INVALID_ARGUMENT
+    q._check(q._lib.qaia_peak_copy(None, None, 0, None))  # empty copy: nothing enqueued
