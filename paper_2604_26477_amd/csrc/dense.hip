@@ -546,6 +546,15 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
             for (int c2 = 0; c2 < 2; ++c2)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) acc[k][r2][c2][i] = 0.0f;
+    // the epilogue's per-column coefficients and the step coefficient are
+    // loaded before the k loop, so their latency hides behind it
+    float cfs[2][M];
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+            cfs[c2][k] = k < m ? j.coef[(size_t)(col0 + wc * 64 + c2 * 32 + lr) * m + k] : 0.0f;
+    const float kt = j.kt_tab[t];
     mma_tile_dma<PREC, M>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds);
 
     // Epilogue in two phases.  (1) h = sum_k coef_k(col) H_k(row, col) from the
@@ -558,10 +567,7 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
 #pragma unroll
     for (int c2 = 0; c2 < 2; ++c2) {
         const int cl = wc * 64 + c2 * 32 + lr;
-        const int col = col0 + cl;
-        float cf[M];
-#pragma unroll
-        for (int k = 0; k < M; ++k) cf[k] = k < m ? j.coef[(size_t)col * m + k] : 0.0f;
+        const float *cf = cfs[c2];
 #pragma unroll
         for (int r2 = 0; r2 < 2; ++r2)
 #pragma unroll
@@ -581,7 +587,6 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
     }
     __syncthreads();
 
-    const float kt = j.kt_tab[t];
     const size_t Np = (size_t)j.Np;
     const int tr = (threadIdx.x & 31) * 4;
     for (int it = 0; it < kT2 / 8; ++it) {
