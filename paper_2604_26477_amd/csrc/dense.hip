@@ -39,6 +39,7 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kDB = 256;      // threads per block
 constexpr int kTileM = 64;    // spins per block
@@ -413,19 +414,22 @@ __device__ __forceinline__ void dma_chunk(char *stage, const char *const (&src)[
     for (int i = 0; i < 2 * (MT + 1); ++i) dma_copy<MT>(stage, src[i], koff, wave, i);
 }
 
-// this wave's copies of all but the newest `later` chunks have landed
-// (later <= 6; later * PER stays within the 6-bit vmcnt field)
-template <int PER>
+// this wave's copies of all but the newest `later` chunks have landed, with
+// X further loads (the epilogue's prefetch) issued after those chunks'
+// copies; later <= 6, and (later * PER + X) must fit the 6-bit vmcnt field
+// for every reachable `later` (asserted by the caller; unreachable cases clamp)
+constexpr int vm_imm(int n) { return n < 63 ? n : 63; }
+
+template <int PER, int X = 0>
 __device__ __forceinline__ void dma_wait(int later) {
-    static_assert(6 * PER <= 63, "vmcnt range");
     switch (later) {
-        case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
-        case 1: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(PER) : "memory"); break;
-        case 2: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * PER) : "memory"); break;
-        case 3: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(3 * PER) : "memory"); break;
-        case 4: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(4 * PER) : "memory"); break;
-        case 5: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(5 * PER) : "memory"); break;
-        default: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(6 * PER) : "memory"); break;
+        case 0: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(vm_imm(X)) : "memory"); break;
+        case 1: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(vm_imm(PER + X)) : "memory"); break;
+        case 2: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(vm_imm(2 * PER + X)) : "memory"); break;
+        case 3: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(vm_imm(3 * PER + X)) : "memory"); break;
+        case 4: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(vm_imm(4 * PER + X)) : "memory"); break;
+        case 5: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(vm_imm(5 * PER + X)) : "memory"); break;
+        default: asm volatile("s_waitcnt vmcnt(%0)" ::"n"(vm_imm(6 * PER + X)) : "memory"); break;
     }
 }
 
@@ -440,15 +444,44 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_barrier" ::: "memory");
 }
 
-template <int PREC, int MT>
+// Epilogue prefetch: NPF / 2 rows of 16 bytes from each of px and py, row i
+// at element offset off0 + i * stride, into xpf / ypf, issued a few chunks
+// before the end of the k loop (the waits that follow count the NPF loads).
+template <int NPF>
+struct EpiPrefetch {
+    static constexpr int N = NPF > 0 ? NPF / 2 : 1;
+    const float *px, *py;
+    size_t off0, stride;
+    f32x4 xpf[N], ypf[N];
+};
+
+// Global-address-space loads: a flat load (what a pointer read from memory
+// compiles to) would also count against the LDS counter that the k loop's
+// barriers drain.
+typedef __attribute__((address_space(1))) const f32x4 global_f32x4;
+
+template <int NPF>
+__device__ __forceinline__ void epi_prefetch(EpiPrefetch<NPF> &pf) {
+    if constexpr (NPF > 0) {
+#pragma unroll
+        for (int i = 0; i < NPF / 2; ++i) {
+            const size_t off = pf.off0 + (size_t)i * pf.stride;
+            pf.xpf[i] = *(global_f32x4 *)(pf.px + off);
+            pf.ypf[i] = *(global_f32x4 *)(pf.py + off);
+        }
+    }
+}
+
+template <int PREC, int MT, int NPF>
 __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, int Np_, int m, int row0, int col0,
                                              int wr, int wc, int half, int lr, f16v (&acc)[MT][2][2],
-                                             char *lds) {
+                                             char *lds, EpiPrefetch<NPF> &pf) {
     typedef typename PrecInfo<PREC>::T T;
     constexpr int ES = sizeof(T);
     constexpr int PER = 2 * (MT + 1);  // copies per wave per chunk
     constexpr int D = dma_stages<MT>();
     static_assert(D >= 2 && D - 2 <= 6, "stage ring depth");
+    static_assert((D - 2) * PER + NPF <= 63, "vmcnt range");
     const size_t Np = (size_t)Np_;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const char *src[PER];
@@ -474,6 +507,17 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
 #pragma unroll
     for (int q = 0; q < D - 1; ++q)
         if (q < nk) dma_chunk<MT>(S[q], src, (size_t)q * kChunkB, wave);
+    // The prefetch is issued at the end of iteration c_pf, PFD chunks before
+    // the one that issues the last chunk's copies (or after the prologue when
+    // c_pf is -1).  Chunks whose copies were issued before it, c_pf < c <=
+    // c_pf + D - 1, wait with its NPF loads counted as newer.  Distances 0 to
+    // 8 measured the same within noise (BF16, m = 3); 0 keeps the registers
+    // free longest.
+    constexpr int PFD = 0;
+    const int c_pf = nk - D - PFD > -1 ? nk - D - PFD : -1;
+    if constexpr (NPF > 0) {
+        if (c_pf < 0) epi_prefetch(pf);
+    }
     // Rotation: after the barrier for chunk c, unit 0 of chunk c is read while
     // unit 1 of chunk c - 1 (already in registers) runs, then unit 1 of chunk c
     // is read while unit 0 of chunk c runs.
@@ -484,7 +528,8 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
             const int c = c0 + u;
             if (c < nk) {
                 const int later = (nk - 1 - c) < (D - 2) ? (nk - 1 - c) : (D - 2);
-                dma_wait<PER>(later);
+                if (NPF > 0 && c > c_pf && c <= c_pf + D - 1) dma_wait<PER, NPF>(later);
+                else dma_wait<PER>(later);
                 lds_barrier();  // chunk c is in LDS for every wave; all waves are done reading chunk c - 1
                 // the copies of chunk c + D - 1 (into the stage chunk c - 1 used):
                 // BF16 / FP32 spread them over this iteration's two MFMA groups,
@@ -516,6 +561,10 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
                 __builtin_amdgcn_sched_barrier(0);
                 frag_mma_cp<PREC, MT, kSpread ? PER / 2 : 0>(f0, m, 0, acc, copy1);
                 __builtin_amdgcn_sched_barrier(0);
+                if constexpr (NPF > 0) {
+                    if (c == c_pf) epi_prefetch(pf);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
     }
@@ -523,8 +572,19 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
     lds_barrier();
 }
 
+// Where the epilogue prefetch fits in 512 registers without spilling (checked
+// on the compiled kernels): m <= 2 everywhere; m = 3 only for BF16 single-job
+// launches (FP32 and FP8 fragments, or the grouped kernel's job lookup, leave
+// no room for the 128 prefetch registers beside 192 accumulators).
+template <int PREC, int MT>
+constexpr bool staged_prefetch(bool grouped) {
+    return MT <= 2 || (MT == 3 && PREC == QAIA_BF16 && !grouped);
+}
+
 // FIXED_M: the job's m equals MT (single-job launches), so objective guards fold away.
-template <int PREC, int MT, bool DSB, bool FIXED_M>
+// PF: the epilogue's x and y are prefetched into registers during the k loop
+// (where they fit beside the accumulators and fragments without spilling).
+template <int PREC, int MT, bool DSB, bool FIXED_M, bool PF>
 __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by, char *lds) {
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int half = l >> 5, lr = l & 31;
@@ -555,7 +615,18 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
         for (int k = 0; k < M; ++k)
             cfs[c2][k] = k < m ? j.coef[(size_t)(col0 + wc * 64 + c2 * 32 + lr) * m + k] : 0.0f;
     const float kt = j.kt_tab[t];
-    mma_tile_dma<PREC, M>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds);
+    // PF: the epilogue's x and y (16 float4 each per thread, the phase-2
+    // mapping below) are loaded into registers once the last chunk's copies
+    // are issued, so their HBM latency overlaps the final chunks' MFMAs
+    const size_t Np = (size_t)j.Np;
+    const int tr = (threadIdx.x & 31) * 4;
+    // native vectors: arrays of HIP's float4 struct are not promoted to registers
+    EpiPrefetch<PF ? 2 * (kT2 / 8) : 0> pf;
+    pf.px = x_in;
+    pf.py = j.y;
+    pf.off0 = (size_t)(col0 + (threadIdx.x >> 5)) * Np + row0 + tr;
+    pf.stride = 8 * Np;
+    mma_tile_dma<PREC, M, PF ? 2 * (kT2 / 8) : 0>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds, pf);
 
     // Epilogue in two phases.  (1) h = sum_k coef_k(col) H_k(row, col) from the
     // accumulators (same k order as the register-tile kernel) into an LDS tile
@@ -587,21 +658,20 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
     }
     __syncthreads();
 
-    const size_t Np = (size_t)j.Np;
-    const int tr = (threadIdx.x & 31) * 4;
-    for (int it = 0; it < kT2 / 8; ++it) {
+    // One 4-spin segment of the update: y += kt x + h (+ dt alpha eta), x +=
+    // dt a0 y, the wall, then x, y, phi and the trace written back.
+    auto update = [&](int it, f32x4 xv, f32x4 yv, auto noise_tag) __attribute__((always_inline)) {
+        constexpr bool NOISE = decltype(noise_tag)::value;
         const int cl = it * 8 + (threadIdx.x >> 5);
         const int col = col0 + cl, row = row0 + tr;
         const size_t off = (size_t)col * Np + row;
         const float4 hv4 = *(const float4 *)(hs + cl * kHsPitch + tr);
-        const float4 xv = *(const float4 *)(x_in + off);
-        const float4 yv = *(const float4 *)(j.y + off);
         float hv[4] = {hv4.x, hv4.y, hv4.z, hv4.w};
         float xs[4] = {xv.x, xv.y, xv.z, xv.w}, ys[4] = {yv.x, yv.y, yv.z, yv.w};
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
             float yn = fmaf(kt, xs[ii], ys[ii]) + hv[ii];
-            if (j.dt_alpha != 0.0f && col < j.cols && row + ii < j.N) {
+            if (NOISE && col < j.cols && row + ii < j.N) {
                 const uint64_t g = (uint64_t)col + j.offset;
                 const uint64_t nidx = (g * (uint64_t)j.steps + (uint64_t)t) * (uint64_t)j.N + (uint64_t)(row + ii);
                 yn = fmaf(j.dt_alpha, noise_value(j.seed, nidx), yn);
@@ -632,6 +702,21 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
             for (int ii = 0; ii < 4; ++ii)
                 if (row + ii < j.N) j.trace[((size_t)col * j.trace_steps + t) * j.N + row + ii] = xs[ii];
         }
+    };
+    auto load = [&](const float *base, int it) __attribute__((always_inline)) {
+        return *(const f32x4 *)(base + (size_t)(col0 + it * 8 + (threadIdx.x >> 5)) * Np + row0 + tr);
+    };
+    if (j.dt_alpha == 0.0f) {
+        // plain SB: fully unrolled, so the prefetched registers are indexed statically
+#pragma unroll
+        for (int it = 0; it < kT2 / 8; ++it) {
+            const int i = PF ? it : 0;
+            update(it, PF ? pf.xpf[i] : load(x_in, it), PF ? pf.ypf[i] : load(j.y, it), std::false_type{});
+        }
+    } else {
+        // noise injection (Eq. 10): the Gaussian draw makes the body too large to
+        // unroll; x and y are read again here
+        for (int it = 0; it < kT2 / 8; ++it) update(it, load(x_in, it), load(j.y, it), std::true_type{});
     }
 }
 
@@ -664,7 +749,7 @@ __global__ __launch_bounds__(kDB) void dense_step_staged_kernel(DenseJob j, int 
     __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<M>()];
     int bx, by;
     xcd_tile(j.tiles_x, j.tiles_y, bx, by);
-    dense_step_staged_body<PREC, M, DSB, true>(j, t, bx, by, lds);
+    dense_step_staged_body<PREC, M, DSB, true, staged_prefetch<PREC, M>(false)>(j, t, bx, by, lds);
 }
 
 // XCD-aware order inside one job of a grouped launch (its first block index
@@ -706,7 +791,7 @@ __global__ __launch_bounds__(kDB) void dense_batch_step_staged_kernel(const Dens
     if (local >= (int64_t)j.tiles_x * j.tiles_y) return;
     int bx, by;
     xcd_tile_local(local, j.tiles_x, j.tiles_y, bx, by);
-    dense_step_staged_body<PREC, MT, DSB, true>(j, t, bx, by, lds);
+    dense_step_staged_body<PREC, MT, DSB, true, staged_prefetch<PREC, MT>(true)>(j, t, bx, by, lds);
 }
 
 // Field mode (reduced-precision error reporting): field[col][k][i] = 2^e_k (J~_k Phi)_i.
