@@ -239,14 +239,25 @@ def batch_run(q, wl, torch, variant="bsb", precision="fp32", T=1500, W=1024, R=3
     torch.cuda.synchronize()
     single_s = time.perf_counter() - t0
     paths = {}
-    for it in items:
+    dense_flops = sparse_flops = 0
+    for (n, m, kind, sd), it in zip(specs, items):
         paths[it.path] = paths.get(it.path, 0) + 1
+        if it.path.startswith("dense"):
+            dense_flops += 2 * m * n * n * W * R * T  # the stacked product, unpadded
+        else:
+            inst = wl.random_instance(n, m, kind, seed=sd)
+            sparse_flops += fma_flops_per_replica_step(n, inst.num_edges) * W * R * T
     total = count * W * R * T
     return {"workload": f"{count} instances, N~U[42,1024], m~U{{3,4}}, class~U{{deg3,10%,50%}}, "
                         f"{W} weight vectors x {R} replicas x {T} steps, {variant} {precision}",
             "autotune_s": tune_s, "paths": paths, "estimated_s": float(est.sum()),
             "batched_graph_s": batch_s, "per_instance_s": single_s,
-            "batched_replica_steps_per_s": total / batch_s, "per_instance_replica_steps_per_s": total / single_s}
+            "batched_replica_steps_per_s": total / batch_s, "per_instance_replica_steps_per_s": total / single_s,
+            "algorithmic_flops": {"dense_matrix": dense_flops, "sparse_fma": sparse_flops},
+            "batched_TFLOPs": (dense_flops + sparse_flops) / batch_s / 1e12,
+            # the dense items' matrix work alone, against the FP32 matrix peak: a
+            # lower bound on matrix-core use (the sparse items take part of the time)
+            "dense_matrix_frac_of_fp32_mfma_peak": dense_flops / batch_s / 1e12 / 157.3}
 
 
 def table2_form(q, wl, torch, sizes=((25, 0.5), (25, 1.0), (100, 0.5), (100, 1.0), (200, 0.5), (200, 1.0))):
