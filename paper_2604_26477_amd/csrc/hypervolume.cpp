@@ -21,8 +21,11 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <numeric>
 #include <thread>
 #include <vector>
+
+#include <sched.h>
 
 #include "internal.hpp"
 
@@ -163,8 +166,11 @@ U256 hv3(std::vector<const uint64_t *> &P) {
 }
 
 // Non-dominated subset in the first d coordinates (dominated and repeated
-// points removed), used to keep the WFG limit sets small.
-void nondominated(std::vector<uint64_t> &buf, int stride, int d, size_t &count) {
+// points removed), used to keep the WFG limit sets small.  In descending
+// order of the coordinate sum, a point is dropped iff some earlier point is
+// >= it in every coordinate (a dominator has a larger sum; of equal points
+// the first is kept); with `threads` > 1 the points are checked in parallel.
+void nondominated(std::vector<uint64_t> &buf, int stride, int d, size_t &count, int threads = 1) {
     std::vector<size_t> order(count);
     for (size_t i = 0; i < count; ++i) order[i] = i;
     auto sum = [&](size_t i) {
@@ -174,30 +180,39 @@ void nondominated(std::vector<uint64_t> &buf, int stride, int d, size_t &count) 
     };
     std::vector<long double> key(count);
     for (size_t i = 0; i < count; ++i) key[i] = sum(i);
-    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return key[a] > key[b]; });
-    std::vector<size_t> keep;
-    for (size_t oi = 0; oi < count; ++oi) {
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return key[a] != key[b] ? key[a] > key[b] : a < b; });
+    std::vector<char> keep(count, 0);
+    auto check = [&](size_t oi) {
         const uint64_t *q = &buf[order[oi] * stride];
-        bool any_zero = false;
-        for (int k = 0; k < d; ++k) any_zero |= q[k] == 0;
-        if (any_zero) continue;
-        bool dominated = false;
-        for (size_t kj : keep) {  // a dominator has a sum at least as large: it is kept already
-            const uint64_t *p = &buf[kj * stride];
+        for (int k = 0; k < d; ++k)
+            if (q[k] == 0) return;  // zero extent: no volume
+        for (size_t oj = 0; oj < oi; ++oj) {
+            const uint64_t *p = &buf[order[oj] * stride];
             bool ge = true;
             for (int k = 0; k < d && ge; ++k) ge = p[k] >= q[k];
-            if (ge) {
-                dominated = true;
-                break;
-            }
+            if (ge) return;
         }
-        if (!dominated) keep.push_back(order[oi]);
+        keep[oi] = 1;
+    };
+    const int nt = (int)std::max<size_t>(1, std::min<size_t>((size_t)threads, count / 256));
+    if (nt == 1) {
+        for (size_t oi = 0; oi < count; ++oi) check(oi);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nt; ++t)
+            pool.emplace_back([&, t]() {
+                for (size_t oi = (size_t)t; oi < count; oi += (size_t)nt) check(oi);
+            });
+        for (auto &th : pool) th.join();
     }
-    std::vector<uint64_t> out(keep.size() * stride);
-    for (size_t i = 0; i < keep.size(); ++i)
-        std::memcpy(&out[i * stride], &buf[keep[i] * stride], sizeof(uint64_t) * stride);
+    size_t kept = 0;
+    for (size_t oi = 0; oi < count; ++oi) kept += keep[oi];
+    std::vector<uint64_t> out(kept * stride);
+    size_t w = 0;
+    for (size_t oi = 0; oi < count; ++oi)
+        if (keep[oi]) std::memcpy(&out[(w++) * stride], &buf[order[oi] * stride], sizeof(uint64_t) * stride);
     buf.swap(out);
-    count = keep.size();
+    count = kept;
 }
 
 U256 wfg(std::vector<uint64_t> buf, int stride, int d, size_t count, int threads);
@@ -259,6 +274,78 @@ U256 wfg(std::vector<uint64_t> buf, int stride, int d, size_t count, int threads
     return total;
 }
 
+// m = 4: the top level of the recursion above with two exact shortcuts.
+// (1) Clipping by min(q, p) keeps the order of the third coordinate, so one
+// descending sort of all points serves every limit set's sweep (filtered to
+// the points after p in the order of the fourth coordinate).  (2) Once the
+// staircase covers p's whole (x, y) face, every lower slab is full, and the
+// sweep stops.
+U256 hv4(const std::vector<uint64_t> &buf, size_t count, int threads) {
+    std::vector<size_t> order(count), zdesc(count), rank(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        return buf[a * 4 + 3] != buf[b * 4 + 3] ? buf[a * 4 + 3] < buf[b * 4 + 3] : a < b;
+    });
+    for (size_t r = 0; r < count; ++r) rank[order[r]] = r;
+    std::iota(zdesc.begin(), zdesc.end(), 0);
+    std::sort(zdesc.begin(), zdesc.end(), [&](size_t a, size_t b) {
+        return buf[a * 4 + 2] != buf[b * 4 + 2] ? buf[a * 4 + 2] > buf[b * 4 + 2] : a < b;
+    });
+    const int nt = (int)std::max<size_t>(1, std::min<size_t>((size_t)threads, count / 64));
+    std::vector<U256> part(nt);
+    auto work = [&](int t) {
+        // interleaved assignment balances the decreasing cost along the order
+        for (size_t r = (size_t)t; r < count; r += (size_t)nt) {
+            const uint64_t *p = &buf[order[r] * 4];
+            if (p[3] == 0) continue;
+            U256 box;
+            box.w[0] = 1;
+            for (int k = 0; k < 3; ++k) box = mul64(box, p[k]);
+            const u128 full = (u128)p[0] * p[1];
+            Staircase st;
+            U256 cov;
+            uint64_t prev = p[2];
+            bool filled = false;
+            for (size_t j : zdesc) {
+                if (rank[j] <= r) continue;
+                const uint64_t *q = &buf[j * 4];
+                const uint64_t z = std::min(q[2], p[2]);
+                if (prev > z && st.area) cov = add(cov, mul64(from128(st.area), prev - z));
+                prev = z;
+                st.insert(std::min(q[0], p[0]), std::min(q[1], p[1]));
+                if (st.area == full) {
+                    if (prev) cov = add(cov, mul64(from128(full), prev));
+                    filled = true;
+                    break;
+                }
+            }
+            if (!filled && st.area && prev) cov = add(cov, mul64(from128(st.area), prev));
+            part[t] = add(part[t], mul64(sub(box, cov), p[3]));
+        }
+    };
+    if (nt == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nt; ++t) pool.emplace_back(work, t);
+        for (auto &th : pool) th.join();
+    }
+    U256 total;
+    for (const U256 &v : part) total = add(total, v);
+    return total;
+}
+
+// Host threads: the CPUs this process may run on (the affinity mask), or
+// QAIA_HV_THREADS.
+int hv_threads() {
+    int n = (int)std::thread::hardware_concurrency();
+    cpu_set_t set;
+    CPU_ZERO(&set);
+    if (sched_getaffinity(0, sizeof(set), &set) == 0 && CPU_COUNT(&set) > 0) n = CPU_COUNT(&set);
+    if (const char *e = std::getenv("QAIA_HV_THREADS")) n = std::atoi(e);
+    return std::max(1, n);
+}
+
 }  // namespace
 
 int32_t hypervolume_exact(const int64_t *pts, int64_t P, int32_t m, const int64_t *ref,
@@ -292,10 +379,9 @@ int32_t hypervolume_exact(const int64_t *pts, int64_t P, int32_t m, const int64_
         v = hv2(Pp, 0, 1);
     } else {
         size_t count = (size_t)P;
-        nondominated(ext, m, m, count);
-        int threads = (int)std::thread::hardware_concurrency();
-        if (const char *e = std::getenv("QAIA_HV_THREADS")) threads = std::atoi(e);
-        v = wfg(ext, m, m, count, std::max(1, threads));
+        const int threads = hv_threads();
+        nondominated(ext, m, m, count, threads);
+        v = m == 4 ? hv4(ext, count, threads) : wfg(ext, m, m, count, threads);
     }
     for (int i = 0; i < 4; ++i) hv[i] = v.w[i];
     if (approx) *approx = to_double(v);

@@ -159,3 +159,22 @@ def test_peak_kernels_argument_errors(q):
             q._check(call())
         assert ei.value.status == q.QAIA_INVALID_ARGUMENT
     q._check(q._lib.qaia_peak_copy(None, None, 0, None))  # empty copy: nothing enqueued
+
+
+@pytest.mark.parametrize("threads", ["1", "3", "8"])
+def test_hypervolume_threaded_paths_match_oracle(q, threads, monkeypatch):
+    """The m = 3 and m = 4 paths with their threaded non-dominated filter and
+    (m = 4) threaded sweep: a front with duplicates, dominated points, ties in
+    every coordinate and points clipped to zero extent, large enough to split
+    over threads."""
+    monkeypatch.setenv("QAIA_HV_THREADS", threads)
+    rng = np.random.default_rng(300 + int(threads))
+    for m in (3, 4):
+        d = np.abs(rng.standard_normal((400, m)))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        front = np.round(d * 3000).astype(np.int64)            # mostly non-dominated, some ties
+        dominated = front[:120] - rng.integers(0, 40, size=(120, m))
+        pts = np.concatenate([front, front[:100], dominated, -front[:20]])  # duplicates, clipped
+        pts = pts[rng.permutation(len(pts))]
+        ref = np.zeros(m, np.int64)
+        assert q.qaia_hypervolume(pts, ref) == oracle.hypervolume(pts, ref), m

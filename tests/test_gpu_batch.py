@@ -33,6 +33,7 @@ SPECS = [  # (n, m, kind, W, R, path)
     (70, 3, "complete", 4, 8, "dense"),
     (260, 3, "p0.3", 5, 30, "dense_staged"),
     (300, 3, "deg3", 2, 3, "sparse_lds"),
+    (180, 2, "p0.4", 4, 20, "dense_staged"),  # m <= 2: the grouped kernel's epilogue prefetch
 ]
 
 
@@ -79,7 +80,7 @@ def test_batch_matches_per_item_calls(q, variant):
 def test_batch_low_precision_dense(q):
     import torch
     specs = [(90, 3, "p0.1", "dense"), (150, 4, "p0.5", "dense_staged"), (130, 3, "complete", "dense"),
-             (200, 3, "complete", "dense_staged")]
+             (200, 3, "complete", "dense_staged"), (160, 2, "complete", "dense_staged")]
     items, refs = [], []
     for i, (n, m, kind, path) in enumerate(specs):
         inst = wl.random_instance(n, m, kind, seed=900 + i)

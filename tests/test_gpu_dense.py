@@ -164,13 +164,16 @@ def test_dense_invalid_rows_and_determinism(q, path):
     assert not a[8:12].any() and not oa[8:12].any()
 
 
+@pytest.mark.parametrize("m", [2, 4])
 @pytest.mark.parametrize("variant,prec", [("bsb", "fp32"), ("dsb", "bf16"), ("dsb", "fp8")])
-def test_staged_tiles_match_register_tiles_when_exact(q, variant, prec):
+def test_staged_tiles_match_register_tiles_when_exact(q, variant, prec, m):
     """Exact weights make every partial sum an exact integer, so the two tile
     kernels must agree bit for bit whatever their k order: 300 spins (three
-    128-spin tiles, ragged) and 20 x 16 replicas (three 128-column tiles, ragged)."""
-    inst = _small_int_instance(300, 4, seed=60, kind="p0.6")
-    c = wl.dirichlet_weights(20, 4, 61)
+    128-spin tiles, ragged) and 20 x 16 replicas (three 128-column tiles,
+    ragged); m = 2 runs the staged epilogue on prefetched x and y, m = 4 loads
+    them after the k loop."""
+    inst = _small_int_instance(300, m, seed=60, kind="p0.6")
+    c = wl.dirichlet_weights(20, m, 61)
     prob = q.problem_from_instance(inst)
     outs = []
     for path in DENSE_PATHS:
