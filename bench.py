@@ -142,9 +142,10 @@ def learned_form(q, wl, torch, budget_rounds=40, ref_factor=10, max_seconds=240.
     Every loop runs rounds of 1024 weight vectors x 256 replicas, filters
     against its archive and computes the exact hypervolume.  Contenders:
     plain FP32 bSB, 2000 steps, uniform Dirichlet vectors (the baseline); the
-    learned proposer (1024 of 65536 scored candidates, same sampler); and
+    learned proposer (1024 of 65536 scored candidates, same sampler);
     noise-injected bSB with the paper's short schedule (50 steps, dt 1,
-    alpha 0.1, Eq. 10), uniform vectors.  The plain loop runs budget_rounds
+    alpha 0.1, Eq. 10), uniform vectors; and the learned proposer feeding that
+    short noise-injected sampler.  The plain loop runs budget_rounds
     rounds; the others run for the same wall time.  References: the plain
     loop's final hypervolume (time_to_ref), and the union hypervolume of a
     plain loop at ref_factor times the budget (fractions)."""
@@ -164,13 +165,15 @@ def learned_form(q, wl, torch, budget_rounds=40, ref_factor=10, max_seconds=240.
     ref_hv = ref_loop.history[-1]["hv"]
     out = {"workload": "42-node degree<=3, m=4; rounds of 1024 weight vectors x 256 replicas; plain: bSB FP32 "
                        "2000 steps dt 0.5, uniform Dirichlet; learned: 1024 of 65536 scored candidates; "
-                       "ni_bsb_short: bSB 50 steps dt 1.0 alpha 0.1, uniform Dirichlet",
+                       "ni_bsb_short: bSB 50 steps dt 1.0 alpha 0.1, uniform Dirichlet; learned_ni_bsb_short: the "
+                       "learned proposer with that sampler",
            "reference": {"rounds": ref_rounds, "hv": str(ref_hv), "front": ref_loop.history[-1]["front"],
                          "seconds": ref_seconds},
            "budget_rounds": budget_rounds}
     contenders = (("plain_fp32_uniform", dict(learned=False)),
                   ("learned_proposer", dict(learned=True)),
-                  ("ni_bsb_short", dict(learned=False, steps=50, dt=1.0, noise_alpha=0.1)))
+                  ("ni_bsb_short", dict(learned=False, steps=50, dt=1.0, noise_alpha=0.1)),
+                  ("learned_ni_bsb_short", dict(learned=True, steps=50, dt=1.0, noise_alpha=0.1)))
     budget_s = None
     for name, extra in contenders:
         args = dict(kw)
@@ -527,7 +530,8 @@ def main():
             result["forms"]["batching"] = batch_form(q, wl, torch)
         if args.table2_form:
             result["forms"]["table2"] = table2_form(q, wl, torch)
-        forms = {k: lf[k]["seconds_to_reference_hv"] for k in ("learned_proposer", "ni_bsb_short")}
+        forms = {k: lf[k]["seconds_to_reference_hv"]
+                 for k in ("learned_proposer", "ni_bsb_short", "learned_ni_bsb_short")}
         reached = {k: v for k, v in forms.items() if v is not None}
         chosen = min(reached, key=reached.get) if reached else None
         result["time_to_ref_hypervolume"] = {
@@ -538,7 +542,8 @@ def main():
             "chosen_form_s": forms[chosen] if chosen else None,
             "plain_fp32_s": lf["reference"]["seconds"],
             "to_plain_final_hv_s": {k: lf[k]["seconds_to_plain_final_hv"]
-                                    for k in ("plain_fp32_uniform", "learned_proposer", "ni_bsb_short")},
+                                    for k in ("plain_fp32_uniform", "learned_proposer", "ni_bsb_short",
+                                              "learned_ni_bsb_short")},
         }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(inst, c_host, R, T)
