@@ -263,6 +263,53 @@ def batch_run(q, wl, torch, variant="bsb", precision="fp32", T=1500, W=1024, R=3
             "dense_matrix_frac_of_fp32_mfma_peak": dense_flops / batch_s / 1e12 / 157.3}
 
 
+def noise_form(q, wl, torch, recovery_budget_s=15.0):
+    """Synthetic analogues of the paper's noise studies on 25-node instances
+    whose exact fronts come from GPU enumeration (2^24 cuts): an Appendix-E
+    three-objective instance (190 Das-Dennis vectors, the paper's alpha 0.15)
+    and a four-objective instance with N(0,1) weights (220 vectors, alpha
+    0.1).  Recovery (Fig. 3 analogue): batches of the vectors x 3000 replicas,
+    each filtered into the archive, until every exact front vector has been
+    sampled; plain SB (1000 steps, dt 0.5) against noise-injected SB (50
+    steps, dt 1, Eq. 10) and uniform random spins, reporting the samples and
+    seconds to full recall (or the recall at the budget).  Noise sweep
+    (Appendix C analogue): one batch of the short schedule per noise
+    amplitude, reporting recall and the hypervolume ratio to the exact front
+    (reference point: the per-objective minimum cut)."""
+    from paper_2604_26477_amd.protocols import run_budget
+    cases = (("appendix_e_n25_m3", wl.appendix_e_instance(25, 0.5, seed=7000), wl.das_dennis_interior(3, 21), 0.15),
+             ("gauss_n25_m4_p0.5", wl.random_instance(25, 4, "p0.5", seed=7001), wl.das_dennis_interior(4, 13), 0.1))
+    out = {"workload": "25-node instances with exact fronts; batches of Das-Dennis vectors x 3000 replicas",
+           "instances": []}
+    for ci, (name, inst, weights, alpha) in enumerate(cases):
+        prob = q.problem_from_instance(inst, 0)
+        _, front, lo = q.exact_front(prob, with_min=True)
+        hv_ref = q.qaia_hypervolume(front, lo)
+        rec = {"name": name, "m": inst.m, "weight_vectors": len(weights), "paper_alpha": alpha,
+               "front_size": int(front.shape[0]), "recovery": {}, "noise_sweep": []}
+        runs = (("random", "random", 50, 1.0, 0.0), ("bsb_plain_T1000", "bsb", 1000, 0.5, 0.0),
+                ("dsb_plain_T1000", "dsb", 1000, 0.5, 0.0), ("bsb_noise_T50", "bsb", 50, 1.0, alpha),
+                ("dsb_noise_T50", "dsb", 50, 1.0, alpha))
+        for ri, (label, method, steps, dt, a) in enumerate(runs):
+            r = run_budget(prob, method, recovery_budget_s, weights=weights, R=3000, steps=steps, dt=dt, alpha=a,
+                           seed=7100 + 10 * ci + ri, target=front)
+            h = r["history"]
+            full = h[-1]["recall"] == 1.0
+            rec["recovery"][label] = {"full_recall": full, "samples": h[-1]["samples"], "seconds": h[-1]["seconds"],
+                                      "recall": h[-1]["recall"], "batches": r["batches"],
+                                      "recall_after_first_batch": h[0]["recall"]}
+            print(json.dumps({"noise_recovery": [name, label, rec["recovery"][label]]}), file=sys.stderr, flush=True)
+        for ai, a in enumerate((0.0, 0.05, 0.1, 0.15, 0.2, 0.3, 0.5, 1.0)):
+            for method in ("bsb", "dsb"):
+                r = run_budget(prob, method, float("inf"), weights=weights, R=3000, steps=50, dt=1.0, alpha=a,
+                               seed=7300 + 10 * ci + ai, max_batches=1, target=front)
+                rec["noise_sweep"].append({"method": method, "alpha": a, "recall": r["history"][-1]["recall"],
+                                           "hv_ratio": q.qaia_hypervolume(r["front"], lo) / hv_ref})
+        out["instances"].append(rec)
+        print(json.dumps({"noise_instance": rec}), file=sys.stderr, flush=True)
+    return out
+
+
 def table2_form(q, wl, torch, sizes=((25, 0.5), (25, 1.0), (100, 0.5), (100, 1.0), (200, 0.5), (200, 1.0))):
     """Budgeted protocol on correlated three-objective instances shaped like
     Appendix E: 190 Das-Dennis weight vectors x 3000 replicas per batch
@@ -341,13 +388,15 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision and learned form measurements")
     ap.add_argument("--batch-form", action="store_true",
                     help="also measure the 64-instance ragged batch (takes minutes in FP32)")
-    ap.add_argument("--only-form", choices=["precision", "learned", "batching", "table2", "peaks"],
+    ap.add_argument("--only-form", choices=["precision", "learned", "batching", "table2", "peaks", "noise"],
                     help="run one form measurement alone and print its JSON (for profiling)")
     ap.add_argument("--precision-steps", type=int, default=1000,
                     help="SB steps of the precision form (shorter runs for counter collection)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one bSB sampling launch of the workload and one 1 GiB device copy, for HBM "
                          "counter collection (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), then exit")
+    ap.add_argument("--noise-form", action="store_true",
+                    help="also run the noise studies (front recovery, noise sweep) on 25-node exact fronts")
     ap.add_argument("--table2-form", action="store_true",
                     help="also run the budgeted protocol on Appendix-E-shaped instances (about 2 minutes)")
     args = ap.parse_args()
@@ -369,6 +418,8 @@ def main():
             res = precision_form(q, wl, torch, T=args.precision_steps)
         elif args.only_form == "peaks":
             res = measured_peaks(q, torch)
+        elif args.only_form == "noise":
+            res = noise_form(q, wl, torch)
         else:
             res = {"learned": learned_form, "batching": batch_form, "table2": table2_form}[args.only_form](q, wl, torch)
         print(json.dumps({"form": args.only_form, "result": res}), flush=True)
@@ -530,6 +581,8 @@ def main():
             result["forms"]["batching"] = batch_form(q, wl, torch)
         if args.table2_form:
             result["forms"]["table2"] = table2_form(q, wl, torch)
+        if args.noise_form:
+            result["forms"]["noise"] = noise_form(q, wl, torch)
         forms = {k: lf[k]["seconds_to_reference_hv"]
                  for k in ("learned_proposer", "ni_bsb_short", "learned_ni_bsb_short")}
         reached = {k: v for k, v in forms.items() if v is not None}

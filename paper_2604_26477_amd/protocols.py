@@ -20,14 +20,20 @@ from . import (make_schedule, qaia_evaluate, qaia_pareto_filter, qaia_pareto_fil
 
 def run_budget(prob, method: str, budget_s: float, weights=None, R: int = 3000, steps: int = 50,
                dt: float = 1.0, alpha: float = 0.1, seed: int = 0, path: str = "auto",
-               precision: str = "fp32", archive_cap: int = 1 << 20):
+               precision: str = "fp32", archive_cap: int = 1 << 20, max_batches: int | None = None,
+               target=None):
     """Sampling-filtering rounds until budget_s seconds of wall time have passed.
 
     method: "random", "bsb" or "dsb".  SB methods sample every weight vector
     (float32 [W, m], host or device) with R replicas per batch; the random
     baseline draws W * R uniform configurations per batch.  Returns a dict
     with the archive (host int64 [P, m]), the per-objective minimum over all
-    samples, the batch and sample counts and the elapsed seconds."""
+    samples, the batch and sample counts and the elapsed seconds.
+
+    max_batches stops after that many batches.  target (host int64 [F, m], a
+    known Pareto front) adds the recall after every batch (the fraction of
+    target vectors in the archive; a front vector, once sampled, is never
+    dominated, so it stays) to "history", and stops at full recall."""
     dev = prob.torch_device
     m = prob.m
     if weights is None:
@@ -49,6 +55,8 @@ def run_budget(prob, method: str, budget_s: float, weights=None, R: int = 3000, 
     A = 0
     lo = None
     batches = 0
+    tset = {tuple(int(v) for v in r) for r in np.asarray(target)} if target is not None else None
+    history = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while True:
@@ -69,8 +77,19 @@ def run_budget(prob, method: str, budget_s: float, weights=None, R: int = 3000, 
         pool[:P] = pool[keep[:P]]
         A = P
         batches += 1
+        if tset is not None:
+            found = sum(1 for r in pool[:A].cpu().tolist() if tuple(r) in tset)
+            history.append({"samples": batches * rows, "seconds": time.perf_counter() - t0,
+                            "recall": found / max(len(tset), 1)})
+            if found == len(tset):
+                break
+        if max_batches is not None and batches >= max_batches:
+            break
         if time.perf_counter() - t0 >= budget_s:
             break
     elapsed = time.perf_counter() - t0
-    return {"front": pool[:A].cpu().numpy(), "min": lo.cpu().numpy(), "batches": batches,
-            "samples": batches * rows, "seconds": elapsed}
+    out = {"front": pool[:A].cpu().numpy(), "min": lo.cpu().numpy(), "batches": batches,
+           "samples": batches * rows, "seconds": elapsed}
+    if tset is not None:
+        out["history"] = history
+    return out
