@@ -55,3 +55,25 @@ def test_budget_archive_is_a_valid_front(q, case, method):
         got0 = {tuple(v) for v in plain["front"]} & fset
         print(f"{method}: {len(got)} (noise) vs {len(got0)} (plain) of {len(front)} front points")
         assert len(got) > len(got0)
+
+
+def test_recall_tracking_against_the_exact_front(q, case):
+    """With the oracle's exact front as the target, the recall recorded per
+    batch is the fraction of front vectors in the archive: non-decreasing (a
+    sampled front vector is never dominated), equal to a recount of the
+    returned archive, and the run stops at full recall (random spins cover
+    the 2^13 configurations of this instance quickly)."""
+    from paper_2604_26477_amd.protocols import run_budget
+    inst, prob, all_obj, front = case
+    w = wl.das_dennis_interior(3, 8)
+    fset = {tuple(v) for v in front}
+    r = run_budget(prob, "random", 30.0, weights=w, R=64, seed=5, target=front)
+    rec = [h["recall"] for h in r["history"]]
+    assert len(rec) == r["batches"] and all(b >= a for a, b in zip(rec, rec[1:]))
+    assert rec[-1] == 1.0 and fset <= {tuple(v) for v in r["front"]}
+    # a capped SB run: the recall matches a recount of its archive
+    s = run_budget(prob, "bsb", 30.0, weights=w, R=64, steps=50, dt=1.0, alpha=0.1, seed=6, target=front,
+                   max_batches=3)
+    assert s["batches"] <= 3
+    found = len({tuple(v) for v in s["front"]} & fset)
+    assert s["history"][-1]["recall"] == found / len(fset)
