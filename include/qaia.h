@@ -260,7 +260,10 @@ int32_t qaia_pareto_ranks(const int64_t *obj, int64_t M, int32_t m, int32_t max_
  *         in units of the product of the coordinate units.
  *   hv_approx : HOST double, may be NULL.
  * Errors: INVALID_ARGUMENT, OVERFLOW if the sum over objectives of the bit
- * lengths of (max_k y_k - ref_k) exceeds 256. */
+ * lengths of (max_k y_k - ref_k) exceeds 256.
+ * Synchronous host computation; for m >= 3 it runs on as many threads as
+ * the calling process's CPU affinity mask allows (QAIA_HV_THREADS in the
+ * environment overrides the count).  Thread-safe: calls share no state. */
 int32_t qaia_hypervolume(const int64_t *pts, int64_t P, int32_t m, const int64_t *ref,
                          uint64_t hv[4], double *hv_approx);
 
