@@ -111,6 +111,11 @@ def test_noise_moments():
     assert abs(eta.var() - 1.0) < 4 * math.sqrt(2.0 / eta.size)
     # fourth moment of N(0,1) is 3
     assert abs((eta ** 4).mean() - 3.0) < 0.15
+    # the whole distribution (Kolmogorov-Smirnov against N(0,1)) and
+    # independence of successive counter positions (lag-1 correlation)
+    from scipy import stats
+    assert stats.kstest(eta, "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(eta[:-1], eta[1:])[0, 1]) < 4 / math.sqrt(eta.size)
 
 
 # --------------------------------------------------------------------------
