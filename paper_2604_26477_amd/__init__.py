@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqaia.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_26477_amd.build` "
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2604_26477_amd/build.py` "
                       "(or __graft_entry__.build())")
 
 _lib = C.CDLL(LIB_PATH)
