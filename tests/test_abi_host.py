@@ -178,3 +178,19 @@ def test_hypervolume_threaded_paths_match_oracle(q, threads, monkeypatch):
         pts = pts[rng.permutation(len(pts))]
         ref = np.zeros(m, np.int64)
         assert q.qaia_hypervolume(pts, ref) == oracle.hypervolume(pts, ref), m
+
+
+def test_header_compiles_as_c99_and_cpp(tmp_path):
+    """include/qaia.h is a C ABI: it must compile as pedantic C99 and as C++."""
+    import shutil
+    import subprocess
+    src = tmp_path / "use.c"
+    src.write_text('#include "qaia.h"\nint main(void) { return qaia_abi_version() > 0 ? 0 : 1; }\n')
+    inc = os.path.join(ROOT, "include")
+    for cc, args in (("gcc", ["-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror"]),
+                     ("g++", ["-std=c++17", "-Wall", "-Wextra", "-Werror", "-x", "c++"])):
+        if shutil.which(cc) is None:
+            pytest.skip(f"{cc} not available")
+        r = subprocess.run([cc, *args, "-I", inc, "-c", str(src), "-o", str(tmp_path / "use.o")],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
