@@ -28,11 +28,18 @@ def _declared_symbols():
 
 def test_every_declared_symbol_is_exported(q):
     import ctypes
+    import shutil
+    import subprocess
     lib = ctypes.CDLL(q.LIB_PATH)
     names = _declared_symbols()
     assert "qaia_sample" in names and "qaia_hypervolume" in names
     for name in names:
         assert hasattr(lib, name), name
+    # and conversely: the library exports no qaia_ entry point the header lacks
+    if shutil.which("nm"):
+        out = subprocess.run(["nm", "-D", "--defined-only", q.LIB_PATH], capture_output=True, text=True).stdout
+        exported = {f for line in out.splitlines() for f in line.split()[2:3] if f.startswith("qaia_")}
+        assert exported == set(names), sorted(exported ^ set(names))
 
 
 def test_version_and_status_strings(q):
