@@ -86,18 +86,21 @@ double to_double(const U256 &a) {
     return r;
 }
 
-// 2-D staircase area of the points seen so far, updated on insertion.
-// Map key x (ascending), value y; kept non-dominated, so y descends with x.
+// 2-D staircase area of the points seen so far, updated on insertion.  The
+// points are kept in a flat vector sorted by x (ascending); non-dominated, so
+// y descends with x.  An insertion removes a contiguous run, so the update is
+// a binary search, a short backward scan and one block move (no per-point
+// allocation, unlike a tree).
 struct Staircase {
-    std::map<uint64_t, uint64_t> pts;
+    typedef std::pair<uint64_t, uint64_t> Pt;
+    std::vector<Pt> pts;
     u128 area = 0;
 
     // area of the segments of the points in [first, last) given the x of the
     // point left of first (0 if none)
-    static u128 seg_sum(std::map<uint64_t, uint64_t>::iterator first,
-                        std::map<uint64_t, uint64_t>::iterator last, uint64_t left_x) {
+    static u128 seg_sum(const Pt *first, const Pt *last, uint64_t left_x) {
         u128 s = 0;
-        for (auto it = first; it != last; ++it) {
+        for (const Pt *it = first; it != last; ++it) {
             s += (u128)(it->first - left_x) * it->second;
             left_x = it->first;
         }
@@ -106,32 +109,32 @@ struct Staircase {
 
     void insert(uint64_t x, uint64_t y) {
         if (x == 0 || y == 0) return;
+        Pt *b = pts.data(), *e = b + pts.size();
         // dominated by (or equal to) a stored point: some stored px >= x with py >= y;
         // among the points with px >= x the first one has the largest y.
-        auto ge = pts.lower_bound(x);
-        if (ge != pts.end() && ge->second >= y) return;
+        Pt *ge = std::lower_bound(b, e, x, [](const Pt &p, uint64_t v) { return p.first < v; });
+        if (ge != e && ge->second >= y) return;
         // every stored point with px >= x now has py < y.  Stored points
         // dominated by (x, y) (px <= x and py <= y) form a contiguous run: the
         // points left of `ge` with py <= y, plus `ge` itself when px == x.
-        auto right = ge;  // first surviving point to the right of x
-        if (right != pts.end() && right->first == x) ++right;
-        auto first = ge;
-        while (first != pts.begin()) {
-            auto prev = std::prev(first);
-            if (prev->second <= y)
-                first = prev;
-            else
-                break;
-        }
-        uint64_t left_x = first == pts.begin() ? 0 : std::prev(first)->first;
+        Pt *right = ge;  // first surviving point to the right of x
+        if (right != e && right->first == x) ++right;
+        Pt *first = ge;
+        while (first != b && (first - 1)->second <= y) --first;
+        const uint64_t left_x = first == b ? 0 : (first - 1)->first;
         // segments whose area changes: the removed run and the right neighbour
-        auto stop = right == pts.end() ? right : std::next(right);
-        u128 before = seg_sum(first, stop, left_x);
+        const Pt *stop = right == e ? right : right + 1;
+        const u128 before = seg_sum(first, stop, left_x);
         u128 after = (u128)(x - left_x) * y;
-        if (right != pts.end()) after += (u128)(right->first - x) * right->second;
-        pts.erase(first, right);
-        pts.emplace(x, y);
+        if (right != e) after += (u128)(right->first - x) * right->second;
         area = area - before + after;
+        const size_t fi = (size_t)(first - b), ri = (size_t)(right - b);
+        if (fi == ri) {
+            pts.insert(pts.begin() + fi, Pt(x, y));
+        } else {
+            pts[fi] = Pt(x, y);
+            pts.erase(pts.begin() + fi + 1, pts.begin() + ri);
+        }
     }
 };
 
