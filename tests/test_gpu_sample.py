@@ -195,6 +195,79 @@ def test_edge_cases_tiny_graphs(q):
     assert obj0.numel() == 0
 
 
+def _traj_rel_error(x_gpu, x_ref):
+    """Per row: max over steps and spins of |x_gpu - x_ref|, over max |x_ref| of the
+    row's whole traced trajectory.  One- and two-spin trajectories pass close to
+    zero every few steps, where a per-step relative norm is undefined."""
+    num = np.abs(x_gpu.astype(np.float64) - x_ref).max(axis=(1, 2))
+    return num / np.maximum(np.abs(x_ref).max(axis=(1, 2)), 1e-30)
+
+
+@pytest.mark.parametrize("path", SPARSE_PATHS + ["dense", "dense_staged"])
+def test_degenerate_graphs_every_path(q, path):
+    """One spin with no edges and two spins with one positive edge, on every path
+    and, for discrete SB on the dense paths, every field precision.
+
+    * One spin: c0 = 0 (the c0 fallback of Eq. 9 with no couplings), so the spin
+      is a free oscillator with stiffness a0 - a(t); its ballistic trace follows
+      the FP64 oracle within 1e-5 of the trajectory's scale (FP32 rounding alone,
+      emulated on the CPU with fused multiply-adds, reaches 1.1e-6 over 100
+      steps); every cut is 0.
+    * Two spins, one edge of positive weight: the antisymmetric normal mode has
+      stiffness a0 - a(t) - c0 J = -a(t) and grows, so ballistic SB ends with the
+      edge cut in every row (the sign of the coupling term in Eq. 9); the
+      oracle ends the same way on these seeds.  Discrete SB can end with both
+      spins aligned, so its rows are checked by exact evaluation only.
+      This mode starts at zero stiffness, so a last-place rounding of the
+      per-step coefficient -dt (a0 - a(t)) is a large relative error in its
+      early growth: a CPU emulation of FP32 fused multiply-adds in the kernels'
+      order, over 3 000 random starts, stays within 7.7e-4 of the trajectory's
+      scale (median 3.5e-7, 99th percentile 7.7e-6).  The trace bound here is
+      therefore 1e-3; a wrong sign, a dropped term or a swapped index gives
+      errors of order 1.
+    """
+    import torch
+    c = wl.dirichlet_weights(5, 2, 81)
+    precs = ["fp32"] if path in SPARSE_PATHS else ["fp32", "bf16", "fp8"]
+
+    lone = wl.Instance(1, 2, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros((2, 0), np.int32))
+    prob = q.problem_from_instance(lone)
+    s = q.make_schedule("bsb", steps=1000, dt=0.5, seed=82, path=path)
+    _, obj, _, tr = q.qaia_sample_trace(prob, _dev(c), 4, s, 100)
+    torch.cuda.synchronize()
+    _, ref = oracle.sb_sample(lone, c, 4, 1000, "bsb", dt=0.5, seed=82, trace_steps=100)
+    err = _traj_rel_error(tr.cpu().numpy(), ref)
+    print(f"{path} one spin: max trajectory-relative error {err.max():.3e}")
+    assert err.max() <= 1e-5
+    assert not obj.cpu().numpy().any()
+    for prec in precs:
+        sp, ob, ws = _sample(q, prob, c, 4, variant="dsb", precision=prec, steps=200, seed=83, path=path)
+        assert q.qaia_workspace_status(ws) is None
+        assert sp.shape == (20, 1) and not ob.any(), prec
+    _, obj0, _ = q.qaia_sample(prob, torch.zeros((0, 2), dtype=torch.float32, device="cuda"), 2,
+                               q.make_schedule(steps=10, path=path))
+    assert obj0.numel() == 0
+
+    # integer weights (5 and 3) x 2^16: exact in bf16 and e4m3 after power-of-two scaling
+    w = (np.array([[5], [3]], np.int64) << 16).astype(np.int32)
+    pair = wl.Instance(2, 2, np.array([0], np.int32), np.array([1], np.int32), w)
+    both_cut = np.array([5 << 16, 3 << 16], np.int64)
+    prob = q.problem_from_instance(pair)
+    s = q.make_schedule("bsb", steps=1000, dt=0.5, seed=84, path=path)
+    spins, obj, _, tr = q.qaia_sample_trace(prob, _dev(c), 32, s, 100)
+    torch.cuda.synchronize()
+    sp_ref, ref = oracle.sb_sample(pair, c, 32, 1000, "bsb", dt=0.5, seed=84, trace_steps=100)
+    assert (oracle.cut_values(pair, sp_ref) == both_cut).all()
+    err = _traj_rel_error(tr.cpu().numpy(), ref)
+    print(f"{path} two spins: max trajectory-relative error {err.max():.3e}")
+    assert err.max() <= 1e-3
+    assert (obj.cpu().numpy() == both_cut).all()
+    for prec in precs:
+        sp, ob, ws = _sample(q, prob, c, 32, variant="dsb", precision=prec, steps=1000, seed=85, path=path)
+        assert q.qaia_workspace_status(ws) is None
+        assert np.array_equal(ob, oracle.cut_values(pair, unpack_spins(sp, 2))), prec
+
+
 # ---------------------------------------------------------------- noise injection (Eq. 10)
 
 # Seeds of the noise-injected trajectory test.  On this instance the error of
