@@ -931,6 +931,10 @@ static uint8_t to_e4m3(double v) {
 }
 
 void dense_build(Problem &p) {
+    if (p.m > 4) {  // the dense kernels hold at most four objective tiles
+        p.dense.why = "the dense path supports m <= 4";
+        return;
+    }
     const int64_t Np = (p.n + 127) / 128 * 128;  // both tile heights (64, 128) divide it
     const double bytes = (double)p.m * Np * Np * 7.0;
     if (bytes > 4.0 * (1ull << 30)) {
