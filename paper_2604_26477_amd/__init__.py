@@ -569,7 +569,8 @@ def qaia_sample_batch(items, s: qaia_schedule, workspace=None, stream=None):
     arr = _items_array(items)
     need = qaia_sample_batch_workspace_bytes(items, s)
     if workspace is None or workspace.numel() < need:
-        workspace = torch.empty(need, dtype=torch.uint8, device=items[0].problem.torch_device)
+        dev = items[0].problem.torch_device if items else torch.device("cuda", torch.cuda.current_device())
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
     _check(_lib.qaia_sample_batch(C.cast(arr, C.c_void_p), len(items), C.byref(s), _ptr(workspace),
                                   workspace.numel(), _stream(stream)))
     return workspace

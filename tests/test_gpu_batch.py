@@ -77,6 +77,56 @@ def test_batch_matches_per_item_calls(q, variant):
         assert np.array_equal(it.obj.cpu().numpy(), oracle.cut_values(inst, unpack_spins(it.spins.cpu().numpy(), inst.n)))
 
 
+@pytest.mark.parametrize("variant", ["bsb", "dsb"])
+def test_batch_empty_single_and_no_items(q, variant):
+    """Items with no weight vectors on every path sit beside full ones and are
+    skipped; a one-item batch and a batch with only empty items work; an empty
+    list is a no-op.  Full items match per-item calls bit for bit."""
+    import torch
+    specs = [  # (n, m, kind, W, R, path)
+        (42, 3, "deg3", 0, 5, "sparse_reg"),
+        (42, 4, "deg3", 6, 7, "sparse_lds"),
+        (150, 3, "p0.5", 0, 8, "dense_staged"),
+        (90, 2, "p0.2", 5, 9, "dense"),
+        (60, 3, "deg3", 0, 4, "sparse_lds"),
+        (42, 3, "deg3", 3, 6, "sparse_reg"),
+        (80, 3, "p0.3", 0, 3, "dense"),
+        (130, 3, "p0.4", 4, 10, "dense_staged"),
+    ]
+    s = q.make_schedule(variant, steps=200, dt=0.5, seed=93)
+    probs, items = [], []
+    for i, (n, m, kind, W, R, path) in enumerate(specs):
+        inst = wl.random_instance(n, m, kind, seed=900 + i)
+        p = q.problem_from_instance(inst)
+        c = _dev(wl.dirichlet_weights(W, m, 950 + i)) if W else torch.zeros((0, m), dtype=torch.float32,
+                                                                               device="cuda")
+        probs.append((inst, p, c, R, path))
+        items.append(q.BatchItem(p, c, R, path))
+
+    def per_item(p, c, R, path):
+        sp, ob, _ = q.qaia_sample(p, c, R, q.make_schedule(variant, steps=200, dt=0.5, seed=93, path=path))
+        return sp, ob
+
+    q.qaia_sample_batch(items, s)
+    torch.cuda.synchronize()
+    for (inst, p, c, R, path), it in zip(probs, items):
+        if c.shape[0] == 0:
+            assert it.spins.numel() == 0 and it.obj.numel() == 0
+            continue
+        sp, ob = per_item(p, c, R, path)
+        torch.cuda.synchronize()
+        assert torch.equal(it.spins, sp) and torch.equal(it.obj, ob), (inst.name, path)
+
+    one = q.BatchItem(probs[7][1], probs[7][2], probs[7][3], "dense_staged")
+    q.qaia_sample_batch([one], s)
+    torch.cuda.synchronize()
+    assert torch.equal(one.spins, items[7].spins) and torch.equal(one.obj, items[7].obj)
+
+    q.qaia_sample_batch([it for it, spec in zip(items, specs) if spec[3] == 0], s)
+    q.qaia_sample_batch([], s)
+    torch.cuda.synchronize()
+
+
 def test_batch_low_precision_dense(q):
     import torch
     specs = [(90, 3, "p0.1", "dense"), (150, 4, "p0.5", "dense_staged"), (130, 3, "complete", "dense"),
