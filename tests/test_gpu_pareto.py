@@ -41,6 +41,21 @@ def test_filter_empty(q):
     assert _filter(q, np.zeros((0, 3), np.int64)).size == 0
 
 
+def test_filter_degenerate_pools(q):
+    """All vectors equal -> the first index; a strict chain -> its top only; one
+    point dominating a random pool, planted twice -> its first copy only."""
+    same = np.tile(np.array([[3, -1, 7]], np.int64), (5000, 1))
+    assert _filter(q, same).tolist() == [0]
+    rng = np.random.default_rng(12)
+    chain = np.repeat(rng.permutation(4000)[:, None], 4, axis=1).astype(np.int64)
+    got = _filter(q, chain)
+    assert got.tolist() == [int(np.argmax(chain[:, 0]))]
+    assert np.array_equal(got, oracle.pareto_filter(chain))
+    pool = rng.integers(-100, 100, size=(6000, 3)).astype(np.int64)
+    pool[1234] = pool[4321] = [100, 100, 100]
+    assert _filter(q, pool).tolist() == [1234]
+
+
 def test_filter_anticorrelated_large_front(q):
     """Points on a hyperplane are mutually non-dominated: the whole set survives
     (spans many chunks in the global pass)."""
