@@ -57,12 +57,23 @@ extern "C" {
 #define QAIA_BF16 1 /* discrete SB, dense path: bf16 J (per-objective scaled) x exact +-1, fp32 accumulate */
 #define QAIA_FP8 2  /* discrete SB, dense path: fp8 e4m3 J (per-objective scaled) x exact +-1, fp32 accumulate */
 
-/* kernel family; AUTO lets the planner decide */
+/* kernel family; AUTO lets the planner decide.  Each family has size limits;
+ * a request for a family past its limit returns QAIA_UNSUPPORTED before
+ * anything is queued.  AUTO takes the first that applies: DENSE_STAGED for
+ * a BF16/FP8 field, SPARSE_REG, SPARSE_LDS, DENSE_STAGED. */
 #define QAIA_PATH_AUTO 0
-#define QAIA_PATH_SPARSE_REG 1 /* per-graph generated kernel, one replica per lane, state in registers */
-#define QAIA_PATH_SPARSE_LDS 2 /* generic kernel, one spin per lane, state and adjacency in LDS */
-#define QAIA_PATH_DENSE 3      /* stacked per-objective matrix product on the matrix cores, 64 x 128 tiles */
-#define QAIA_PATH_DENSE_STAGED 4 /* as QAIA_PATH_DENSE with 128 x 128 tiles staged through LDS */
+/* per-graph generated kernel, one replica per lane, state in registers:
+ * 2n + num_edges <= 232, FP32 */
+#define QAIA_PATH_SPARSE_REG 1
+/* generic kernel, one spin per lane, state and adjacency in LDS:
+ * n <= 4096, every degree <= 32, FP32 */
+#define QAIA_PATH_SPARSE_LDS 2
+/* stacked per-objective matrix product on the matrix cores, 64 x 128 tiles:
+ * m <= 4 and dense images of at most 4 GiB (m * Np^2 * 7 bytes, Np = n
+ * rounded up to a multiple of 128) */
+#define QAIA_PATH_DENSE 3
+/* as QAIA_PATH_DENSE with 128 x 128 tiles staged through LDS; same limits */
+#define QAIA_PATH_DENSE_STAGED 4
 
 typedef struct qaia_problem qaia_problem;
 
