@@ -18,6 +18,7 @@
 #include <sys/wait.h>
 #include <unistd.h>
 
+#include <cerrno>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -243,8 +244,13 @@ static std::vector<char> compile(const std::string &src, bool device_libs) {
         err = "cannot start " + clang + ": " + std::strerror(rc);
     } else {
         int status = 0;
-        waitpid(pid, &status, 0);
-        if (!WIFEXITED(status) || WEXITSTATUS(status) != 0) {
+        pid_t w;
+        do {  // a signal may interrupt the wait before the compiler exits
+            w = waitpid(pid, &status, 0);
+        } while (w < 0 && errno == EINTR);
+        if (w < 0) {
+            err = std::string("waiting for the kernel compiler failed: ") + std::strerror(errno);
+        } else if (!WIFEXITED(status) || WEXITSTATUS(status) != 0) {
             std::ifstream lf(log);
             std::stringstream ls;
             ls << lf.rdbuf();
