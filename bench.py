@@ -30,9 +30,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "replica-steps/s & time-to-ref-hypervolume: chosen form vs plain FP32, 1 GPU"
 WORKLOAD = "c2_n42_m4"
-# FP32 FMA on the vector ALUs with packed FP32 disabled (the build turns it
-# off): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s (the
-# datasheet's 157.3 counts packed FMA).
+# Datasheet FP32 vector peak of the MI355X (256 CUs x 2.4 GHz, counting packed
+# FP32 FMA): the denominator of the sparse kernel's algorithmic roofline.
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+# Non-packed FP32 FMA issue (256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz);
+# the library is compiled with packed FP32 disabled.
 PEAK_FP32_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # HBM bytes of one qaia_sb_reg launch on this workload, from two rocprofv3
@@ -47,15 +49,41 @@ _WRITE_SCALE = 1048576.0 / 1048576.0
 SB_REG_TRAFFIC_BYTES = (3699.6875 * _FETCH_SCALE + 200000.0 * _WRITE_SCALE) * _KIB
 
 
+def algorithmic_flops_per_replica_step(n: int, E: int) -> int:
+    """Algorithmic work of one sparse replica-step in the combined-weight form:
+    2|E| field FMAs plus three per spin (the stiffness term, the coupling scale
+    and the x update), two flops each."""
+    return 2 * (2 * E + 3 * n)
+
+
 def fma_flops_per_replica_step(n: int, E: int) -> int:
-    """Algorithmic flops of one replica-step of the sparse kernel: 2|E| field
-    FMAs plus, per spin, one FMA for -(a0 - a_t) x and one for x += dt a0 y,
-    two flops each.  The wall's compare/select/clamp (and dSB's sign) are
-    integer-like selects, not flops."""
+    """Flops the generated kernel performs per replica-step: 2|E| field FMAs
+    (c0 folded into the coefficients) plus one FMA for -(a0 - a_t) x and one
+    for x += dt a0 y per spin."""
     return 2 * (2 * E + 2 * n)
 
 
+def valu_instructions_per_replica_step(inst, variant: str) -> int:
+    """VALU instructions of the generated kernel's step loop per replica (one
+    replica per lane): 2|E| + 2n FMAs, three wall operations per spin
+    (compare, select, clamp) and, for discrete SB, one copysign per spin that
+    feeds a neighbour.  For the 42-node, 48-edge graph: 306 (bSB), 347 (dSB),
+    as counted in the compiled loop."""
+    n, E = inst.n, inst.num_edges
+    base = 2 * E + 5 * n
+    if variant == "dsb":
+        deg = np.bincount(np.concatenate([inst.edge_u, inst.edge_v]), minlength=n)
+        base += int((deg > 0).sum())
+    return base
+
+
 def cpu_baseline(inst, weights, R, T, budget_s=12.0):
+    """The oracle on the host cores, on bounded slices of the same workload: bSB
+    and dSB sampling (fp64 dynamics + exact cuts) on the first weight vectors,
+    the non-dominated filter on the oracle's own sample pool (at most 200 000
+    rows) and the exact hypervolume of its front.  value: replica-steps/s of
+    the whole step (both variants, filter and hypervolume) extrapolated from
+    the per-row and per-replica-step costs of the slices."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     probe = weights[:4]
@@ -63,23 +91,49 @@ def cpu_baseline(inst, weights, R, T, budget_s=12.0):
     oracle.sb_sample(inst, probe, R, T, "bsb", dt=0.5, seed=7, nthreads=threads)
     dt_probe = time.perf_counter() - t0
     rate = probe.shape[0] * R * T / max(dt_probe, 1e-9)
-    nw = int(max(4, min(weights.shape[0], budget_s * rate / (R * T))))
+    nw = int(max(4, min(weights.shape[0], budget_s * 0.6 * rate / (R * T))))
     t0 = time.perf_counter()
     spins = oracle.sb_sample(inst, weights[:nw], R, T, "bsb", dt=0.5, seed=7, nthreads=threads)
-    oracle.cut_values(inst, spins)
-    el = time.perf_counter() - t0
-    value = nw * R * T / el
-    # the same oracle on one core, on about 3 s of work
-    n1 = int(max(1, min(weights.shape[0], 3.0 * value / threads / (R * T))))
+    obj_b = oracle.cut_values(inst, spins)
+    el_b = time.perf_counter() - t0
+    rate_b = nw * R * T / el_b
+    nwd = int(max(4, min(weights.shape[0], budget_s * 0.25 * rate / (R * T))))
+    t0 = time.perf_counter()
+    spins = oracle.sb_sample(inst, weights[:nwd], R, T, "dsb", dt=0.5, seed=8, nthreads=threads)
+    obj_d = oracle.cut_values(inst, spins)
+    el_d = time.perf_counter() - t0
+    rate_d = nwd * R * T / el_d
+    pool = np.concatenate([obj_b, obj_d])[:200000]
+    t0 = time.perf_counter()
+    keep = oracle.pareto_filter(pool)
+    el_f = time.perf_counter() - t0
+    front = pool[keep]
+    t0 = time.perf_counter()
+    oracle.hypervolume(front, np.zeros(inst.m, np.int64))
+    el_hv = time.perf_counter() - t0
+    rows = weights.shape[0] * R
+    # one step on the CPU at these rates: both variants, the filter at the
+    # slice's cost per row (a lower bound: the oracle's filter grows faster
+    # than linearly), one hypervolume
+    step_s = rows * T / rate_b + rows * T / rate_d + 2 * rows * el_f / pool.shape[0] + el_hv
+    value = 2 * rows * T / step_s
+    # the bSB sampler on one core, on about 3 s of work
+    n1 = int(max(1, min(weights.shape[0], 3.0 * rate_b / threads / (R * T))))
     t0 = time.perf_counter()
     spins = oracle.sb_sample(inst, weights[:n1], R, T, "bsb", dt=0.5, seed=7, nthreads=1)
     oracle.cut_values(inst, spins)
     el1 = time.perf_counter() - t0
     return {"value": value, "unit": "replica-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"bSB on the first {nw} of {weights.shape[0]} weight vectors x {R} replicas x "
-                      f"{T} steps, fp64 dynamics + exact cuts ({el:.1f} s)",
+            "sample": f"bSB on the first {nw} and dSB on the first {nwd} of {weights.shape[0]} weight vectors "
+                      f"x {R} replicas x {T} steps (fp64 dynamics + exact cuts, {el_b:.1f} s + {el_d:.1f} s); "
+                      f"filter of {pool.shape[0]} of those cut vectors ({el_f:.2f} s, front {front.shape[0]}); "
+                      f"exact hypervolume of that front ({el_hv:.2f} s); whole-step rate extrapolated to "
+                      f"{2 * rows} rows",
+            "stages": {"bsb_replica_steps_per_s": rate_b, "dsb_replica_steps_per_s": rate_d,
+                       "filter_rows": int(pool.shape[0]), "filter_s": el_f, "filter_rows_per_s": pool.shape[0] / el_f,
+                       "front": int(front.shape[0]), "hypervolume_s": el_hv},
             "one_core": {"value": n1 * R * T / el1, "unit": "replica-steps/s",
-                         "sample": f"the first {n1} weight vectors, 1 thread ({el1:.1f} s)"}}
+                         "sample": f"bSB on the first {n1} weight vectors, 1 thread ({el1:.1f} s)"}}
 
 
 def precision_form(q, wl, torch, T=1000):
@@ -133,6 +187,9 @@ def measured_peaks(q, torch, reps=3):
     fma_iters = 1 << 15
     ms = best_ms(lambda: q.qaia_peak_fma(4096, fma_iters, 1.0, 1.0, out=out))
     res = {"fp32_fma_TFLOPs": 4096 * 256 * fma_iters * 16 / (ms * 1e-3) / 1e12}
+    mix_iters = 1 << 13
+    ms = best_ms(lambda: q.qaia_peak_valu(4096, mix_iters, 0.0, out=out))
+    res["valu_mix_Tinstr_per_s"] = 4096 * 256 * mix_iters * 102 / (ms * 1e-3) / 1e12
     for prec, K, iters in (("fp32", 2, 8192), ("bf16", 16, 16384), ("fp8", 64, 16384)):
         ms = best_ms(lambda: q.qaia_peak_mfma(prec, 1024, iters, out=out))
         res[f"{prec}_mfma_TFLOPs"] = 1024 * 4 * iters * 4 * 2 * 32 * 32 * K / (ms * 1e-3) / 1e12
@@ -141,8 +198,9 @@ def measured_peaks(q, torch, reps=3):
     ms = best_ms(lambda: q.qaia_peak_copy(src, dst))
     res["hbm_copy_GBps"] = 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
     del src, dst
-    res["method"] = ("library measurement kernels: 4096 x 256 lanes of 8 FMA chains; 1024 x 4 waves of 4 "
-                     "independent 32x32 MFMAs (operands 1.0); 1 GiB device copy; best of 3")
+    res["method"] = ("library measurement kernels: 4096 x 256 lanes of 8 FMA chains; 4096 x 256 lanes of the "
+                     "sparse SB instruction mix (60 FMAs + 42 compare/select/clamp per iteration); 1024 x 4 waves "
+                     "of 4 independent 32x32 MFMAs (operands 1.0); 1 GiB device copy; best of 3")
     return res
 
 
@@ -551,13 +609,16 @@ def main():
     stage = {k: float(np.mean([p[k] for p in per])) for k in per[0]}
 
     # roofline of the dominant kernel: the generated sparse SB kernel, whose
-    # launches (one bSB, one dSB per step) do the same flops each
-    flops_per_launch = fma_flops_per_replica_step(inst.n, inst.num_edges) * rows * T
+    # launches (one bSB, one dSB per step) do the same algorithmic work each
+    algo_flops_per_launch = algorithmic_flops_per_replica_step(inst.n, inst.num_edges) * rows * T
+    performed_flops_per_launch = fma_flops_per_replica_step(inst.n, inst.num_edges) * rows * T
     # algorithmic HBM bytes of one launch: spins + cut vectors out, folded
     # coefficients, c0 and the step table in
     algo_bytes = rows * 8 * (prob.words + inst.m) + W * (4 * inst.num_edges + 8) + 4 * T
     avg_launch_ms = float(np.mean([stage[f"{v}_ms"] for v in variants]))
-    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    achieved = algo_flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    instr = {v: valu_instructions_per_replica_step(inst, v) for v in variants}
+    issue_rate = sum(instr[v] * rows * T for v in variants) / (sum(stage[f"{v}_ms"] for v in variants) * 1e-3) / 1e12
     result = {
         "metric": METRIC, "value": total_rs / (ms_per_step * 1e-3), "unit": "replica-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -571,18 +632,28 @@ def main():
                    "path": args.path,
                    "pipelining": "step k+1 is queued before step k's front is read back (device-side gather, copy stream); the host hypervolume of step k overlaps the device work of step k+1"},
         "roofline": {"bound": "alu", "kernel": "qaia_sb_reg (bSB and dSB launches)",
-                     "achieved": achieved, "peak": PEAK_FP32_FMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_FMA_TFLOPS, "traffic": SB_REG_TRAFFIC_BYTES,
+                     "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": SB_REG_TRAFFIC_BYTES,
                      "traffic_unit": "bytes per launch (HBM, counters)", "algorithmic_bytes_per_launch": algo_bytes,
-                     "avg_launch_ms": avg_launch_ms, "flops_per_launch": flops_per_launch},
+                     "avg_launch_ms": avg_launch_ms,
+                     "algorithmic_flops_per_replica_step": algorithmic_flops_per_replica_step(inst.n, inst.num_edges),
+                     "flops_per_launch": algo_flops_per_launch,
+                     "performed_fma_flops": {
+                         "per_replica_step": fma_flops_per_replica_step(inst.n, inst.num_edges),
+                         "TFLOPs": performed_flops_per_launch / (avg_launch_ms * 1e-3) / 1e12,
+                         "frac_of_nonpacked_fma_peak": performed_flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+                         / PEAK_FP32_FMA_TFLOPS, "nonpacked_fma_peak": PEAK_FP32_FMA_TFLOPS},
+                     "issue": {"valu_instructions_per_replica_step": instr,
+                               "achieved_Tinstr_per_s": issue_rate}},
         "stages_ms": stage,
         "sampling_replica_steps_per_s": {v: rows * T / (stage[f"{v}_ms"] * 1e-3) for v in variants},
         "front_size": P, "hypervolume": str(hv),
     }
     peaks = measured_peaks(q, torch)
     result["measured_peaks"] = peaks
-    result["roofline"]["measured_peak"] = peaks["fp32_fma_TFLOPs"]
-    result["roofline"]["frac_of_measured_peak"] = achieved / peaks["fp32_fma_TFLOPs"]
+    result["roofline"]["issue"]["measured_mix_peak_Tinstr_per_s"] = peaks["valu_mix_Tinstr_per_s"]
+    result["roofline"]["issue"]["frac"] = issue_rate / peaks["valu_mix_Tinstr_per_s"]
+    result["roofline"]["performed_fma_flops"]["measured_fma_peak"] = peaks["fp32_fma_TFLOPs"]
     if not args.no_forms:
         result["forms"] = {"precision": precision_form(q, wl, torch)}
         for prec in ("fp32", "bf16", "fp8"):

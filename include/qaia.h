@@ -244,6 +244,18 @@ int32_t qaia_pareto_filter_workspace_bytes(int64_t M, int32_t m, size_t *bytes);
 int32_t qaia_pareto_filter(const int64_t *obj, int64_t M, int32_t m, int64_t *keep_idx,
                            int64_t *num_keep, void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* Per-objective minimum of a pool, the reference point of the hypervolume
+ * comparisons in section "Comparison to evolutionary algorithm-based
+ * heuristics" (the worst value of each objective over all sampled or
+ * enumerated solutions):
+ *   obj : DEVICE int64[M][m], 1 <= m <= 8, M >= 0.
+ *   lo  : DEVICE int64[m]; accumulate = 0: lo[k] = min_r obj[r][k] (INT64_MAX
+ *         when M = 0); accumulate = 1: lo[k] = min(lo[k], min_r obj[r][k]),
+ *         so that successive pools fold into one minimum.
+ * Asynchronous on hip_stream; allocates nothing.  Errors: INVALID_ARGUMENT. */
+int32_t qaia_objective_min(const int64_t *obj, int64_t M, int32_t m, int64_t *lo, int32_t accumulate,
+                           void *hip_stream);
+
 /* Non-dominated ranks of all M rows (non-dominated sorting of the sample
  * pool; the fronts behind section "Pareto filtering"): rank[i] = 0 for rows
  * whose vector no other row dominates (Eq. 4), and r for rows that become
@@ -404,6 +416,19 @@ int32_t qaia_peak_fma(int64_t blocks, int32_t iters, float a, float b, float *ou
  * blocks * 4 * iters * 4 * 2 * 32 * 32 * K flop.  blocks in [1, 2^31),
  * iters >= 1 and 4 * K * iters < 2^24 (exact accumulation). */
 int32_t qaia_peak_mfma(int32_t precision, int64_t blocks, int32_t iters, float *out, void *hip_stream);
+
+/* blocks x 256 lanes running the sparse SB update's instruction mix: per
+ * iteration 14 soft spins per lane take 60 FMAs (y_i += k x_i, k x of its two
+ * ring neighbours, k x_(i+7) for i < 4; x_i += k y_i) and 42 wall operations
+ * (|x_i| > 1 compare, y select, x clamp to [-1, 1]), the 10 : 7 ratio of the
+ * generated kernel's 180 FMAs to 126 wall operations per replica-step on the
+ * 42-node, 48-edge graph (section "Simulated Bifurcation with Gaussian
+ * noise", Eq. 9).  With k = 0 the state stays at its start values
+ * x_i = ((t + i) mod 8) / 8 - 1/2, y_i = ((t + 3i) mod 4) / 4 (lane t), so
+ * out[t] (DEVICE float [blocks * 256]) = sum_i (x_i + y_i) exactly.  Work:
+ * blocks * 256 * iters * 102 lane instructions.  blocks in [1, 2^31),
+ * iters >= 1, k finite. */
+int32_t qaia_peak_valu(int64_t blocks, int32_t iters, float k, float *out, void *hip_stream);
 
 /* dst = src, `bytes` (a multiple of 16) between two DEVICE buffers that are
  * 16-byte aligned and do not overlap; 2 * bytes of HBM traffic. */

@@ -64,6 +64,7 @@ _SIGS = {
     "qaia_pareto_filter_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "qaia_pareto_filter": (_i32, [_P, _i64, _i32, _P, _P, _P, _sz, _P]),
     "qaia_hypervolume": (_i32, [_P, _i64, _i32, _P, _P, _P]),
+    "qaia_objective_min": (_i32, [_P, _i64, _i32, _P, _i32, _P]),
     "qaia_pareto_ranks_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "qaia_pareto_ranks": (_i32, [_P, _i64, _i32, _i32, _P, C.POINTER(_i32), _P, _sz, _P]),
     "qaia_dense_field_workspace_bytes": (_i32, [_P, _i32, _i64, C.POINTER(_sz)]),
@@ -88,6 +89,7 @@ _SIGS = {
     "qaia_peak_fma": (_i32, [_i64, _i32, C.c_float, C.c_float, _P, _P]),
     "qaia_peak_mfma": (_i32, [_i32, _i64, _i32, _P, _P]),
     "qaia_peak_copy": (_i32, [_P, _P, _sz, _P]),
+    "qaia_peak_valu": (_i32, [_i64, _i32, C.c_float, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -300,33 +302,46 @@ def exact_front(p: Problem, chunk: int = 1 << 26, with_min: bool = False):
     and returns (codes int64 [P] host, obj int64 [P, m] host): the spin words
     of one representative per non-dominated objective vector (the smallest
     code) and their cut values, in ascending code order.  with_min also
-    returns the per-objective minimum cut value over all configurations."""
+    returns the per-objective minimum cut value over all configurations
+    (qaia_objective_min folded over the chunks)."""
     if p.n > 36:
         raise ValueError("exhaustive enumeration is limited to n <= 36")
     total = 1 << (p.n - 1)
     dev = p.torch_device
     front_codes = torch.zeros(0, dtype=torch.int64, device=dev)
     front_obj = torch.zeros((0, p.m), dtype=torch.int64, device=dev)
-    lo = None
+    lo = torch.empty(p.m, dtype=torch.int64, device=dev)
     first = 0
     while first < total:
         cnt = min(chunk, total - first)
         F = front_obj.shape[0]
         pool = torch.empty((F + cnt, p.m), dtype=torch.int64, device=dev)
+        codes = torch.empty(F + cnt, dtype=torch.int64, device=dev)
         pool[:F] = front_obj
+        codes[:F] = front_codes
+        codes[F:] = torch.arange(first, first + cnt, dtype=torch.int64, device=dev)  # the row's spin word
         qaia_enumerate_cuts(p, first, cnt, obj=pool[F:])
         if with_min:
-            cmin = pool[F:].amin(dim=0)
-            lo = cmin if lo is None else torch.minimum(lo, cmin)
-        keep = pareto_front(pool)
-        old = keep < F
-        codes = keep - F + first
-        if F:
-            codes = torch.where(old, front_codes[keep.clamp(max=F - 1)], codes)
-        front_codes, front_obj = codes, pool[keep]
+            qaia_objective_min(pool[F:], out=lo, accumulate=first > 0)
+        keep, nkeep, _ = qaia_pareto_filter(pool)
+        P = int(nkeep.item())
+        front_obj = torch.empty((P, p.m), dtype=torch.int64, device=dev)
+        front_codes = torch.empty(P, dtype=torch.int64, device=dev)
+        qaia_gather_rows(pool, keep, nkeep, front_obj, P)
+        qaia_gather_rows(codes.view(-1, 1), keep, nkeep, front_codes.view(-1, 1), P)
         first += cnt
     out = (front_codes.cpu().numpy(), front_obj.cpu().numpy())
     return out + (lo.cpu().numpy(),) if with_min else out
+
+
+def qaia_objective_min(obj: torch.Tensor, out=None, accumulate: bool = False, stream=None) -> torch.Tensor:
+    """Per-objective minimum of the rows of obj (int64 [M, m] device); with
+    accumulate, folded into the values already in out."""
+    M, m = obj.shape
+    out = _dev_tensor(out, torch.int64, (m,), obj.device)
+    _check(_lib.qaia_objective_min(_ptr(obj) if M else None, M, m, _ptr(out), 1 if accumulate else 0,
+                                   _stream(stream)))
+    return out
 
 
 # ------------------------------------------------------------------ filtering
@@ -511,6 +526,14 @@ def qaia_peak_fma(blocks: int, iters: int, a: float = 1.0, b: float = 1.0, out=N
     dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
     out = _dev_tensor(out, torch.float32, (blocks * 256,), dev)
     _check(_lib.qaia_peak_fma(blocks, iters, a, b, _ptr(out), _stream(stream)))
+    return out
+
+
+def qaia_peak_valu(blocks: int, iters: int, k: float = 0.0, out=None, device=None, stream=None) -> torch.Tensor:
+    """Sparse-SB instruction-mix ceiling (60 FMAs + 42 wall operations per lane-iteration)."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = _dev_tensor(out, torch.float32, (blocks * 256,), dev)
+    _check(_lib.qaia_peak_valu(blocks, iters, k, _ptr(out), _stream(stream)))
     return out
 
 

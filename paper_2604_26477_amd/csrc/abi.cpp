@@ -308,6 +308,18 @@ int32_t qaia_pareto_filter(const int64_t *obj, int64_t M, int32_t m, int64_t *ke
     });
 }
 
+int32_t qaia_objective_min(const int64_t *obj, int64_t M, int32_t m, int64_t *lo, int32_t accumulate,
+                           void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(M >= 0, QAIA_INVALID_ARGUMENT, "M must be >= 0");
+        QAIA_CHECK(m >= 1 && m <= 8, QAIA_INVALID_ARGUMENT, "m must be in [1, 8]");
+        QAIA_CHECK(lo != nullptr && (M == 0 || obj != nullptr), QAIA_INVALID_ARGUMENT, "null obj or lo");
+        QAIA_CHECK(accumulate == 0 || accumulate == 1, QAIA_INVALID_ARGUMENT, "accumulate must be 0 or 1");
+        launch_objective_min(obj, M, m, lo, accumulate != 0, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
 int32_t qaia_pareto_ranks_workspace_bytes(int64_t M, int32_t m, size_t *bytes) {
     return guarded([&]() -> int32_t {
         QAIA_CHECK(bytes != nullptr, QAIA_INVALID_ARGUMENT, "null argument");
@@ -474,6 +486,17 @@ int32_t qaia_peak_fma(int64_t blocks, int32_t iters, float a, float b, float *ou
         QAIA_CHECK(iters >= 1, QAIA_INVALID_ARGUMENT, "iters must be >= 1");
         QAIA_CHECK(out != nullptr, QAIA_INVALID_ARGUMENT, "null out");
         launch_peak_fma(blocks, iters, a, b, out, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_peak_valu(int64_t blocks, int32_t iters, float k, float *out, void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(blocks >= 1 && blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "blocks must be in [1, 2^31)");
+        QAIA_CHECK(iters >= 1, QAIA_INVALID_ARGUMENT, "iters must be >= 1");
+        QAIA_CHECK(out != nullptr, QAIA_INVALID_ARGUMENT, "null out");
+        QAIA_CHECK(std::isfinite(k), QAIA_INVALID_ARGUMENT, "k must be finite");
+        launch_peak_valu(blocks, iters, k, out, (hipStream_t)hip_stream);
         return QAIA_OK;
     });
 }

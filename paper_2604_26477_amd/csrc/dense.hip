@@ -398,13 +398,14 @@ constexpr int dma_stages() {
 // insertion does not see an LDS-writing memory operation: with one pending it
 // treats the LDS counter as out of order and drains it completely before every
 // MFMA group, serialising the fragment reads with the MFMAs.  The copies are
-// ordered by hand (dma_wait, lds_barrier); M0 is written nowhere else here.
+// ordered by hand (dma_wait, lds_barrier).  M0 is declared clobbered, so the
+// compiler keeps nothing it needs in M0 across the copy.
 template <int MT>
 __device__ __forceinline__ void dma_copy(char *stage, const char *src, size_t koff, int wave, int i) {
     const uint32_t base = (uint32_t)(uintptr_t)(lds_void_t *)stage;
     const uint32_t dst = __builtin_amdgcn_readfirstlane(base + (uint32_t)(wave * 2 * (MT + 1) + i) * 64 * 16);
     asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src + koff), "s"(dst)
-                 : "memory");
+                 : "memory", "m0");
 }
 
 template <int MT>

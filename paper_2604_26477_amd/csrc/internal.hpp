@@ -222,6 +222,7 @@ void launch_gather_rows(const uint32_t *src, int width, const int64_t *idx, cons
 void launch_peak_fma(int64_t blocks, int32_t iters, float a, float b, float *out, hipStream_t st);
 void launch_peak_mfma(int32_t precision, int64_t blocks, int32_t iters, float *out, hipStream_t st);
 void launch_peak_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
+void launch_peak_valu(int64_t blocks, int32_t iters, float k, float *out, hipStream_t st);
 
 // batching form (batch.cpp)
 size_t batch_ws_bytes(const qaia_batch_item *items, int32_t count, const qaia_schedule &s);
@@ -236,6 +237,8 @@ size_t pareto_ranks_ws_bytes(int64_t M, int32_t m);
 int32_t launch_pareto_ranks(const int64_t *obj, int64_t M, int32_t m, int32_t max_rank, int32_t *rank, void *ws,
                             size_t ws_bytes, hipStream_t st);
 size_t pareto_ws_bytes(int64_t M, int32_t m);
+void launch_objective_min(const int64_t *obj, int64_t M, int32_t m, int64_t *lo, bool accumulate,
+                          hipStream_t st);
 void launch_pareto(const int64_t *obj, int64_t M, int32_t m, int64_t *keep, int64_t *num_keep,
                    void *ws, size_t ws_bytes, hipStream_t st);
 

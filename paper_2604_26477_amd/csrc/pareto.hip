@@ -168,6 +168,32 @@ __global__ void u8_to_i32_kernel(const uint8_t *__restrict__ f, int32_t *__restr
     if (i < n) o[i] = f[i];
 }
 
+// Per-objective minimum over the rows of a pool (the reference point of the
+// hypervolume comparisons in section "Comparison to evolutionary
+// algorithm-based heuristics" is the worst value of each objective).  Each
+// thread folds a strided range of rows, the block reduces in LDS, and one
+// atomic min per objective and block merges the blocks.
+__global__ void objective_min_init_kernel(int64_t *lo, int m) {
+    if ((int)threadIdx.x < m) lo[threadIdx.x] = INT64_MAX;
+}
+
+__global__ __launch_bounds__(kB) void objective_min_kernel(const int64_t *__restrict__ obj, int64_t M, int m,
+                                                           int64_t *__restrict__ lo) {
+    __shared__ int64_t red[8][kB];
+    int64_t mn[8];
+    for (int k = 0; k < 8; ++k) mn[k] = INT64_MAX;
+    for (int64_t r = (int64_t)blockIdx.x * kB + threadIdx.x; r < M; r += (int64_t)gridDim.x * kB)
+        for (int k = 0; k < m; ++k) mn[k] = min(mn[k], obj[r * m + k]);
+    for (int k = 0; k < m; ++k) red[k][threadIdx.x] = mn[k];
+    __syncthreads();
+    for (int s = kB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < m; ++k) red[k][threadIdx.x] = min(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < m) atomicMin((long long *)&lo[threadIdx.x], (long long)red[threadIdx.x][0]);
+}
+
 struct PLayout {
     size_t idxA, idxB, keyA, keyB, flag, uidx, sidx, keep, counts, temp, temp_bytes, total;
     size_t list2 = 0, rem = 0, run = 0;  // ranks only
@@ -288,6 +314,16 @@ void launch_pareto(const int64_t *obj, int64_t M, int32_t m, int64_t *keep_idx, 
         hipcub::CountingInputIterator<int64_t> it(0);
         QAIA_CUB(hipcub::DeviceSelect::Flagged(temp, t, it, keep, keep_idx, num_keep, M, st));
     }
+}
+
+void launch_objective_min(const int64_t *obj, int64_t M, int32_t m, int64_t *lo, bool accumulate,
+                          hipStream_t st) {
+    if (!accumulate) hipLaunchKernelGGL(objective_min_init_kernel, dim3(1), dim3(64), 0, st, lo, m);
+    if (M > 0) {
+        const unsigned grid = (unsigned)std::min<int64_t>((M + kB - 1) / kB, 2048);
+        hipLaunchKernelGGL(objective_min_kernel, dim3(grid), dim3(kB), 0, st, obj, M, m, lo);
+    }
+    QAIA_HIP(hipGetLastError());
 }
 
 size_t pareto_ranks_ws_bytes(int64_t M, int32_t m) {

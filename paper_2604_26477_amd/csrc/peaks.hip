@@ -10,6 +10,13 @@
 //                      all 1.0 in the instruction's format (fp32 32x32x2,
 //                      bf16 32x32x16, e4m3 32x32x64), back-to-back MFMAs.
 //   copy_peak_kernel : 16 bytes per lane, grid-stride, nontemporal, HBM to HBM.
+//   valu_mix_peak_kernel : the sparse SB update's instruction mix with full
+//                      occupancy: per iteration 14 soft spins x, y per lane
+//                      take 60 FMAs (own term, ring couplings, x update) and
+//                      42 wall operations (compare, select, clamp), the
+//                      10 : 7 ratio of the generated kernel's 180 FMAs and
+//                      126 wall operations per replica-step on the 42-node
+//                      48-edge graph.
 #include "internal.hpp"
 
 namespace qaia {
@@ -77,6 +84,45 @@ __global__ __launch_bounds__(kPB) void mfma_peak_kernel(uint32_t one, int iters,
     out[(int64_t)blockIdx.x * kPB + threadIdx.x] = s;
 }
 
+constexpr int kMixSpins = 14;
+
+// Per iteration and spin i: y_i += k x_i, y_i += k x_(i+-1) (ring), spins
+// 0..3 also y_i += k x_(i+7), then x_i += k y_i and the wall (|x| > 1 zeroes
+// y and clamps x).  With k = 0 every FMA returns its addend exactly and no
+// spin reaches the wall (|x| <= 0.5), so the state never changes: the closed
+// form is the sum of the start values.  k is a kernel argument, so the
+// compiler cannot drop the work.
+__global__ __launch_bounds__(kPB) void valu_mix_peak_kernel(float k, int iters, float *out) {
+    const int64_t t = (int64_t)blockIdx.x * kPB + threadIdx.x;
+    float x[kMixSpins], y[kMixSpins];
+#pragma unroll
+    for (int i = 0; i < kMixSpins; ++i) {
+        x[i] = (float)((t + i) & 7) * 0.125f - 0.5f;
+        y[i] = (float)((t + 3 * i) & 3) * 0.25f;
+    }
+    for (int it = 0; it < iters; ++it) {
+        float yn[kMixSpins];
+#pragma unroll
+        for (int i = 0; i < kMixSpins; ++i) {
+            float a = __builtin_fmaf(k, x[i], y[i]);
+            a = __builtin_fmaf(k, x[(i + 1) % kMixSpins], a);
+            a = __builtin_fmaf(k, x[(i + kMixSpins - 1) % kMixSpins], a);
+            if (i < 4) a = __builtin_fmaf(k, x[i + 7], a);
+            yn[i] = a;
+        }
+#pragma unroll
+        for (int i = 0; i < kMixSpins; ++i) {
+            float xi = __builtin_fmaf(k, yn[i], x[i]);
+            y[i] = __builtin_fabsf(xi) > 1.0f ? 0.0f : yn[i];
+            x[i] = __builtin_fminf(__builtin_fmaxf(xi, -1.0f), 1.0f);
+        }
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kMixSpins; ++i) s += x[i] + y[i];
+    out[t] = s;
+}
+
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 // nontemporal 16-byte loads and stores (the data are touched once); a sweep
@@ -102,6 +148,11 @@ void launch_peak_mfma(int32_t precision, int64_t blocks, int32_t iters, float *o
         hipLaunchKernelGGL(mfma_peak_kernel<QAIA_BF16>, grid, dim3(kPB), 0, st, 0x3F80u, iters, out);
     else
         hipLaunchKernelGGL(mfma_peak_kernel<QAIA_FP8>, grid, dim3(kPB), 0, st, 0x38u, iters, out);
+    QAIA_HIP(hipGetLastError());
+}
+
+void launch_peak_valu(int64_t blocks, int32_t iters, float k, float *out, hipStream_t st) {
+    hipLaunchKernelGGL(valu_mix_peak_kernel, dim3((unsigned)blocks), dim3(kPB), 0, st, k, iters, out);
     QAIA_HIP(hipGetLastError());
 }
 

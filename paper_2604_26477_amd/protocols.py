@@ -14,8 +14,8 @@ import time
 import numpy as np
 import torch
 
-from . import (make_schedule, qaia_evaluate, qaia_pareto_filter, qaia_pareto_filter_workspace_bytes,
-               qaia_random_spins, qaia_sample, qaia_sample_workspace_bytes)
+from . import (make_schedule, qaia_evaluate, qaia_gather_rows, qaia_objective_min, qaia_pareto_filter,
+               qaia_pareto_filter_workspace_bytes, qaia_random_spins, qaia_sample, qaia_sample_workspace_bytes)
 
 
 def run_budget(prob, method: str, budget_s: float, weights=None, R: int = 3000, steps: int = 50,
@@ -41,6 +41,7 @@ def run_budget(prob, method: str, budget_s: float, weights=None, R: int = 3000, 
     c = torch.as_tensor(np.ascontiguousarray(weights, np.float32)).to(dev)
     rows = c.shape[0] * R
     pool = torch.empty((archive_cap + rows, m), dtype=torch.int64, device=dev)
+    front = torch.empty((archive_cap + rows, m), dtype=torch.int64, device=dev)
     spins = torch.empty((rows, prob.words), dtype=torch.int64, device=dev)
     keep = torch.empty(archive_cap + rows, dtype=torch.int64, device=dev)
     nkeep = torch.empty(1, dtype=torch.int64, device=dev)
@@ -53,7 +54,7 @@ def run_budget(prob, method: str, budget_s: float, weights=None, R: int = 3000, 
     elif method != "random":
         raise ValueError(method)
     A = 0
-    lo = None
+    lo = torch.empty(m, dtype=torch.int64, device=dev)
     batches = 0
     tset = {tuple(int(v) for v in r) for r in np.asarray(target)} if target is not None else None
     history = []
@@ -68,13 +69,13 @@ def run_budget(prob, method: str, budget_s: float, weights=None, R: int = 3000, 
             s = make_schedule(method, precision=precision, steps=steps, dt=dt, noise_alpha=alpha, seed=seed,
                               replica_offset=batches * rows, path=path)
             qaia_sample(prob, c, R, s, spins=spins, obj=new, workspace=ws_s)
-        bmin = new.amin(dim=0)
-        lo = bmin if lo is None else torch.minimum(lo, bmin)
+        qaia_objective_min(new, out=lo, accumulate=batches > 0)
         qaia_pareto_filter(pool[:A + rows], keep_idx=keep, num_keep=nkeep, workspace=ws_f)
         P = int(nkeep.item())
         if P > archive_cap:
             raise RuntimeError("archive capacity exceeded")
-        pool[:P] = pool[keep[:P]]
+        qaia_gather_rows(pool, keep, nkeep, front, P)
+        pool[:P] = front[:P]
         A = P
         batches += 1
         if tset is not None:

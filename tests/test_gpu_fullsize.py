@@ -102,3 +102,58 @@ def test_precision_workload_full_launch(q, prec):
         torch.cuda.synchronize()
         assert np.array_equal(sp1.cpu().numpy()[0], spins[w * R + r]), (w, r)
         assert np.array_equal(ob1.cpu().numpy()[0], obj[w * R + r]), (w, r)
+
+
+def test_headline_filter_full_pool(q):
+    """The filter of the benchmark step at full size: the 10.24 M cut vectors of
+    one bSB and one dSB launch of the headline workload, pooled.  The oracle's
+    quadratic filter cannot take the whole pool, so the result is checked by
+    properties that define it ("Pareto filtering", Eq. 4) plus a slice:
+
+    * kept rows are pairwise distinct and mutually non-dominated;
+    * each kept row is the smallest sample index carrying its vector
+      (host lexicographic sort of the whole pool);
+    * 10 000 sampled pool rows are each dominated by or equal to a kept row;
+    * on the first 200 000 rows the GPU filter equals the oracle bit for bit.
+    """
+    import torch
+    cfg = wl.WORKLOADS["c2_n42_m4"]
+    W, R, T = cfg["W"], cfg["R"], cfg["T"]
+    inst = wl.workload_instance("c2_n42_m4")
+    prob = q.problem_from_instance(inst)
+    c = _dev(wl.workload_weights("c2_n42_m4"))
+    rows = W * R
+    obj = torch.empty((2 * rows, inst.m), dtype=torch.int64, device="cuda")
+    for i, v in enumerate(("bsb", "dsb")):
+        s = q.make_schedule(v, steps=T, dt=0.5, seed=cfg["seed"] + 3 + i)
+        q.qaia_sample(prob, c, R, s, obj=obj[i * rows:(i + 1) * rows])
+    keep, num, _ = q.qaia_pareto_filter(obj)
+    torch.cuda.synchronize()
+    keep = keep[: int(num.item())].cpu().numpy()
+    pool = obj.cpu().numpy()
+    print(f"pool {pool.shape[0]} rows, front {keep.size}")
+    assert keep.size > 100 and np.all(np.diff(keep) > 0)
+    front = pool[keep]
+    # distinct and mutually non-dominated
+    ge = np.ones((keep.size, keep.size), bool)
+    for k in range(inst.m):
+        ge &= front[:, None, k] >= front[None, :, k]
+    np.fill_diagonal(ge, False)
+    assert not ge.any()
+    # smallest index per vector: first row of each run in a stable lexicographic sort
+    order = np.lexsort(tuple(pool[:, k] for k in reversed(range(inst.m))))
+    srt = pool[order]
+    first = np.ones(order.size, bool)
+    first[1:] = (srt[1:] != srt[:-1]).any(axis=1)
+    firsts = {tuple(v): int(i) for v, i in zip(srt[first], order[first])}
+    for i in keep:
+        assert firsts[tuple(pool[i])] == i
+    # sampled rows are dominated by or equal to a kept row
+    rng = np.random.default_rng(5)
+    for r in rng.choice(pool.shape[0], size=10000, replace=False):
+        assert (front >= pool[r]).all(axis=1).any()
+    # a slice against the oracle
+    sl = torch.from_numpy(pool[:200000].copy()).cuda()
+    k2, n2, _ = q.qaia_pareto_filter(sl)
+    torch.cuda.synchronize()
+    assert np.array_equal(k2[: int(n2.item())].cpu().numpy(), oracle.pareto_filter(pool[:200000]))

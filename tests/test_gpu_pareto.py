@@ -145,3 +145,20 @@ def test_ranks_large_pool_properties(q):
         else:
             assert rk[ge].max() == rk[i] - 1
             assert (rk[ge] < rk[i]).all()
+
+
+@pytest.mark.parametrize("M,m", [(0, 3), (1, 1), (257, 4), (100000, 8), (1 << 20, 2)])
+def test_objective_min(q, M, m):
+    """Per-objective minimum (the hypervolume reference point of the Table 2
+    protocol), alone and folded over two pools."""
+    import torch
+    rng = np.random.default_rng(M + m)
+    a = rng.integers(-2**62, 2**62, size=(M, m), dtype=np.int64)
+    b = rng.integers(-2**40, 2**40, size=(M // 3 + 1, m), dtype=np.int64)
+    lo = q.qaia_objective_min(torch.from_numpy(a).cuda())
+    torch.cuda.synchronize()
+    want = a.min(axis=0) if M else np.full(m, np.iinfo(np.int64).max)
+    assert np.array_equal(lo.cpu().numpy(), want)
+    q.qaia_objective_min(torch.from_numpy(b).cuda(), out=lo, accumulate=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(lo.cpu().numpy(), np.minimum(want, b.min(axis=0)))

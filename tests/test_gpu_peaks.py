@@ -31,6 +31,19 @@ def test_mfma_all_ones_closed_form(q, prec, K):
     assert torch.all(out == 4.0 * K * iters).item()
 
 
+def test_valu_mix_closed_form(q):
+    """k = 0: the sparse-SB instruction mix leaves every spin at its start value."""
+    blocks, iters = 6, 700
+    out = q.qaia_peak_valu(blocks, iters, 0.0)
+    t = torch.arange(blocks * 256, dtype=torch.int64)
+    x0 = sum(((t + i) % 8).to(torch.float64) / 8 - 0.5 for i in range(14))
+    y0 = sum(((t + 3 * i) % 4).to(torch.float64) / 4 for i in range(14))
+    assert torch.equal(out.cpu().to(torch.float64), x0 + y0)
+    # a non-zero coefficient changes the state (the FMAs are really executed)
+    moved = q.qaia_peak_valu(blocks, 3, 1e-3)
+    assert not torch.equal(moved.cpu(), out.cpu())
+
+
 def test_copy_is_exact(q):
     g = torch.Generator(device="cuda").manual_seed(11)
     src = torch.randint(-2**31, 2**31 - 1, (1 << 20,), dtype=torch.int32, device="cuda", generator=g)

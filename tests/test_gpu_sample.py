@@ -3,6 +3,8 @@ against the CPU oracle, through the C ABI."""
 import numpy as np
 import pytest
 
+import fp32_bounds as fb
+import noise_model as nm
 import oracle
 import workloads as wl
 from gpu_helpers import pack_spins, rel_inf_error, unpack_spins
@@ -220,11 +222,9 @@ def test_degenerate_graphs_every_path(q, path):
       spins aligned, so its rows are checked by exact evaluation only.
       This mode starts at zero stiffness, so a last-place rounding of the
       per-step coefficient -dt (a0 - a(t)) is a large relative error in its
-      early growth: a CPU emulation of FP32 fused multiply-adds in the kernels'
-      order, over 3 000 random starts, stays within 7.7e-4 of the trajectory's
-      scale (median 3.5e-7, 99th percentile 7.7e-6).  The trace bound here is
-      therefore 1e-3; a wrong sign, a dropped term or a swapped index gives
-      errors of order 1.
+      early growth; the trace is held to the first-order FP32 error bound
+      carried along the oracle's trajectory (tests/fp32_bounds.py), which
+      follows that amplification.
     """
     import torch
     c = wl.dirichlet_weights(5, 2, 81)
@@ -258,9 +258,10 @@ def test_degenerate_graphs_every_path(q, path):
     torch.cuda.synchronize()
     sp_ref, ref = oracle.sb_sample(pair, c, 32, 1000, "bsb", dt=0.5, seed=84, trace_steps=100)
     assert (oracle.cut_values(pair, sp_ref) == both_cut).all()
-    err = _traj_rel_error(tr.cpu().numpy(), ref)
-    print(f"{path} two spins: max trajectory-relative error {err.max():.3e}")
-    assert err.max() <= 1e-3
+    bound = fb.Bound(pair, c, 32, 1000, "bsb", seed=84, steps=100)
+    ok, ratio, frac = bound.check(tr.cpu().numpy(), ref)
+    print(f"{path} two spins: worst error / FP32 bound {ratio:.3f} over {frac:.0%} of the steps")
+    assert ok and frac >= 0.9
     assert (obj.cpu().numpy() == both_cut).all()
     for prec in precs:
         sp, ob, ws = _sample(q, prob, c, 32, variant="dsb", precision=prec, steps=1000, seed=85, path=path)
@@ -270,32 +271,78 @@ def test_degenerate_graphs_every_path(q, path):
 
 # ---------------------------------------------------------------- noise injection (Eq. 10)
 
-# Seeds of the noise-injected trajectory test.  On this instance the error of
-# FP32 rounding alone (a CPU emulation of the kernels' operation order with
-# correctly rounded eta) ranges over 8.5e-7 .. 4.4e-4 across seeds 43..59 for
-# ballistic SB; the test uses seeds whose emulated error stays below 1e-6 and,
-# for discrete SB, whose oracle trajectories keep |x| >= 1e-4.
-NOISE_SEEDS = {"bsb": 46, "dsb": 51}
+ALL_PATHS = ["sparse_reg", "sparse_lds", "dense", "dense_staged"]
 
 
-@pytest.mark.parametrize("path", ["sparse_reg", "sparse_lds", "dense", "dense_staged"])
-@pytest.mark.parametrize("variant", ["bsb", "dsb"])
-def test_noise_injected_trace_parity(q, path, variant):
-    """NI-SB follows the FP64 oracle (same counter-based Gaussian stream) within
-    1e-5 over the first 50 steps on every kernel family; alpha = 0 is plain SB."""
+@pytest.mark.parametrize("path", ALL_PATHS)
+def test_noise_draws_elementwise(q, path):
+    """The device's Gaussian draws, one by one, against the oracle's float64
+    Box-Muller.  Four spins without couplings (c0 = 0) start at x = y = 0
+    (init_amp = 0); with dt = 0.5 and alpha = 0.25 the first step makes
+    y = fl(dt alpha) eta = eta / 8 and x = dt a0 y = eta / 16 exactly, so the
+    first traced x times 16 is the float32 draw itself.  16 384 replicas x 4
+    spins = 65 536 draws, each within eta_error_bound(r, theta) of the exact
+    value (the logf, sqrtf, cosf and argument roundings, at most
+    2^-24 r (6 + 2 theta))."""
+    import torch
+    n, W, R, T, seed = 4, 64, 256, 1000, 91
+    inst = wl.Instance(n, 1, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros((1, 0), np.int32))
+    prob = q.problem_from_instance(inst)
+    c = np.ones((W, 1), np.float32)
+    s = q.make_schedule("bsb", steps=T, dt=0.5, init_amp=0.0, noise_alpha=0.25, seed=seed, path=path)
+    _, _, ws, tr = q.qaia_sample_trace(prob, _dev(c), R, s, 1)
+    torch.cuda.synchronize()
+    assert q.qaia_workspace_status(ws) is None
+    eta_dev = tr.cpu().numpy()[:, 0, :].astype(np.float64) * 16.0
+    rows = W * R
+    idx = [(g * T) * n + i for g in range(rows) for i in range(n)]
+    eta_ref = np.array([oracle.noise_value(seed, k) for k in idx]).reshape(rows, n)
+    model = np.array([nm.noise(seed, k) for k in idx]).reshape(rows, n, 3)
+    assert np.abs(model[..., 0] - eta_ref).max() <= 1e-12 * np.maximum(model[..., 1], 1)
+    bound = fb.eta_error_bound(model[..., 1], model[..., 2])
+    err = np.abs(eta_dev - eta_ref)
+    worst = float((err / np.where(bound > 0, bound, 1)).max())
+    print(f"{path}: max |eta_f32 - eta| = {err.max():.3e}, worst fraction of the bound {worst:.3f}")
+    assert (err <= bound).all()
+    assert not (eta_dev == eta_dev[:, :1]).all()  # spins draw different values
+
+
+def _noise_trace_case():
     inst = wl.random_instance(12, 3, "deg3", seed=41, num_edges=16)
     c = wl.dirichlet_weights(6, 3, 42)
+    return inst, c, 8, 1000, 50, 0.15
+
+
+@pytest.mark.parametrize("variant", ["bsb", "dsb"])
+def test_noise_injected_trace_parity_every_seed(q, variant):
+    """NI-SB (Eq. 10) against the FP64 oracle on every kernel family and every
+    SB seed 43..59, 50 steps.  The tolerance is the first-order FP32 error
+    bound carried along the oracle's trajectory (tests/fp32_bounds.py: local
+    roundings, the device draw's error bound, propagation through the
+    update's Jacobians, comparisons stopped where a wall or sign decision is
+    within the bound of its threshold).  alpha = 0 must differ (the noise
+    acts)."""
+    import torch
+    inst, c, R, T, steps, alpha = _noise_trace_case()
     prob = q.problem_from_instance(inst)
-    seed = NOISE_SEEDS[variant]
-    s = q.make_schedule(variant, steps=1000, dt=0.5, seed=seed, noise_alpha=0.15, path=path)
-    _, _, _, tr = q.qaia_sample_trace(prob, _dev(c), 8, s, 50)
-    _, ref = oracle.sb_sample(inst, c, 8, 1000, variant, dt=0.5, seed=seed, alpha=0.15, trace_steps=50)
-    err = rel_inf_error(tr.cpu().numpy(), ref)
-    print(f"noise-injected {variant} {path}: max rel err over 50 steps {err.max():.3e}")
-    assert err.max() <= 1e-5
-    plain = q.make_schedule(variant, steps=1000, dt=0.5, seed=seed, path=path)
-    _, _, _, tr0 = q.qaia_sample_trace(prob, _dev(c), 8, plain, 50)
-    assert not np.array_equal(tr0.cpu().numpy(), tr.cpu().numpy())
+    worst, checked = 0.0, []
+    for seed in range(43, 60):
+        _, ref = oracle.sb_sample(inst, c, R, T, variant, dt=0.5, seed=seed, alpha=alpha, trace_steps=steps)
+        bound = fb.Bound(inst, c, R, T, variant, alpha=alpha, seed=seed, steps=steps)
+        for path in ALL_PATHS:
+            s = q.make_schedule(variant, steps=T, dt=0.5, seed=seed, noise_alpha=alpha, path=path)
+            _, _, _, tr = q.qaia_sample_trace(prob, _dev(c), R, s, steps)
+            torch.cuda.synchronize()
+            ok, ratio, frac = bound.check(tr.cpu().numpy(), ref)
+            assert ok, (seed, path, ratio)
+            worst = max(worst, ratio)
+            checked.append(frac)
+        if seed == 43:
+            plain = q.make_schedule(variant, steps=T, dt=0.5, seed=seed, path="sparse_lds")
+            _, _, _, tr0 = q.qaia_sample_trace(prob, _dev(c), R, plain, steps)
+            assert not np.array_equal(tr0.cpu().numpy(), tr.cpu().numpy())
+    print(f"noise-injected {variant}: worst error / bound {worst:.3f}, steps checked {np.mean(checked):.1%}")
+    assert np.mean(checked) >= 0.95
 
 
 @pytest.mark.parametrize("variant", ["bsb", "dsb"])

@@ -328,6 +328,136 @@ def test_two_spin_normal_modes_exact(jsign):
     assert (spins[0, 0] != spins[0, 1]) == (jsign > 0)
 
 
+def _exact_sb(x, y, edges, jnorm, T, dt, a0, variant, noise=None):
+    """Eq. (9)/(10) in exact rationals, every spin written out.
+
+    x, y: lists of Fractions; edges: [(u, v, c0 J(c)_uv)] with the scaled
+    coupling as a Fraction; noise(t, i) -> alpha * eta as a Fraction or None.
+    Returns the x trace [T][n] (Fractions).  The force on spin i is
+    -(a0 - a_t) x_i - sum_j c0 J(c)_ij phi(x_j) (+ alpha eta_i), phi the
+    identity (bSB) or sgn with sgn(0) = +1 (dSB); y is updated first from
+    the pre-step x, then x from the new y, then the inelastic wall.
+    """
+    n = len(x)
+    out = []
+    for t in range(T):
+        at = a0 * Fraction(t, T - 1) if T > 1 else Fraction(0)
+        if variant == "dsb":
+            phi = [Fraction(1) if v >= 0 else Fraction(-1) for v in x]
+        else:
+            phi = list(x)
+        force = [-(a0 - at) * x[i] for i in range(n)]
+        for u, v, j in edges:
+            force[u] -= j * phi[v]
+            force[v] -= j * phi[u]
+        if noise is not None:
+            force = [force[i] + noise(t, i) for i in range(n)]
+        y = [y[i] + dt * force[i] for i in range(n)]
+        x = [x[i] + dt * a0 * y[i] for i in range(n)]
+        for i in range(n):
+            if abs(x[i]) > 1:
+                x[i] = Fraction(1) if x[i] > 0 else Fraction(-1)
+                y[i] = Fraction(0)
+        out.append(list(x))
+    return out
+
+
+@pytest.mark.parametrize("jsign", [1, -1])
+def test_two_spin_discrete_sb_exact(jsign):
+    """dSB (phi = sgn) on two spins joined by one edge, in exact rationals.
+
+    With W = 4 * 2^16 and c = 1 the scaled coupling c0 J(c) is exactly 1, so
+    the discrete force is piecewise constant; the recursion runs through the
+    wall hits to the end.  phi = x (which turns dSB into bSB) or a dropped
+    coupling term gives a different trajectory; J > 0 must end cut, J < 0
+    uncut (the coupling sign of Eq. 9 under the minimised Ising energy).
+    """
+    inst = _instance(2, 1, [(0, 1)], [[jsign * 4 * 2**16]])
+    T, dt, a0, amp, seed = 60, Fraction(1, 2), Fraction(1), 0.1, 17
+    c = np.array([1.0], np.float32)
+    spins, trace = oracle.sb_sample(inst, c, R=1, T=T, variant="dsb", dt=0.5, seed=seed,
+                                    trace_steps=T, amp=amp)
+    x = [_exact_init(seed, 0, 2, i, 0, amp) for i in range(2)]
+    y = [_exact_init(seed, 0, 2, i, 1, amp) for i in range(2)]
+    want = _exact_sb(x, y, [(0, 1, Fraction(jsign))], None, T, dt, a0, "dsb")
+    walls = 0
+    for t in range(T):
+        for i in range(2):
+            assert trace[0, t, i] == pytest.approx(float(want[t][i]), rel=1e-12, abs=1e-14), (t, i)
+        walls += sum(abs(v) == 1 for v in want[t])
+    assert walls > 0  # the comparison ran through wall hits
+    assert (spins[0, 0] != spins[0, 1]) == (jsign > 0)
+    # and the discrete trajectory is not the ballistic one
+    _, trace_b = oracle.sb_sample(inst, c, R=1, T=T, variant="bsb", dt=0.5, seed=seed, trace_steps=T, amp=amp)
+    assert np.abs(trace_b - trace).max() > 0.1
+
+
+def test_discrete_sb_sign_of_zero_is_plus_one():
+    """init_amp = 0: every spin starts at x = y = 0, so the first discrete force
+    is -c0 J(c) sgn(0) = -c0 J(c) with sgn(0) = +1 (the read-out convention).
+    sgn(0) = 0 would leave x at 0 forever and sgn(0) = -1 would move it the
+    other way.  Three spins: an edge 0-1 (J > 0) and a lone spin 2, which has
+    no force and stays at 0 (read out as +1)."""
+    inst = _instance(3, 1, [(0, 1)], [[2 * 2**16]])
+    T, dt, a0 = 40, Fraction(1, 2), Fraction(1)
+    c = np.array([1.0], np.float32)
+    spins, trace = oracle.sb_sample(inst, c, R=2, T=T, variant="dsb", dt=0.5, seed=3, trace_steps=T, amp=0.0)
+    zero = [Fraction(0)] * 3
+    want = _exact_sb(list(zero), list(zero), [(0, 1, Fraction(1))], None, T, dt, a0, "dsb")
+    assert float(want[0][0]) == -0.25 and float(want[0][1]) == -0.25
+    for r in range(2):
+        for t in range(T):
+            for i in range(3):
+                assert trace[r, t, i] == pytest.approx(float(want[t][i]), rel=1e-12, abs=1e-14), (r, t, i)
+    assert (spins[:, 2] == 1).all()
+    # ballistic SB from the origin never moves (phi(0) = 0)
+    _, trace_b = oracle.sb_sample(inst, c, R=1, T=T, variant="bsb", dt=0.5, seed=3, trace_steps=T, amp=0.0)
+    assert not trace_b.any()
+
+
+@pytest.mark.parametrize("variant", ["bsb", "dsb"])
+def test_noise_injection_exact_on_free_spins(variant):
+    """Eq. (10) on spins without couplings (c0 = 0): each spin is a driven
+    oscillator y += dt (-(a0 - a_t) x + alpha eta), x += dt a0 y, with the wall.
+
+    eta comes from the test's own SplitMix64 + Box-Muller (tests/noise_model),
+    counter (g T + t) n + i of the stream keyed seed ^ 0xd1b54a32d192ed03, and
+    the recursion runs in exact rationals.  Noise added to x instead of y, a
+    missing dt factor, a wrong sign or a wrong counter (replica, step or spin
+    index) each give a different trajectory.  Two weight vectors x three
+    replicas x two spins cover the counter layout."""
+    import noise_model as nm
+    inst = _instance(2, 1, [], np.zeros((1, 0)))
+    W, R, T, alpha, seed, amp = 2, 3, 40, 0.3, 29, 0.1
+    dt, a0 = Fraction(1, 2), Fraction(1)
+    c = np.array([[1.0], [0.5]], np.float32)
+    _, trace = oracle.sb_sample(inst, c, R=R, T=T, variant=variant, dt=0.5, seed=seed, alpha=alpha,
+                                trace_steps=T, amp=amp)
+    hits = 0
+    for g in range(W * R):
+        x = [_exact_init(seed, g, 2, i, 0, amp) for i in range(2)]
+        y = [_exact_init(seed, g, 2, i, 1, amp) for i in range(2)]
+
+        def noise(t, i, g=g):
+            return Fraction(alpha) * Fraction(nm.noise(seed, nm.noise_counter(g, T, t, 2, i))[0])
+        want = _exact_sb(x, y, [], None, T, dt, a0, variant, noise=noise)
+        for t in range(T):
+            for i in range(2):
+                assert trace[g, t, i] == pytest.approx(float(want[t][i]), rel=1e-12, abs=1e-14), (g, t, i)
+            hits += sum(abs(v) == 1 for v in want[t])
+    assert hits > 0  # the noise drives spins into the wall within T steps
+
+
+def test_python_splitmix_matches_published_outputs(golden_dir):
+    import noise_model as nm
+    with open(os.path.join(golden_dir, "splitmix64_seed0.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            seed, idx, val = line.split()
+            assert nm.splitmix64(int(seed), int(idx)) == int(val, 16)
+
+
 def test_wall_is_inelastic_and_bounds_x():
     inst = wl.random_instance(10, 2, "deg3", seed=3, num_edges=12)
     c = wl.dirichlet_weights(4, 2, 1)
