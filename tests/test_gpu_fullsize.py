@@ -145,9 +145,10 @@ def test_headline_filter_full_pool(q):
     srt = pool[order]
     first = np.ones(order.size, bool)
     first[1:] = (srt[1:] != srt[:-1]).any(axis=1)
-    firsts = {tuple(v): int(i) for v, i in zip(srt[first], order[first])}
-    for i in keep:
-        assert firsts[tuple(pool[i])] == i
+    run_start = np.maximum.accumulate(np.where(first, np.arange(order.size), 0))
+    pos = np.empty_like(order)
+    pos[order] = np.arange(order.size)
+    assert np.array_equal(order[run_start[pos[keep]]], keep)
     # sampled rows are dominated by or equal to a kept row
     rng = np.random.default_rng(5)
     for r in rng.choice(pool.shape[0], size=10000, replace=False):

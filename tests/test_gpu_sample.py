@@ -298,7 +298,7 @@ def test_noise_draws_elementwise(q, path):
     idx = [(g * T) * n + i for g in range(rows) for i in range(n)]
     eta_ref = np.array([oracle.noise_value(seed, k) for k in idx]).reshape(rows, n)
     model = np.array([nm.noise(seed, k) for k in idx]).reshape(rows, n, 3)
-    assert np.abs(model[..., 0] - eta_ref).max() <= 1e-12 * np.maximum(model[..., 1], 1)
+    assert (np.abs(model[..., 0] - eta_ref) <= 1e-12 * np.maximum(model[..., 1], 1)).all()
     bound = fb.eta_error_bound(model[..., 1], model[..., 2])
     err = np.abs(eta_dev - eta_ref)
     worst = float((err / np.where(bound > 0, bound, 1)).max())
