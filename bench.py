@@ -36,6 +36,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 # Non-packed FP32 FMA issue (256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz);
 # the library is compiled with packed FP32 disabled.
 PEAK_FP32_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
 
 # HBM bytes of one qaia_sb_reg launch on this workload, from two rocprofv3
 # --pmc passes over `bench.py --traffic-probe` (FETCH_SIZE, then WRITE_SIZE,
@@ -433,15 +434,27 @@ def table2_form(q, wl, torch, sizes=((25, 0.5), (25, 1.0), (100, 0.5), (100, 1.0
     return out
 
 
-def traffic_probe(q, wl, torch):
-    """One bSB sampling launch of the benchmark workload and, as the counters'
-    calibration, one plain device copy of 1 GiB (1 GiB read, 1 GiB written)."""
-    cfg = wl.WORKLOADS[WORKLOAD]
-    inst = wl.workload_instance(WORKLOAD)
-    prob = q.problem_from_instance(inst, 0)
-    c = torch.from_numpy(wl.workload_weights(WORKLOAD)).cuda()
-    s = q.make_schedule("bsb", steps=cfg["T"], dt=0.5, seed=cfg["seed"] + 3)
-    spins, obj, ws = q.qaia_sample(prob, c, cfg["R"], s)
+def traffic_probe(q, wl, torch, kind="sparse"):
+    """For counter collection.  sparse: one bSB sampling launch of the
+    benchmark workload.  dense: one 20-step dSB call of the precision workload
+    per operand format (FP32, BF16, FP8).  Then, as the counters' calibration,
+    one plain device copy of 1 GiB (1 GiB read, 1 GiB written)."""
+    if kind == "dense":
+        N, m, W, R = 2048, 3, 512, 8
+        inst = wl.random_instance(N, m, "complete", seed=3000)
+        prob = q.problem_from_instance(inst, 0)
+        c = torch.from_numpy(wl.dirichlet_weights(W, m, 3002)).cuda()
+        for prec in ("fp32", "bf16", "fp8"):
+            s = q.make_schedule("dsb", precision=prec, steps=20, dt=0.5, seed=3003, path="dense_staged")
+            spins, obj, ws = q.qaia_sample(prob, c, R, s)
+            torch.cuda.synchronize()
+    else:
+        cfg = wl.WORKLOADS[WORKLOAD]
+        inst = wl.workload_instance(WORKLOAD)
+        prob = q.problem_from_instance(inst, 0)
+        c = torch.from_numpy(wl.workload_weights(WORKLOAD)).cuda()
+        s = q.make_schedule("bsb", steps=cfg["T"], dt=0.5, seed=cfg["seed"] + 3)
+        spins, obj, ws = q.qaia_sample(prob, c, cfg["R"], s)
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -463,9 +476,10 @@ def main():
                     help="run one form measurement alone and print its JSON (for profiling)")
     ap.add_argument("--precision-steps", type=int, default=1000,
                     help="SB steps of the precision form (shorter runs for counter collection)")
-    ap.add_argument("--traffic-probe", action="store_true",
-                    help="run one bSB sampling launch of the workload and one 1 GiB device copy, for HBM "
-                         "counter collection (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), then exit")
+    ap.add_argument("--traffic-probe", nargs="?", const="sparse", choices=["sparse", "dense"],
+                    help="run one bSB sampling launch of the workload (sparse) or 20 dSB steps of the "
+                         "precision workload per operand format (dense), then one 1 GiB device copy, for "
+                         "counter collection (rocprofv3 --pmc), then exit")
     ap.add_argument("--noise-form", action="store_true",
                     help="also run the noise studies (front recovery, noise sweep) on 25-node exact fronts")
     ap.add_argument("--table2-form", action="store_true",
@@ -482,7 +496,7 @@ def main():
     import workloads as wl
 
     if args.traffic_probe:
-        traffic_probe(q, wl, torch)
+        traffic_probe(q, wl, torch, args.traffic_probe)
         return
     if args.only_form:
         if args.only_form == "precision":
@@ -619,6 +633,8 @@ def main():
     achieved = algo_flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     instr = {v: valu_instructions_per_replica_step(inst, v) for v in variants}
     issue_rate = sum(instr[v] * rows * T for v in variants) / (sum(stage[f"{v}_ms"] for v in variants) * 1e-3) / 1e12
+    fma_per_rs = fma_flops_per_replica_step(inst.n, inst.num_edges) // 2
+    fma_ceiling = SIMDS * CLOCK_HZ / 4 * 64 / fma_per_rs
     result = {
         "metric": METRIC, "value": total_rs / (ms_per_step * 1e-3), "unit": "replica-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -644,15 +660,21 @@ def main():
                          "frac_of_nonpacked_fma_peak": performed_flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
                          / PEAK_FP32_FMA_TFLOPS, "nonpacked_fma_peak": PEAK_FP32_FMA_TFLOPS},
                      "issue": {"valu_instructions_per_replica_step": instr,
-                               "achieved_Tinstr_per_s": issue_rate}},
+                               "fma_instructions_per_replica_step": fma_per_rs,
+                               "achieved_Tinstr_per_s": issue_rate,
+                               "fma_slot_ceiling_replica_steps_per_s": fma_ceiling,
+                               "frac": {v: rows * T / (stage[f"{v}_ms"] * 1e-3) / fma_ceiling for v in variants},
+                               "model": "a SIMD issues one wave64 VALU instruction per 4 cycles, or two from "
+                                        "two waves when they differ in kind; FMAs never pair with FMAs "
+                                        "(SQ_ACTIVE_INST_VALU2), so the FMAs of a replica-step bound it: "
+                                        "1024 SIMDs x 2.4 GHz / 4 x 64 lanes / FMAs per replica-step"}},
         "stages_ms": stage,
         "sampling_replica_steps_per_s": {v: rows * T / (stage[f"{v}_ms"] * 1e-3) for v in variants},
         "front_size": P, "hypervolume": str(hv),
     }
     peaks = measured_peaks(q, torch)
     result["measured_peaks"] = peaks
-    result["roofline"]["issue"]["measured_mix_peak_Tinstr_per_s"] = peaks["valu_mix_Tinstr_per_s"]
-    result["roofline"]["issue"]["frac"] = issue_rate / peaks["valu_mix_Tinstr_per_s"]
+    result["roofline"]["issue"]["measured_mix_Tinstr_per_s"] = peaks["valu_mix_Tinstr_per_s"]
     result["roofline"]["performed_fma_flops"]["measured_fma_peak"] = peaks["fp32_fma_TFLOPs"]
     if not args.no_forms:
         result["forms"] = {"precision": precision_form(q, wl, torch)}
