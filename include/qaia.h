@@ -169,6 +169,33 @@ int32_t qaia_sample_trace(const qaia_problem *p, const float *weights, int64_t W
                           const qaia_schedule *s, uint64_t *spins, int64_t *obj, void *workspace,
                           size_t ws_bytes, float *x_trace, int32_t trace_steps, void *hip_stream);
 
+/* Bytes of the static scratch array behind qaia_sample_noalloc (16 MiB). */
+#define QAIA_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): qaia_sample
+ * with its workspace in a static device array of QAIA_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each GPU it runs on until the process ends.  The
+ * call allocates nothing (no hipMalloc, no allocating library routine); the
+ * caller still passes weights, spins and obj as for qaia_sample, with the
+ * same layouts and results.
+ *   bad_row : DEVICE int64[1] or NULL.  Once the stream has passed this
+ *             call it holds the smallest weight row that is negative,
+ *             non-finite or all-zero (whose spins and cuts are left zero),
+ *             or -1 if every row was valid.
+ * Errors returned synchronously, before anything is queued: those of
+ * qaia_sample; WORKSPACE_TOO_SMALL when the call needs more scratch than
+ * QAIA_NOALLOC_SCRATCH_BYTES (qaia_sample_workspace_bytes gives the need);
+ * UNSUPPORTED when the chosen path would generate a kernel variant on first
+ * use (the noise-injected generated kernel is built by the first qaia_sample
+ * call with a nonzero noise_alpha; call that once first).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (on different streams, or from
+ * different threads) race and give undefined results. */
+int32_t qaia_sample_noalloc(const qaia_problem *p, const float *weights, int64_t W, int32_t R,
+                            const qaia_schedule *s, uint64_t *spins, int64_t *obj, int64_t *bad_row,
+                            void *hip_stream);
+
 /* After synchronising the stream of a qaia_sample call: QAIA_OK if every
  * weight row was valid, else QAIA_INVALID_ARGUMENT with *bad_row = the
  * smallest offending row (HOST int64, may be NULL).  workspace is the

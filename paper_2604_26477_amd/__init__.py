@@ -56,6 +56,7 @@ _SIGS = {
     "qaia_sample": (_i32, [_P, _P, _i64, _i32, C.POINTER(qaia_schedule), _P, _P, _P, _sz, _P]),
     "qaia_sample_trace": (_i32, [_P, _P, _i64, _i32, C.POINTER(qaia_schedule), _P, _P, _P, _sz, _P,
                                  _i32, _P]),
+    "qaia_sample_noalloc": (_i32, [_P, _P, _i64, _i32, C.POINTER(qaia_schedule), _P, _P, _P, _P]),
     "qaia_workspace_status": (_i32, [_P, C.POINTER(_i64)]),
     "qaia_evaluate": (_i32, [_P, _P, _i64, _P, _P]),
     "qaia_enumerate_cuts": (_i32, [_P, C.c_uint64, _i64, _P, _P]),
@@ -248,6 +249,29 @@ def _sample(p, weights, R, s, spins, obj, workspace, stream, trace, trace_steps)
                                     trace_steps, _stream(stream))
     _check(rc)
     return spins, obj, workspace
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20  # QAIA_NOALLOC_SCRATCH_BYTES
+
+
+def qaia_sample_noalloc(p: Problem, weights: torch.Tensor, R: int, s: qaia_schedule, spins: torch.Tensor,
+                        obj: torch.Tensor, bad_row: torch.Tensor | None = None, stream=None):
+    """qaia_sample with the library's static scratch as workspace: allocates
+    nothing, so spins [W*R, words] int64, obj [W*R, m] int64 and the optional
+    bad_row (int64 [1]) are caller-provided device tensors."""
+    if weights.dtype != torch.float32 or not weights.is_cuda or not weights.is_contiguous():
+        raise ValueError("weights must be a contiguous float32 CUDA tensor [W, m]")
+    if spins is None or obj is None:
+        raise ValueError("qaia_sample_noalloc takes caller-provided spins and obj tensors")
+    W = weights.shape[0]
+    dev = p.torch_device
+    spins = _dev_tensor(spins, torch.int64, (W * R, p.words), dev)
+    obj = _dev_tensor(obj, torch.int64, (W * R, p.m), dev)
+    if bad_row is not None:
+        bad_row = _dev_tensor(bad_row, torch.int64, (1,), dev)
+    _check(_lib.qaia_sample_noalloc(p.handle, _ptr(weights), W, R, C.byref(s), _ptr(spins), _ptr(obj),
+                                    _ptr(bad_row), _stream(stream)))
+    return spins, obj
 
 
 def qaia_workspace_status(workspace: torch.Tensor):

@@ -72,9 +72,12 @@ WsLayout full_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule
     return L;
 }
 
+// no_alloc: the workspace is the library's static scratch array; a call that
+// would build a generated kernel variant on first use (and so allocate code
+// memory) is refused instead, and a too-small scratch is reported as such.
 int32_t sample_impl(const qaia_problem *pp, const float *weights, int64_t W, int32_t R,
                     const qaia_schedule *s, uint64_t *spins, int64_t *obj, void *ws, size_t ws_bytes,
-                    float *trace, int32_t trace_steps, void *stream) {
+                    float *trace, int32_t trace_steps, void *stream, bool no_alloc = false) {
     QAIA_CHECK(pp != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
     const Problem &p = *reinterpret_cast<const Problem *>(pp);
     check_schedule(p, s);
@@ -88,6 +91,17 @@ int32_t sample_impl(const qaia_problem *pp, const float *weights, int64_t W, int
     const int path = plan_path(p, *s, trace_steps > 0);
     const WsLayout L = full_layout(p, W, R, *s, path);
     QAIA_CHECK(ws != nullptr, QAIA_INVALID_ARGUMENT, "null workspace");
+    if (no_alloc) {
+        QAIA_CHECK(L.total <= ws_bytes, QAIA_WORKSPACE_TOO_SMALL,
+                   "this call needs " + std::to_string(L.total) +
+                       " bytes of scratch; the allocation-free entry point holds at most " +
+                       std::to_string(ws_bytes));
+        QAIA_CHECK(path != QAIA_PATH_SPARSE_REG ||
+                       sparse_reg_ready(p, s->variant, trace_steps > 0, s->dt * s->noise_alpha != 0.0f),
+                   QAIA_UNSUPPORTED,
+                   "the generated kernel for this schedule is built on first use, which allocates; "
+                   "run qaia_sample once with the same schedule kind first, or choose another path");
+    }
     QAIA_CHECK(ws_bytes >= L.total, QAIA_WORKSPACE_TOO_SMALL,
                "sample workspace needs " + std::to_string(L.total) + " bytes");
     hipStream_t st = (hipStream_t)stream;
@@ -188,6 +202,23 @@ int32_t qaia_sample_trace(const qaia_problem *p, const float *weights, int64_t W
     return guarded([&]() {
         return sample_impl(p, weights, W, R, s, spins, obj, workspace, ws_bytes, x_trace,
                            trace_steps, hip_stream);
+    });
+}
+
+int32_t qaia_sample_noalloc(const qaia_problem *pp, const float *weights, int64_t W, int32_t R,
+                            const qaia_schedule *s, uint64_t *spins, int64_t *obj, int64_t *bad_row,
+                            void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(pp != nullptr, QAIA_INVALID_ARGUMENT, "null problem");
+        const Problem &p = *reinterpret_cast<const Problem *>(pp);
+        void *scratch = noalloc_scratch(p.device);
+        const int32_t rc = sample_impl(pp, weights, W, R, s, spins, obj, scratch, noalloc_scratch_bytes(),
+                                       nullptr, 0, hip_stream, true);
+        if (rc == QAIA_OK && bad_row != nullptr) {
+            DeviceGuard g(p.device);
+            launch_noalloc_bad_row(scratch, bad_row, (hipStream_t)hip_stream);
+        }
+        return rc;
     });
 }
 

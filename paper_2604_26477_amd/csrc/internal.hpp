@@ -109,6 +109,17 @@ struct WsLayout {
 WsLayout sample_ws_layout(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, bool edge_coefs);
 void dense_ws_extend(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, WsLayout &L);
 
+// Allocation-free sampling (noalloc.hip): this device's static scratch array
+// (its address from hipGetSymbolAddress, taken once per device), its size,
+// and a copy of the invalid-row flag from the scratch header (the workspace
+// header sits at offset 0) into a caller-owned device word.
+void *noalloc_scratch(int device);
+size_t noalloc_scratch_bytes();
+void launch_noalloc_bad_row(const void *scratch, int64_t *bad_row, hipStream_t st);
+// Whether the generated register kernel for this schedule kind exists already
+// (the tracing and noise variants are generated on first use).
+bool sparse_reg_ready(const Problem &p, int variant, bool trace, bool noise);
+
 // One problem's rows for the generic sparse kernel (passed by value, or as a
 // device array for a ragged batch).
 struct SparseJob {

@@ -326,6 +326,13 @@ static const JitKernel *kernel_for(const Problem &p, int variant, bool trace, bo
     return slot;
 }
 
+bool sparse_reg_ready(const Problem &p, int variant, bool trace, bool noise) {
+    if (!trace && !noise) return p.jit[variant] != nullptr;
+    Problem &mp = const_cast<Problem &>(p);
+    std::lock_guard<std::mutex> lk(mp.mu);
+    return (noise ? mp.jit_noise[variant][trace ? 1 : 0] : mp.jit_trace[variant]) != nullptr;
+}
+
 void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, const qaia_schedule &s,
                        void *ws, const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
                        int32_t trace_steps, hipStream_t st) {
