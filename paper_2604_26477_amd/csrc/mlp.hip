@@ -6,11 +6,10 @@
 // scalarisation weight vectors (Eq. 7) the sampler runs next.
 //
 // Parameter layout (flat): W1 [H][D], b1 [H], W2 [H][H], b2 [H], w3 [H], b3.
-#include <hipcub/hipcub.hpp>
 
 #include <cmath>
 
-#include "internal.hpp"
+#include "radix.hpp"
 
 namespace qaia {
 namespace {
@@ -40,118 +39,190 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     u += 0x7FFFu + ((u >> 16) & 1u);  // round half to even (finite values)
     return (uint16_t)(u >> 16);
 }
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// 1 + erf(z / sqrt 2) is evaluated as erfc(-z / sqrt 2): for negative z the
+// sum would cancel (at z = -5 it is 1.5e-6, below the float32 spacing of the
+// erf value near -1), the complementary function keeps full relative accuracy.
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * erfcf(-z * 0.70710678118654752f); }
 __device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    return 0.5f * erfcf(-z * 0.70710678118654752f) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
 // ---------------------------------------------------------------- MLP passes
+//
+// One block of 256 threads (four waves) handles 32 samples.  Layer 1
+// (D -> 128, tiny) runs on the vector units; the 128 x 128 contractions run
+// on the matrix cores as fp32 32x32x2 MFMAs (the bf16 weights widen exactly to
+// fp32, so activations and accumulation stay fp32):
+//   forward : Z2 = A1 W2^T, wave w takes the 32 units 32w .. 32w+31;
+//   backward: dZ1 = dZ2 W2 (wave w: hidden units 32w ..), and
+//             dW2 = dZ2^T A1 (wave w: rows u = 32w .., all 128 columns).
+// For every MFMA the A and B fragments of a lane come from the same k
+// position (k = 2t + lane / 32), which pairs them for any internal k order.
+// Accumulator slot i of lane l holds row (i/4)*8 + (l/32)*4 + i%4, column l%32.
+// Training writes the block's gradient contribution (every parameter) to
+// partial[block]; a second kernel sums the blocks in a fixed order.
+constexpr int kS = 32;          // samples per block
+constexpr int kP = kH + 2;      // LDS pitch (floats) of the 128-wide tiles: a 32-lane strided read and its
+                                // neighbour column fall on disjoint banks
 
-// a1 = gelu(W1 x + b1), g1 = gelu'(.) (optional); one thread per (sample, unit)
-__global__ void layer1_kernel(const uint16_t *__restrict__ P, int D, const float *__restrict__ X,
-                              int64_t N, float *__restrict__ a1, float *__restrict__ g1) {
-    const int64_t idx = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (idx >= N * kH) return;
-    const int64_t s = idx / kH;
-    const int h = (int)(idx % kH);
-    const ParamOffsets o = offsets(D);
-    float z = bf16_to_f32(P[o.b1 + h]);
-    for (int d = 0; d < D; ++d) z = fmaf(bf16_to_f32(P[o.W1 + (int64_t)h * D + d]), X[s * D + d], z);
-    a1[idx] = gelu(z);
-    if (g1) g1[idx] = gelu_grad(z);
-}
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// a2 = gelu(W2 a1 + b2), g2 = gelu'(.) (optional); one thread per (sample, unit)
-__global__ void layer2_kernel(const uint16_t *__restrict__ P, int D, const float *__restrict__ a1,
-                              int64_t N, float *__restrict__ a2, float *__restrict__ g2) {
-    // transposed copy: lanes (consecutive units u) read consecutive words
-    __shared__ float w2t[kH][kH];
+__device__ __forceinline__ int acc_row(int half, int i) { return (i >> 2) * 8 + half * 4 + (i & 3); }
+
+template <bool TRAIN>
+__global__ __launch_bounds__(kB) void mlp_fused_kernel(const uint16_t *__restrict__ P, int D,
+                                                       const float *__restrict__ X, int64_t N,
+                                                       const float *__restrict__ y, float *__restrict__ logits,
+                                                       float *__restrict__ partial) {
+    __shared__ float w2[kH * kP];          // W2[u][h] at u * kP + h
+    __shared__ float w1[kH][kMaxD + 1];
+    __shared__ float xs[kS][kMaxD + 1];
+    __shared__ float a1[kS * kP];          // A1[s][h]
+    __shared__ float g1[TRAIN ? kS * kP : 1];   // gelu'(z1)[s][h]
+    __shared__ float dz2[TRAIN ? kS * kP : 1];  // dZ2[s][u]
+    __shared__ float dz1[TRAIN ? kS * kP : 1];  // dZ1[s][h]
+    __shared__ float lpart[4][kS];
+    __shared__ float dz3[kS];
     const ParamOffsets o = offsets(D);
-    for (int i = threadIdx.x; i < kH * kH; i += kB) w2t[i % kH][i / kH] = bf16_to_f32(P[o.W2 + i]);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5, lr = lane & 31;
+    const int64_t s0 = (int64_t)blockIdx.x * kS;
+    const int ns = (int)(N - s0 < kS ? N - s0 : kS);
+    for (int i = tid; i < kH * kH; i += kB) w2[(i >> 7) * kP + (i & (kH - 1))] = bf16_to_f32(P[o.W2 + i]);
+    for (int i = tid; i < kH * kMaxD; i += kB) {
+        const int h = i / kMaxD, d = i % kMaxD;
+        w1[h][d] = d < D ? bf16_to_f32(P[o.W1 + (int64_t)h * D + d]) : 0.0f;
+    }
+    for (int i = tid; i < kS * kMaxD; i += kB) {
+        const int s = i / kMaxD, d = i % kMaxD;
+        xs[s][d] = (s < ns && d < D) ? X[(s0 + s) * D + d] : 0.0f;
+    }
     __syncthreads();
-    const int64_t idx = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (idx >= N * kH) return;
-    const int64_t s = idx / kH;
-    const int u = (int)(idx % kH);
-    const float *a = a1 + s * kH;
-    float z = bf16_to_f32(P[o.b2 + u]);
+    // layer 1: thread t takes sample t % 32 and hidden units 16 (t / 32) ..
+    {
+        const int s = tid & (kS - 1), hg = tid >> 5;
+#pragma unroll 4
+        for (int j = 0; j < 16; ++j) {
+            const int h = hg * 16 + j;
+            float z = bf16_to_f32(P[o.b1 + h]);
+            for (int d = 0; d < D; ++d) z = fmaf(w1[h][d], xs[s][d], z);
+            a1[s * kP + h] = gelu(z);
+            if constexpr (TRAIN) g1[s * kP + h] = gelu_grad(z);
+        }
+    }
+    __syncthreads();
+    // layer 2 on the matrix cores: this wave's 32 units
+    const int u = wave * 32 + lr;
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
 #pragma unroll 8
-    for (int h = 0; h < kH; ++h) z = fmaf(w2t[h][u], a[h], z);
-    a2[idx] = gelu(z);
-    if (g2) g2[idx] = gelu_grad(z);
-}
-
-// logit = w3 . a2 + b3; with labels: dz3 = (sigmoid(logit) - y) / B and
-// dz2 = dz3 w3 gelu'(z2); one thread per sample
-__global__ void head_kernel(const uint16_t *__restrict__ P, int D, const float *__restrict__ a2,
-                            const float *__restrict__ g2, int64_t N, const float *__restrict__ y,
-                            float *__restrict__ logits, float *__restrict__ dz3,
-                            float *__restrict__ dz2) {
-    const int64_t s = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (s >= N) return;
-    const ParamOffsets o = offsets(D);
-    float z = bf16_to_f32(P[o.b3]);
-    for (int u = 0; u < kH; ++u) z = fmaf(bf16_to_f32(P[o.w3 + u]), a2[s * kH + u], z);
-    if (logits) logits[s] = z;
-    if (y) {
-        const float d = (1.0f / (1.0f + expf(-z)) - y[s]) / (float)N;
-        dz3[s] = d;
-        for (int u = 0; u < kH; ++u) dz2[s * kH + u] = d * bf16_to_f32(P[o.w3 + u]) * g2[s * kH + u];
+    for (int t = 0; t < kH / 2; ++t) {
+        const int k = 2 * t + half;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[lr * kP + k], w2[u * kP + k], acc, 0, 0, 0);
+    }
+    const float b2u = bf16_to_f32(P[o.b2 + u]), w3u = bf16_to_f32(P[o.w3 + u]);
+    float z2[16], part[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        z2[i] = acc[i] + b2u;
+        part[i] = w3u * gelu(z2[i]);
+    }
+    // head: sum over this wave's units (the 32 lanes of each half), per row
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        for (int off = 16; off > 0; off >>= 1) part[i] += __shfl_xor(part[i], off, 64);
+    if (lr == 0)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lpart[wave][acc_row(half, i)] = part[i];
+    __syncthreads();
+    if (tid < kS) {
+        // the four waves' unit ranges in a fixed order
+        const float z = bf16_to_f32(P[o.b3]) + ((lpart[0][tid] + lpart[1][tid]) + (lpart[2][tid] + lpart[3][tid]));
+        if (tid < ns && logits) logits[s0 + tid] = z;
+        if constexpr (TRAIN) dz3[tid] = tid < ns ? (1.0f / (1.0f + expf(-z)) - y[s0 + tid]) / (float)N : 0.0f;
+    }
+    if constexpr (!TRAIN) return;
+    __syncthreads();
+    float *pg = partial + (int64_t)blockIdx.x * o.total;
+    // dZ2 = dz3 w3 gelu'(z2); gb2[u] = sum_s dZ2, gw3[u] = sum_s dz3 a2
+    {
+        float gb2 = 0.0f, gw3 = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int s = acc_row(half, i);
+            const float d3 = dz3[s];
+            const float d2 = d3 * w3u * gelu_grad(z2[i]);
+            dz2[s * kP + u] = d2;
+            gb2 += d2;
+            gw3 = fmaf(d3, gelu(z2[i]), gw3);
+        }
+        gb2 += __shfl_xor(gb2, 32, 64);
+        gw3 += __shfl_xor(gw3, 32, 64);
+        if (half == 0) {
+            pg[o.b2 + u] = gb2;
+            pg[o.w3 + u] = gw3;
+        }
+        if (tid == 0) {
+            float g3 = 0.0f;
+            for (int s = 0; s < kS; ++s) g3 += dz3[s];
+            pg[o.b3] = g3;
+        }
+    }
+    __syncthreads();
+    // dZ1 = (dZ2 W2) * gelu'(z1): this wave's hidden units h = 32w + lr
+    {
+        const int h = wave * 32 + lr;
+        f32x16 d;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) d[i] = 0.0f;
+#pragma unroll 8
+        for (int t = 0; t < kH / 2; ++t) {
+            const int k = 2 * t + half;  // the unit index u
+            d = __builtin_amdgcn_mfma_f32_32x32x2f32(dz2[lr * kP + k], w2[k * kP + h], d, 0, 0, 0);
+        }
+        float gb1 = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int s = acc_row(half, i);
+            const float v = d[i] * g1[s * kP + h];
+            dz1[s * kP + h] = v;
+            gb1 += v;
+        }
+        gb1 += __shfl_xor(gb1, 32, 64);
+        if (half == 0) pg[o.b1 + h] = gb1;
+    }
+    // dW2 = dZ2^T A1: rows u = 32w + .., columns h in four 32-wide tiles, k = sample
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        f32x16 g;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) g[i] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < kS / 2; ++t) {
+            const int s = 2 * t + half;
+            g = __builtin_amdgcn_mfma_f32_32x32x2f32(dz2[s * kP + wave * 32 + lr], a1[s * kP + c * 32 + lr], g, 0, 0,
+                                                     0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) pg[o.W2 + (int64_t)(wave * 32 + acc_row(half, i)) * kH + c * 32 + lr] = g[i];
+    }
+    __syncthreads();
+    // dW1[h][d] = sum_s dZ1[s][h] x[s][d]: thread t takes hidden unit t / 2 and eight inputs
+    {
+        const int h = tid >> 1, d0 = (tid & 1) * 8;
+        float g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int s = 0; s < kS; ++s) {
+            const float v = dz1[s * kP + h];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) g[j] = fmaf(v, xs[s][d0 + j], g[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (d0 + j < D) pg[o.W1 + (int64_t)h * D + d0 + j] = g[j];
     }
 }
 
-// dz1 = (W2^T dz2) * gelu'(z1); one thread per (sample, unit)
-__global__ void back1_kernel(const uint16_t *__restrict__ P, int D, const float *__restrict__ dz2,
-                             const float *__restrict__ g1, int64_t N, float *__restrict__ dz1) {
-    __shared__ float w2[kH][kH];  // natural layout: lanes (consecutive h) read consecutive words
-    const ParamOffsets o = offsets(D);
-    for (int i = threadIdx.x; i < kH * kH; i += kB) w2[i / kH][i % kH] = bf16_to_f32(P[o.W2 + i]);
-    __syncthreads();
-    const int64_t idx = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (idx >= N * kH) return;
-    const int64_t s = idx / kH;
-    const int h = (int)(idx % kH);
-    float a = 0.0f;
-#pragma unroll 8
-    for (int u = 0; u < kH; ++u) a = fmaf(w2[u][h], dz2[s * kH + u], a);
-    dz1[idx] = a * g1[idx];
-}
-
-// parameter gradients in two passes: pass 1 gives each (parameter, slice of
-// kSlice samples) one thread, pass 2 sums the slices in order (deterministic)
-constexpr int kSlice = 64;
-
-__global__ void grads_partial_kernel(int D, const float *__restrict__ X, const float *__restrict__ a1,
-                                     const float *__restrict__ a2, const float *__restrict__ dz1,
-                                     const float *__restrict__ dz2, const float *__restrict__ dz3, int64_t N,
-                                     float *__restrict__ partial) {
-    const ParamOffsets o = offsets(D);
-    const int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (p >= o.total) return;
-    const int64_t s0 = (int64_t)blockIdx.y * kSlice;
-    const int64_t s1 = s0 + kSlice < N ? s0 + kSlice : N;
-    float g = 0.0f;
-    if (p < o.b1) {
-        const int h = (int)(p / D), d = (int)(p % D);
-        for (int64_t s = s0; s < s1; ++s) g = fmaf(dz1[s * kH + h], X[s * D + d], g);
-    } else if (p < o.W2) {
-        const int h = (int)(p - o.b1);
-        for (int64_t s = s0; s < s1; ++s) g += dz1[s * kH + h];
-    } else if (p < o.b2) {
-        const int u = (int)((p - o.W2) / kH), h = (int)((p - o.W2) % kH);
-        for (int64_t s = s0; s < s1; ++s) g = fmaf(dz2[s * kH + u], a1[s * kH + h], g);
-    } else if (p < o.w3) {
-        const int u = (int)(p - o.b2);
-        for (int64_t s = s0; s < s1; ++s) g += dz2[s * kH + u];
-    } else if (p < o.b3) {
-        const int u = (int)(p - o.w3);
-        for (int64_t s = s0; s < s1; ++s) g = fmaf(dz3[s], a2[s * kH + u], g);
-    } else {
-        for (int64_t s = s0; s < s1; ++s) g += dz3[s];
-    }
-    partial[(int64_t)blockIdx.y * o.total + p] = g;
-}
-
+// the gradient is the sum of the blocks' contributions, in block order (deterministic)
 __global__ void grads_reduce_kernel(const float *__restrict__ partial, int slices, int64_t total,
                                     float *__restrict__ grad) {
     const int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x;
@@ -393,9 +464,28 @@ __global__ void gumbel_keys_kernel(const float *__restrict__ scores, int64_t N, 
     keys[i] = scores[i] * inv_tau - logf(-logf(u));
 }
 
-__global__ void iota64_kernel(int64_t *p, int64_t n) {
+// Sort keys of the top-k selection: descending score order as an ascending
+// unsigned key (the IEEE bit pattern made monotone, then complemented; -0 is
+// taken as +0), value = item index.  Block 0 also stores the item and digit
+// pass counts the sort reads from device memory.
+__global__ void topk_key_kernel(const float *__restrict__ s, int64_t N, uint64_t *__restrict__ key,
+                                int32_t *__restrict__ val, int64_t *__restrict__ d_n, int32_t *__restrict__ d_passes) {
     const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i < n) p[i] = i;
+    if (i == 0) {
+        *d_n = N;
+        *d_passes = 4;
+    }
+    if (i >= N) return;
+    const float f = s[i];
+    uint32_t b = f == 0.0f ? 0u : __float_as_uint(f);
+    b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    key[i] = (uint64_t)(~b);
+    val[i] = (int32_t)i;
+}
+
+__global__ void topk_out_kernel(const int32_t *__restrict__ val, int64_t k, int64_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (i < k) out[i] = val[i];
 }
 
 __global__ void labels_kernel(const int64_t *__restrict__ keep, const int64_t *__restrict__ num_keep,
@@ -427,38 +517,31 @@ __global__ void gather_rows_kernel(const uint32_t *__restrict__ src, int width,
 
 unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kB - 1) / kB); }
 
-size_t topk_temp(int64_t N) {
-    size_t b = 0;
-    hipcub::DeviceRadixSort::SortPairsDescending(nullptr, b, (const float *)nullptr, (float *)nullptr,
-                                                 (const int64_t *)nullptr, (int64_t *)nullptr,
-                                                 (int)std::max<int64_t>(N, 1), 0, 32, (hipStream_t)0);
-    return b;
-}
-
 }  // namespace
 
 int64_t mlp_param_count(int D) { return offsets(D).total; }
 
-static int64_t grad_slices(int64_t B) { return (B + kSlice - 1) / kSlice; }
+static int64_t grad_blocks(int64_t B) { return (B + kS - 1) / kS; }
 
 size_t mlp_backward_ws_bytes(int D, int64_t B) {
-    // a1, g1, a2, g2, dz1, dz2 [B][H], dz3 [B], per-slice partial gradients [slices][params]
-    return align256(sizeof(float) * (size_t)B * kH) * 6 + align256(sizeof(float) * (size_t)B) +
-           align256(sizeof(float) * (size_t)grad_slices(B) * (size_t)offsets(std::max(D, 1)).total);
+    return align256(sizeof(float) * (size_t)std::max<int64_t>(grad_blocks(B), 1) *
+                    (size_t)offsets(std::max(D, 1)).total);
 }
 
-size_t mlp_forward_ws_bytes(int64_t N) { return align256(sizeof(float) * (size_t)N * kH) * 2; }
+size_t mlp_forward_ws_bytes(int64_t N) {
+    (void)N;
+    return 256;  // the fused forward keeps everything on chip
+}
 
 void launch_mlp_forward(const uint16_t *P, int D, const float *X, int64_t N, float *logits, void *ws,
                         hipStream_t st) {
+    (void)ws;
     QAIA_CHECK(D >= 1 && D <= kMaxD, QAIA_INVALID_ARGUMENT, "input width must be in [1, 16]");
     if (N == 0) return;
-    char *b = (char *)ws;
-    float *a1 = (float *)b, *a2 = (float *)(b + align256(sizeof(float) * (size_t)N * kH));
-    hipLaunchKernelGGL(layer1_kernel, dim3(blocks_for(N * kH)), dim3(kB), 0, st, P, D, X, N, a1, nullptr);
-    hipLaunchKernelGGL(layer2_kernel, dim3(blocks_for(N * kH)), dim3(kB), 0, st, P, D, a1, N, a2, nullptr);
-    hipLaunchKernelGGL(head_kernel, dim3(blocks_for(N)), dim3(kB), 0, st, P, D, a2, nullptr, N, nullptr,
-                       logits, nullptr, nullptr);
+    const int64_t blocks = grad_blocks(N);
+    QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many samples");
+    hipLaunchKernelGGL(mlp_fused_kernel<false>, dim3((unsigned)blocks), dim3(kB), 0, st, P, D, X, N,
+                       (const float *)nullptr, logits, (float *)nullptr);
     QAIA_HIP(hipGetLastError());
 }
 
@@ -466,21 +549,12 @@ void launch_mlp_backward(const uint16_t *P, int D, const float *X, const float *
                          float *grad, float *loss_logits, void *ws, hipStream_t st) {
     QAIA_CHECK(D >= 1 && D <= kMaxD, QAIA_INVALID_ARGUMENT, "input width must be in [1, 16]");
     QAIA_CHECK(B >= 1, QAIA_INVALID_ARGUMENT, "batch must be >= 1");
-    char *b = (char *)ws;
-    const size_t S = align256(sizeof(float) * (size_t)B * kH);
-    float *a1 = (float *)b, *g1 = (float *)(b + S), *a2 = (float *)(b + 2 * S), *g2 = (float *)(b + 3 * S);
-    float *dz1 = (float *)(b + 4 * S), *dz2 = (float *)(b + 5 * S), *dz3 = (float *)(b + 6 * S);
-    float *partial = (float *)(b + 6 * S + align256(sizeof(float) * (size_t)B));
-    hipLaunchKernelGGL(layer1_kernel, dim3(blocks_for(B * kH)), dim3(kB), 0, st, P, D, X, B, a1, g1);
-    hipLaunchKernelGGL(layer2_kernel, dim3(blocks_for(B * kH)), dim3(kB), 0, st, P, D, a1, B, a2, g2);
-    hipLaunchKernelGGL(head_kernel, dim3(blocks_for(B)), dim3(kB), 0, st, P, D, a2, g2, B, y, loss_logits,
-                       dz3, dz2);
-    hipLaunchKernelGGL(back1_kernel, dim3(blocks_for(B * kH)), dim3(kB), 0, st, P, D, dz2, g1, B, dz1);
-    const int64_t total = offsets(D).total, slices = grad_slices(B);
-    QAIA_CHECK(slices <= 65535, QAIA_INVALID_ARGUMENT, "batch too large");
-    hipLaunchKernelGGL(grads_partial_kernel, dim3(blocks_for(total), (unsigned)slices), dim3(kB), 0, st, D, X, a1,
-                       a2, dz1, dz2, dz3, B, partial);
-    hipLaunchKernelGGL(grads_reduce_kernel, dim3(blocks_for(total)), dim3(kB), 0, st, partial, (int)slices, total,
+    const int64_t total = offsets(D).total, blocks = grad_blocks(B);
+    QAIA_CHECK(blocks <= 65535, QAIA_INVALID_ARGUMENT, "batch too large");
+    float *partial = (float *)ws;
+    hipLaunchKernelGGL(mlp_fused_kernel<true>, dim3((unsigned)blocks), dim3(kB), 0, st, P, D, X, B, y, loss_logits,
+                       partial);
+    hipLaunchKernelGGL(grads_reduce_kernel, dim3(blocks_for(total)), dim3(kB), 0, st, partial, (int)blocks, total,
                        grad);
     QAIA_HIP(hipGetLastError());
 }
@@ -541,7 +615,8 @@ void launch_features(const int64_t *front, int64_t Pn, int m, const float *cands
 
 size_t topk_ws_bytes(int64_t N) {
     const size_t n = (size_t)std::max<int64_t>(N, 1);
-    return 2 * align256(sizeof(float) * n) + 2 * align256(sizeof(int64_t) * n) + align256(topk_temp(N));
+    return align256(sizeof(float) * n) + 2 * align256(sizeof(uint64_t) * n) + 2 * align256(sizeof(int32_t) * n) +
+           align256(4 * radix_hist_words(N)) + align256(4 * 256) + align256(64);
 }
 
 void launch_topk(const float *scores, int64_t N, int64_t k, float temperature, uint64_t seed, int64_t *idx_out,
@@ -553,27 +628,36 @@ void launch_topk(const float *scores, int64_t N, int64_t k, float temperature, u
                "temperature must be finite and >= 0");
     char *b = (char *)ws;
     size_t off = 0;
-    float *keys = (float *)(b + off);
-    off += align256(sizeof(float) * (size_t)N);
-    float *pert = (float *)(b + off);
-    off += align256(sizeof(float) * (size_t)N);
-    int64_t *iota = (int64_t *)(b + off);
-    off += align256(sizeof(int64_t) * (size_t)N);
-    int64_t *sorted = (int64_t *)(b + off);
-    off += align256(sizeof(int64_t) * (size_t)N);
-    size_t tb = topk_temp(N);
-    hipLaunchKernelGGL(iota64_kernel, dim3(blocks_for(N)), dim3(kB), 0, st, iota, N);
-    QAIA_HIP(hipGetLastError());
-    // stable: equal scores keep increasing index order
+    auto take = [&](size_t bytes) {
+        char *p = b + off;
+        off += align256(bytes);
+        return p;
+    };
+    float *pert = (float *)take(sizeof(float) * (size_t)N);
+    uint64_t *keyA = (uint64_t *)take(sizeof(uint64_t) * (size_t)N), *keyB = (uint64_t *)take(sizeof(uint64_t) * (size_t)N);
+    int32_t *valA = (int32_t *)take(sizeof(int32_t) * (size_t)N), *valB = (int32_t *)take(sizeof(int32_t) * (size_t)N);
+    uint32_t *hist = (uint32_t *)take(4 * radix_hist_words(N)), *total = (uint32_t *)take(4 * 256);
+    char *small = take(64);
+    int64_t *d_n = (int64_t *)small;
+    int32_t *d_passes = (int32_t *)(small + 8);
     const float *src = scores;
     if (temperature > 0.0f) {
         hipLaunchKernelGGL(gumbel_keys_kernel, dim3(blocks_for(N)), dim3(kB), 0, st, scores, N, 1.0f / temperature,
                            seed, pert);
         src = pert;
     }
-    QAIA_HIP(hipcub::DeviceRadixSort::SortPairsDescending(b + off, tb, src, keys, iota, sorted, (int)N, 0,
-                                                          32, st));
-    if (k > 0) QAIA_HIP(hipMemcpyAsync(idx_out, sorted, sizeof(int64_t) * (size_t)k, hipMemcpyDeviceToDevice, st));
+    // stable: equal scores keep increasing index order; four passes leave the result in A
+    hipLaunchKernelGGL(topk_key_kernel, dim3(blocks_for(N)), dim3(kB), 0, st, src, N, keyA, valA, d_n, d_passes);
+    QAIA_HIP(hipGetLastError());
+    for (int pass = 0; pass < 4; ++pass) {
+        const bool even = (pass & 1) == 0;
+        radix_pass(even ? keyA : keyB, even ? valA : valB, even ? keyB : keyA, even ? valB : valA, N, d_n, d_passes,
+                   pass, hist, total, st);
+    }
+    if (k > 0) {
+        hipLaunchKernelGGL(topk_out_kernel, dim3(blocks_for(k)), dim3(kB), 0, st, valA, k, idx_out);
+        QAIA_HIP(hipGetLastError());
+    }
 }
 
 void launch_labels(const int64_t *keep, const int64_t *num_keep, int64_t archive, int R, int64_t W,

@@ -42,25 +42,64 @@ def _params(D, seed=0):
 def test_forward_matches_oracle(q):
     D = 12
     _, vals, bits = _params(D, 1)
-    X = np.random.default_rng(2).standard_normal((1000, D)).astype(np.float32)
-    got = q.qaia_mlp_forward(_dev(bits.view(np.int16)), D, _dev(X)).cpu().numpy()
-    want, _ = omlp.forward(vals, X.astype(np.float64), D)
-    err = np.abs(got - want).max() / np.abs(want).max()
-    print(f"forward rel err {err:.2e}")
-    assert err < 1e-4
+    for N in (1000, 31, 65536):
+        X = np.random.default_rng(2).standard_normal((N, D)).astype(np.float32)
+        got = q.qaia_mlp_forward(_dev(bits.view(np.int16)), D, _dev(X)).cpu().numpy()
+        want, _ = omlp.forward(vals, X.astype(np.float64), D)
+        err = np.abs(got - want).max() / np.abs(want).max()
+        print(f"forward N={N} rel err {err:.2e}")
+        assert err < 1e-4
 
 
-@pytest.mark.parametrize("D,B", [(12, 1024), (11, 77)])
+def _grad_magnitude(vals, X, y, D):
+    """Running error magnitudes of the float32 forward and backward passes:
+    every quantity is replaced by the sum of the magnitudes of the terms it is
+    computed from, carried through the forward pass (so a pre-activation that
+    cancels keeps the size of its terms) and then through the backward pass
+    (first-order: a factor f(z) contributes |f'(z)| times the magnitude of z).
+    Per parameter this is the scale to which float32 rounding along the whole
+    chain is relative."""
+    W1, b1, W2, b2, w3, b3 = (np.abs(p) for p in omlp.unpack(vals, D))
+    z3, (X, z1, a1, z2, a2) = omlp.forward(vals, X, D)
+    B = X.shape[0]
+    phi = lambda z: np.exp(-0.5 * z * z) / np.sqrt(2.0 * np.pi)  # noqa: E731
+    g1, g2 = np.abs(omlp.gelu_grad(z1)), np.abs(omlp.gelu_grad(z2))
+    h1, h2 = np.abs(phi(z1) * (2.0 - z1 * z1)), np.abs(phi(z2) * (2.0 - z2 * z2))  # |gelu''|
+    Xm = np.abs(X)
+    Z1m = Xm @ W1.T + b1
+    A1m = g1 * Z1m + np.abs(a1)
+    Z2m = A1m @ W2.T + b2
+    A2m = g2 * Z2m + np.abs(a2)
+    Z3m = A2m @ w3 + b3[0]
+    sig = 1.0 / (1.0 + np.exp(-z3))
+    d3 = (sig * (1.0 - sig) * Z3m + np.abs(sig - y)) / B
+    d2 = np.outer(d3, w3) * (g2 + h2 * Z2m)
+    d1 = (d2 @ W2) * (g1 + h1 * Z1m)
+    parts = [d1.T @ Xm, d1.sum(axis=0), d2.T @ A1m, d2.sum(axis=0), A2m.T @ d3, np.array([d3.sum()])]
+    return np.concatenate([p.ravel() for p in parts])
+
+
+@pytest.mark.parametrize("D,B", [(12, 1024), (11, 77), (12, 1), (16, 4097)])
 def test_backward_matches_oracle(q, D, B):
+    """Element by element: |g - g_ref| <= 1e-3 |g_ref| + 1e-5 S, with S the
+    element's running error magnitude (_grad_magnitude).  1e-5 is about the
+    float32 unit roundoff times the longest chain of operations (a 128-term
+    sum plus the 12-term input layer and the activations), so an element that
+    cancels to nearly zero is held to float32 rounding of its terms instead of
+    a relative bound no float32 evaluation can meet."""
     _, vals, bits = _params(D, 3)
     rng = np.random.default_rng(4)
     X = rng.standard_normal((B, D)).astype(np.float32)
     y = rng.integers(0, 2, size=B).astype(np.float32)
     got = q.qaia_mlp_backward(_dev(bits.view(np.int16)), D, _dev(X), _dev(y)).cpu().numpy()
     want = omlp.backward(vals, X.astype(np.float64), y.astype(np.float64), D)
-    err = np.abs(got - want).max() / np.abs(want).max()
-    print(f"backward rel err (D={D}, B={B}) {err:.2e}")
-    assert err < 1e-3
+    scale = _grad_magnitude(vals, X.astype(np.float64), y.astype(np.float64), D)
+    bound = 1e-3 * np.abs(want) + 1e-5 * scale
+    excess = np.abs(got - want) / bound
+    worst = int(np.argmax(excess))
+    print(f"backward (D={D}, B={B}): worst element {worst} at {excess[worst]:.3f} of its bound, "
+          f"max relative error {np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-30)):.2e}")
+    assert excess.max() <= 1.0
     # the output-bias gradient is mean(sigmoid(z) - y)
     assert got[-1] == pytest.approx(want[-1], rel=1e-3, abs=1e-6)
 
@@ -110,6 +149,10 @@ def test_topk_gather_and_labels(q):
     assert np.array_equal(idx, np.argsort(-scores, kind="stable")[:1024])
     ties = np.repeat(np.arange(10, dtype=np.float32), 7)
     assert np.array_equal(q.qaia_topk(_dev(ties), 9).cpu().numpy(), np.argsort(-ties, kind="stable")[:9])
+    # signed zeros tie, infinities at the ends, every item returned
+    mix = np.array([0.0, -0.0, -np.inf, 1.5, -0.0, np.inf, -2.0, 0.0, 1.5, -np.inf], np.float32)
+    mix = np.tile(mix, 1000)
+    assert np.array_equal(q.qaia_topk(_dev(mix), len(mix)).cpu().numpy(), np.argsort(-mix, kind="stable"))
     # gather of float rows
     src = rng.standard_normal((100, 6)).astype(np.float32)
     pick = np.array([5, 0, 99, 42], np.int64)

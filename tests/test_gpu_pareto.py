@@ -37,6 +37,39 @@ def test_filter_matches_oracle_random(q, M, m, lo, hi):
     assert np.array_equal(_filter(q, obj), oracle.pareto_filter(obj))
 
 
+def test_filter_near_front_pool_with_duplicates(q):
+    """A pool shaped like a sampler's: 100 000 rows, each a copy of one of 300
+    mutually non-dominated vectors lowered by a small random amount in some
+    objectives (zero for about a third of the rows, so every front vector
+    occurs many times, first at a random position).  Most rows are removed by
+    the pivot pruning; the result is compared with the oracle bit for bit."""
+    rng = np.random.default_rng(21)
+    m = 4
+    base = rng.integers(0, 2**20, size=(300, m - 1))
+    front = np.concatenate([base, (3 * 2**20 - base.sum(axis=1))[:, None]], axis=1).astype(np.int64)
+    pick = rng.integers(0, len(front), size=100_000)
+    drop = rng.integers(0, 16, size=(len(pick), m)) * (rng.random((len(pick), m)) < 0.3)
+    drop[rng.random(len(pick)) < 0.35] = 0
+    obj = front[pick] - drop
+    got = _filter(q, obj)
+    assert len(got) == 300
+    assert np.array_equal(got, oracle.pareto_filter(obj))
+
+
+def test_filter_wide_ranges_and_ties(q):
+    """Objective ranges of 1, 9, 33 and 64 bits (one to eight digit passes of
+    the sort) with many ties, and a pool whose rows all lie on the front."""
+    rng = np.random.default_rng(22)
+    M = 50_000
+    obj = np.stack([rng.integers(0, 2, M), rng.integers(-256, 256, M), rng.integers(0, 2**33, M),
+                    rng.integers(-2**63, 2**63 - 1, M, dtype=np.int64)], axis=1).astype(np.int64)
+    obj[rng.integers(0, M, 500)] = obj[rng.integers(0, M, 500)]
+    assert np.array_equal(_filter(q, obj), oracle.pareto_filter(obj))
+    a = rng.permutation(40_000).astype(np.int64)
+    line = np.stack([a, 40_000 - a], axis=1)
+    assert np.array_equal(_filter(q, line), np.arange(40_000))
+
+
 def test_filter_empty(q):
     assert _filter(q, np.zeros((0, 3), np.int64)).size == 0
 
