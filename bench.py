@@ -205,72 +205,65 @@ def measured_peaks(q, torch, reps=3):
     return res
 
 
-def learned_form(q, wl, torch, budget_rounds=40, ref_factor=10, max_seconds=240.0):
-    """Time to a reference hypervolume on the 42-node, 4-objective instance.
-    Every loop runs rounds of 1024 weight vectors x 256 replicas, filters
-    against its archive and computes the exact hypervolume.  Contenders:
-    plain FP32 bSB, 2000 steps, uniform Dirichlet vectors (the baseline); the
-    learned proposer (1024 of 65536 scored candidates, same sampler);
-    noise-injected bSB with the paper's short schedule (50 steps, dt 1,
-    alpha 0.1, Eq. 10), uniform vectors; and the learned proposer feeding that
-    short noise-injected sampler.  The plain loop runs budget_rounds
-    rounds; the others run for the same wall time.  References: the plain
-    loop's final hypervolume (time_to_ref), and the union hypervolume of a
-    plain loop at ref_factor times the budget (fractions)."""
-    from paper_2604_26477_amd.learned import ProposerLoop, run_until
+def _race(q, prob, base, ref_rounds, contenders, seeds, cap=1.6):
+    """One time-to-reference race: the reference hypervolume is the final
+    archive of the plain FP32 loop (uniform Dirichlet vectors, seed 777) after
+    ref_rounds rounds (10x the budget); every contender runs, per seed, until
+    its archive reaches it or cap x the reference's rounds / seconds pass,
+    and is judged afterwards (learned.time_to_hypervolume)."""
+    from paper_2604_26477_amd.learned import ProposerLoop, reference_run, time_to_hypervolume
+    ProposerLoop(prob, learned=False, seed=5, judge="record", **base).round()  # warm-up
+    ref_hv, ref_s, ref_front = reference_run(prob, ref_rounds, 777, **base)
+    out = {"reference": {"rounds": ref_rounds, "seconds": ref_s, "front": ref_front, "hv": str(ref_hv)},
+           "seeds": list(seeds), "contenders": {}}
+    for name, extra in contenders:
+        kw = dict(base)
+        kw.update(extra)
+        ProposerLoop(prob, seed=5, judge="record", **kw).round()  # kernels built on first use, caches
+        runs = []
+        for sd in seeds:
+            loop = ProposerLoop(prob, seed=sd, judge="record", **kw)
+            runs.append(time_to_hypervolume(loop, ref_hv, int(ref_rounds * cap) + 1, max_seconds=ref_s * cap))
+        secs = [r["seconds"] for r in runs if r["reached"]]
+        rnds = [r["rounds"] for r in runs if r["reached"]]
+        out["contenders"][name] = {
+            "reached": f"{len(secs)}/{len(runs)}",
+            "seconds_median": float(np.median(secs)) if len(secs) == len(runs) else None,
+            "seconds_min": min(secs) if secs else None, "seconds_max": max(secs) if secs else None,
+            "rounds_median": float(np.median(rnds)) if len(rnds) == len(runs) else None,
+            "seconds_per_round": float(np.median([r["seconds_run"] / r["rounds_run"] for r in runs])),
+            "runs": runs}
+    return out
+
+
+def learned_form(q, wl, torch, seeds=(11, 12, 13)):
+    """Time to a reference hypervolume (the benchmark spec's third target and the
+    learned form's measurement).  Both workloads run rounds of 1024 weight
+    vectors, each sampled, filtered against the loop's archive and labelled;
+    the reference is the plain FP32 loop at 10x its budget.
+      42-node m = 4 (sparse, 256 replicas, 2000 steps): plain FP32 bSB, the
+        learned proposer with the same sampler, and noise-injected bSB with the
+        paper's short schedule (50 steps, dt 1, alpha 0.1, Eq. 10) as its own
+        contender;
+      complete N = 512 m = 4 (dense, 8 replicas, 1000 steps): plain FP32 bSB on
+        the matrix cores, discrete SB on the BF16 path with uniform vectors, and
+        the benchmark spec form: the learned proposer with discrete SB on the BF16
+        path (each round one batched launch of all its weight vectors x
+        replicas)."""
+    out = {}
     inst = wl.instance_42_node(4, seed=2000)
     prob = q.problem_from_instance(inst, 0)
-    kw = dict(R=256, steps=2000, n_cand=65536, n_sel=1024)
-    ref_loop = ProposerLoop(prob, learned=False, seed=777, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(budget_rounds * ref_factor):
-        ref_loop.round()
-        if time.perf_counter() - t0 > max_seconds / 2:
-            break
-    ref_seconds = time.perf_counter() - t0  # the plain loop reaches the reference here, by construction
-    ref_rounds = ref_loop.round_no
-    ref_hv = ref_loop.history[-1]["hv"]
-    out = {"workload": "42-node degree<=3, m=4; rounds of 1024 weight vectors x 256 replicas; plain: bSB FP32 "
-                       "2000 steps dt 0.5, uniform Dirichlet; learned: 1024 of 65536 scored candidates; "
-                       "ni_bsb_short: bSB 50 steps dt 1.0 alpha 0.1, uniform Dirichlet; learned_ni_bsb_short: the "
-                       "learned proposer with that sampler",
-           "reference": {"rounds": ref_rounds, "hv": str(ref_hv), "front": ref_loop.history[-1]["front"],
-                         "seconds": ref_seconds},
-           "budget_rounds": budget_rounds}
-    contenders = (("plain_fp32_uniform", dict(learned=False)),
-                  ("learned_proposer", dict(learned=True)),
-                  ("ni_bsb_short", dict(learned=False, steps=50, dt=1.0, noise_alpha=0.1)),
-                  ("learned_ni_bsb_short", dict(learned=True, steps=50, dt=1.0, noise_alpha=0.1)))
-    budget_s = None
-    for name, extra in contenders:
-        args = dict(kw)
-        args.update(extra)
-        ProposerLoop(prob, seed=5, **args).round()  # warm-up: kernels built on first use, caches
-        loop = ProposerLoop(prob, seed=11, **args)
-        if budget_s is None:
-            rounds, secs, reached = run_until(loop, ref_hv, budget_rounds)
-            budget_s = secs
-        else:
-            rounds, secs, reached = run_until(loop, ref_hv, 100000, max_seconds=budget_s)
-        hist = loop.history
-        frac = [h["hv"] / ref_hv for h in hist]
-        out[name] = {"reached_reference": reached, "rounds": rounds, "seconds": secs,
-                     "seconds_per_round": secs / max(rounds, 1), "final_hv_fraction": frac[-1],
-                     "final_front": hist[-1]["front"], "hv_by_round": [str(h["hv"]) for h in hist],
-                     "elapsed_by_round": list(np.cumsum([h["seconds"] for h in hist]))}
-    # times to the reference and to the plain run's final hypervolume
-    target = int(out["plain_fp32_uniform"]["hv_by_round"][-1])
-
-    def first_time(r, level):
-        for hv, el in zip(r["hv_by_round"], r["elapsed_by_round"]):
-            if int(hv) >= level:
-                return el
-        return None
-    for name, _ in contenders:
-        r = out[name]
-        r["seconds_to_reference_hv"] = first_time(r, ref_hv)
-        r["seconds_to_plain_final_hv"] = first_time(r, target)
+    out["n42_m4"] = _race(q, prob, dict(R=256, steps=2000, n_cand=65536, n_sel=1024), 400,
+                          (("plain_fp32_bsb", dict(learned=False)),
+                           ("learned_fp32_bsb", dict(learned=True)),
+                           ("ni_bsb_short", dict(learned=False, steps=50, dt=1.0, noise_alpha=0.1))), seeds)
+    inst = wl.random_instance(512, 4, "complete", seed=5000)
+    prob = q.problem_from_instance(inst, 0)
+    out["complete512_m4"] = _race(q, prob, dict(R=8, steps=1000, n_cand=65536, n_sel=1024, variant="bsb",
+                                                precision="fp32"), 20,
+                                  (("plain_fp32_bsb", dict(learned=False)),
+                                   ("uniform_dsb_bf16", dict(learned=False, variant="dsb", precision="bf16")),
+                                   ("learned_dsb_bf16", dict(learned=True, variant="dsb", precision="bf16"))), seeds)
     return out
 
 
@@ -689,20 +682,20 @@ def main():
             result["forms"]["table2"] = table2_form(q, wl, torch)
         if args.noise_form:
             result["forms"]["noise"] = noise_form(q, wl, torch)
-        forms = {k: lf[k]["seconds_to_reference_hv"]
-                 for k in ("learned_proposer", "ni_bsb_short", "learned_ni_bsb_short")}
-        reached = {k: v for k, v in forms.items() if v is not None}
-        chosen = min(reached, key=reached.get) if reached else None
+        dense = lf["complete512_m4"]["contenders"]
+        sparse = lf["n42_m4"]["contenders"]
         result["time_to_ref_hypervolume"] = {
-            "reference": f"hypervolume of the plain FP32 uniform-Dirichlet loop after {lf['reference']['rounds']} "
-                         f"rounds ({lf['reference']['rounds'] // lf['budget_rounds']}x the budget)",
-            "forms_s": forms,
-            "chosen_form": chosen,
-            "chosen_form_s": forms[chosen] if chosen else None,
-            "plain_fp32_s": lf["reference"]["seconds"],
-            "to_plain_final_hv_s": {k: lf[k]["seconds_to_plain_final_hv"]
-                                    for k in ("plain_fp32_uniform", "learned_proposer", "ni_bsb_short",
-                                              "learned_ni_bsb_short")},
+            "reference": "hypervolume of the plain FP32 uniform-Dirichlet loop at 10x its budget (seed 777); "
+                         "medians over seeds 11, 12, 13",
+            "chosen_form": "learned proposer + discrete SB on the BF16 matrix-core path (complete N=512, m=4)",
+            "chosen_form_s": dense["learned_dsb_bf16"]["seconds_median"],
+            "plain_fp32_s": dense["plain_fp32_bsb"]["seconds_median"],
+            "speedup": (dense["plain_fp32_bsb"]["seconds_median"] / dense["learned_dsb_bf16"]["seconds_median"]
+                        if dense["plain_fp32_bsb"]["seconds_median"] and dense["learned_dsb_bf16"]["seconds_median"]
+                        else None),
+            "complete512_m4_s": {k: v["seconds_median"] for k, v in dense.items()},
+            "n42_m4_s": {k: v["seconds_median"] for k, v in sparse.items()},
+            "n42_m4_rounds": {k: v["rounds_median"] for k, v in sparse.items()},
         }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(inst, c_host, R, T)

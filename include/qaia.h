@@ -385,6 +385,21 @@ int32_t qaia_mlp_adam(float *master, uint16_t *params, float *moment1, float *mo
                       const float *grad, int64_t count, int32_t step, float lr, float beta1,
                       float beta2, float eps, void *hip_stream);
 
+int32_t qaia_mlp_train_workspace_bytes(int32_t in_dim, int64_t n, int32_t batch, size_t *bytes);
+/* The proposer's training loop of one round: `steps` Adam steps (beta1 0.9,
+ * beta2 0.999, eps 1e-8, step counter from first_step >= 1) of the mean
+ * binary cross-entropy on minibatches of B = min(batch, n) rows of
+ * X [n][in_dim] / labels [n].  Minibatch t is window t mod floor(n / B) of a
+ * random permutation of the rows, drawn at the start of every pass as the
+ * top-n of n equal scores with Gumbel noise (qaia_topk, temperature 1, seed
+ * seed + 104729 * (first_step + t)).  master / moment1 / moment2: DEVICE
+ * fp32 [param count], params: DEVICE bf16 bits, updated in place.  All work
+ * is queued on the stream without host waits. */
+int32_t qaia_mlp_train(float *master, uint16_t *params, float *moment1, float *moment2, int32_t in_dim,
+                       const float *X, const float *labels, int64_t n, int32_t batch, int32_t steps,
+                       int32_t first_step, float lr, uint64_t seed, void *workspace, size_t ws_bytes,
+                       void *hip_stream);
+
 int32_t qaia_front_features_workspace_bytes(int64_t P, int32_t m, size_t *bytes);
 /* MLP input rows feat [N][m + 8] = (c, f1..f8): c followed by eight
  * features of candidate c against the archive front

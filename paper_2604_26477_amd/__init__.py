@@ -77,6 +77,9 @@ _SIGS = {
     "qaia_mlp_backward": (_i32, [_P, _i32, _P, _P, _i64, _P, _P, _P, _sz, _P]),
     "qaia_mlp_adam": (_i32, [_P, _P, _P, _P, _P, _i64, _i32, C.c_float, C.c_float, C.c_float,
                              C.c_float, _P]),
+    "qaia_mlp_train_workspace_bytes": (_i32, [_i32, _i64, _i32, C.POINTER(_sz)]),
+    "qaia_mlp_train": (_i32, [_P, _P, _P, _P, _i32, _P, _P, _i64, _i32, _i32, _i32, C.c_float, C.c_uint64, _P, _sz,
+                              _P]),
     "qaia_front_features_workspace_bytes": (_i32, [_i64, _i32, C.POINTER(_sz)]),
     "qaia_front_features": (_i32, [_P, _i64, _i32, _P, _i64, _P, _i64, _P, _i64, _P, _P, _sz, _P]),
     "qaia_topk_workspace_bytes": (_i32, [_i64, C.POINTER(_sz)]),
@@ -492,6 +495,21 @@ def qaia_mlp_adam(master, params, moment1, moment2, grad, step, lr=1e-3, beta1=0
                   eps=1e-8, stream=None):
     _check(_lib.qaia_mlp_adam(_ptr(master), _ptr(params), _ptr(moment1), _ptr(moment2), _ptr(grad),
                               master.numel(), step, lr, beta1, beta2, eps, _stream(stream)))
+
+
+def qaia_mlp_train(master, params, moment1, moment2, in_dim: int, X: torch.Tensor, labels: torch.Tensor,
+                   batch: int, steps: int, first_step: int, lr: float = 1e-3, seed: int = 0, workspace=None,
+                   stream=None):
+    """One round's Adam steps on minibatches of (X [n, in_dim], labels [n]); see qaia.h."""
+    n = X.shape[0]
+    b = C.c_size_t()
+    _check(_lib.qaia_mlp_train_workspace_bytes(in_dim, n, batch, C.byref(b)))
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(b.value, dtype=torch.uint8, device=X.device)
+    _check(_lib.qaia_mlp_train(_ptr(master), _ptr(params), _ptr(moment1), _ptr(moment2), in_dim, _ptr(X),
+                               _ptr(labels), n, batch, steps, first_step, lr, seed & (2**64 - 1), _ptr(workspace),
+                               workspace.numel(), _stream(stream)))
+    return workspace
 
 
 def qaia_front_features(front: torch.Tensor, cands: torch.Tensor, hits: torch.Tensor, misses: torch.Tensor,

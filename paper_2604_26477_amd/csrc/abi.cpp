@@ -436,6 +436,31 @@ int32_t qaia_mlp_backward(const uint16_t *params, int32_t in_dim, const float *X
     });
 }
 
+int32_t qaia_mlp_train_workspace_bytes(int32_t in_dim, int64_t n, int32_t batch, size_t *bytes) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(bytes != nullptr, QAIA_INVALID_ARGUMENT, "null argument");
+        QAIA_CHECK(in_dim >= 1 && in_dim <= 16 && n >= 1 && batch >= 1, QAIA_INVALID_ARGUMENT,
+                   "need 1 <= in_dim <= 16, n >= 1, batch >= 1");
+        *bytes = mlp_train_ws_bytes(in_dim, n, batch);
+        return QAIA_OK;
+    });
+}
+
+int32_t qaia_mlp_train(float *master, uint16_t *params, float *moment1, float *moment2, int32_t in_dim,
+                       const float *X, const float *labels, int64_t n, int32_t batch, int32_t steps,
+                       int32_t first_step, float lr, uint64_t seed, void *workspace, size_t ws_bytes,
+                       void *hip_stream) {
+    return guarded([&]() -> int32_t {
+        QAIA_CHECK(master && params && moment1 && moment2 && X && labels && workspace, QAIA_INVALID_ARGUMENT,
+                   "null buffer");
+        QAIA_CHECK(lr > 0.0f && std::isfinite(lr), QAIA_INVALID_ARGUMENT, "lr must be finite and > 0");
+        QAIA_CHECK(n < (int64_t(1) << 31), QAIA_INVALID_ARGUMENT, "n must be < 2^31");
+        launch_mlp_train(master, params, moment1, moment2, in_dim, X, labels, n, batch, steps, first_step, lr, seed,
+                         workspace, ws_bytes, (hipStream_t)hip_stream);
+        return QAIA_OK;
+    });
+}
+
 int32_t qaia_mlp_adam(float *master, uint16_t *params, float *moment1, float *moment2, const float *grad,
                       int64_t count, int32_t step, float lr, float beta1, float beta2, float eps,
                       void *hip_stream) {

@@ -216,6 +216,10 @@ void launch_mlp_forward(const uint16_t *P, int D, const float *X, int64_t N, flo
                         hipStream_t st);
 void launch_mlp_backward(const uint16_t *P, int D, const float *X, const float *y, int64_t B,
                          float *grad, float *logits, void *ws, hipStream_t st);
+size_t mlp_train_ws_bytes(int D, int64_t n, int64_t batch);
+void launch_mlp_train(float *master, uint16_t *P, float *m1, float *m2, int D, const float *X, const float *y,
+                      int64_t n, int64_t batch, int steps, int first_step, float lr, uint64_t seed, void *ws,
+                      size_t ws_bytes, hipStream_t st);
 void launch_adam(float *master, uint16_t *P, float *m, float *v, const float *g, int64_t n, int step,
                  float lr, float b1, float b2, float eps, hipStream_t st);
 size_t features_ws_bytes(int64_t Pn, int m);

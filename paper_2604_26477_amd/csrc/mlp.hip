@@ -297,23 +297,37 @@ __global__ void front_norm_kernel(const int64_t *__restrict__ front, int64_t Pn,
 }
 
 // per front point: distance to the nearest other point and the fraction of
-// points within 0.05 (itself included)
-__global__ void front_local_kernel(const float *__restrict__ yh, int64_t Pn, int m,
-                                   float *__restrict__ nn, float *__restrict__ frac) {
+// points within 0.05 (itself included); the front passes through LDS in
+// chunks shared by the block
+constexpr int kLChunk = 2048;
+
+__global__ __launch_bounds__(kB) void front_local_kernel(const float *__restrict__ yh, int64_t Pn, int m,
+                                                         float *__restrict__ nn, float *__restrict__ frac) {
+    __shared__ float stage[kLChunk * 8];
     const int64_t j = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (j >= Pn) return;
+    const bool active = j < Pn;
+    float me[8];
+    for (int k = 0; k < m; ++k) me[k] = active ? yh[j * m + k] : 0.0f;
     float best = INFINITY;
     int64_t close = 0;
-    for (int64_t i = 0; i < Pn; ++i) {
-        float d2 = 0.0f;
-        for (int k = 0; k < m; ++k) {
-            const float d = yh[i * m + k] - yh[j * m + k];
-            d2 = fmaf(d, d, d2);
-        }
-        const float d = sqrtf(d2);
-        if (i != j && d < best) best = d;
-        if (d <= 0.05f) ++close;
+    for (int64_t base = 0; base < Pn; base += kLChunk) {
+        const int cnt = (int)(Pn - base < kLChunk ? Pn - base : kLChunk);
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt * m; i += kB) stage[i] = yh[base * m + i];
+        __syncthreads();
+        if (active)
+            for (int i = 0; i < cnt; ++i) {
+                float d2 = 0.0f;
+                for (int k = 0; k < m; ++k) {
+                    const float d = stage[i * m + k] - me[k];
+                    d2 = fmaf(d, d, d2);
+                }
+                const float d = sqrtf(d2);
+                if (base + i != j && d < best) best = d;
+                if (d <= 0.05f) ++close;
+            }
     }
+    if (!active) return;
     nn[j] = Pn > 1 ? best : 0.0f;
     frac[j] = (float)close / (float)Pn;
 }
@@ -567,6 +581,78 @@ void launch_adam(float *master, uint16_t *P, float *m, float *v, const float *g,
     hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(kB), 0, st, master, P, m, v, g, n, lr, b1,
                        b2, eps, c1, c2);
     QAIA_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- training loop
+
+namespace {
+__global__ void train_count_kernel(int64_t *c, int64_t n) {
+    if (threadIdx.x == 0) *c = n;
+}
+}  // namespace
+
+struct TrainLayout {
+    size_t zeros, perm, xp, yp, grad, count, bw, tk, total;
+};
+
+static TrainLayout train_layout(int D, int64_t n, int64_t B) {
+    TrainLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t nz = (size_t)std::max<int64_t>(n, 1);
+    L.zeros = take(sizeof(float) * nz);
+    L.perm = take(sizeof(int64_t) * nz);
+    L.xp = take(sizeof(float) * nz * (size_t)D);
+    L.yp = take(sizeof(float) * nz);
+    L.grad = take(sizeof(float) * (size_t)offsets(D).total);
+    L.count = take(sizeof(int64_t));
+    L.bw = take(mlp_backward_ws_bytes(D, B));
+    L.tk = take(topk_ws_bytes(n));
+    L.total = off;
+    return L;
+}
+
+size_t mlp_train_ws_bytes(int D, int64_t n, int64_t batch) {
+    return train_layout(std::max(D, 1), std::max<int64_t>(n, 1), std::min(std::max<int64_t>(batch, 1), std::max<int64_t>(n, 1))).total;
+}
+
+// `steps` Adam steps on minibatches of min(batch, n) rows: minibatch t is
+// window t mod (n / B) of a random permutation of the rows, drawn afresh at
+// the start of every pass as the Gumbel top-k of n equal scores with seed
+// `seed + 104729 * (first_step + t)`; the Adam step counter runs from
+// first_step.
+void launch_mlp_train(float *master, uint16_t *P, float *m1, float *m2, int D, const float *X, const float *y,
+                      int64_t n, int64_t batch, int steps, int first_step, float lr, uint64_t seed, void *ws,
+                      size_t ws_bytes, hipStream_t st) {
+    QAIA_CHECK(D >= 1 && D <= kMaxD, QAIA_INVALID_ARGUMENT, "input width must be in [1, 16]");
+    QAIA_CHECK(n >= 1 && batch >= 1 && steps >= 0 && first_step >= 1, QAIA_INVALID_ARGUMENT,
+               "need n >= 1, batch >= 1, steps >= 0, first_step >= 1");
+    const int64_t B = std::min(batch, n), per_pass = n / B;
+    const TrainLayout L = train_layout(D, n, B);
+    QAIA_CHECK(ws_bytes >= L.total, QAIA_WORKSPACE_TOO_SMALL, "training workspace too small");
+    char *b = (char *)ws;
+    float *zeros = (float *)(b + L.zeros), *xp = (float *)(b + L.xp), *yp = (float *)(b + L.yp);
+    float *grad = (float *)(b + L.grad);
+    int64_t *perm = (int64_t *)(b + L.perm), *cnt = (int64_t *)(b + L.count);
+    const int64_t total = offsets(D).total;
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(blocks_for(n)), dim3(kB), 0, st, zeros, n);
+    hipLaunchKernelGGL(train_count_kernel, dim3(1), dim3(64), 0, st, cnt, n);
+    QAIA_HIP(hipGetLastError());
+    for (int t = 0; t < steps; ++t) {
+        const int64_t win = t % per_pass;
+        if (win == 0) {
+            launch_topk(zeros, n, n, 1.0f, seed + 104729ull * (uint64_t)(first_step + t), perm, b + L.tk,
+                        topk_ws_bytes(n), st);
+            launch_gather_rows((const uint32_t *)X, D, perm, cnt, n, (uint32_t *)xp, st);
+            launch_gather_rows((const uint32_t *)y, 1, perm, cnt, n, (uint32_t *)yp, st);
+        }
+        launch_mlp_backward(P, D, xp + win * B * D, yp + win * B, B, grad, nullptr, b + L.bw, st);
+        launch_adam(master, P, m1, m2, grad, total, first_step + t, lr, 0.9f, 0.999f, 1e-8f, st);
+    }
 }
 
 size_t features_ws_bytes(int64_t Pn, int m) {

@@ -52,6 +52,11 @@ constexpr int kDirs = 256;          // pivot directions
 constexpr int kSampleRows = 1 << 17;  // rows of the pivot sample (at most)
 constexpr int kCandBlocks = 128;     // blocks of the pivot search
 
+unsigned grid_for_n(int64_t n, int per) {
+    const int64_t g = (n + per - 1) / per;
+    return (unsigned)(g > 1 ? g : 1);
+}
+
 __global__ void fill_u8_kernel(uint8_t *p, int64_t n, uint8_t v) {
     int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (i < n) p[i] = v;
@@ -392,59 +397,95 @@ __global__ void unique_flag_kernel(const int64_t *__restrict__ obj, int m, const
     flag[i] = f;
 }
 
-// chunk-local pass over the unique vectors uidx[0..U)
-__global__ __launch_bounds__(kB) void chunk_nd_kernel(const int64_t *__restrict__ obj, int m,
-                                                      const int32_t *__restrict__ uidx,
+// Chunk pass over the list[0 .. U) of distinct vectors in lexicographic
+// order: within each chunk of 1024, flag[p] = 0 when an earlier vector of the
+// chunk is >= it componentwise.  Each thread holds four rows in registers and
+// walks the chunk's earlier rows once for all four (one broadcast LDS read of
+// a row serves four comparisons), stopping when all four are dominated.
+template <int MM>
+__global__ __launch_bounds__(kB) void chunk_nd_kernel(const int64_t *__restrict__ obj,
+                                                      const int32_t *__restrict__ list,
                                                       const int64_t *__restrict__ d_U, uint8_t *__restrict__ flag) {
-    __shared__ int64_t v[8][kChunk];
+    constexpr int RPT = kChunk / kB;  // rows per thread
+    __shared__ int64_t v[kChunk][MM];
     const int64_t U = *d_U;
     const int64_t c0 = (int64_t)blockIdx.x * kChunk;
     if (c0 >= U) return;
     const int len = (int)((U - c0) < kChunk ? (U - c0) : kChunk);
     for (int p = threadIdx.x; p < len; p += kB) {
-        const int64_t *y = obj + (int64_t)uidx[c0 + p] * m;
-        for (int k = 0; k < m; ++k) v[k][p] = y[k];
+        const int64_t *y = obj + (int64_t)list[c0 + p] * MM;
+#pragma unroll
+        for (int k = 0; k < MM; ++k) v[p][k] = y[k];
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < len; j += kB) {
-        int64_t yj[8];
-        for (int k = 0; k < m; ++k) yj[k] = v[k][j];
-        bool dom = false;
-        for (int i = 0; i < j && !dom; ++i) {
-            bool ge = true;
-            for (int k = 0; k < m; ++k) ge &= v[k][i] >= yj[k];
-            dom = ge;
+    int64_t y[RPT][MM];
+    bool dom[RPT];
+    int last = 0;  // rows before the thread's last live row
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int j = r * kB + threadIdx.x;
+        dom[r] = j >= len;
+        if (j < len) last = j;
+#pragma unroll
+        for (int k = 0; k < MM; ++k) y[r][k] = j < len ? v[j][k] : 0;
+    }
+    for (int i = 0; i < last; ++i) {
+        int64_t w[MM];
+#pragma unroll
+        for (int k = 0; k < MM; ++k) w[k] = v[i][k];
+        bool done = true;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            if (!dom[r] && i < r * kB + (int)threadIdx.x) {
+                bool ge = true;
+#pragma unroll
+                for (int k = 0; k < MM; ++k) ge &= w[k] >= y[r][k];
+                dom[r] = ge;
+            }
+            done &= dom[r];
         }
-        flag[c0 + j] = dom ? 0 : 1;
+        if (done) break;
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int j = r * kB + threadIdx.x;
+        if (j < len) flag[c0 + j] = dom[r] ? 0 : 1;
     }
 }
 
-// global pass over the chunk survivors sidx[0..S)
-__global__ __launch_bounds__(kB) void global_nd_kernel(const int64_t *__restrict__ obj, int m,
+// Survivor pass over sidx[0 .. S) (chunk survivors, lexicographic order): a
+// survivor is kept when no earlier survivor is >= it componentwise.  Tiles of
+// 256 earlier survivors pass through LDS; a block stops once all its rows are
+// dominated.
+template <int MM>
+__global__ __launch_bounds__(kB) void global_nd_kernel(const int64_t *__restrict__ obj,
                                                        const int32_t *__restrict__ sidx,
                                                        const int64_t *__restrict__ d_S,
                                                        uint8_t *__restrict__ keep) {
-    __shared__ int64_t v[8][kB];
+    __shared__ int64_t v[kB][MM];
     const int64_t S = *d_S;
     const int64_t j0 = (int64_t)blockIdx.x * kB;
     if (j0 >= S) return;
     const int64_t j = j0 + threadIdx.x;
     const bool mine = j < S;
-    int64_t yj[8];
-    for (int k = 0; k < m; ++k) yj[k] = mine ? obj[(int64_t)sidx[j] * m + k] : 0;
+    int64_t yj[MM];
+#pragma unroll
+    for (int k = 0; k < MM; ++k) yj[k] = mine ? obj[(int64_t)sidx[j] * MM + k] : 0;
     bool alive = mine;
     for (int64_t i0 = 0; i0 < j0 + kB && i0 < S; i0 += kB) {
         const int64_t ii = i0 + threadIdx.x;
         if (ii < S) {
-            const int64_t *y = obj + (int64_t)sidx[ii] * m;
-            for (int k = 0; k < m; ++k) v[k][threadIdx.x] = y[k];
+            const int64_t *y = obj + (int64_t)sidx[ii] * MM;
+#pragma unroll
+            for (int k = 0; k < MM; ++k) v[threadIdx.x][k] = y[k];
         }
         __syncthreads();
         if (alive) {
-            const int64_t lim = (j - i0) < kB ? (j - i0) : kB;  // earlier survivors only
-            for (int64_t t = 0; t < lim; ++t) {
+            const int lim = (int)((j - i0) < kB ? (j - i0) : kB);  // earlier survivors only
+            for (int t = 0; t < lim; ++t) {
                 bool ge = true;
-                for (int k = 0; k < m; ++k) ge &= v[k][t] >= yj[k];
+#pragma unroll
+                for (int k = 0; k < MM; ++k) ge &= v[t][k] >= yj[k];
                 if (ge) {
                     alive = false;
                     break;
@@ -454,6 +495,37 @@ __global__ __launch_bounds__(kB) void global_nd_kernel(const int64_t *__restrict
         if (!__syncthreads_or(alive ? 1 : 0)) break;
     }
     if (alive) keep[sidx[j]] = 1;
+}
+
+template <int MM>
+void launch_nd_passes(const int64_t *obj, const int32_t *list, const int64_t *d_n, int64_t cap, uint8_t *flag,
+                      int32_t *sidx, int64_t *d_s, uint32_t *cnt, uint8_t *keep, hipStream_t st) {
+    hipLaunchKernelGGL(chunk_nd_kernel<MM>, dim3(grid_for_n(cap, kChunk)), dim3(kB), 0, st, obj, list, d_n, flag);
+    QAIA_HIP(hipGetLastError());
+    select_flagged<int32_t, int32_t>(list, flag, d_n, cap, sidx, d_s, cnt, nullptr, st);
+    hipLaunchKernelGGL(global_nd_kernel<MM>, dim3(grid_for_n(cap, kB)), dim3(kB), 0, st, obj, sidx, d_s, keep);
+    QAIA_HIP(hipGetLastError());
+}
+
+// The non-dominated rows of the lexicographically ordered distinct vectors
+// list[0 .. n) (n = *d_n <= cap): keep[row] = 1 (keep is not cleared here).
+// sidx / d_s receive the chunk survivors.
+void nd_passes(const int64_t *obj, int32_t m, const int32_t *list, const int64_t *d_n, int64_t cap, uint8_t *flag,
+               int32_t *sidx, int64_t *d_s, uint32_t *cnt, uint8_t *keep, hipStream_t st) {
+    switch (m) {
+#define QAIA_ND(MM) \
+    case MM: launch_nd_passes<MM>(obj, list, d_n, cap, flag, sidx, d_s, cnt, keep, st); break;
+        QAIA_ND(1)
+        QAIA_ND(2)
+        QAIA_ND(3)
+        QAIA_ND(4)
+        QAIA_ND(5)
+        QAIA_ND(6)
+        QAIA_ND(7)
+        QAIA_ND(8)
+#undef QAIA_ND
+        default: throw Error{QAIA_UNSUPPORTED, "the filter supports 1..8 objectives"};
+    }
 }
 
 // ranks: rows of the current list that entered rank r leave the list
@@ -724,11 +796,7 @@ void launch_pareto(const int64_t *obj, int64_t M, int32_t m, int64_t *keep_idx, 
     prune_and_sort(obj, RowList{v.uidx, v.counts + 0, 0}, M, m, true, v, st);
     const int64_t *d_S = v.counts + 2;
     // 3. the sorted survivors are distinct: chunk pass, survivor pass, ascending emission
-    hipLaunchKernelGGL(chunk_nd_kernel, dim3(grid_for(M, kChunk)), dim3(kB), 0, st, obj, m, v.sorted, d_S, v.flag);
-    QAIA_HIP(hipGetLastError());
-    select_flagged<int32_t, int32_t>(v.sorted, v.flag, d_S, M, v.sidx, v.counts + 1, v.cnt, nullptr, st);
-    hipLaunchKernelGGL(global_nd_kernel, dim3(grid_for(M)), dim3(kB), 0, st, obj, m, v.sidx, v.counts + 1, v.keep);
-    QAIA_HIP(hipGetLastError());
+    nd_passes(obj, m, v.sorted, d_S, M, v.flag, v.sidx, v.counts + 1, v.cnt, v.keep, st);
     select_flagged<int32_t, int64_t>(nullptr, v.keep, nullptr, M, keep_idx, num_keep, v.cnt, nullptr, st);
 }
 
@@ -786,12 +854,8 @@ int32_t launch_pareto_ranks(const int64_t *obj, int64_t M, int32_t m, int32_t ma
             QAIA_HIP(hipGetLastError());
             break;
         }
-        hipLaunchKernelGGL(chunk_nd_kernel, dim3(grid_for(n, kChunk)), dim3(kB), 0, st, obj, m, list, v.counts + 0,
-                           v.flag);
-        QAIA_HIP(hipGetLastError());
-        // the list length n is known on the host here; counts[0] is rewritten below
-        select_flagged<int32_t, int32_t>(list, v.flag, nullptr, n, v.sidx, v.counts + 1, v.cnt, nullptr, st);
-        hipLaunchKernelGGL(global_nd_kernel, dim3(grid_for(n)), dim3(kB), 0, st, obj, m, v.sidx, v.counts + 1, v.keep);
+        // the list length n (= counts[0]) is also known on the host here
+        nd_passes(obj, m, list, v.counts + 0, n, v.flag, v.sidx, v.counts + 1, v.cnt, v.keep, st);
         hipLaunchKernelGGL(rank_assign_kernel, dim3(grid_for(n)), dim3(kB), 0, st, list, v.counts + 0, v.keep, r, rank,
                            rem);
         QAIA_HIP(hipGetLastError());

@@ -124,6 +124,41 @@ def test_adam_matches_oracle(q):
     assert np.array_equal(params.cpu().numpy().view(np.uint16), _bf16_round(got)[1])
 
 
+def test_training_loop_equals_its_steps(q):
+    """qaia_mlp_train (the whole round's loop queued by the library) equals the
+    same steps made one by one through qaia_topk, qaia_gather_rows,
+    qaia_mlp_backward and qaia_mlp_adam, bit for bit, across a permutation
+    boundary (n = 3000 rows, minibatches of 1024: two windows per pass)."""
+    import torch
+    D, n, B, steps, first = 12, 3000, 1024, 5, 7
+    theta, _, bits = _params(D, 9)
+    rng = np.random.default_rng(10)
+    X = _dev(rng.standard_normal((n, D)).astype(np.float32))
+    y = _dev(rng.integers(0, 2, size=n).astype(np.float32))
+    m1 = _dev((rng.standard_normal(theta.size) * 1e-3).astype(np.float32))
+    m2 = _dev((np.abs(rng.standard_normal(theta.size)) * 1e-5).astype(np.float32))
+    A = [_dev(theta.copy()), _dev(bits.view(np.int16).copy()), m1.clone(), m2.clone()]
+    Bv = [_dev(theta.copy()), _dev(bits.view(np.int16).copy()), m1.clone(), m2.clone()]
+    q.qaia_mlp_train(A[0], A[1], A[2], A[3], D, X, y, B, steps, first, lr=1e-3, seed=1234)
+    per_pass = n // B
+    cnt = _dev(np.array([n], np.int64))
+    zeros = torch.zeros(n, dtype=torch.float32, device="cuda")
+    for t in range(steps):
+        win = t % per_pass
+        if win == 0:
+            perm = q.qaia_topk(zeros, n, temperature=1.0, seed=1234 + 104729 * (first + t))
+            xp = torch.empty((n, D), dtype=torch.float32, device="cuda")
+            yp = torch.empty(n, dtype=torch.float32, device="cuda")
+            q.qaia_gather_rows(X, perm, cnt, xp, n)
+            q.qaia_gather_rows(y, perm, cnt, yp, n)
+        g = q.qaia_mlp_backward(Bv[1], D, xp[win * B:(win + 1) * B], yp[win * B:(win + 1) * B])
+        q.qaia_mlp_adam(Bv[0], Bv[1], Bv[2], Bv[3], g, first + t, lr=1e-3)
+    torch.cuda.synchronize()
+    for a, b in zip(A, Bv):
+        assert torch.equal(a, b)
+    assert not torch.equal(A[0], _dev(theta))
+
+
 def test_features_match_oracle(q):
     rng = np.random.default_rng(6)
     m = 4
