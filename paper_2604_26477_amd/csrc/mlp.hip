@@ -87,7 +87,22 @@ __global__ __launch_bounds__(kB) void mlp_fused_kernel(const uint16_t *__restric
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5, lr = lane & 31;
     const int64_t s0 = (int64_t)blockIdx.x * kS;
     const int ns = (int)(N - s0 < kS ? N - s0 : kS);
-    for (int i = tid; i < kH * kH; i += kB) w2[(i >> 7) * kP + (i & (kH - 1))] = bf16_to_f32(P[o.W2 + i]);
+    if ((((uintptr_t)(P + o.W2)) & 15) == 0) {
+        // eight bf16 weights per 16-byte load (W2 starts at 128 (D + 1) elements)
+        const uint4 *src = (const uint4 *)(P + o.W2);
+        for (int i = tid; i < kH * kH / 8; i += kB) {
+            const uint4 w = src[i];
+            float *dst = w2 + ((i * 8) >> 7) * kP + ((i * 8) & (kH - 1));
+            const uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                dst[2 * e] = __uint_as_float(u[e] << 16);
+                dst[2 * e + 1] = __uint_as_float(u[e] & 0xFFFF0000u);
+            }
+        }
+    } else {
+        for (int i = tid; i < kH * kH; i += kB) w2[(i >> 7) * kP + (i & (kH - 1))] = bf16_to_f32(P[o.W2 + i]);
+    }
     for (int i = tid; i < kH * kMaxD; i += kB) {
         const int h = i / kMaxD, d = i % kMaxD;
         w1[h][d] = d < D ? bf16_to_f32(P[o.W1 + (int64_t)h * D + d]) : 0.0f;

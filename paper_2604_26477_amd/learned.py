@@ -147,11 +147,12 @@ class ProposerLoop:
         """Whether the network takes the larger share of the picks.  It does
         unless, over the last rounds, its picks found new non-dominated points
         significantly less often than the uniform picks (one-sided
-        two-proportion z-test, z < -2), or the labels carry no contrast (fewer
-        than 2 % or more than 98 % positive: nothing to learn, e.g. when almost
-        every sample is a new point), in which case the uniform Dirichlet
-        fallback takes the larger share and the network keeps the smaller one
-        (which keeps measuring it)."""
+        two-proportion z-test, z < -2), or the labels are saturated (more than
+        98 % positive: nothing to learn when almost every weight vector finds
+        a new point), in which case the uniform Dirichlet fallback takes the
+        larger share and the network keeps the smaller one (which keeps
+        measuring it).  Rare positives are not a reason to fall back: finding
+        them is what the network is for."""
         n1 = sum(a[0] for a in self.arms)
         h1 = sum(a[1] for a in self.arms)
         n2 = sum(a[2] for a in self.arms)
@@ -159,7 +160,9 @@ class ProposerLoop:
         if n1 == 0 or n2 == 0:
             return True
         p = (h1 + h2) / (n1 + n2)
-        if p < 0.02 or p > 0.98:
+        if p == 0.0:
+            return True
+        if p > 0.98:
             return False
         se = (p * (1.0 - p) * (1.0 / n1 + 1.0 / n2)) ** 0.5
         return (h1 / n1 - h2 / n2) >= -2.0 * se

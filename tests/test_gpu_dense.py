@@ -128,6 +128,26 @@ def test_low_precision_reproduces_fp32_bitwise_when_exact(q, path):
         assert np.array_equal(outs[prec][1], outs["fp32"][1]), prec
 
 
+def test_staged_tile_order_at_scale_matches_register_tiles(q):
+    """At 512 spins x 8192 columns the staged kernel deals its tiles to the
+    XCDs in 4 x 8 patches; with exact weights both dense kernels compute exact
+    fields, so their spins and cuts agree bit for bit in every precision."""
+    import torch
+    inst = _small_int_instance(512, 3, seed=61)
+    c = wl.dirichlet_weights(1024, 3, 62)
+    prob = q.problem_from_instance(inst)
+    for prec in ("fp32", "bf16", "fp8"):
+        got = {}
+        for path in DENSE_PATHS:
+            s = q.make_schedule("dsb", precision=prec, steps=150, dt=0.5, seed=63, path=path)
+            sp, ob, _ = q.qaia_sample(prob, _dev(c), 8, s)
+            torch.cuda.synchronize()
+            got[path] = (sp.cpu().numpy(), ob.cpu().numpy())
+        a, b = (got[p_] for p_ in DENSE_PATHS)
+        assert np.array_equal(a[0], b[0]), prec
+        assert np.array_equal(a[1], b[1]), prec
+
+
 # ---------------------------------------------------------------- exact cuts
 
 @pytest.mark.parametrize("path", DENSE_PATHS)
