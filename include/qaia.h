@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define QAIA_ABI_VERSION 1
+#define QAIA_ABI_VERSION 2
 
 /* status codes */
 #define QAIA_OK 0
@@ -330,28 +330,36 @@ typedef struct qaia_batch_item {
     int32_t path;         /* QAIA_PATH_*; AUTO = the planner's default */
     uint64_t *spins;      /* DEVICE [W*R][ceil(n/64)] */
     int64_t *obj;         /* DEVICE [W*R][m] */
+    int32_t tile;         /* kernel tile knob; 0 = the family's default.  QAIA_PATH_SPARSE_LDS:
+                           * replicas per 256-lane block (their spins must fit 16 per lane,
+                           * replicas * n <= 4096); other families: must be 0 */
+    int32_t reserved;     /* 0 */
 } qaia_batch_item;
 
 int32_t qaia_sample_batch_workspace_bytes(const qaia_batch_item *items, int32_t count,
                                           const qaia_schedule *s, size_t *bytes);
-/* Samples every item with one graph launch: per-item weight preparation, one
- * launch of the batched generic sparse kernel for all items on that path
- * (their whole step loops on chip), each item on a generated kernel as its
- * own launch, and for the dense items one grouped step launch per step over
- * all their tiles, the step loop captured in the graph.  items: HOST array,
- * buffers DEVICE, all on one device.  Errors as qaia_sample; the call
- * synchronises the host with the caller's stream once (descriptor upload). */
+/* Samples every item with one graph launch: per-item weight preparation; for
+ * the items on the generic sparse kernel one persistent launch per kernel
+ * shape whose blocks take (item, replica tile) work units from a device queue
+ * (items in decreasing cost per tile, each unit's whole step loop on chip);
+ * each item on a generated kernel as its own launch; for the dense items one
+ * grouped step launch per step over all their tiles, the step loop captured
+ * in the graph.  items: HOST array, buffers DEVICE, all on one device.
+ * Errors as qaia_sample; the call synchronises the host with the caller's
+ * stream once (descriptor upload). */
 int32_t qaia_sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedule *s,
                           void *workspace, size_t ws_bytes, void *hip_stream);
 
 int32_t qaia_plan_autotune_workspace_bytes(const qaia_batch_item *items, int32_t count,
                                            const qaia_schedule *s, int32_t probe_steps, size_t *bytes);
-/* Autotuner: for every item, times each kernel family available to it
- * (generated one-replica-per-lane kernel, generic one-spin-per-lane kernel,
- * matrix-core tiles) on probe_steps steps of its real shape, and writes the
- * fastest into items[i].path (HOST, in place); est_seconds (HOST [count], may
- * be NULL) receives the probe time scaled to s->steps.  The items' outputs
- * are overwritten.  Synchronises the host with hip_stream. */
+/* Autotuner: for every item, times each kernel family and tile available to
+ * it (generated one-replica-per-lane kernel; generic one-spin-per-lane kernel
+ * with 1x, 2x and 4x its default replicas per block; 64 x 128 register and
+ * 128 x 128 LDS-staged matrix-core tiles) on probe_steps steps of its real
+ * shape, and writes the fastest into items[i].path and items[i].tile (HOST,
+ * in place); est_seconds (HOST [count], may be NULL) receives the probe time
+ * scaled to s->steps.  The items' outputs are overwritten.  Synchronises the
+ * host with hip_stream. */
 int32_t qaia_plan_autotune(qaia_batch_item *items, int32_t count, const qaia_schedule *s,
                            int32_t probe_steps, double *est_seconds, void *workspace, size_t ws_bytes,
                            void *hip_stream);

@@ -41,7 +41,8 @@ class qaia_schedule(C.Structure):
 
 class qaia_batch_item(C.Structure):
     _fields_ = [("problem", C.c_void_p), ("weights", C.c_void_p), ("W", C.c_int64), ("R", C.c_int32),
-                ("path", C.c_int32), ("spins", C.c_void_p), ("obj", C.c_void_p)]
+                ("path", C.c_int32), ("spins", C.c_void_p), ("obj", C.c_void_p), ("tile", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _P, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
@@ -603,16 +604,17 @@ class BatchItem:
     """One item of a ragged batch: a problem, device weights [W, m], replicas R,
     an optional forced path, and its outputs (allocated when not given)."""
 
-    def __init__(self, problem: Problem, weights: torch.Tensor, R: int, path: str = "auto", spins=None, obj=None):
+    def __init__(self, problem: Problem, weights: torch.Tensor, R: int, path: str = "auto", spins=None, obj=None,
+                 tile: int = 0):
         W = weights.shape[0]
-        self.problem, self.weights, self.R, self.path = problem, weights, R, path
+        self.problem, self.weights, self.R, self.path, self.tile = problem, weights, R, path, tile
         self.spins = _dev_tensor(spins, torch.int64, (W * R, problem.words), problem.torch_device)
         self.obj = _dev_tensor(obj, torch.int64, (W * R, problem.m), problem.torch_device)
 
     def c_struct(self):
         return qaia_batch_item(self.problem.handle.value if isinstance(self.problem.handle, C.c_void_p)
                                else self.problem.handle, self.weights.data_ptr(), self.weights.shape[0], self.R,
-                               PATHS[self.path], self.spins.data_ptr(), self.obj.data_ptr())
+                               PATHS[self.path], self.spins.data_ptr(), self.obj.data_ptr(), self.tile, 0)
 
 
 def _items_array(items):
@@ -642,8 +644,9 @@ def qaia_sample_batch(items, s: qaia_schedule, workspace=None, stream=None):
 
 
 def qaia_plan_autotune(items, s: qaia_schedule, probe_steps: int = 20, stream=None):
-    """Times each kernel family per item; sets item.path to the fastest and
-    returns the estimated seconds per item at s.steps."""
+    """Times each kernel family and tile per item; sets item.path and
+    item.tile to the fastest and returns the estimated seconds per item at
+    s.steps."""
     arr = _items_array(items)
     b = C.c_size_t()
     _check(_lib.qaia_plan_autotune_workspace_bytes(C.cast(arr, C.c_void_p), len(items), C.byref(s), probe_steps,
@@ -655,4 +658,5 @@ def qaia_plan_autotune(items, s: qaia_schedule, probe_steps: int = 20, stream=No
     inv = {v: k for k, v in PATHS.items()}
     for i, it in enumerate(items):
         it.path = inv[arr[i].path]
+        it.tile = arr[i].tile
     return est

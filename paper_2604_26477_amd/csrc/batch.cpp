@@ -5,18 +5,21 @@
 // Execution of qaia_sample_batch, captured once into a hipGraph on a private
 // stream and launched as one graph:
 //   - per item: workspace header reset and weight preparation;
-//   - branch A (forked stream): every item on the generic sparse kernel runs
-//     in ONE launch of the batched sparse kernel (blocks map to items through
-//     a prefix table; each item's whole T-step loop stays on chip), and items
-//     on the per-graph generated kernels run their own launches;
+//   - branch A (forked stream): the items on the generic sparse kernel run in
+//     one persistent launch per kernel shape: the grid is what the GPU holds
+//     at once, and blocks take (item, replica tile) work units from a device
+//     queue, items in decreasing cost per unit (each unit's whole T-step loop
+//     stays on chip); items on the per-graph generated kernels run their own
+//     launches;
 //   - branch B: dense items are set up, then each of the T steps is ONE launch
 //     of the grouped dense step kernel over the tiles of all dense items, then
 //     each dense item is read out and evaluated;
 //   - the branches join and the caller's stream waits for the graph.
 // The kernel families differ in their tile shape and replicas per wave: one
 // replica per lane (64 replicas per wave, generated kernel), one spin per
-// lane (floor(256/n) replicas per 256-lane block, generic kernel), or 64-spin
-// x 128-replica matrix-core tiles (dense kernel).
+// lane (floor(256/n) replicas per 256-lane block by default, or the item's
+// tile knob: more replicas per block put several spins on each lane, generic
+// kernel), or 64- / 128-spin x 128-replica matrix-core tiles (dense kernels).
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -69,9 +72,17 @@ void check_path(const Problem &p, const qaia_schedule &s, int path) {
     }
 }
 
+void check_tile(const Problem &p, int path, int tile, int64_t rows) {
+    QAIA_CHECK(tile >= 0, QAIA_INVALID_ARGUMENT, "tile must be >= 0");
+    if (tile == 0) return;
+    QAIA_CHECK(path == QAIA_PATH_SPARSE_LDS, QAIA_INVALID_ARGUMENT,
+               "a tile knob applies to the generic sparse kernel only");
+    (void)sparse_lds_shape(p, std::max<int64_t>(rows, 1), tile);  // throws past 16 spins per lane
+}
+
 struct BatchLayout {
     std::vector<ItemPlan> items;
-    size_t jobs_off = 0, total = 0;
+    size_t jobs_off = 0, queue_off = 0, total = 0;
     int n_sparse = 0, n_dense = 0;
 };
 
@@ -88,6 +99,7 @@ BatchLayout batch_layout(const qaia_batch_item *items, int32_t count, const qaia
                    "item " + std::to_string(i) + ": null buffer");
         const int path = it.path == QAIA_PATH_AUTO ? default_path(p, s) : it.path;
         check_path(p, s, path);
+        check_tile(p, path, it.tile, it.W * (int64_t)it.R);
         ItemPlan ip{&p, path, sample_ws_layout(p, it.W, it.R, s, !is_dense_path(path)), off};
         if (is_dense_path(path)) {
             dense_ws_extend(p, it.W, it.R, s, ip.L);
@@ -103,6 +115,9 @@ BatchLayout batch_layout(const qaia_batch_item *items, int32_t count, const qaia
     off += align256(sizeof(DenseJob) * (size_t)std::max(B.n_dense, 1));
     // start tables: one per generic-sparse shape class and one per dense group
     off += (kSparseClasses + kDenseGroups) * align256(sizeof(int64_t) * (size_t)(count + 1));
+    // work-queue counters of the persistent sparse launches, one per shape class
+    B.queue_off = off;
+    off += align256(sizeof(unsigned long long) * kSparseClasses);
     B.total = off;
     return B;
 }
@@ -173,6 +188,12 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
     // generic-sparse jobs grouped by kernel shape (maximum degree class x spins
     // per lane), so that no item runs with a larger unrolled neighbour loop or
     // more spins per lane than its own graph needs
+    struct SparseCand {
+        SparseJob job;
+        int64_t units;
+        double cost;  // work per unit: replicas x spins x maximum degree (the step loop's length is common)
+    };
+    std::vector<SparseCand> scand[kSparseClasses];
     std::vector<SparseJob> sjobs[kSparseClasses];
     std::vector<int64_t> sstart[kSparseClasses];
     for (auto &v : sstart) v.assign(1, 0);
@@ -191,10 +212,10 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
         void *iws = base + ip.base;
         if (it.W * it.R == 0) continue;
         if (ip.path == QAIA_PATH_SPARSE_LDS) {
-            const SparseShape sh = sparse_lds_shape(*ip.p, it.W * (int64_t)it.R);
+            const SparseShape sh = sparse_lds_shape(*ip.p, it.W * (int64_t)it.R, it.tile);
             const int c = sparse_class(sh);
-            sjobs[c].push_back(sparse_job(*ip.p, it.W, it.R, s, iws, ip.L, it.spins, it.obj, nullptr, 0));
-            sstart[c].push_back(sstart[c].back() + sh.blocks);
+            scand[c].push_back({sparse_job(*ip.p, it.W, it.R, s, iws, ip.L, it.spins, it.obj, nullptr, 0, it.tile),
+                                sh.blocks, (double)sh.rpb * ip.p->n * std::max(ip.p->max_degree, 1)});
             smaxdeg[c] = sh.maxdeg;
             snpt[c] = sh.npt;
             shmem[c] = std::max(shmem[c], sh.shmem);
@@ -206,6 +227,17 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
             dstart[g].push_back(dstart[g].back() + (g != 0 ? (tiles + 7) / 8 * 8 : tiles));
         }
     }
+    // queue order inside a shape class: decreasing work per unit, so the long
+    // units start first and the short ones fill the tail
+    for (int c = 0; c < kSparseClasses; ++c) {
+        std::stable_sort(scand[c].begin(), scand[c].end(),
+                         [](const SparseCand &a, const SparseCand &b) { return a.cost > b.cost; });
+        for (const SparseCand &sc : scand[c]) {
+            sjobs[c].push_back(sc.job);
+            sstart[c].push_back(sstart[c].back() + sc.units);
+        }
+    }
+    unsigned long long *queues = (unsigned long long *)(base + B.queue_off);
     char *jobs = base + B.jobs_off;
     SparseJob *d_sjobs = (SparseJob *)jobs;
     DenseJob *d_djobs = (DenseJob *)(jobs + align256(sizeof(SparseJob) * (size_t)std::max(B.n_sparse, 1)));
@@ -274,8 +306,8 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
         // branch A: sparse items
         for (int c = 0; c < kSparseClasses; ++c)
             if (!sjobs[c].empty())
-                launch_sparse_lds_jobs(nullptr, d_sjobs_c[c], (int)sjobs[c].size(), d_sstart_c[c], sstart[c].back(),
-                                       smaxdeg[c], snpt[c], shmem[c], dsb, ps.b);
+                launch_sparse_lds_queue(d_sjobs_c[c], (int)sjobs[c].size(), d_sstart_c[c], sstart[c].back(),
+                                        smaxdeg[c], snpt[c], shmem[c], dsb, queues + c, ps.b);
         for (int i = 0; i < count; ++i) {
             const ItemPlan &ip = B.items[i];
             const qaia_batch_item &it = items[i];
@@ -339,7 +371,10 @@ void sample_batch(const qaia_batch_item *items, int32_t count, const qaia_schedu
 void autotune(qaia_batch_item *items, int32_t count, const qaia_schedule &s, int32_t probe_steps,
               double *est_seconds, void *ws, size_t ws_bytes, hipStream_t st) {
     QAIA_CHECK(probe_steps >= 1, QAIA_INVALID_ARGUMENT, "probe_steps must be >= 1");
-    for (int i = 0; i < count; ++i) items[i].path = QAIA_PATH_AUTO;
+    for (int i = 0; i < count; ++i) {
+        items[i].path = QAIA_PATH_AUTO;
+        items[i].tile = 0;
+    }
     // a layout with every item on its default path bounds nothing: size each
     // probe by its own single-item layout, placed at the workspace start
     qaia_schedule ps = s;
@@ -353,7 +388,7 @@ void autotune(qaia_batch_item *items, int32_t count, const qaia_schedule &s, int
         const Problem &p = *reinterpret_cast<const Problem *>(it.problem);
         DeviceGuard g(p.device);
         double best = 1e300;
-        int best_path = default_path(p, s);
+        int best_path = default_path(p, s), best_tile = 0;
         for (int path : {QAIA_PATH_SPARSE_REG, QAIA_PATH_SPARSE_LDS, QAIA_PATH_DENSE, QAIA_PATH_DENSE_STAGED}) {
             try {
                 check_path(p, s, path);
@@ -364,26 +399,39 @@ void autotune(qaia_batch_item *items, int32_t count, const qaia_schedule &s, int
             if (is_dense_path(path)) dense_ws_extend(p, it.W, it.R, ps, L);
             if (L.total > ws_bytes) continue;
             if (it.W * it.R == 0) break;
-            QAIA_HIP(hipEventRecord(e0, st));
-            launch_prep(p, it.weights, it.W, ps, ws, L, st);
-            if (is_dense_path(path))
-                launch_dense(p, it.weights, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0,
-                             path == QAIA_PATH_DENSE_STAGED, st);
-            else if (path == QAIA_PATH_SPARSE_REG)
-                launch_sparse_reg(p, s.variant, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0, st);
-            else
-                launch_sparse_lds(p, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0, st);
-            QAIA_HIP(hipEventRecord(e1, st));
-            QAIA_HIP(hipEventSynchronize(e1));
-            float ms = 0.0f;
-            QAIA_HIP(hipEventElapsedTime(&ms, e0, e1));
-            const double est = ms * 1e-3 * (double)s.steps / (double)probe_steps;
-            if (est < best) {
-                best = est;
-                best_path = path;
+            // tiles of the family: the generic sparse kernel at 1x, 2x and 4x
+            // its default replicas per block (more spins per lane), others one
+            std::vector<int> tiles{0};
+            if (path == QAIA_PATH_SPARSE_LDS) {
+                const int base_rpb = sparse_lds_default_rpb(p);
+                for (int k : {2, 4})
+                    if ((int64_t)base_rpb * k * p.n <= 16 * 256 && base_rpb * k <= it.W * (int64_t)it.R)
+                        tiles.push_back(base_rpb * k);
+            }
+            for (int tile : tiles) {
+                QAIA_HIP(hipEventRecord(e0, st));
+                launch_prep(p, it.weights, it.W, ps, ws, L, st);
+                if (is_dense_path(path))
+                    launch_dense(p, it.weights, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0,
+                                 path == QAIA_PATH_DENSE_STAGED, st);
+                else if (path == QAIA_PATH_SPARSE_REG)
+                    launch_sparse_reg(p, s.variant, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0, st);
+                else
+                    launch_sparse_lds(p, it.W, it.R, ps, ws, L, it.spins, it.obj, nullptr, 0, st, tile);
+                QAIA_HIP(hipEventRecord(e1, st));
+                QAIA_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                QAIA_HIP(hipEventElapsedTime(&ms, e0, e1));
+                const double est = ms * 1e-3 * (double)s.steps / (double)probe_steps;
+                if (est < best) {
+                    best = est;
+                    best_path = path;
+                    best_tile = tile;
+                }
             }
         }
         it.path = best_path;
+        it.tile = best_tile;
         if (est_seconds) est_seconds[i] = best < 1e299 ? best : 0.0;
     }
     (void)hipEventDestroy(e0);

@@ -165,11 +165,18 @@ void launch_prep(const Problem &p, const float *weights, int64_t W, const qaia_s
                  void *ws, const WsLayout &L, hipStream_t st);
 void launch_sparse_lds(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws,
                        const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
-                       int32_t trace_steps, hipStream_t st);
+                       int32_t trace_steps, hipStream_t st, int rpb = 0);
 bool sparse_lds_supported(const Problem &p, std::string *why);
-SparseShape sparse_lds_shape(const Problem &p, int64_t rows);
+// rpb: replicas per block, 0 = the default floor(256 / n) (UNSUPPORTED past 16 spins per lane)
+int sparse_lds_default_rpb(const Problem &p);
+SparseShape sparse_lds_shape(const Problem &p, int64_t rows, int rpb = 0);
 SparseJob sparse_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws,
-                     const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace, int32_t trace_steps);
+                     const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace, int32_t trace_steps,
+                     int rpb = 0);
+// persistent launch over `count` device jobs whose work units are numbered by
+// the prefix `starts` (units in total); `queue` is a device counter it resets
+void launch_sparse_lds_queue(const SparseJob *jobs, int count, const int64_t *starts, int64_t units, int maxdeg,
+                             int npt, size_t shmem, bool dsb, unsigned long long *queue, hipStream_t st);
 // single: one job by value; otherwise `count` device jobs with block prefix `starts`
 void launch_sparse_lds_jobs(const SparseJob *single, const SparseJob *jobs, int count, const int64_t *starts,
                             int64_t blocks, int maxdeg, int npt, size_t shmem, bool dsb, hipStream_t st);

@@ -299,6 +299,39 @@ __global__ __launch_bounds__(kBlock) void sparse_lds_batch_kernel(const SparseJo
     sparse_lds_body<MAXDEG, NPT, DSB>(j, b - block_start[i], xs);
 }
 
+// Persistent ragged batch: the grid is what the GPU holds at once, and each
+// block takes work units (one block's worth of one job's replicas) from a
+// device queue until it is empty; unit u belongs to job i with
+// block_start[i] <= u < block_start[i + 1] (jobs in decreasing cost per unit,
+// so the long units start first).
+template <int MAXDEG, int NPT, bool DSB>
+__global__ __launch_bounds__(kBlock) void sparse_lds_queue_kernel(const SparseJob *__restrict__ jobs, int count,
+                                                                  const int64_t *__restrict__ block_start,
+                                                                  int64_t units,
+                                                                  unsigned long long *__restrict__ queue) {
+    extern __shared__ float xs[];
+    __shared__ int64_t unit_sh;
+    while (true) {
+        if (threadIdx.x == 0) unit_sh = (int64_t)atomicAdd(queue, 1ull);
+        __syncthreads();
+        const int64_t u = unit_sh;
+        __syncthreads();  // every thread has read unit_sh (and the previous unit's LDS use is over)
+        if (u >= units) break;
+        int lo = 0, hi = count - 1;  // the last job whose start is <= u
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (block_start[mid] <= u) lo = mid;
+            else hi = mid - 1;
+        }
+        const SparseJob j = jobs[lo];
+        sparse_lds_body<MAXDEG, NPT, DSB>(j, u - block_start[lo], xs);
+    }
+}
+
+__global__ void queue_reset_kernel(unsigned long long *q) {
+    if (threadIdx.x == 0) *q = 0ull;
+}
+
 bool sparse_lds_supported(const Problem &p, std::string *why) {
     if (p.max_degree > 32) {
         if (why) *why = "maximum degree above 32 (use the dense path)";
@@ -315,9 +348,13 @@ bool sparse_lds_supported(const Problem &p, std::string *why) {
     return true;
 }
 
-SparseShape sparse_lds_shape(const Problem &p, int64_t rows) {
+int sparse_lds_default_rpb(const Problem &p) { return p.n <= kBlock ? kBlock / p.n : 1; }
+
+SparseShape sparse_lds_shape(const Problem &p, int64_t rows, int rpb) {
     SparseShape sh;
-    sh.rpb = p.n <= kBlock ? kBlock / p.n : 1;
+    sh.rpb = rpb > 0 ? rpb : sparse_lds_default_rpb(p);
+    QAIA_CHECK((int64_t)sh.rpb * p.n <= 16 * kBlock, QAIA_UNSUPPORTED,
+               "replicas per block x spins exceeds 16 spins per lane");
     const int span = sh.rpb * p.n;
     sh.npt = 1;
     while (sh.npt * kBlock < span) sh.npt <<= 1;
@@ -328,7 +365,8 @@ SparseShape sparse_lds_shape(const Problem &p, int64_t rows) {
 }
 
 SparseJob sparse_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws,
-                     const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace, int32_t trace_steps) {
+                     const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace, int32_t trace_steps,
+                     int rpb) {
     char *b = (char *)ws;
     SparseJob j{};
     j.n = p.n;
@@ -338,7 +376,7 @@ SparseJob sparse_job(const Problem &p, int64_t W, int32_t R, const qaia_schedule
     j.R = R;
     j.T = s.steps;
     j.rows = W * (int64_t)R;
-    j.rpb = sparse_lds_shape(p, j.rows).rpb;
+    j.rpb = sparse_lds_shape(p, j.rows, rpb).rpb;
     j.rowptr = p.d_rowptr;
     j.col = p.d_col;
     j.eid = p.d_eid;
@@ -369,6 +407,51 @@ static void launch_one(const SparseJob *single, const SparseJob *jobs, int count
     else
         hipLaunchKernelGGL((sparse_lds_batch_kernel<MAXDEG, NPT, DSB>), dim3((unsigned)blocks), dim3(kBlock),
                            shmem, st, jobs, count, starts);
+}
+
+template <int MAXDEG, int NPT, bool DSB>
+static void launch_queue(const SparseJob *jobs, int count, const int64_t *starts, int64_t units, size_t shmem,
+                         unsigned long long *queue, hipStream_t st) {
+    auto kern = sparse_lds_queue_kernel<MAXDEG, NPT, DSB>;
+    int per_cu = 0, dev = 0, cus = 0;
+    QAIA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, shmem));
+    QAIA_HIP(hipGetDevice(&dev));
+    QAIA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t grid = std::min<int64_t>(units, (int64_t)std::max(per_cu, 1) * cus);
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, queue);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kBlock), shmem, st, jobs, count, starts, units, queue);
+}
+
+template <int MAXDEG>
+static void dispatch_queue(int npt, bool dsb, const SparseJob *jobs, int count, const int64_t *starts, int64_t units,
+                           size_t shmem, unsigned long long *queue, hipStream_t st) {
+#define QAIA_NPT(N)                                                                       \
+    case N:                                                                               \
+        if (dsb) launch_queue<MAXDEG, N, true>(jobs, count, starts, units, shmem, queue, st);  \
+        else launch_queue<MAXDEG, N, false>(jobs, count, starts, units, shmem, queue, st);     \
+        break;
+    switch (npt) {
+        QAIA_NPT(1)
+        QAIA_NPT(2)
+        QAIA_NPT(4)
+        QAIA_NPT(8)
+        QAIA_NPT(16)
+        default:
+            throw Error{QAIA_UNSUPPORTED, "spins per lane out of range"};
+    }
+#undef QAIA_NPT
+}
+
+void launch_sparse_lds_queue(const SparseJob *jobs, int count, const int64_t *starts, int64_t units, int maxdeg,
+                             int npt, size_t shmem, bool dsb, unsigned long long *queue, hipStream_t st) {
+    if (units == 0) return;
+    switch (maxdeg) {
+        case 4: dispatch_queue<4>(npt, dsb, jobs, count, starts, units, shmem, queue, st); break;
+        case 8: dispatch_queue<8>(npt, dsb, jobs, count, starts, units, shmem, queue, st); break;
+        case 16: dispatch_queue<16>(npt, dsb, jobs, count, starts, units, shmem, queue, st); break;
+        default: dispatch_queue<32>(npt, dsb, jobs, count, starts, units, shmem, queue, st); break;
+    }
+    QAIA_HIP(hipGetLastError());
 }
 
 template <int MAXDEG>
@@ -406,13 +489,13 @@ void launch_sparse_lds_jobs(const SparseJob *single, const SparseJob *jobs, int 
 
 void launch_sparse_lds(const Problem &p, int64_t W, int32_t R, const qaia_schedule &s, void *ws,
                        const WsLayout &L, uint64_t *spins, int64_t *obj, float *trace,
-                       int32_t trace_steps, hipStream_t st) {
+                       int32_t trace_steps, hipStream_t st, int rpb) {
     std::string why;
     QAIA_CHECK(sparse_lds_supported(p, &why), QAIA_UNSUPPORTED, "sparse LDS path: " + why);
     const int64_t rows = W * (int64_t)R;
     if (rows == 0) return;
-    const SparseShape sh = sparse_lds_shape(p, rows);
-    const SparseJob j = sparse_job(p, W, R, s, ws, L, spins, obj, trace, trace_steps);
+    const SparseShape sh = sparse_lds_shape(p, rows, rpb);
+    const SparseJob j = sparse_job(p, W, R, s, ws, L, spins, obj, trace, trace_steps, rpb);
     launch_sparse_lds_jobs(&j, nullptr, 1, nullptr, sh.blocks, sh.maxdeg, sh.npt, sh.shmem,
                            s.variant == QAIA_DSB, st);
 }

@@ -43,7 +43,7 @@ def test_every_declared_symbol_is_exported(q):
 
 
 def test_version_and_status_strings(q):
-    assert q.qaia_abi_version() == 1
+    assert q.qaia_abi_version() == 2
     assert q.qaia_status_string(0) == "ok"
     assert q.qaia_status_string(5) == "overflow"
     assert q.qaia_status_string(99) == "unknown status"

@@ -152,7 +152,8 @@ def test_autotune_picks_valid_paths(q):
         it.path = "auto"
     s = q.make_schedule("bsb", steps=400, dt=0.5, seed=5)
     est = q.qaia_plan_autotune(items, s, probe_steps=20)
-    print([(spec[:3], it.path, f"{e * 1e3:.2f} ms") for spec, it, e in zip(SPECS, items, est)])
+    print([(spec[:3], it.path, it.tile, f"{e * 1e3:.2f} ms") for spec, it, e in zip(SPECS, items, est)])
+    assert all(it.tile == 0 or it.path == "sparse_lds" for it in items)
     assert all(e > 0 for e in est)
     assert all(it.path in ("sparse_reg", "sparse_lds", "dense", "dense_staged") for it in items)
     # a small sparse graph never goes to the matrix cores, a 50%-dense one never to the LDS kernel
@@ -163,3 +164,49 @@ def test_autotune_picks_valid_paths(q):
         sp, ob, _ = q.qaia_sample(p, c, R, q.make_schedule("bsb", steps=400, dt=0.5, seed=5, path=it.path))
         torch.cuda.synchronize()
         assert torch.equal(it.spins, sp) and torch.equal(it.obj, ob)
+
+
+@pytest.mark.parametrize("variant", ["bsb", "dsb"])
+def test_sparse_tiles_and_queue_match_per_item_calls(q, variant):
+    """The generic sparse kernel with 2x and 4x its default replicas per block
+    (several spins per lane), and many items of different sizes sharing one
+    persistent work-queue launch: outputs equal per-item qaia_sample calls at
+    the default tile, bit for bit, on two replays."""
+    import torch
+    specs = [  # (n, m, kind, W, R, tile multiplier)
+        (42, 4, "deg3", 9, 7, 1), (42, 4, "deg3", 5, 13, 2), (42, 3, "deg3", 3, 30, 4),
+        (100, 3, "deg3", 4, 17, 2), (64, 4, "deg3", 11, 3, 4), (250, 2, "deg3", 2, 9, 1),
+        (120, 3, "deg3", 6, 8, 2), (33, 4, "deg3", 1, 50, 4),
+    ]
+    s = q.make_schedule(variant, steps=250, dt=0.5, seed=97)
+    probs, items, refs = [], [], []
+    for i, (n, m, kind, W, R, mult) in enumerate(specs):
+        inst = wl.random_instance(n, m, kind, seed=1100 + i)
+        p = q.problem_from_instance(inst)
+        c = _dev(wl.dirichlet_weights(W, m, 1200 + i))
+        probs.append((inst, p, c, R))
+        items.append(q.BatchItem(p, c, R, "sparse_lds", tile=(256 // n) * mult if mult > 1 else 0))
+        sp, ob, _ = q.qaia_sample(p, c, R, q.make_schedule(variant, steps=250, dt=0.5, seed=97, path="sparse_lds"))
+        refs.append((sp, ob))
+    ws = None
+    for replay in range(2):
+        for it in items:
+            it.spins.fill_(-1)
+            it.obj.fill_(-1)
+        ws = q.qaia_sample_batch(items, s, workspace=ws)
+        torch.cuda.synchronize()
+        for spec, it, (sp, ob) in zip(specs, items, refs):
+            assert torch.equal(it.spins, sp) and torch.equal(it.obj, ob), (replay, spec)
+
+
+def test_tile_knob_rejected_where_it_does_not_apply(q):
+    inst = wl.random_instance(42, 3, "deg3", seed=1300)
+    p = q.problem_from_instance(inst)
+    c = _dev(wl.dirichlet_weights(2, 3, 1301))
+    s = q.make_schedule("bsb", steps=10, seed=1)
+    with pytest.raises(q.QaiaError) as e:
+        q.qaia_sample_batch([q.BatchItem(p, c, 4, "dense_staged", tile=8)], s)
+    assert e.value.status == q.QAIA_INVALID_ARGUMENT
+    with pytest.raises(q.QaiaError) as e:  # 100 replicas x 42 spins > 16 spins per lane
+        q.qaia_sample_batch([q.BatchItem(p, c, 4, "sparse_lds", tile=100)], s)
+    assert e.value.status == q.QAIA_UNSUPPORTED
