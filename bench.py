@@ -350,12 +350,16 @@ def noise_form(q, wl, torch, recovery_budget_s=15.0):
         hv_ref = q.qaia_hypervolume(front, lo)
         rec = {"name": name, "m": inst.m, "weight_vectors": len(weights), "paper_alpha": alpha,
                "front_size": int(front.shape[0]), "recovery": {}, "noise_sweep": []}
-        runs = (("random", "random", 50, 1.0, 0.0), ("bsb_plain_T1000", "bsb", 1000, 0.5, 0.0),
-                ("dsb_plain_T1000", "dsb", 1000, 0.5, 0.0), ("bsb_noise_T50", "bsb", 50, 1.0, alpha),
-                ("dsb_noise_T50", "dsb", 50, 1.0, alpha))
-        for ri, (label, method, steps, dt, a) in enumerate(runs):
+        # the paper's protocol samples in half precision: the noise-injected
+        # runs again in binary16 (the generated kernel, two replicas per lane)
+        runs = (("random", "random", 50, 1.0, 0.0, "fp32"), ("bsb_plain_T1000", "bsb", 1000, 0.5, 0.0, "fp32"),
+                ("dsb_plain_T1000", "dsb", 1000, 0.5, 0.0, "fp32"), ("bsb_noise_T50", "bsb", 50, 1.0, alpha, "fp32"),
+                ("dsb_noise_T50", "dsb", 50, 1.0, alpha, "fp32"),
+                ("bsb_noise_T50_fp16", "bsb", 50, 1.0, alpha, "fp16"),
+                ("dsb_noise_T50_fp16", "dsb", 50, 1.0, alpha, "fp16"))
+        for ri, (label, method, steps, dt, a, prec) in enumerate(runs):
             r = run_budget(prob, method, recovery_budget_s, weights=weights, R=3000, steps=steps, dt=dt, alpha=a,
-                           seed=7100 + 10 * ci + ri, target=front)
+                           seed=7100 + 10 * ci + ri, target=front, precision=prec)
             h = r["history"]
             full = h[-1]["recall"] == 1.0
             rec["recovery"][label] = {"full_recall": full, "samples": h[-1]["samples"], "seconds": h[-1]["seconds"],

@@ -56,6 +56,15 @@ extern "C" {
 #define QAIA_FP32 0 /* float32 everywhere */
 #define QAIA_BF16 1 /* discrete SB, dense path: bf16 J (per-objective scaled) x exact +-1, fp32 accumulate */
 #define QAIA_FP8 2  /* discrete SB, dense path: fp8 e4m3 J (per-objective scaled) x exact +-1, fp32 accumulate */
+/* ballistic or discrete SB on the generated sparse kernel (QAIA_PATH_SPARSE_REG)
+ * in IEEE binary16, the half precision of the paper's GPU sampling runs
+ * (section "Sampling time advantage"): x, y, the step coefficient, dt a0,
+ * dt alpha and the folded edge coefficients are the float32 values of the
+ * FP32 form rounded to binary16 (x0 and y0: the float32 draws rounded), every
+ * update is a binary16 fused multiply-add in the FP32 form's order, two
+ * replicas per lane as packed pairs; read-out and cut evaluation are exact.
+ * Built on first use of each variant. */
+#define QAIA_FP16 3
 
 /* kernel family; AUTO lets the planner decide.  Each family has size limits;
  * a request for a family past its limit returns QAIA_UNSUPPORTED before

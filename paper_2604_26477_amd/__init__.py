@@ -28,7 +28,7 @@ _lib = C.CDLL(LIB_PATH)
 QAIA_OK, QAIA_INVALID_ARGUMENT, QAIA_UNSUPPORTED, QAIA_OUT_OF_MEMORY = 0, 1, 2, 3
 QAIA_DEVICE_ERROR, QAIA_OVERFLOW, QAIA_WORKSPACE_TOO_SMALL = 4, 5, 6
 VARIANTS = {"bsb": 0, "dsb": 1}
-PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "fp16": 3}
 PATHS = {"auto": 0, "sparse_reg": 1, "sparse_lds": 2, "dense": 3, "dense_staged": 4}
 
 

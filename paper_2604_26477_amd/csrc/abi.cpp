@@ -32,7 +32,8 @@ void check_schedule(const Problem &p, const qaia_schedule *s) {
     QAIA_CHECK(s != nullptr, QAIA_INVALID_ARGUMENT, "null schedule");
     QAIA_CHECK(s->variant == QAIA_BSB || s->variant == QAIA_DSB, QAIA_INVALID_ARGUMENT,
                "variant must be QAIA_BSB or QAIA_DSB");
-    QAIA_CHECK(s->precision == QAIA_FP32 || s->precision == QAIA_BF16 || s->precision == QAIA_FP8,
+    QAIA_CHECK(s->precision == QAIA_FP32 || s->precision == QAIA_BF16 || s->precision == QAIA_FP8 ||
+                   s->precision == QAIA_FP16,
                QAIA_INVALID_ARGUMENT, "unknown precision");
     QAIA_CHECK(s->steps >= 1, QAIA_INVALID_ARGUMENT, "steps must be >= 1");
     QAIA_CHECK(std::isfinite(s->dt) && s->dt > 0.0f, QAIA_INVALID_ARGUMENT, "dt must be finite and > 0");
@@ -43,19 +44,25 @@ void check_schedule(const Problem &p, const qaia_schedule *s) {
                "noise_alpha must be finite and >= 0");
     QAIA_CHECK(s->path >= QAIA_PATH_AUTO && s->path <= QAIA_PATH_DENSE_STAGED, QAIA_INVALID_ARGUMENT,
                "unknown path");
-    if (s->precision != QAIA_FP32) {
+    if (s->precision == QAIA_FP16) {
+        QAIA_CHECK(s->path == QAIA_PATH_AUTO || s->path == QAIA_PATH_SPARSE_REG, QAIA_UNSUPPORTED,
+                   "binary16 runs on the generated sparse kernel only");
+        QAIA_CHECK(p.jit[s->variant] != nullptr, QAIA_UNSUPPORTED,
+                   "binary16 needs the generated sparse kernel: " +
+                       (p.jit_error.empty() ? std::string("not built") : p.jit_error));
+    } else if (s->precision != QAIA_FP32) {
         QAIA_CHECK(s->variant == QAIA_DSB, QAIA_UNSUPPORTED,
                    "reduced precision needs discrete SB (its phi(x) = sgn(x) is exact)");
         QAIA_CHECK(s->path == QAIA_PATH_AUTO || is_dense_path(s->path), QAIA_UNSUPPORTED,
                    "reduced precision runs on the dense path only");
     }
-    (void)p;
 }
 
 // Picks the kernel family for a sampling call.
 int plan_path(const Problem &p, const qaia_schedule &s, bool tracing) {
     (void)tracing;
     if (s.path != QAIA_PATH_AUTO) return s.path;
+    if (s.precision == QAIA_FP16) return QAIA_PATH_SPARSE_REG;
     if (s.precision != QAIA_FP32) return QAIA_PATH_DENSE_STAGED;
     if (p.jit[s.variant] != nullptr) return QAIA_PATH_SPARSE_REG;
     if (sparse_lds_supported(p, nullptr)) return QAIA_PATH_SPARSE_LDS;
@@ -97,7 +104,8 @@ int32_t sample_impl(const qaia_problem *pp, const float *weights, int64_t W, int
                        " bytes of scratch; the allocation-free entry point holds at most " +
                        std::to_string(ws_bytes));
         QAIA_CHECK(path != QAIA_PATH_SPARSE_REG ||
-                       sparse_reg_ready(p, s->variant, trace_steps > 0, s->dt * s->noise_alpha != 0.0f),
+                       sparse_reg_ready(p, s->variant, trace_steps > 0, s->dt * s->noise_alpha != 0.0f,
+                                        s->precision == QAIA_FP16),
                    QAIA_UNSUPPORTED,
                    "the generated kernel for this schedule is built on first use, which allocates; "
                    "run qaia_sample once with the same schedule kind first, or choose another path");

@@ -50,6 +50,7 @@ struct ItemPlan {
 };
 
 int default_path(const Problem &p, const qaia_schedule &s) {
+    if (s.precision == QAIA_FP16) return QAIA_PATH_SPARSE_REG;
     if (s.precision != QAIA_FP32) return QAIA_PATH_DENSE_STAGED;
     if (p.jit[s.variant] != nullptr) return QAIA_PATH_SPARSE_REG;
     if (sparse_lds_supported(p, nullptr)) return QAIA_PATH_SPARSE_LDS;
@@ -60,11 +61,13 @@ void check_path(const Problem &p, const qaia_schedule &s, int path) {
     std::string why;
     if (path == QAIA_PATH_SPARSE_REG) {
         QAIA_CHECK(p.jit[s.variant] != nullptr, QAIA_UNSUPPORTED, "generated kernel unavailable: " + p.jit_error);
-        QAIA_CHECK(s.precision == QAIA_FP32, QAIA_UNSUPPORTED, "generated kernel runs FP32");
+        QAIA_CHECK(s.precision == QAIA_FP32 || s.precision == QAIA_FP16, QAIA_UNSUPPORTED,
+                   "generated kernel runs FP32 or binary16");
     } else if (path == QAIA_PATH_SPARSE_LDS) {
         QAIA_CHECK(sparse_lds_supported(p, &why), QAIA_UNSUPPORTED, "sparse LDS path: " + why);
-        QAIA_CHECK(s.precision == QAIA_FP32, QAIA_UNSUPPORTED, "sparse paths run FP32");
+        QAIA_CHECK(s.precision == QAIA_FP32, QAIA_UNSUPPORTED, "the generic sparse kernel runs FP32");
     } else if (is_dense_path(path)) {
+        QAIA_CHECK(s.precision != QAIA_FP16, QAIA_UNSUPPORTED, "binary16 runs on the generated sparse kernel only");
         QAIA_CHECK(dense_supported(p, &why), QAIA_UNSUPPORTED, "dense path: " + why);
         QAIA_CHECK(p.m <= 4, QAIA_UNSUPPORTED, "dense path supports m <= 4");
     } else {

@@ -74,6 +74,7 @@ struct Problem {
     JitKernel *jit[2] = {nullptr, nullptr};
     JitKernel *jit_trace[2] = {nullptr, nullptr};  // tracing variants, built on first use
     JitKernel *jit_noise[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [variant][trace], noise-injected, built on first use
+    JitKernel *jit16[2][2][2] = {};  // [variant][trace][noise], binary16 form, built on first use
     std::string jit_error;
     DenseImages dense;
     std::mutex mu;
@@ -118,7 +119,7 @@ size_t noalloc_scratch_bytes();
 void launch_noalloc_bad_row(const void *scratch, int64_t *bad_row, hipStream_t st);
 // Whether the generated register kernel for this schedule kind exists already
 // (the tracing and noise variants are generated on first use).
-bool sparse_reg_ready(const Problem &p, int variant, bool trace, bool noise);
+bool sparse_reg_ready(const Problem &p, int variant, bool trace, bool noise, bool half = false);
 
 // One problem's rows for the generic sparse kernel (passed by value, or as a
 // device array for a ragged batch).

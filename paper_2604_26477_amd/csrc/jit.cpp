@@ -175,6 +175,116 @@ static std::string generate(const Problem &p, int variant, bool trace, bool nois
     return s.str();
 }
 
+// Half-precision form (QAIA_FP16): each lane carries two replicas (rows
+// 2l and 2l + 1) as packed binary16 pairs, so every update is one packed
+// fused multiply-add for both.  x and y start as the float32 draws rounded to
+// binary16; the folded edge coefficients (per replica: the two rows may
+// belong to different weight vectors), the step coefficient, dt a0 and
+// dt alpha are the float32 values of the single-precision form rounded to
+// binary16; the noise draw is computed in float32 and rounded.  Read-out and
+// cut evaluation are exact, per replica.
+static std::string generate16(const Problem &p, int variant, bool trace, bool noise) {
+    const int n = p.n, m = p.m;
+    const int64_t E = p.E;
+    const bool dsb = variant == QAIA_DSB;
+    std::ostringstream s;
+    s << kPrelude;
+    if (noise) s << kNoisePrelude;
+    s << "typedef _Float16 h2 __attribute__((ext_vector_type(2)));\n"
+         "__device__ __forceinline__ h2 hp(float a, float b) { h2 r; r.x = (_Float16)a; r.y = (_Float16)b; return r; }\n"
+         "__device__ __forceinline__ h2 fm(h2 a, h2 b, h2 c) { return __builtin_elementwise_fma(a, b, c); }\n";
+    s << "extern \"C\" __global__ __attribute__((amdgpu_flat_work_group_size(1, 256)))\n"
+         "void qaia_sb_reg(const float* __restrict__ jcp, const double* __restrict__ c0s,\n"
+         "  const float* __restrict__ kt_tab, i64 rows, int R, int T, float dta0, u64 seed,\n"
+         "  u64 offset, float amp, u64* __restrict__ spins, i64* __restrict__ obj,\n"
+         "  float* __restrict__ trace, int trace_steps, float dt_alpha) {\n";
+    s << "  const i64 pr = (i64)__builtin_amdgcn_workgroup_id_x() * 256 + (i64)__builtin_amdgcn_workitem_id_x();\n";
+    // "+ zero" turns a -0 start into +0 (sgn 0 = +1 through copysign)
+    s << "  const h2 one = hp(1.0f, 1.0f), zero = hp(0.0f, 0.0f);\n";
+    s << "  const i64 r0 = pr * 2, r1 = r0 + 1;\n";
+    s << "  if (r0 >= rows) return;\n";
+    s << "  const bool has1 = r1 < rows;\n";
+    s << "  const i64 w0 = r0 / R, w1 = has1 ? r1 / R : w0;\n";
+    s << "  const u64 g0 = (u64)r0 + offset, g1 = (u64)r1 + offset;\n";
+    s << "  const bool ok0 = c0s[w0] >= 0.0, ok1 = has1 && c0s[w1] >= 0.0;\n";
+    for (int i = 0; i < n; ++i)
+        s << "  h2 X" << i << " = hp(initv(seed, ((g0 * " << n << "ull + " << i << "ull) << 1), amp), initv(seed, ((g1 * "
+          << n << "ull + " << i << "ull) << 1), amp)) + zero, Y" << i << " = hp(initv(seed, ((g0 * " << n
+          << "ull + " << i << "ull) << 1) | 1ull, amp), initv(seed, ((g1 * " << n << "ull + " << i
+          << "ull) << 1) | 1ull, amp));\n";
+    s << "  const float* ja = jcp + w0 * " << E << "ll;\n";
+    s << "  const float* jb = jcp + w1 * " << E << "ll;\n";
+    for (int64_t e = 0; e < E; ++e) s << "  const h2 J" << e << " = hp(ja[" << e << "], jb[" << e << "]);\n";
+    s << "  const h2 dA = hp(dta0, dta0), mB = hp(-1024.0f, -1024.0f), pB = hp(1025.0f, 1025.0f);\n";
+    if (noise) s << "  const h2 dN = hp(dt_alpha, dt_alpha);\n";
+    s << "  for (int t = 0; t < T; ++t) {\n";
+    s << "    const h2 kt = hp(kt_tab[t], kt_tab[t]);\n";
+    if (noise) {
+        s << "    const u64 na = (g0 * (u64)T + (u64)t) * " << n << "ull;\n";
+        s << "    const u64 nb = (g1 * (u64)T + (u64)t) * " << n << "ull;\n";
+    }
+    if (dsb)
+        for (int i = 0; i < n; ++i)
+            s << "    const h2 S" << i << " = __builtin_elementwise_copysign(one, X" << i << ");\n";
+    for (int i = 0; i < n; ++i) {
+        s << "    Y" << i << " = fm(kt, X" << i << ", Y" << i << ");";
+        for (int q = p.rowptr[i]; q < p.rowptr[i + 1]; ++q)
+            s << " Y" << i << " = fm(J" << p.eid[q] << ", " << (dsb ? "S" : "X") << p.col[q] << ", Y" << i << ");";
+        if (noise)
+            s << " Y" << i << " = fm(dN, hp(nzv(seed, na + " << i << "ull), nzv(seed, nb + " << i << "ull)), Y" << i
+              << ");";
+        s << "\n";
+    }
+    // the wall without per-half compares: with a = |x| (sign bits cleared),
+    // f = min(max(1025 - 1024 a, 0), 1) is 1 for a <= 1 and 0 for a > 1
+    // (the binary16 values above 1 start at 1 + 2^-10, where 1025 - 1024 a = 0;
+    // the fused form rounds once and monotonically, so no value crosses), and
+    // y * f zeroes y exactly where the wall hits
+    for (int i = 0; i < n; ++i) {
+        s << "    X" << i << " = fm(dA, Y" << i << ", X" << i << "); Y" << i
+          << " = Y" << i << " * __builtin_elementwise_min(__builtin_elementwise_max(fm(__builtin_bit_cast(h2, "
+             "__builtin_bit_cast(u32, X" << i << ") & 0x7fff7fffu), mB, pB), zero), one); X" << i
+          << " = __builtin_elementwise_min(__builtin_elementwise_max(X" << i << ", -one), one);\n";
+    }
+    if (trace) {
+        s << "    if (t < trace_steps) {\n";
+        s << "      float* t0 = trace + (r0 * trace_steps + t) * " << n << "ll;\n";
+        s << "      float* t1 = trace + (r1 * trace_steps + t) * " << n << "ll;\n";
+        for (int i = 0; i < n; ++i)
+            s << "      t0[" << i << "] = (float)X" << i << ".x; if (has1) t1[" << i << "] = (float)X" << i << ".y;\n";
+        s << "    }\n";
+    }
+    s << "  }\n";
+    for (int half = 0; half < 2; ++half) {
+        const char *row = half ? "r1" : "r0";
+        const char *ok = half ? "ok1" : "ok0";
+        const char *c = half ? ".y" : ".x";
+        s << "  if (" << (half ? "has1" : "true") << ") {\n";
+        for (int wd = 0; wd < p.words; ++wd) {
+            s << "    { u64 b = 0ull;";
+            for (int i = wd * 64; i < n && i < wd * 64 + 64; ++i)
+                s << " b |= (u64)(X" << i << c << " < (_Float16)0.0f) << " << (i - wd * 64) << ";";
+            s << " spins[" << row << " * " << p.words << " + " << wd << "] = " << ok << " ? b : 0ull; }\n";
+        }
+        for (int k = 0; k < m; ++k) {
+            int64_t absum = 0;
+            for (int64_t e = 0; e < E; ++e) absum += std::llabs((long long)p.W[(size_t)k * E + e]);
+            const bool narrow = absum < (int64_t(1) << 31);
+            s << "    { " << (narrow ? "int" : "i64") << " a = 0;";
+            for (int64_t e = 0; e < E; ++e) {
+                const int32_t wv = p.W[(size_t)k * E + e];
+                if (wv == 0) continue;
+                s << " a += ((X" << p.eu[e] << c << " < (_Float16)0.0f) != (X" << p.ev[e] << c
+                  << " < (_Float16)0.0f)) ? (" << (narrow ? "int" : "i64") << ")(" << wv << ") : 0;";
+            }
+            s << " obj[" << row << " * " << m << " + " << k << "] = " << ok << " ? (i64)a : 0ll; }\n";
+        }
+        s << "  }\n";
+    }
+    s << "}\n";
+    return s.str();
+}
+
 static uint64_t fnv1a(const std::string &s) {
     uint64_t h = 0xcbf29ce484222325ull;
     for (unsigned char c : s) {
@@ -272,8 +382,8 @@ static std::vector<char> compile(const std::string &src, bool device_libs) {
 static std::mutex g_cache_mu;
 static std::map<uint64_t, std::vector<char>> g_cache;  // source hash -> code object
 
-static JitKernel *build_kernel(const Problem &p, int variant, bool trace, bool noise) {
-    const std::string src = generate(p, variant, trace, noise);
+static JitKernel *build_kernel(const Problem &p, int variant, bool trace, bool noise, bool half = false) {
+    const std::string src = half ? generate16(p, variant, trace, noise) : generate(p, variant, trace, noise);
     const uint64_t h = fnv1a(src);
     std::vector<char> code;
     {
@@ -317,20 +427,23 @@ void jit_prepare(Problem &p) {
 
 // The tracing variants (trajectory tests) and the noise-injected variants are
 // generated on first use.
-static const JitKernel *kernel_for(const Problem &p, int variant, bool trace, bool noise) {
-    if (!trace && !noise) return p.jit[variant];
+// The binary16 variants too.
+static const JitKernel *kernel_for(const Problem &p, int variant, bool trace, bool noise, bool half) {
+    if (!trace && !noise && !half) return p.jit[variant];
     Problem &mp = const_cast<Problem &>(p);
     std::lock_guard<std::mutex> lk(mp.mu);
-    JitKernel *&slot = noise ? mp.jit_noise[variant][trace ? 1 : 0] : mp.jit_trace[variant];
-    if (!slot) slot = build_kernel(p, variant, trace, noise);
+    JitKernel *&slot = half ? mp.jit16[variant][trace ? 1 : 0][noise ? 1 : 0]
+                            : noise ? mp.jit_noise[variant][trace ? 1 : 0] : mp.jit_trace[variant];
+    if (!slot) slot = build_kernel(p, variant, trace, noise, half);
     return slot;
 }
 
-bool sparse_reg_ready(const Problem &p, int variant, bool trace, bool noise) {
-    if (!trace && !noise) return p.jit[variant] != nullptr;
+bool sparse_reg_ready(const Problem &p, int variant, bool trace, bool noise, bool half) {
+    if (!trace && !noise && !half) return p.jit[variant] != nullptr;
     Problem &mp = const_cast<Problem &>(p);
     std::lock_guard<std::mutex> lk(mp.mu);
-    return (noise ? mp.jit_noise[variant][trace ? 1 : 0] : mp.jit_trace[variant]) != nullptr;
+    return (half ? mp.jit16[variant][trace ? 1 : 0][noise ? 1 : 0]
+                 : noise ? mp.jit_noise[variant][trace ? 1 : 0] : mp.jit_trace[variant]) != nullptr;
 }
 
 void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, const qaia_schedule &s,
@@ -339,10 +452,12 @@ void launch_sparse_reg(const Problem &p, int variant, int64_t W, int32_t R, cons
     QAIA_CHECK(p.jit[variant] != nullptr, QAIA_UNSUPPORTED,
                "register-resident path unavailable: " + (p.jit_error.empty() ? std::string("not built") : p.jit_error));
     float dt_alpha = s.dt * s.noise_alpha;
-    const JitKernel *k = kernel_for(p, variant, trace != nullptr, dt_alpha != 0.0f);
+    const bool half = s.precision == QAIA_FP16;
+    const JitKernel *k = kernel_for(p, variant, trace != nullptr, dt_alpha != 0.0f, half);
     const int64_t rows = W * (int64_t)R;
     if (rows == 0) return;
-    const int64_t blocks = (rows + 255) / 256;
+    const int64_t lanes = half ? (rows + 1) / 2 : rows;  // binary16: two replicas per lane
+    const int64_t blocks = (lanes + 255) / 256;
     QAIA_CHECK(blocks <= INT32_MAX, QAIA_INVALID_ARGUMENT, "too many replicas for one launch");
     char *b = (char *)ws;
     const float *jcp = (const float *)(b + L.jcp), *kt = (const float *)(b + L.kt);

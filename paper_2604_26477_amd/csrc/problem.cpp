@@ -41,6 +41,12 @@ Problem::~Problem() {
             jit_release(k);
             k = nullptr;
         }
+    for (auto &plane : jit16)
+        for (auto &row : plane)
+            for (auto &k : row) {
+                jit_release(k);
+                k = nullptr;
+            }
     dense_release(*this);
     DeviceGuard g(device);
     for (void *ptr : {(void *)d_eu, (void *)d_ev, (void *)d_W, (void *)d_rowptr, (void *)d_col,

@@ -43,6 +43,7 @@ import numpy as np
 import noise_model as nm
 
 U32 = 2.0 ** -24
+U16 = 2.0 ** -11  # IEEE binary16 (the half-precision form)
 
 
 def eta_error_bound(r: np.ndarray, theta: np.ndarray) -> np.ndarray:
@@ -133,7 +134,12 @@ class Bound:
     """
 
     def __init__(self, inst, c, R, T, variant="bsb", dt=0.5, a0=1.0, amp=0.1, alpha=0.0, seed=0,
-                 steps=100, replica_offset=0):
+                 steps=100, replica_offset=0, u=U32, rounded_start=False):
+        """u: the unit roundoff of the arithmetic (U32, or U16 for the binary16
+        form, whose values also take the float32 coefficients rounded once
+        more, within the same K u S term); rounded_start: x0 and y0 are the
+        float32 draws rounded to that precision (an initial error u |x0|,
+        u |y0| carried like the others)."""
         n, m = inst.n, inst.m
         nw = c.shape[0]
         rows = nw * R
@@ -160,7 +166,11 @@ class Bound:
         # propagators of the local errors made so far: [rows, s, 2n, 2n]
         P = np.zeros((rows, 0, 2 * n, 2 * n))
         L = np.zeros((rows, 0, 2 * n))
-        ex_post = np.zeros((rows, n))
+        if rounded_start:
+            P = np.broadcast_to(np.eye(2 * n), (rows, 1, 2 * n, 2 * n)).copy()
+            L = (u * np.concatenate([np.abs(x), np.abs(y)], axis=1))[:, None, :]
+        ex_post = np.matmul(np.abs(P), L[..., None])[..., 0].sum(axis=1)[:, :n] if rounded_start \
+            else np.zeros((rows, n))
         for t in range(steps):
             at = a0 * t / (T - 1) if T > 1 else 0.0
             kt = -dt * (a0 - at)
@@ -178,14 +188,14 @@ class Bound:
                 for j, e in nbr[i]:
                     fa[:, i] += jabs[wrow, e] * np.abs(phi[:, j])
             S = np.abs(y) + np.abs(kt * x) + dtc0[:, None] * fa
-            ly = K[None, :] * U32 * S
+            ly = K[None, :] * u * S
             force = -(a0 - at) * x - f
             if alpha != 0.0:
                 force = force + alpha * eta[:, t, :]
-                ly = ly + dt * alpha * (beta[:, t, :] + U32 * np.abs(eta[:, t, :]))
+                ly = ly + dt * alpha * (beta[:, t, :] + u * np.abs(eta[:, t, :]))
             y = y + dt * force
             xn = x + dt * a0 * y
-            lx = U32 * (np.abs(xn) + np.abs(dt * a0 * y))
+            lx = u * (np.abs(xn) + np.abs(dt * a0 * y))
             # Jacobian of the step before the wall: y' = y + (kt I - dt J Dphi) x,
             # x' = x + dt a0 y'
             dydx = kt * eye[None] - dt * dphi
@@ -277,5 +287,56 @@ def emulate_fp32(inst, c, R, T, variant="bsb", dt=0.5, a0=1.0, amp=0.1, alpha=0.
         clamp = np.abs(X) > 1
         Y = np.where(clamp, np.float32(0), Y)
         X = np.clip(X, -1, 1).astype(np.float32)
+        out[:, t] = X
+    return out
+
+
+def fma16(a, b, c):
+    """binary16 fused multiply-add: a*b + c formed exactly in float64 (the
+    product of two binary16 values has at most 22 significant bits and the
+    exponents of binary16 span 40 binary places, so the sum is exact), then
+    rounded once to binary16."""
+    return (np.asarray(a, np.float64) * np.asarray(b, np.float64) + np.asarray(c, np.float64)).astype(np.float16)
+
+
+def emulate_fp16(inst, c, R, T, variant="bsb", dt=0.5, a0=1.0, amp=0.1, alpha=0.0, seed=0, steps=100,
+                 replica_offset=0):
+    """The binary16 form's update order (QAIA_FP16): the FP32 form's values
+    (x0, y0, k_t, the folded coefficients, dt a0, dt alpha, the noise draw)
+    rounded to binary16, every update a binary16 fused multiply-add in the
+    FP32 form's order, the wall on binary16 values.  Returns the x trace."""
+    n = inst.n
+    nw = c.shape[0]
+    rows = nw * R
+    nbr = _csr(inst)
+    jc, _, c0 = _scalarise(inst, np.asarray(c, np.float32))
+    x0, y0 = _init(seed, replica_offset, rows, n, amp)
+    X = x0.astype(np.float16) + np.float16(0.0)
+    Y = y0.astype(np.float16)
+    wrow = np.arange(rows) // R
+    jf = (-dt * c0[:, None] * jc).astype(np.float32).astype(np.float16)
+    dta0 = np.float16(np.float32(dt * a0))
+    dtal = np.float16(np.float32(np.float32(dt) * np.float32(alpha)))
+    if alpha != 0.0:
+        eta, _, _ = _draws(seed, replica_offset, rows, T, steps, n)
+        eta16 = eta.astype(np.float32).astype(np.float16)
+    out = np.zeros((rows, steps, n), np.float16)
+    for t in range(steps):
+        at = a0 * t / (T - 1) if T > 1 else 0.0
+        kt = np.float16(np.float32(-dt * (a0 - at)))
+        phi = np.where(X >= 0, np.float16(1), np.float16(-1)) if variant == "dsb" else X
+        Yn = Y.copy()
+        for i in range(n):
+            acc = fma16(kt, X[:, i], Y[:, i])
+            for j, e in nbr[i]:
+                acc = fma16(jf[wrow, e], phi[:, j], acc)
+            if alpha != 0.0:
+                acc = fma16(dtal, eta16[:, t, i], acc)
+            Yn[:, i] = acc
+        Y = Yn
+        X = fma16(dta0, Y, X)
+        clamp = np.abs(X) > 1
+        Y = np.where(clamp, np.float16(0), Y)
+        X = np.clip(X, -1, 1).astype(np.float16)
         out[:, t] = X
     return out

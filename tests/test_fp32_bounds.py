@@ -116,3 +116,23 @@ def test_eta_bound_covers_float32_box_muller():
         if r > 0:
             worst = max(worst, abs(ef - eta) / bound)
     assert worst > 0.05  # the bound is not loose by orders of magnitude
+
+
+@pytest.mark.parametrize("variant,alpha", [("bsb", 0.0), ("dsb", 0.0), ("bsb", 0.15)])
+def test_bound_contains_fp16_emulation(variant, alpha):
+    """The same bound at the binary16 unit roundoff (u = 2^-11, rounded
+    start) contains the binary16 emulation of the half-precision form on
+    seeds 43..49 over 30 steps; where it is defined the ratio stays well
+    below 1."""
+    inst = wl.random_instance(12, 3, "deg3", seed=41, num_edges=16)
+    c = wl.dirichlet_weights(6, 3, 42)
+    worst, checked = 0.0, []
+    for seed in range(43, 50):
+        b = fb.Bound(inst, c, 8, 1000, variant, alpha=alpha, seed=seed, steps=30, u=fb.U16, rounded_start=True)
+        _, ref = oracle.sb_sample(inst, c, 8, 1000, variant, dt=0.5, seed=seed, alpha=alpha, trace_steps=30)
+        emu = fb.emulate_fp16(inst, c, 8, 1000, variant, alpha=alpha, seed=seed, steps=30)
+        ok, ratio, frac = b.check(emu.astype(np.float64), ref)
+        assert ok, (seed, ratio)
+        worst = max(worst, ratio)
+        checked.append(frac)
+    assert worst < 0.8 and np.mean(checked) > 0.1, (worst, checked)
