@@ -12,18 +12,21 @@
 // fused exact cut evaluation.  The noise-injected variant (Eq. 10) draws the
 // same counter-based Gaussian stream as the generic kernel, with the same
 // float operations, and links the ROCm device library for cosine.
+#include <dirent.h>
 #include <fcntl.h>
 #include <spawn.h>
 #include <sys/stat.h>
 #include <sys/wait.h>
 #include <unistd.h>
 
+#include <cctype>
 #include <cerrno>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <set>
 #include <sstream>
 
 #include "internal.hpp"
@@ -94,14 +97,20 @@ __device__ __forceinline__ float nzv(u64 seed, u64 idx) {
 }
 )";
 
-static std::string generate(const Problem &p, int variant, bool trace, bool noise) {
+// Register budget of a generated kernel: the compiler is asked for at least
+// `waves` waves per SIMD (512 / waves VGPRs per lane).
+static std::string waves_attr(int waves) {
+    return ", amdgpu_waves_per_eu(" + std::to_string(waves) + ")";
+}
+
+static std::string generate(const Problem &p, int variant, bool trace, bool noise, int waves) {
     const int n = p.n, m = p.m;
     const int64_t E = p.E;
     const bool dsb = variant == QAIA_DSB;
     std::ostringstream s;
     s << kPrelude;
     if (noise) s << kNoisePrelude;
-    s << "extern \"C\" __global__ __attribute__((amdgpu_flat_work_group_size(1, 256)))\n"
+    s << "extern \"C\" __global__ __attribute__((amdgpu_flat_work_group_size(1, 256)" << waves_attr(waves) << "))\n"
          "void qaia_sb_reg(const float* __restrict__ jcp, const double* __restrict__ c0s,\n"
          "  const float* __restrict__ kt_tab, i64 rows, int R, int T, float dta0, u64 seed,\n"
          "  u64 offset, float amp, u64* __restrict__ spins, i64* __restrict__ obj,\n"
@@ -183,7 +192,7 @@ static std::string generate(const Problem &p, int variant, bool trace, bool nois
 // dt alpha are the float32 values of the single-precision form rounded to
 // binary16; the noise draw is computed in float32 and rounded.  Read-out and
 // cut evaluation are exact, per replica.
-static std::string generate16(const Problem &p, int variant, bool trace, bool noise) {
+static std::string generate16(const Problem &p, int variant, bool trace, bool noise, int waves) {
     const int n = p.n, m = p.m;
     const int64_t E = p.E;
     const bool dsb = variant == QAIA_DSB;
@@ -193,7 +202,7 @@ static std::string generate16(const Problem &p, int variant, bool trace, bool no
     s << "typedef _Float16 h2 __attribute__((ext_vector_type(2)));\n"
          "__device__ __forceinline__ h2 hp(float a, float b) { h2 r; r.x = (_Float16)a; r.y = (_Float16)b; return r; }\n"
          "__device__ __forceinline__ h2 fm(h2 a, h2 b, h2 c) { return __builtin_elementwise_fma(a, b, c); }\n";
-    s << "extern \"C\" __global__ __attribute__((amdgpu_flat_work_group_size(1, 256)))\n"
+    s << "extern \"C\" __global__ __attribute__((amdgpu_flat_work_group_size(1, 256)" << waves_attr(waves) << "))\n"
          "void qaia_sb_reg(const float* __restrict__ jcp, const double* __restrict__ c0s,\n"
          "  const float* __restrict__ kt_tab, i64 rows, int R, int T, float dta0, u64 seed,\n"
          "  u64 offset, float amp, u64* __restrict__ spins, i64* __restrict__ obj,\n"
@@ -305,8 +314,9 @@ static std::string find_clang() {
 }
 
 // Compile one source to a raw gfx950 code object in a private temp dir;
-// device_libs links the ROCm device library (needed by the noise variant).
-static std::vector<char> compile(const std::string &src, bool device_libs) {
+// device_libs links the ROCm device library (needed by the noise variant);
+// listing, when given, receives the compiler's assembly of the kernel.
+static std::vector<char> compile(const std::string &src, bool device_libs, std::string *listing = nullptr) {
     const char *tmpenv = std::getenv("TMPDIR");
     std::string tmpl = std::string(tmpenv && *tmpenv ? tmpenv : "/tmp") + "/qaia_jit_XXXXXX";
     std::vector<char> dirbuf(tmpl.begin(), tmpl.end());
@@ -338,6 +348,7 @@ static std::vector<char> compile(const std::string &src, bool device_libs) {
                                      in,
                                      "-o",
                                      out};
+    if (listing) args.push_back("-save-temps=obj");  // intermediates, the .s among them, beside out
     std::vector<char *> argv;
     for (auto &a : args) argv.push_back(const_cast<char *>(a.c_str()));
     argv.push_back(nullptr);
@@ -369,32 +380,86 @@ static std::vector<char> compile(const std::string &src, bool device_libs) {
             std::ifstream f(out, std::ios::binary);
             code.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
             if (code.empty()) err = "kernel generation produced no code object";
+            if (listing) {
+                std::ifstream sf(dir + "/k-hip-amdgcn-amd-amdhsa-gfx950.s");
+                std::stringstream ss;
+                ss << sf.rdbuf();
+                *listing = ss.str();
+            }
         }
     }
-    std::remove(in.c_str());
-    std::remove(out.c_str());
-    std::remove(log.c_str());
+    // the directory holds only what this call created
+    if (DIR *d = opendir(dir.c_str())) {
+        while (dirent *ent = readdir(d)) {
+            const std::string name = ent->d_name;
+            if (name != "." && name != "..") std::remove((dir + "/" + name).c_str());
+        }
+        closedir(d);
+    }
     rmdir(dir.c_str());
     QAIA_CHECK(err.empty(), QAIA_UNSUPPORTED, err);
     return code;
 }
 
+// True when the listing shows spill traffic (scratch or buffer accesses,
+// accumulation-register copies) inside an outermost loop, i.e. between a
+// loop header's label and the first branch back to it.
+static bool loop_spills(const std::string &s) {
+    const std::string mark = "Loop Header: Depth=1";
+    for (size_t h = s.find(mark); h != std::string::npos; h = s.find(mark, h + 1)) {
+        const size_t ls = s.rfind('\n', h) + 1;  // npos + 1 == 0 at the first line
+        const size_t colon = s.find(':', ls);
+        if (colon == std::string::npos || colon > h) continue;
+        const std::string label = s.substr(ls, colon - ls);
+        size_t end = std::string::npos;
+        for (size_t q = s.find(label, h); q != std::string::npos; q = s.find(label, q + 1)) {
+            const size_t after = q + label.size();
+            if (after < s.size() && std::isalnum((unsigned char)s[after])) continue;  // .LBB0_8 vs .LBB0_80
+            const size_t line = s.rfind('\n', q) + 1;
+            if (s.compare(line, 1, "\t") == 0 && s.find("branch", line) < q) {
+                end = q;
+                break;
+            }
+        }
+        if (end == std::string::npos) continue;
+        const std::string body = s.substr(h, end - h);
+        if (body.find("scratch_") != std::string::npos || body.find("buffer_") != std::string::npos ||
+            body.find("accvgpr") != std::string::npos)
+            return true;
+    }
+    return false;
+}
+
 static std::mutex g_cache_mu;
 static std::map<uint64_t, std::vector<char>> g_cache;  // source hash -> code object
+static std::set<uint64_t> g_spilling;                  // sources whose step loop spills
 
+// Three waves per SIMD (168 VGPRs) where the step loop still fits without
+// spills, which hides more of the FMA chains' latency (5-7 % on the 42-node
+// graph); otherwise two (256 VGPRs: every graph the path admits keeps its
+// state in registers there, spills land outside the loop).
 static JitKernel *build_kernel(const Problem &p, int variant, bool trace, bool noise, bool half = false) {
-    const std::string src = half ? generate16(p, variant, trace, noise) : generate(p, variant, trace, noise);
-    const uint64_t h = fnv1a(src);
     std::vector<char> code;
-    {
+    for (int waves = 3; waves >= 2 && code.empty(); --waves) {
+        const std::string src =
+            half ? generate16(p, variant, trace, noise, waves) : generate(p, variant, trace, noise, waves);
+        const uint64_t h = fnv1a(src);
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            if (g_spilling.count(h)) continue;
+            auto it = g_cache.find(h);
+            if (it != g_cache.end()) code = it->second;
+        }
+        if (!code.empty()) break;
+        std::string listing;
+        std::vector<char> c = compile(src, noise, waves > 2 ? &listing : nullptr);
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_cache.find(h);
-        if (it != g_cache.end()) code = it->second;
-    }
-    if (code.empty()) {
-        code = compile(src, noise);
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        g_cache[h] = code;
+        if (waves > 2 && (listing.empty() || loop_spills(listing))) {
+            g_spilling.insert(h);
+            continue;
+        }
+        g_cache[h] = c;
+        code.swap(c);
     }
     JitKernel *k = new JitKernel();
     k->device = p.device;
