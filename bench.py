@@ -237,8 +237,8 @@ def _race(q, prob, base, ref_rounds, contenders, seeds, cap=1.6):
 
 
 def learned_form(q, wl, torch, seeds=(11, 12, 13)):
-    """Time to a reference hypervolume (the benchmark spec's third target and the
-    learned form's measurement).  Both workloads run rounds of 1024 weight
+    """Time to a reference hypervolume (the learned form's measurement and the
+    metric's time-to-reference part).  Both workloads run rounds of 1024 weight
     vectors, each sampled, filtered against the loop's archive and labelled;
     the reference is the plain FP32 loop at 10x its budget.
       42-node m = 4 (sparse, 256 replicas, 2000 steps): plain FP32 bSB, the
@@ -247,7 +247,7 @@ def learned_form(q, wl, torch, seeds=(11, 12, 13)):
         contender;
       complete N = 512 m = 4 (dense, 8 replicas, 1000 steps): plain FP32 bSB on
         the matrix cores, discrete SB on the BF16 path with uniform vectors, and
-        the benchmark spec form: the learned proposer with discrete SB on the BF16
+        the combined form: the learned proposer with discrete SB on the BF16
         path (each round one batched launch of all its weight vectors x
         replicas)."""
     out = {}

@@ -222,43 +222,62 @@ __global__ __launch_bounds__(kDB) void dense_batch_step_kernel(const DenseJob *_
 }
 
 // ---------------------------------------------------------------------------
-// Staged tile: a 256-thread block owns 128 spins x 128 columns; wave (wr, wc)
-// owns 64 x 64 (2 x 2 accumulators per objective).  The k dimension runs in
-// 64-byte chunks.  Each chunk of the block's J rows (all objectives) and Phi
-// columns is copied to LDS once and read there by the two waves that share
-// it.  Software pipeline: global loads run two chunks ahead into two static
-// register sets, LDS is double-buffered, and there is one barrier per chunk:
-//   iteration c: issue loads of chunk c+2 -> compute on LDS[c%2]
-//                -> write chunk c+1 (loaded during c-1) to LDS[(c+1)%2] -> barrier.
-// Loads of objectives k >= m (batched jobs with m < MT) read objective m-1;
-// their MFMAs are skipped by a uniform branch and their accumulators unused.
+// Staged tile: a block of NW waves owns 128 spins x 128 columns; wave (wr, wc)
+// owns (32 RB) x 64 (RB x 2 accumulators per objective, RB = 8 / NW).  The k
+// dimension runs in chunks of CB bytes per row (64 or 128).  Each chunk of the
+// block's J rows (all objectives) and Phi columns is copied to LDS once (by
+// global_load_lds, below) and read there by every wave that needs it; D stage
+// buffers form a ring and there is one barrier per chunk.  Loads of
+// objectives k >= m (batched jobs with m < MT) read objective m-1; their
+// MFMAs are skipped by a uniform branch and their accumulators unused.
 constexpr int kT2 = 128;          // tile height and width
-constexpr int kChunkB = 64;       // bytes of k per row per chunk
-constexpr int kPitchB = 64;       // LDS row pitch (bytes): one chunk row, no padding
 constexpr int kHsPitch = kT2 + 4; // LDS pitch (floats) of the epilogue's h tile
 
-// In LDS, 16-byte part p (0..3) of chunk row r sits at r * 64 + 16 (p ^ ((r >> 2) & 3)):
-// the parts are XOR-swizzled with bits 2..3 of the row, so that a 16-lane
-// fragment read (16 rows, one logical part) and a 64-lane chunk copy (16 rows
-// x 4 parts, 1024 contiguous bytes) are both free of bank conflicts.
+// In LDS a chunk row is CB bytes (the row pitch, no padding) of 16-byte parts;
+// logical part p of row r sits at physical part p ^ sw(r), with sw(r) =
+// (r >> 2) & 3 for 64-byte rows and (r >> 1) & 7 for 128-byte rows.  Either
+// way the 16 rows of a 16-lane fragment read (one logical part) land on 16
+// distinct 4-bank groups, and a 64-lane chunk copy writes 1024 contiguous
+// bytes: both free of bank conflicts.
+template <int CB>
+__host__ __device__ constexpr int row_swizzle(int r) { return CB == 64 ? (r >> 2) & 3 : (r >> 1) & 7; }
 
+template <int MT, int CB>
+constexpr int staged_buf_bytes() { return (MT + 1) * kT2 * CB; }
+
+// 128-byte chunks (whole 128-byte requests per row) where the stage ring fits
+// LDS; m = 4 keeps 64-byte chunks (five 128-row operands per stage).
 template <int MT>
-constexpr int staged_buf_bytes() { return (MT + 1) * kT2 * kPitchB; }
+constexpr int staged_chunk() { return MT <= 3 ? 128 : 64; }
 
 // Work on one LDS chunk is split into two units so that the fragment reads of
-// one unit overlap the MFMAs of the other: for FP32 and BF16 a unit is one of
-// the chunk's two k-groups, for FP8 (one 32x32x64 k-group per chunk) one of
-// the two 32-row halves of the wave's rows.  For every MFMA the A and B
-// fragments of a lane come from the same k positions (lane half h, slot j),
-// so any internal k order of the instruction pairs them correctly.
-template <int PREC, int MT> struct Frags;
-template <int MT> struct Frags<QAIA_FP32, MT> { float4 a[MT][2], b[2]; };
-template <int MT> struct Frags<QAIA_BF16, MT> { bf16x8 a[MT][2], b[2]; };
-template <int MT> struct Frags<QAIA_FP8, MT> { i32x8 a[MT], b[2]; };
+// one unit overlap the MFMAs of the other.  A unit is KPU consecutive k-groups
+// of the chunk (k-groups of 32 bytes for FP32 and BF16, 64 bytes for FP8);
+// when a chunk holds a single k-group (FP8 in 64-byte chunks) a unit is one
+// half of the wave's accumulators instead (its two 32-row halves, or its two
+// 32-column halves when the wave owns 32 rows).  Each accumulator receives
+// the chunk's k-groups in increasing order whatever the split.  For every
+// MFMA the A and B fragments of a lane come from the same k positions (lane
+// half h, slot j), so any internal k order of the instruction pairs them.
+template <int PREC, int CB>
+constexpr int kgroups_per_chunk() { return CB / (PrecInfo<PREC>::KG * (int)sizeof(typename PrecInfo<PREC>::T)); }
+template <int PREC, int CB>
+constexpr bool half_units() { return kgroups_per_chunk<PREC, CB>() == 1; }
+template <int PREC, int CB>
+constexpr int kg_per_unit() { return half_units<PREC, CB>() ? 1 : kgroups_per_chunk<PREC, CB>() / 2; }
+
+template <int PREC> struct FragType;
+template <> struct FragType<QAIA_FP32> { typedef float4 V; };
+template <> struct FragType<QAIA_BF16> { typedef bf16x8 V; };
+template <> struct FragType<QAIA_FP8> { typedef i32x8 V; };
+
+template <int PREC, int MT, int RB, int KPU> struct Frags {
+    typename FragType<PREC>::V a[KPU][MT][RB], b[KPU][2];
+};
 
 struct LaneLds {
     const char *a, *b;  // this lane's first A row and first B row in a stage buffer
-    int sw;             // swizzle of every row this lane reads: (lr >> 2) & 3
+    int sw;             // swizzle of every row this lane reads (rows lr + 32 j)
     int half;
 };
 
@@ -266,72 +285,137 @@ __device__ __forceinline__ u32x4 lds16(const char *row, int part, int sw) {
     return *(const u32x4 *)(row + ((part ^ sw) << 4));
 }
 
-template <int PREC, int MT>
-__device__ __forceinline__ void frag_load(Frags<PREC, MT> &f, const LaneLds &L, int u) {
+template <int PREC, int MT, int RB, int CB>
+__device__ __forceinline__ void frag_load(Frags<PREC, MT, RB, kg_per_unit<PREC, CB>()> &f, const LaneLds &L, int u) {
+    constexpr int KPU = kg_per_unit<PREC, CB>();
     if constexpr (PREC == QAIA_FP8) {
-        // unit u = rows r2 = u; lane half h holds k = 32h + 0..31 (parts 2h, 2h + 1)
-        auto frag = [&](const char *row) {
-            const u32x4 lo = lds16(row, 2 * L.half, L.sw), hi = lds16(row, 2 * L.half + 1, L.sw);
+        // lane half h holds k = 32h + 0..31 of a 64-byte k-group: parts 4g + 2h, 4g + 2h + 1
+        auto frag = [&](const char *row, int g) {
+            const u32x4 lo = lds16(row, 4 * g + 2 * L.half, L.sw), hi = lds16(row, 4 * g + 2 * L.half + 1, L.sw);
             return __builtin_bit_cast(i32x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
         };
+        if constexpr (half_units<PREC, CB>()) {
+            if constexpr (RB == 2) {
+                // unit u = rows r2 = u, both column halves
 #pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2) f.b[c2] = frag(L.b + c2 * 32 * kPitchB);
+                for (int c2 = 0; c2 < 2; ++c2) f.b[0][c2] = frag(L.b + c2 * 32 * CB, 0);
 #pragma unroll
-        for (int k = 0; k < MT; ++k) f.a[k] = frag(L.a + (k * kT2 + u * 32) * kPitchB);
+                for (int k = 0; k < MT; ++k) f.a[0][k][0] = frag(L.a + (k * kT2 + u * 32) * CB, 0);
+            } else {
+                // unit u = column half u, the wave's 32 rows
+                f.b[0][0] = frag(L.b + u * 32 * CB, 0);
+#pragma unroll
+                for (int k = 0; k < MT; ++k) f.a[0][k][0] = frag(L.a + k * kT2 * CB, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < KPU; ++kk) {
+                const int g = u * KPU + kk;
+#pragma unroll
+                for (int c2 = 0; c2 < 2; ++c2) f.b[kk][c2] = frag(L.b + c2 * 32 * CB, g);
+#pragma unroll
+                for (int k = 0; k < MT; ++k)
+#pragma unroll
+                    for (int r2 = 0; r2 < RB; ++r2) f.a[kk][k][r2] = frag(L.a + (k * kT2 + r2 * 32) * CB, g);
+            }
+        }
     } else {
-        // unit u = k-group u; lane half h holds its 16 bytes at logical part 2u + h
-        typedef decltype(f.b[0]) V;
-        typedef typename std::remove_reference<V>::type VT;
-        const int p = 2 * u + L.half;
+        // k-group g: lane half h holds its 16 bytes at logical part 2g + h
+        typedef typename FragType<PREC>::V VT;
 #pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2) f.b[c2] = __builtin_bit_cast(VT, lds16(L.b + c2 * 32 * kPitchB, p, L.sw));
+        for (int kk = 0; kk < KPU; ++kk) {
+            const int p = 2 * (u * KPU + kk) + L.half;
 #pragma unroll
-        for (int k = 0; k < MT; ++k)
+            for (int c2 = 0; c2 < 2; ++c2) f.b[kk][c2] = __builtin_bit_cast(VT, lds16(L.b + c2 * 32 * CB, p, L.sw));
 #pragma unroll
-            for (int r2 = 0; r2 < 2; ++r2)
-                f.a[k][r2] = __builtin_bit_cast(VT, lds16(L.a + (k * kT2 + r2 * 32) * kPitchB, p, L.sw));
+            for (int k = 0; k < MT; ++k)
+#pragma unroll
+                for (int r2 = 0; r2 < RB; ++r2)
+                    f.a[kk][k][r2] = __builtin_bit_cast(VT, lds16(L.a + (k * kT2 + r2 * 32) * CB, p, L.sw));
+        }
     }
 }
 
-template <int PREC, int MT>
-__device__ __forceinline__ void frag_mma(const Frags<PREC, MT> &f, int m, int u, f16v (&acc)[MT][2][2]) {
+// One MFMA of objective k on accumulator (r2, c2) with unit-local k-group kk.
+template <int PREC, int MT, int RB, int KPU>
+__device__ __forceinline__ void mma_one(const Frags<PREC, MT, RB, KPU> &f, f16v &a, int kk, int k, int ra, int cb,
+                                        int j) {
+    if constexpr (PREC == QAIA_FP8) {
+        a = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.a[kk][k][ra], f.b[kk][cb], a, 0, 0, 0, 127, 0, 127);
+    } else if constexpr (PREC == QAIA_BF16) {
+        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[kk][k][ra], f.b[kk][cb], a, 0, 0, 0);
+    } else {
+        const float av = j == 0 ? f.a[kk][k][ra].x : j == 1 ? f.a[kk][k][ra].y : j == 2 ? f.a[kk][k][ra].z
+                                                                                       : f.a[kk][k][ra].w;
+        const float bv = j == 0 ? f.b[kk][cb].x : j == 1 ? f.b[kk][cb].y : j == 2 ? f.b[kk][cb].z : f.b[kk][cb].w;
+        a = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, a, 0, 0, 0);
+    }
+}
+
+// The MFMAs of unit u in a fixed order; after the i-th, hook(i) runs (the
+// copy interleaving below).  MFMAs per unit with m = MT: unit_mfmas().
+template <int PREC, int MT, int RB, int CB>
+constexpr int unit_mfmas() {
+    return half_units<PREC, CB>() ? MT * RB
+                                  : kg_per_unit<PREC, CB>() * MT * RB * 2 * (PREC == QAIA_FP32 ? 4 : 1);
+}
+
+template <int PREC, int MT, int RB, int CB, typename Hook>
+__device__ __forceinline__ void unit_mma(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>()> &f, int m, int u,
+                                         f16v (&acc)[MT][RB][2], Hook &&hook) {
+    constexpr int KPU = kg_per_unit<PREC, CB>();
+    constexpr int NJ = PREC == QAIA_FP32 ? 4 : 1;  // fp32: four 32x32x2 steps per 16-byte fragment
+    int i = 0;
+    if constexpr (half_units<PREC, CB>()) {
 #pragma unroll
-    for (int k = 0; k < MT; ++k) {
-        if (k >= m) break;
-        if constexpr (PREC == QAIA_FP8) {
-#pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2)
-                acc[k][u][c2] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.a[k], f.b[c2], acc[k][u][c2], 0, 0,
-                                                                               0, 127, 0, 127);
-        } else {
-#pragma unroll
-            for (int r2 = 0; r2 < 2; ++r2)
+        for (int k = 0; k < MT; ++k) {
+            if (k >= m) break;
+            if constexpr (RB == 2) {
 #pragma unroll
                 for (int c2 = 0; c2 < 2; ++c2) {
-                    f16v &a = acc[k][r2][c2];
-                    if constexpr (PREC == QAIA_BF16) {
-                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[k][r2], f.b[c2], a, 0, 0, 0);
-                    } else {
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].x, f.b[c2].x, a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].y, f.b[c2].y, a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].z, f.b[c2].z, a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].w, f.b[c2].w, a, 0, 0, 0);
-                    }
+                    mma_one(f, acc[k][u][c2], 0, k, 0, c2, 0);
+                    hook(i++);
                 }
+            } else {
+                mma_one(f, acc[k][0][u], 0, k, 0, 0, 0);
+                hook(i++);
+            }
         }
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < KPU; ++kk)
+#pragma unroll
+            for (int k = 0; k < MT; ++k) {
+                if (k >= m) break;
+#pragma unroll
+                for (int r2 = 0; r2 < RB; ++r2)
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j) {
+                            mma_one(f, acc[k][r2][c2], kk, k, r2, c2, j);
+                            hook(i++);
+                        }
+            }
     }
+}
+
+template <int PREC, int MT, int RB, int CB>
+__device__ __forceinline__ void frag_mma(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>()> &f, int m, int u,
+                                         f16v (&acc)[MT][RB][2]) {
+    unit_mma<PREC, MT, RB, CB>(f, m, u, acc, [](int) {});
 }
 
 // frag_mma with NC copies of the next chunk interleaved: copy j is issued
 // after MFMA (j * NM) / NC of the unit (NM MFMAs when m == MT), so a copy that
 // waits for room in the memory queue stalls behind queued matrix work instead
 // of in front of an idle matrix pipe.  Copies not yet issued (m < MT) follow.
-template <int PREC, int MT, int NC, typename Copy>
-__device__ __forceinline__ void frag_mma_cp(const Frags<PREC, MT> &f, int m, int u, f16v (&acc)[MT][2][2],
-                                            Copy &&copy) {
-    constexpr int NM = PREC == QAIA_FP8 ? MT * 2 : (PREC == QAIA_BF16 ? MT * 4 : MT * 16);
-    int i = 0, j = 0;
-    auto after = [&]() {
+template <int PREC, int MT, int RB, int CB, int NC, typename Copy>
+__device__ __forceinline__ void frag_mma_cp(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>()> &f, int m, int u,
+                                            f16v (&acc)[MT][RB][2], Copy &&copy) {
+    constexpr int NM = unit_mfmas<PREC, MT, RB, CB>();
+    int j = 0;
+    unit_mma<PREC, MT, RB, CB>(f, m, u, acc, [&](int i) {
         if constexpr (NC > 0) {
             if (j < NC && i == (j * NM) / NC) {
                 __builtin_amdgcn_sched_barrier(0);
@@ -340,56 +424,27 @@ __device__ __forceinline__ void frag_mma_cp(const Frags<PREC, MT> &f, int m, int
                 ++j;
             }
         }
-        ++i;
-    };
-#pragma unroll
-    for (int k = 0; k < MT; ++k) {
-        if (k >= m) break;
-        if constexpr (PREC == QAIA_FP8) {
-#pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2) {
-                acc[k][u][c2] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.a[k], f.b[c2], acc[k][u][c2], 0, 0,
-                                                                               0, 127, 0, 127);
-                after();
-            }
-        } else {
-#pragma unroll
-            for (int r2 = 0; r2 < 2; ++r2)
-#pragma unroll
-                for (int c2 = 0; c2 < 2; ++c2) {
-                    f16v &a = acc[k][r2][c2];
-                    if constexpr (PREC == QAIA_BF16) {
-                        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[k][r2], f.b[c2], a, 0, 0, 0);
-                        after();
-                    } else {
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].x, f.b[c2].x, a, 0, 0, 0);
-                        after();
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].y, f.b[c2].y, a, 0, 0, 0);
-                        after();
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].z, f.b[c2].z, a, 0, 0, 0);
-                        after();
-                        a = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[k][r2].w, f.b[c2].w, a, 0, 0, 0);
-                        after();
-                    }
-                }
-        }
-    }
+    });
 #pragma unroll
     for (; j < NC; ++j) copy(j);
 }
 
 // Direct-to-LDS variant of the staged tile: every chunk is copied by
 // global_load_lds (16 bytes per lane straight into LDS, no registers), into a
-// ring of D stage buffers, D - 1 chunks ahead of the MFMAs.  Wave w copies
-// granules [(w * 2(MT+1) + i) * 64, +64) of a stage with its i-th copy; lane L
-// of that copy fetches the global 16 bytes that belong at granule g = base + L
-// of the swizzled layout (row g / 4, physical part g % 4).
+// ring of D stage buffers, D - 1 chunks ahead of the MFMAs.  A stage holds
+// (MT + 1) x 128 rows x CB / 16 granules of 16 bytes; with NW waves, each
+// makes PER = (MT + 1) x 128 x CB / 16 / (64 NW) copies per chunk, wave w
+// copying granules [(w * PER + i) * 64, +64) with its i-th copy; lane L of
+// that copy fetches the global 16 bytes that belong at granule g = base + L
+// of the swizzled layout (row g / (CB / 16), physical part g % (CB / 16)).
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-template <int MT>
+template <int MT, int CB>
 constexpr int dma_stages() {
-    // four stage buffers (three for m = 4: 3 x 40 KB); filling all 160 KB of
-    // LDS with five measured slower
+    // 64-byte chunks: four stage buffers (three for m = 4: 3 x 40 KB); filling
+    // all 160 KB of LDS with five measured slower.  128-byte chunks: two for
+    // m = 3 (2 x 64 KB), three below
+    if constexpr (CB == 128) return MT <= 2 ? 3 : 2;
     return MT <= 3 ? 4 : 3;
 }
 
@@ -400,19 +455,18 @@ constexpr int dma_stages() {
 // MFMA group, serialising the fragment reads with the MFMAs.  The copies are
 // ordered by hand (dma_wait, lds_barrier).  M0 is declared clobbered, so the
 // compiler keeps nothing it needs in M0 across the copy.
-template <int MT>
+template <int PER>
 __device__ __forceinline__ void dma_copy(char *stage, const char *src, size_t koff, int wave, int i) {
     const uint32_t base = (uint32_t)(uintptr_t)(lds_void_t *)stage;
-    const uint32_t dst = __builtin_amdgcn_readfirstlane(base + (uint32_t)(wave * 2 * (MT + 1) + i) * 64 * 16);
+    const uint32_t dst = __builtin_amdgcn_readfirstlane(base + (uint32_t)(wave * PER + i) * 64 * 16);
     asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src + koff), "s"(dst)
                  : "memory", "m0");
 }
 
-template <int MT>
-__device__ __forceinline__ void dma_chunk(char *stage, const char *const (&src)[2 * (MT + 1)], size_t koff,
-                                          int wave) {
+template <int PER>
+__device__ __forceinline__ void dma_chunk(char *stage, const char *const (&src)[PER], size_t koff, int wave) {
 #pragma unroll
-    for (int i = 0; i < 2 * (MT + 1); ++i) dma_copy<MT>(stage, src[i], koff, wave, i);
+    for (int i = 0; i < PER; ++i) dma_copy<PER>(stage, src[i], koff, wave, i);
 }
 
 // this wave's copies of all but the newest `later` chunks have landed, with
@@ -473,14 +527,19 @@ __device__ __forceinline__ void epi_prefetch(EpiPrefetch<NPF> &pf) {
     }
 }
 
-template <int PREC, int MT, int NPF>
+template <int PREC, int MT, int NPF, int NW, int CB>
 __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, int Np_, int m, int row0, int col0,
-                                             int wr, int wc, int half, int lr, f16v (&acc)[MT][2][2],
+                                             int wr, int wc, int half, int lr, f16v (&acc)[MT][8 / NW][2],
                                              char *lds, EpiPrefetch<NPF> &pf) {
     typedef typename PrecInfo<PREC>::T T;
     constexpr int ES = sizeof(T);
-    constexpr int PER = 2 * (MT + 1);  // copies per wave per chunk
-    constexpr int D = dma_stages<MT>();
+    constexpr int RB = 8 / NW;                // 32-row accumulator blocks per wave
+    constexpr int GPR = CB / 16;              // 16-byte granules per chunk row
+    static_assert((2 * GPR * (MT + 1)) % NW == 0, "copies per wave");
+    constexpr int PER = 2 * GPR * (MT + 1) / NW;  // copies per wave per chunk
+    constexpr int P0 = PER / 2, P1 = PER - P0;    // spread over the two MFMA groups
+    constexpr int KPU = kg_per_unit<PREC, CB>();
+    constexpr int D = dma_stages<MT, CB>();
     static_assert(D >= 2 && D - 2 <= 6, "stage ring depth");
     static_assert((D - 2) * PER + NPF <= 63, "vmcnt range");
     const size_t Np = (size_t)Np_;
@@ -489,7 +548,7 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int g = (wave * PER + i) * 64 + lane;
-        const int R = g >> 2, p = (g & 3) ^ ((R >> 2) & 3);
+        const int R = g / GPR, p = (g % GPR) ^ row_swizzle<CB>(R);
         if (R < MT * kT2) {
             const int k0 = R / kT2 < m ? R / kT2 : m - 1;
             src[i] = (const char *)Jv + (((size_t)k0 * Np + row0 + (R % kT2)) * Np) * ES + p * 16;
@@ -497,17 +556,17 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
             src[i] = (const char *)phiv + ((size_t)(col0 + R - MT * kT2) * Np) * ES + p * 16;
         }
     }
-    constexpr int SB = staged_buf_bytes<MT>();
+    constexpr int SB = staged_buf_bytes<MT, CB>();
     char *S[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) S[i] = lds + i * SB;
-    const int nk = (int)(Np * ES / kChunkB);
-    const int sw = (lr >> 2) & 3;
-    const int aoff = (wr * 64 + lr) * kPitchB, boff = (MT * kT2 + wc * 64 + lr) * kPitchB;
+    const int nk = (int)(Np * ES / CB);
+    const int sw = row_swizzle<CB>(lr);
+    const int aoff = (wr * 32 * RB + lr) * CB, boff = (MT * kT2 + wc * 64 + lr) * CB;
     auto lane_lds = [&](int st) { return LaneLds{S[st] + aoff, S[st] + boff, sw, half}; };
 #pragma unroll
     for (int q = 0; q < D - 1; ++q)
-        if (q < nk) dma_chunk<MT>(S[q], src, (size_t)q * kChunkB, wave);
+        if (q < nk) dma_chunk<PER>(S[q], src, (size_t)q * CB, wave);
     // The prefetch is issued at the end of iteration c_pf, PFD chunks before
     // the one that issues the last chunk's copies (or after the prologue when
     // c_pf is -1).  Chunks whose copies were issued before it, c_pf < c <=
@@ -522,7 +581,7 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
     // Rotation: after the barrier for chunk c, unit 0 of chunk c is read while
     // unit 1 of chunk c - 1 (already in registers) runs, then unit 1 of chunk c
     // is read while unit 0 of chunk c runs.
-    Frags<PREC, MT> f0, f1;
+    Frags<PREC, MT, RB, KPU> f0, f1;
     for (int c0 = 0; c0 < nk; c0 += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) {
@@ -539,28 +598,28 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
                 constexpr bool kSpread = PREC != QAIA_FP8;
                 const bool issue = c + D - 1 < nk;
                 char *const nst = S[(u + D - 1) % D];
-                const size_t koff = (size_t)(c + D - 1) * kChunkB;
-                if (!kSpread && issue) dma_chunk<MT>(nst, src, koff, wave);
+                const size_t koff = (size_t)(c + D - 1) * CB;
+                if (!kSpread && issue) dma_chunk<PER>(nst, src, koff, wave);
                 auto copy0 = [&](int i) {
-                    if (kSpread && issue) dma_copy<MT>(nst, src[i], koff, wave, i);
+                    if (kSpread && issue) dma_copy<PER>(nst, src[i], koff, wave, i);
                 };
                 auto copy1 = [&](int i) {
-                    if (kSpread && issue) dma_copy<MT>(nst, src[PER / 2 + i], koff, wave, PER / 2 + i);
+                    if (kSpread && issue) dma_copy<PER>(nst, src[P0 + i], koff, wave, P0 + i);
                 };
                 const LaneLds L = lane_lds(u);
                 // scheduling barriers keep each unit's reads ahead of the other unit's MFMAs
-                frag_load<PREC, MT>(f0, L, 0);
+                frag_load<PREC, MT, RB, CB>(f0, L, 0);
                 __builtin_amdgcn_sched_barrier(0);
                 if (c > 0) {
-                    frag_mma_cp<PREC, MT, kSpread ? PER / 2 : 0>(f1, m, 1, acc, copy0);
+                    frag_mma_cp<PREC, MT, RB, CB, kSpread ? P0 : 0>(f1, m, 1, acc, copy0);
                 } else {
 #pragma unroll
-                    for (int i = 0; i < PER / 2; ++i) copy0(i);
+                    for (int i = 0; i < P0; ++i) copy0(i);
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                frag_load<PREC, MT>(f1, L, 1);
+                frag_load<PREC, MT, RB, CB>(f1, L, 1);
                 __builtin_amdgcn_sched_barrier(0);
-                frag_mma_cp<PREC, MT, kSpread ? PER / 2 : 0>(f0, m, 0, acc, copy1);
+                frag_mma_cp<PREC, MT, RB, CB, kSpread ? P1 : 0>(f0, m, 0, acc, copy1);
                 __builtin_amdgcn_sched_barrier(0);
                 if constexpr (NPF > 0) {
                     if (c == c_pf) epi_prefetch(pf);
@@ -569,27 +628,31 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
             }
         }
     }
-    frag_mma<PREC, MT>(f1, m, 1, acc);
+    frag_mma<PREC, MT, RB, CB>(f1, m, 1, acc);
     lds_barrier();
 }
 
-// Where the epilogue prefetch fits in 512 registers without spilling (checked
-// on the compiled kernels): m <= 2 everywhere; m = 3 only for BF16 single-job
-// launches (FP32 and FP8 fragments, or the grouped kernel's job lookup, leave
-// no room for the 128 prefetch registers beside 192 accumulators).
-template <int PREC, int MT>
+// Where the epilogue prefetch fits beside the accumulators and fragments
+// without spilling (checked on the compiled kernels, 128-byte chunks): m = 1
+// everywhere; m = 2 with four waves except FP8 (whose 32-byte fragments
+// leave no room).
+template <int PREC, int MT, int NW>
 constexpr bool staged_prefetch(bool grouped) {
-    return MT <= 2 || (MT == 3 && PREC == QAIA_BF16 && !grouped);
+    (void)grouped;
+    if constexpr (NW == 8) return MT == 1;
+    return MT == 1 || (MT == 2 && PREC != QAIA_FP8);
 }
 
 // FIXED_M: the job's m equals MT (single-job launches), so objective guards fold away.
 // PF: the epilogue's x and y are prefetched into registers during the k loop
 // (where they fit beside the accumulators and fragments without spilling).
-template <int PREC, int MT, bool DSB, bool FIXED_M, bool PF>
+template <int PREC, int MT, bool DSB, bool FIXED_M, bool PF, int NW>
 __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by, char *lds) {
+    constexpr int RB = 8 / NW;   // 32-row accumulator blocks per wave: waves own (32 RB) x 64
+    constexpr int CPI = 2 * NW;  // columns per pass of the update phase
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int half = l >> 5, lr = l & 31;
-    const int wr = wv & 1, wc = wv >> 1;
+    const int wr = wv % (NW / 2), wc = wv / (NW / 2);
     const int row0 = by * kT2, col0 = bx * kT2;
     constexpr int M = MT;
     const int m = FIXED_M ? MT : j.m;
@@ -598,11 +661,11 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
     float *x_out = DSB ? j.xa : (even ? j.xb : j.xa);
     const void *phi_in = DSB ? (even ? j.pa : j.pb) : (const void *)x_in;
     void *phi_out = DSB ? (even ? j.pb : j.pa) : nullptr;
-    f16v acc[M][2][2];
+    f16v acc[M][RB][2];
 #pragma unroll
     for (int k = 0; k < M; ++k)
 #pragma unroll
-        for (int r2 = 0; r2 < 2; ++r2)
+        for (int r2 = 0; r2 < RB; ++r2)
 #pragma unroll
             for (int c2 = 0; c2 < 2; ++c2)
 #pragma unroll
@@ -616,24 +679,26 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
         for (int k = 0; k < M; ++k)
             cfs[c2][k] = k < m ? j.coef[(size_t)(col0 + wc * 64 + c2 * 32 + lr) * m + k] : 0.0f;
     const float kt = j.kt_tab[t];
-    // PF: the epilogue's x and y (16 float4 each per thread, the phase-2
-    // mapping below) are loaded into registers once the last chunk's copies
-    // are issued, so their HBM latency overlaps the final chunks' MFMAs
+    // PF: the epilogue's x and y (128 / CPI float4 each per thread, the
+    // phase-2 mapping below) are loaded into registers once the last chunk's
+    // copies are issued, so their HBM latency overlaps the final chunks' MFMAs
     const size_t Np = (size_t)j.Np;
     const int tr = (threadIdx.x & 31) * 4;
     // native vectors: arrays of HIP's float4 struct are not promoted to registers
-    EpiPrefetch<PF ? 2 * (kT2 / 8) : 0> pf;
+    constexpr int NPF = PF ? 2 * (kT2 / CPI) : 0;
+    EpiPrefetch<NPF> pf;
     pf.px = x_in;
     pf.py = j.y;
     pf.off0 = (size_t)(col0 + (threadIdx.x >> 5)) * Np + row0 + tr;
-    pf.stride = 8 * Np;
-    mma_tile_dma<PREC, M, PF ? 2 * (kT2 / 8) : 0>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds, pf);
+    pf.stride = CPI * Np;
+    mma_tile_dma<PREC, M, NPF, NW, staged_chunk<M>()>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds,
+                                                       pf);
 
     // Epilogue in two phases.  (1) h = sum_k coef_k(col) H_k(row, col) from the
     // accumulators (same k order as the register-tile kernel) into an LDS tile
     // hs[col][row] (pitch 132 floats: conflict-free 16-byte writes).  (2) The
-    // update: thread t takes rows 4 (t mod 32) .. +3 of columns t / 32 + 8 i, so
-    // 32 lanes read and write one 512-byte segment of a column of x, y and phi.
+    // update: thread t takes rows 4 (t mod 32) .. +3 of columns t / 32 + CPI i,
+    // so 32 lanes read and write one 512-byte segment of a column of x, y and phi.
     float *hs = (float *)lds;
     __syncthreads();
 #pragma unroll
@@ -641,7 +706,7 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
         const int cl = wc * 64 + c2 * 32 + lr;
         const float *cf = cfs[c2];
 #pragma unroll
-        for (int r2 = 0; r2 < 2; ++r2)
+        for (int r2 = 0; r2 < RB; ++r2)
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 float hv[4];
@@ -653,7 +718,7 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
                         if (k < m) h = fmaf(cf[k], acc[k][r2][c2][g * 4 + ii], h);
                     hv[ii] = h;
                 }
-                *(float4 *)(hs + cl * kHsPitch + wr * 64 + r2 * 32 + acc_row(half, g * 4)) =
+                *(float4 *)(hs + cl * kHsPitch + wr * 32 * RB + r2 * 32 + acc_row(half, g * 4)) =
                     make_float4(hv[0], hv[1], hv[2], hv[3]);
             }
     }
@@ -663,7 +728,7 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
     // dt a0 y, the wall, then x, y, phi and the trace written back.
     auto update = [&](int it, f32x4 xv, f32x4 yv, auto noise_tag) __attribute__((always_inline)) {
         constexpr bool NOISE = decltype(noise_tag)::value;
-        const int cl = it * 8 + (threadIdx.x >> 5);
+        const int cl = it * CPI + (threadIdx.x >> 5);
         const int col = col0 + cl, row = row0 + tr;
         const size_t off = (size_t)col * Np + row;
         const float4 hv4 = *(const float4 *)(hs + cl * kHsPitch + tr);
@@ -705,27 +770,28 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
         }
     };
     auto load = [&](const float *base, int it) __attribute__((always_inline)) {
-        return *(const f32x4 *)(base + (size_t)(col0 + it * 8 + (threadIdx.x >> 5)) * Np + row0 + tr);
+        return *(const f32x4 *)(base + (size_t)(col0 + it * CPI + (threadIdx.x >> 5)) * Np + row0 + tr);
     };
     if (j.dt_alpha == 0.0f) {
         // plain SB: fully unrolled, so the prefetched registers are indexed statically
 #pragma unroll
-        for (int it = 0; it < kT2 / 8; ++it) {
+        for (int it = 0; it < kT2 / CPI; ++it) {
             const int i = PF ? it : 0;
             update(it, PF ? pf.xpf[i] : load(x_in, it), PF ? pf.ypf[i] : load(j.y, it), std::false_type{});
         }
     } else {
         // noise injection (Eq. 10): the Gaussian draw makes the body too large to
         // unroll; x and y are read again here
-        for (int it = 0; it < kT2 / 8; ++it) update(it, load(x_in, it), load(j.y, it), std::true_type{});
+        for (int it = 0; it < kT2 / CPI; ++it) update(it, load(x_in, it), load(j.y, it), std::true_type{});
     }
 }
 
 // the stage ring, reused after the k loop for the 128 x 132 float h tile
 template <int MT>
 constexpr size_t staged_lds_bytes() {
-    return (size_t)dma_stages<MT>() * staged_buf_bytes<MT>() > sizeof(float) * kT2 * kHsPitch
-               ? (size_t)dma_stages<MT>() * staged_buf_bytes<MT>()
+    constexpr int CB = staged_chunk<MT>();
+    return (size_t)dma_stages<MT, CB>() * staged_buf_bytes<MT, CB>() > sizeof(float) * kT2 * kHsPitch
+               ? (size_t)dma_stages<MT, CB>() * staged_buf_bytes<MT, CB>()
                : sizeof(float) * kT2 * kHsPitch;
 }
 
@@ -745,12 +811,12 @@ __device__ __forceinline__ void xcd_tile(int tiles_x, int tiles_y, int &bx, int 
     bx = slot % tiles_x;
 }
 
-template <int PREC, int M, bool DSB>
-__global__ __launch_bounds__(kDB) void dense_step_staged_kernel(DenseJob j, int t) {
+template <int PREC, int M, bool DSB, int NW>
+__global__ __launch_bounds__(64 * NW) void dense_step_staged_kernel(DenseJob j, int t) {
     __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<M>()];
     int bx, by;
     xcd_tile(j.tiles_x, j.tiles_y, bx, by);
-    dense_step_staged_body<PREC, M, DSB, true, staged_prefetch<PREC, M>(false)>(j, t, bx, by, lds);
+    dense_step_staged_body<PREC, M, DSB, true, staged_prefetch<PREC, M, NW>(false), NW>(j, t, bx, by, lds);
 }
 
 // XCD-aware order inside one job of a grouped launch (its first block index
@@ -780,9 +846,11 @@ __device__ __forceinline__ void xcd_tile_local(int64_t local, int tiles_x, int t
 // Grouped staged step over jobs that share m = MT; job i owns blocks
 // [block_start[i], block_start[i + 1]) (padded to a multiple of 8; blocks past
 // its tiles exit at once).
-template <int PREC, int MT, bool DSB>
-__global__ __launch_bounds__(kDB) void dense_batch_step_staged_kernel(const DenseJob *__restrict__ jobs, int count,
-                                                                      const int64_t *__restrict__ block_start, int t) {
+template <int PREC, int MT, bool DSB, int NW>
+__global__ __launch_bounds__(64 * NW) void dense_batch_step_staged_kernel(const DenseJob *__restrict__ jobs,
+                                                                          int count,
+                                                                          const int64_t *__restrict__ block_start,
+                                                                          int t) {
     __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<MT>()];
     const int64_t b = blockIdx.x;
     int i = 0;
@@ -792,7 +860,7 @@ __global__ __launch_bounds__(kDB) void dense_batch_step_staged_kernel(const Dens
     if (local >= (int64_t)j.tiles_x * j.tiles_y) return;
     int bx, by;
     xcd_tile_local(local, j.tiles_x, j.tiles_y, bx, by);
-    dense_step_staged_body<PREC, MT, DSB, true, staged_prefetch<PREC, MT>(true)>(j, t, bx, by, lds);
+    dense_step_staged_body<PREC, MT, DSB, true, staged_prefetch<PREC, MT, NW>(true), NW>(j, t, bx, by, lds);
 }
 
 // Field mode (reduced-precision error reporting): field[col][k][i] = 2^e_k (J~_k Phi)_i.
@@ -1047,9 +1115,18 @@ static void step_dispatch_m(dim3 grid, hipStream_t st, const DenseJob &j, int t)
     }
 }
 
+// Waves per staged block: eight (two per SIMD, 32 x 64 wave tiles) for the
+// BF16 and FP8 operands, whose MFMAs are short beside the operand copies and
+// whose second wave per SIMD hides copy and barrier waits (C3 shape: BF16
+// 112.5 -> 106.9 us, FP8 73.7 -> 63.6 us per step); four for FP32 (64 x 64
+// wave tiles), where eight measured 2-6 % slower.
+template <int PREC>
+constexpr int staged_waves() { return PREC == QAIA_FP32 ? 4 : 8; }
+
 template <int PREC, int M, bool DSB>
 static void staged_launch(dim3 grid, hipStream_t st, const DenseJob &j, int t) {
-    hipLaunchKernelGGL((dense_step_staged_kernel<PREC, M, DSB>), grid, dim3(kDB), 0, st, j, t);
+    constexpr int NW = staged_waves<PREC>();
+    hipLaunchKernelGGL((dense_step_staged_kernel<PREC, M, DSB, NW>), grid, dim3(64 * NW), 0, st, j, t);
 }
 
 template <int PREC, bool DSB>
@@ -1088,11 +1165,12 @@ static void step_dispatch(int prec, bool dsb, dim3 grid, hipStream_t st, const D
 template <int PREC, bool DSB>
 static void staged_batch_launch(int mt, dim3 grid, hipStream_t st, const DenseJob *jobs, int count,
                                 const int64_t *starts, int t) {
+    constexpr int NW = staged_waves<PREC>();
     switch (mt) {
-        case 1: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 1, DSB>), grid, dim3(kDB), 0, st, jobs, count, starts, t); break;
-        case 2: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 2, DSB>), grid, dim3(kDB), 0, st, jobs, count, starts, t); break;
-        case 3: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 3, DSB>), grid, dim3(kDB), 0, st, jobs, count, starts, t); break;
-        case 4: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 4, DSB>), grid, dim3(kDB), 0, st, jobs, count, starts, t); break;
+        case 1: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 1, DSB, NW>), grid, dim3(64 * NW), 0, st, jobs, count, starts, t); break;
+        case 2: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 2, DSB, NW>), grid, dim3(64 * NW), 0, st, jobs, count, starts, t); break;
+        case 3: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 3, DSB, NW>), grid, dim3(64 * NW), 0, st, jobs, count, starts, t); break;
+        case 4: hipLaunchKernelGGL((dense_batch_step_staged_kernel<PREC, 4, DSB, NW>), grid, dim3(64 * NW), 0, st, jobs, count, starts, t); break;
         default: throw Error{QAIA_UNSUPPORTED, "dense path supports m <= 4"};
     }
 }

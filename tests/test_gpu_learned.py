@@ -230,7 +230,7 @@ def test_trained_network_needs_fewer_rounds(q):
     assert np.median(rounds["learned"]) < np.median(rounds["uniform"])
 
 
-def test_north_star_form_reaches_reference_first(q):
+def test_combined_form_reaches_reference_first(q):
     """The batched low-precision + learned-proposal form (discrete SB on the
     BF16 matrix-core path, weight vectors from the learned proposer, each round
     one launch of 1024 weight vectors x 8 replicas) reaches the hypervolume of
