@@ -41,13 +41,13 @@ SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
 # HBM bytes of one qaia_sb_reg launch on this workload, from two rocprofv3
 # --pmc passes over `bench.py --traffic-probe` (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch), each scaled by the same counter's reading for a plain
-# 1 GiB device copy in the same process (read 524308.9375 KiB, written
-# 1048576 KiB).  Set to None whenever the generated kernel changes, until the
-# counters are taken again.
+# 1 GiB device copy in the same process (nine copy dispatches: read 524322.4375
+# KiB, written 1048579.46875 KiB).  Set to None whenever the generated kernel
+# changes, until the counters are taken again.
 _KIB = 1024.0
-_FETCH_SCALE = 1048576.0 / 524308.9375
-_WRITE_SCALE = 1048576.0 / 1048576.0
-SB_REG_TRAFFIC_BYTES = (3699.6875 * _FETCH_SCALE + 200000.0 * _WRITE_SCALE) * _KIB
+_FETCH_SCALE = 1048576.0 / 524322.4375
+_WRITE_SCALE = 1048576.0 / 1048579.46875
+SB_REG_TRAFFIC_BYTES = (3681.25 * _FETCH_SCALE + 200000.0 * _WRITE_SCALE) * _KIB
 
 
 def algorithmic_flops_per_replica_step(n: int, E: int) -> int:

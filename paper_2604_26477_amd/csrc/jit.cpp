@@ -126,9 +126,13 @@ static std::string generate(const Problem &p, int variant, bool trace, bool nois
     s << "    return;\n  }\n";
     // "+ 0.0f" turns a -0 start (init_amp = 0) into +0, so x is never -0 and
     // sgn(x) = copysign(1, x) agrees with sgn(0) = +1
+    // an empty asm after each spin's start values keeps the compiler from
+    // interleaving all 2n 64-bit hash computations, which pushed the prologue
+    // past the register budget and spilled to scratch
     for (int i = 0; i < n; ++i)
         s << "  float X" << i << " = initv(seed, ((g * " << n << "ull + " << i << "ull) << 1), amp) + 0.0f, Y"
-          << i << " = initv(seed, ((g * " << n << "ull + " << i << "ull) << 1) | 1ull, amp);\n";
+          << i << " = initv(seed, ((g * " << n << "ull + " << i << "ull) << 1) | 1ull, amp);\n"
+          << "  asm volatile(\"\" : \"+v\"(X" << i << "), \"+v\"(Y" << i << "));\n";
     s << "  const float* jr = jcp + w * " << E << "ll;\n";
     for (int64_t e = 0; e < E; ++e) s << "  const float J" << e << " = jr[" << e << "];\n";
     s << "  for (int t = 0; t < T; ++t) {\n";
@@ -220,7 +224,8 @@ static std::string generate16(const Problem &p, int variant, bool trace, bool no
         s << "  h2 X" << i << " = hp(initv(seed, ((g0 * " << n << "ull + " << i << "ull) << 1), amp), initv(seed, ((g1 * "
           << n << "ull + " << i << "ull) << 1), amp)) + zero, Y" << i << " = hp(initv(seed, ((g0 * " << n
           << "ull + " << i << "ull) << 1) | 1ull, amp), initv(seed, ((g1 * " << n << "ull + " << i
-          << "ull) << 1) | 1ull, amp));\n";
+          << "ull) << 1) | 1ull, amp));\n"
+          << "  asm volatile(\"\" : \"+v\"(X" << i << "), \"+v\"(Y" << i << "));\n";
     s << "  const float* ja = jcp + w0 * " << E << "ll;\n";
     s << "  const float* jb = jcp + w1 * " << E << "ll;\n";
     for (int64_t e = 0; e < E; ++e) s << "  const h2 J" << e << " = hp(ja[" << e << "], jb[" << e << "]);\n";
@@ -437,10 +442,12 @@ static std::set<uint64_t> g_spilling;                  // sources whose step loo
 // Three waves per SIMD (168 VGPRs) where the step loop still fits without
 // spills, which hides more of the FMA chains' latency (5-7 % on the 42-node
 // graph); otherwise two (256 VGPRs: every graph the path admits keeps its
-// state in registers there, spills land outside the loop).
+// state in registers there, spills land outside the loop).  The binary16
+// kernels always ask for two: their packed instructions issue one per slot
+// whatever the occupancy, and three measured 1-4 % slower.
 static JitKernel *build_kernel(const Problem &p, int variant, bool trace, bool noise, bool half = false) {
     std::vector<char> code;
-    for (int waves = 3; waves >= 2 && code.empty(); --waves) {
+    for (int waves = half ? 2 : 3; waves >= 2 && code.empty(); --waves) {
         const std::string src =
             half ? generate16(p, variant, trace, noise, waves) : generate(p, variant, trace, noise, waves);
         const uint64_t h = fnv1a(src);
