@@ -127,7 +127,8 @@ def test_batch_empty_single_and_no_items(q, variant):
     torch.cuda.synchronize()
 
 
-def test_batch_low_precision_dense(q):
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_batch_low_precision_dense(q, prec):
     import torch
     specs = [(90, 3, "p0.1", "dense"), (150, 4, "p0.5", "dense_staged"), (130, 3, "complete", "dense"),
              (200, 3, "complete", "dense_staged"), (160, 2, "complete", "dense_staged")]
@@ -137,9 +138,9 @@ def test_batch_low_precision_dense(q):
         p = q.problem_from_instance(inst)
         c = _dev(wl.dirichlet_weights(5, m, 950 + i))
         items.append(q.BatchItem(p, c, 16, path))
-        sp, ob, _ = q.qaia_sample(p, c, 16, q.make_schedule("dsb", precision="bf16", steps=200, seed=3, path=path))
+        sp, ob, _ = q.qaia_sample(p, c, 16, q.make_schedule("dsb", precision=prec, steps=200, seed=3, path=path))
         refs.append((sp, ob))
-    q.qaia_sample_batch(items, q.make_schedule("dsb", precision="bf16", steps=200, seed=3))
+    q.qaia_sample_batch(items, q.make_schedule("dsb", precision=prec, steps=200, seed=3))
     torch.cuda.synchronize()
     for it, (sp, ob) in zip(items, refs):
         assert torch.equal(it.spins, sp) and torch.equal(it.obj, ob)

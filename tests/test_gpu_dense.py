@@ -184,14 +184,17 @@ def test_dense_invalid_rows_and_determinism(q, path):
     assert not a[8:12].any() and not oa[8:12].any()
 
 
-@pytest.mark.parametrize("m", [2, 4])
+@pytest.mark.parametrize("m", [1, 2, 3, 4])
 @pytest.mark.parametrize("variant,prec", [("bsb", "fp32"), ("dsb", "bf16"), ("dsb", "fp8")])
 def test_staged_tiles_match_register_tiles_when_exact(q, variant, prec, m):
     """Exact weights make every partial sum an exact integer, so the two tile
     kernels must agree bit for bit whatever their k order: 300 spins (three
     128-spin tiles, ragged) and 20 x 16 replicas (three 128-column tiles,
-    ragged); m = 2 runs the staged epilogue on prefetched x and y, m = 4 loads
-    them after the k loop."""
+    ragged).  The staged variants this covers: 128-byte chunks in three
+    stages (m <= 2) or two (m = 3), 64-byte chunks for m = 4 (where an FP8
+    chunk holds one k-group and the units split the accumulators); four
+    waves (FP32) or eight (BF16, FP8); x and y prefetched during the k loop
+    (m = 1, and m = 2 in FP32) or loaded after it."""
     inst = _small_int_instance(300, m, seed=60, kind="p0.6")
     c = wl.dirichlet_weights(20, m, 61)
     prob = q.problem_from_instance(inst)
