@@ -796,9 +796,14 @@ constexpr size_t staged_lds_bytes() {
 }
 
 // XCD-aware tile order for a single job: blocks are dealt to the eight XCDs
-// round robin (block b runs on XCD b % 8), so when the row-tile count divides
-// by 8, XCD x is given row tiles [x*ty/8, (x+1)*ty/8) across all column tiles
-// and the J rows it reads stay in its own L2.
+// round robin (block b runs on XCD b % 8).  When the row-tile count divides by
+// 8 and the column-tile count is even, XCD x owns a quarter of the row tiles
+// (group x & 3) times half of the column tiles (group x >> 2), and its
+// consecutive blocks sweep the group's row tiles first: with 16 row tiles its
+// 32 CUs hold 4 x 8 patches, so each J and phi chunk they copy serves 8 or 4
+// blocks from its own L2 (about 2 % faster in BF16 and FP8 than giving each
+// XCD whole row tiles across all columns, which is the order used when the
+// column-tile count is odd).
 __device__ __forceinline__ void xcd_tile(int tiles_x, int tiles_y, int &bx, int &by) {
     const int b = blockIdx.y * gridDim.x + blockIdx.x;
     if ((tiles_y & 7) != 0) {
@@ -807,6 +812,12 @@ __device__ __forceinline__ void xcd_tile(int tiles_x, int tiles_y, int &bx, int 
         return;
     }
     const int xcd = b & 7, slot = b >> 3;
+    if ((tiles_x & 1) == 0) {
+        const int RG = tiles_y >> 2, CG = tiles_x >> 1;
+        by = (xcd & 3) * RG + slot % RG;
+        bx = (xcd >> 2) * CG + slot / RG;
+        return;
+    }
     by = xcd * (tiles_y >> 3) + slot / tiles_x;
     bx = slot % tiles_x;
 }

@@ -129,12 +129,14 @@ def test_low_precision_reproduces_fp32_bitwise_when_exact(q, path):
 
 
 def test_staged_tile_order_at_scale_matches_register_tiles(q):
-    """At 512 spins x 8192 columns the staged kernel deals its tiles to the
-    XCDs in 4 x 8 patches; with exact weights both dense kernels compute exact
-    fields, so their spins and cuts agree bit for bit in every precision."""
+    """At 1024 spins x 2048 columns (8 x 16 tiles) the staged kernel deals its
+    tiles to the XCDs in row-first patches (each XCD a quarter of the row
+    tiles times half of the column tiles); with exact weights both dense
+    kernels compute exact fields, so their spins and cuts agree bit for bit
+    in every precision: a tile computed twice or not at all would not."""
     import torch
-    inst = _small_int_instance(512, 3, seed=61)
-    c = wl.dirichlet_weights(1024, 3, 62)
+    inst = _small_int_instance(1024, 3, seed=61)
+    c = wl.dirichlet_weights(256, 3, 62)
     prob = q.problem_from_instance(inst)
     for prec in ("fp32", "bf16", "fp8"):
         got = {}
