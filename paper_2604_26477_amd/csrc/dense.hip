@@ -25,6 +25,7 @@
 // any internal k order of the instruction.  The staged tile (below) doubles
 // the block to 128 x 128 and reads each operand chunk once through LDS.
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -222,9 +223,10 @@ __global__ __launch_bounds__(kDB) void dense_batch_step_kernel(const DenseJob *_
 }
 
 // ---------------------------------------------------------------------------
-// Staged tile: a block of NW waves owns 128 spins x 128 columns; wave (wr, wc)
-// owns (32 RB) x 64 (RB x 2 accumulators per objective, RB = 8 / NW).  The k
-// dimension runs in chunks of CB bytes per row (64 or 128).  Each chunk of the
+// Staged tile: a block of NW waves owns 128 spins x 64 CBW columns (CBW = 2,
+// or 4 for the wide BF16 tile); wave (wr, wc) owns (32 RB) x (32 CBW) (RB x CBW
+// accumulators per objective, RB = 8 / NW).  The k dimension runs in chunks
+// of CB bytes per row (64 or 128).  Each chunk of the
 // block's J rows (all objectives) and Phi columns is copied to LDS once (by
 // global_load_lds, below) and read there by every wave that needs it; D stage
 // buffers form a ring and there is one barrier per chunk.  Loads of
@@ -271,8 +273,8 @@ template <> struct FragType<QAIA_FP32> { typedef float4 V; };
 template <> struct FragType<QAIA_BF16> { typedef bf16x8 V; };
 template <> struct FragType<QAIA_FP8> { typedef i32x8 V; };
 
-template <int PREC, int MT, int RB, int KPU> struct Frags {
-    typename FragType<PREC>::V a[KPU][MT][RB], b[KPU][2];
+template <int PREC, int MT, int RB, int KPU, int CBW = 2> struct Frags {
+    typename FragType<PREC>::V a[KPU][MT][RB], b[KPU][CBW];
 };
 
 struct LaneLds {
@@ -285,8 +287,8 @@ __device__ __forceinline__ u32x4 lds16(const char *row, int part, int sw) {
     return *(const u32x4 *)(row + ((part ^ sw) << 4));
 }
 
-template <int PREC, int MT, int RB, int CB>
-__device__ __forceinline__ void frag_load(Frags<PREC, MT, RB, kg_per_unit<PREC, CB>()> &f, const LaneLds &L, int u) {
+template <int PREC, int MT, int RB, int CB, int CBW = 2>
+__device__ __forceinline__ void frag_load(Frags<PREC, MT, RB, kg_per_unit<PREC, CB>(), CBW> &f, const LaneLds &L, int u) {
     constexpr int KPU = kg_per_unit<PREC, CB>();
     if constexpr (PREC == QAIA_FP8) {
         // lane half h holds k = 32h + 0..31 of a 64-byte k-group: parts 4g + 2h, 4g + 2h + 1
@@ -312,7 +314,7 @@ __device__ __forceinline__ void frag_load(Frags<PREC, MT, RB, kg_per_unit<PREC, 
             for (int kk = 0; kk < KPU; ++kk) {
                 const int g = u * KPU + kk;
 #pragma unroll
-                for (int c2 = 0; c2 < 2; ++c2) f.b[kk][c2] = frag(L.b + c2 * 32 * CB, g);
+                for (int c2 = 0; c2 < CBW; ++c2) f.b[kk][c2] = frag(L.b + c2 * 32 * CB, g);
 #pragma unroll
                 for (int k = 0; k < MT; ++k)
 #pragma unroll
@@ -326,7 +328,7 @@ __device__ __forceinline__ void frag_load(Frags<PREC, MT, RB, kg_per_unit<PREC, 
         for (int kk = 0; kk < KPU; ++kk) {
             const int p = 2 * (u * KPU + kk) + L.half;
 #pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2) f.b[kk][c2] = __builtin_bit_cast(VT, lds16(L.b + c2 * 32 * CB, p, L.sw));
+            for (int c2 = 0; c2 < CBW; ++c2) f.b[kk][c2] = __builtin_bit_cast(VT, lds16(L.b + c2 * 32 * CB, p, L.sw));
 #pragma unroll
             for (int k = 0; k < MT; ++k)
 #pragma unroll
@@ -337,8 +339,8 @@ __device__ __forceinline__ void frag_load(Frags<PREC, MT, RB, kg_per_unit<PREC, 
 }
 
 // One MFMA of objective k on accumulator (r2, c2) with unit-local k-group kk.
-template <int PREC, int MT, int RB, int KPU>
-__device__ __forceinline__ void mma_one(const Frags<PREC, MT, RB, KPU> &f, f16v &a, int kk, int k, int ra, int cb,
+template <int PREC, int MT, int RB, int KPU, int CBW>
+__device__ __forceinline__ void mma_one(const Frags<PREC, MT, RB, KPU, CBW> &f, f16v &a, int kk, int k, int ra, int cb,
                                         int j) {
     if constexpr (PREC == QAIA_FP8) {
         a = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.a[kk][k][ra], f.b[kk][cb], a, 0, 0, 0, 127, 0, 127);
@@ -354,15 +356,15 @@ __device__ __forceinline__ void mma_one(const Frags<PREC, MT, RB, KPU> &f, f16v 
 
 // The MFMAs of unit u in a fixed order; after the i-th, hook(i) runs (the
 // copy interleaving below).  MFMAs per unit with m = MT: unit_mfmas().
-template <int PREC, int MT, int RB, int CB>
+template <int PREC, int MT, int RB, int CB, int CBW = 2>
 constexpr int unit_mfmas() {
     return half_units<PREC, CB>() ? MT * RB
-                                  : kg_per_unit<PREC, CB>() * MT * RB * 2 * (PREC == QAIA_FP32 ? 4 : 1);
+                                  : kg_per_unit<PREC, CB>() * MT * RB * CBW * (PREC == QAIA_FP32 ? 4 : 1);
 }
 
-template <int PREC, int MT, int RB, int CB, typename Hook>
-__device__ __forceinline__ void unit_mma(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>()> &f, int m, int u,
-                                         f16v (&acc)[MT][RB][2], Hook &&hook) {
+template <int PREC, int MT, int RB, int CB, int CBW, typename Hook>
+__device__ __forceinline__ void unit_mma(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>(), CBW> &f, int m, int u,
+                                         f16v (&acc)[MT][RB][CBW], Hook &&hook) {
     constexpr int KPU = kg_per_unit<PREC, CB>();
     constexpr int NJ = PREC == QAIA_FP32 ? 4 : 1;  // fp32: four 32x32x2 steps per 16-byte fragment
     int i = 0;
@@ -390,7 +392,7 @@ __device__ __forceinline__ void unit_mma(const Frags<PREC, MT, RB, kg_per_unit<P
 #pragma unroll
                 for (int r2 = 0; r2 < RB; ++r2)
 #pragma unroll
-                    for (int c2 = 0; c2 < 2; ++c2)
+                    for (int c2 = 0; c2 < CBW; ++c2)
 #pragma unroll
                         for (int j = 0; j < NJ; ++j) {
                             mma_one(f, acc[k][r2][c2], kk, k, r2, c2, j);
@@ -400,22 +402,22 @@ __device__ __forceinline__ void unit_mma(const Frags<PREC, MT, RB, kg_per_unit<P
     }
 }
 
-template <int PREC, int MT, int RB, int CB>
-__device__ __forceinline__ void frag_mma(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>()> &f, int m, int u,
-                                         f16v (&acc)[MT][RB][2]) {
-    unit_mma<PREC, MT, RB, CB>(f, m, u, acc, [](int) {});
+template <int PREC, int MT, int RB, int CB, int CBW = 2>
+__device__ __forceinline__ void frag_mma(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>(), CBW> &f, int m, int u,
+                                         f16v (&acc)[MT][RB][CBW]) {
+    unit_mma<PREC, MT, RB, CB, CBW>(f, m, u, acc, [](int) {});
 }
 
 // frag_mma with NC copies of the next chunk interleaved: copy j is issued
 // after MFMA (j * NM) / NC of the unit (NM MFMAs when m == MT), so a copy that
 // waits for room in the memory queue stalls behind queued matrix work instead
 // of in front of an idle matrix pipe.  Copies not yet issued (m < MT) follow.
-template <int PREC, int MT, int RB, int CB, int NC, typename Copy>
-__device__ __forceinline__ void frag_mma_cp(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>()> &f, int m, int u,
-                                            f16v (&acc)[MT][RB][2], Copy &&copy) {
-    constexpr int NM = unit_mfmas<PREC, MT, RB, CB>();
+template <int PREC, int MT, int RB, int CB, int NC, int CBW = 2, typename Copy>
+__device__ __forceinline__ void frag_mma_cp(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>(), CBW> &f, int m, int u,
+                                            f16v (&acc)[MT][RB][CBW], Copy &&copy) {
+    constexpr int NM = unit_mfmas<PREC, MT, RB, CB, CBW>();
     int j = 0;
-    unit_mma<PREC, MT, RB, CB>(f, m, u, acc, [&](int i) {
+    unit_mma<PREC, MT, RB, CB, CBW>(f, m, u, acc, [&](int i) {
         if constexpr (NC > 0) {
             if (j < NC && i == (j * NM) / NC) {
                 __builtin_amdgcn_sched_barrier(0);
@@ -527,19 +529,30 @@ __device__ __forceinline__ void epi_prefetch(EpiPrefetch<NPF> &pf) {
     }
 }
 
-template <int PREC, int MT, int NPF, int NW, int CB>
+// The wide tile (CBW = 4) copies 3 x 128 + 256 rows of 64 bytes per chunk
+// into three 40 KB stages; its epilogue's 256-column h tile (135 KB) reuses
+// them.  It keeps one fragment set (the 192 accumulator registers of m = 3
+// leave no room for two; the second wave on each SIMD overlaps the fragment
+// reads instead).
+template <int MT, int CB, int CBW>
+constexpr int wide_stages() { return CBW == 2 ? dma_stages<MT, CB>() : 3; }
+
+template <int PREC, int MT, int NPF, int NW, int CB, int CBW = 2>
 __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, int Np_, int m, int row0, int col0,
-                                             int wr, int wc, int half, int lr, f16v (&acc)[MT][8 / NW][2],
+                                             int wr, int wc, int half, int lr, f16v (&acc)[MT][8 / NW][CBW],
                                              char *lds, EpiPrefetch<NPF> &pf) {
     typedef typename PrecInfo<PREC>::T T;
     constexpr int ES = sizeof(T);
     constexpr int RB = 8 / NW;                // 32-row accumulator blocks per wave
     constexpr int GPR = CB / 16;              // 16-byte granules per chunk row
-    static_assert((2 * GPR * (MT + 1)) % NW == 0, "copies per wave");
-    constexpr int PER = 2 * GPR * (MT + 1) / NW;  // copies per wave per chunk
+    constexpr int TW = 64 * CBW;              // tile columns
+    constexpr int ROWS = MT * kT2 + TW;       // stage rows
+    static_assert((ROWS * GPR) % (64 * NW) == 0, "copies per wave");
+    constexpr int PER = ROWS * GPR / (64 * NW);  // copies per wave per chunk
     constexpr int P0 = PER / 2, P1 = PER - P0;    // spread over the two MFMA groups
     constexpr int KPU = kg_per_unit<PREC, CB>();
-    constexpr int D = dma_stages<MT, CB>();
+    constexpr bool SINGLE = CBW > 2;          // one fragment set (register budget)
+    constexpr int D = wide_stages<MT, CB, CBW>();
     static_assert(D >= 2 && D - 2 <= 6, "stage ring depth");
     static_assert((D - 2) * PER + NPF <= 63, "vmcnt range");
     const size_t Np = (size_t)Np_;
@@ -556,13 +569,13 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
             src[i] = (const char *)phiv + ((size_t)(col0 + R - MT * kT2) * Np) * ES + p * 16;
         }
     }
-    constexpr int SB = staged_buf_bytes<MT, CB>();
+    constexpr int SB = ROWS * CB;
     char *S[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) S[i] = lds + i * SB;
     const int nk = (int)(Np * ES / CB);
     const int sw = row_swizzle<CB>(lr);
-    const int aoff = (wr * 32 * RB + lr) * CB, boff = (MT * kT2 + wc * 64 + lr) * CB;
+    const int aoff = (wr * 32 * RB + lr) * CB, boff = (MT * kT2 + wc * 32 * CBW + lr) * CB;
     auto lane_lds = [&](int st) { return LaneLds{S[st] + aoff, S[st] + boff, sw, half}; };
 #pragma unroll
     for (int q = 0; q < D - 1; ++q)
@@ -581,7 +594,7 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
     // Rotation: after the barrier for chunk c, unit 0 of chunk c is read while
     // unit 1 of chunk c - 1 (already in registers) runs, then unit 1 of chunk c
     // is read while unit 0 of chunk c runs.
-    Frags<PREC, MT, RB, KPU> f0, f1;
+    Frags<PREC, MT, RB, KPU, CBW> f0, f1;
     for (int c0 = 0; c0 < nk; c0 += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) {
@@ -608,18 +621,28 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
                 };
                 const LaneLds L = lane_lds(u);
                 // scheduling barriers keep each unit's reads ahead of the other unit's MFMAs
-                frag_load<PREC, MT, RB, CB>(f0, L, 0);
+                if constexpr (SINGLE) {
+                    frag_load<PREC, MT, RB, CB, CBW>(f0, L, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    frag_mma_cp<PREC, MT, RB, CB, kSpread ? P0 : 0, CBW>(f0, m, 0, acc, copy0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    frag_load<PREC, MT, RB, CB, CBW>(f0, L, 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    frag_mma_cp<PREC, MT, RB, CB, kSpread ? P1 : 0, CBW>(f0, m, 1, acc, copy1);
+                } else {
+                frag_load<PREC, MT, RB, CB, CBW>(f0, L, 0);
                 __builtin_amdgcn_sched_barrier(0);
                 if (c > 0) {
-                    frag_mma_cp<PREC, MT, RB, CB, kSpread ? P0 : 0>(f1, m, 1, acc, copy0);
+                    frag_mma_cp<PREC, MT, RB, CB, kSpread ? P0 : 0, CBW>(f1, m, 1, acc, copy0);
                 } else {
 #pragma unroll
                     for (int i = 0; i < P0; ++i) copy0(i);
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                frag_load<PREC, MT, RB, CB>(f1, L, 1);
+                frag_load<PREC, MT, RB, CB, CBW>(f1, L, 1);
                 __builtin_amdgcn_sched_barrier(0);
-                frag_mma_cp<PREC, MT, RB, CB, kSpread ? P1 : 0>(f0, m, 0, acc, copy1);
+                frag_mma_cp<PREC, MT, RB, CB, kSpread ? P1 : 0, CBW>(f0, m, 0, acc, copy1);
+                }
                 __builtin_amdgcn_sched_barrier(0);
                 if constexpr (NPF > 0) {
                     if (c == c_pf) epi_prefetch(pf);
@@ -628,7 +651,7 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
             }
         }
     }
-    frag_mma<PREC, MT, RB, CB>(f1, m, 1, acc);
+    if constexpr (!SINGLE) frag_mma<PREC, MT, RB, CB, CBW>(f1, m, 1, acc);
     lds_barrier();
 }
 
@@ -646,14 +669,15 @@ constexpr bool staged_prefetch(bool grouped) {
 // FIXED_M: the job's m equals MT (single-job launches), so objective guards fold away.
 // PF: the epilogue's x and y are prefetched into registers during the k loop
 // (where they fit beside the accumulators and fragments without spilling).
-template <int PREC, int MT, bool DSB, bool FIXED_M, bool PF, int NW>
+template <int PREC, int MT, bool DSB, bool FIXED_M, bool PF, int NW, int CBW = 2>
 __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t, int bx, int by, char *lds) {
-    constexpr int RB = 8 / NW;   // 32-row accumulator blocks per wave: waves own (32 RB) x 64
+    constexpr int RB = 8 / NW;   // 32-row accumulator blocks per wave: waves own (32 RB) x (32 CBW)
     constexpr int CPI = 2 * NW;  // columns per pass of the update phase
+    constexpr int TW = 64 * CBW; // tile columns
     const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int half = l >> 5, lr = l & 31;
     const int wr = wv % (NW / 2), wc = wv / (NW / 2);
-    const int row0 = by * kT2, col0 = bx * kT2;
+    const int row0 = by * kT2, col0 = bx * TW;
     constexpr int M = MT;
     const int m = FIXED_M ? MT : j.m;
     const bool even = (t & 1) == 0;
@@ -661,23 +685,26 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
     float *x_out = DSB ? j.xa : (even ? j.xb : j.xa);
     const void *phi_in = DSB ? (even ? j.pa : j.pb) : (const void *)x_in;
     void *phi_out = DSB ? (even ? j.pb : j.pa) : nullptr;
-    f16v acc[M][RB][2];
+    f16v acc[M][RB][CBW];
 #pragma unroll
     for (int k = 0; k < M; ++k)
 #pragma unroll
         for (int r2 = 0; r2 < RB; ++r2)
 #pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2)
+            for (int c2 = 0; c2 < CBW; ++c2)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) acc[k][r2][c2][i] = 0.0f;
     // the epilogue's per-column coefficients and the step coefficient are
     // loaded before the k loop, so their latency hides behind it
-    float cfs[2][M];
+    float cfs[CBW][M];
+    auto load_cfs = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2)
+        for (int c2 = 0; c2 < CBW; ++c2)
 #pragma unroll
-        for (int k = 0; k < M; ++k)
-            cfs[c2][k] = k < m ? j.coef[(size_t)(col0 + wc * 64 + c2 * 32 + lr) * m + k] : 0.0f;
+            for (int k = 0; k < M; ++k)
+                cfs[c2][k] = k < m ? j.coef[(size_t)(col0 + wc * 32 * CBW + c2 * 32 + lr) * m + k] : 0.0f;
+    };
+    if constexpr (CBW == 2) load_cfs();
     const float kt = j.kt_tab[t];
     // PF: the epilogue's x and y (128 / CPI float4 each per thread, the
     // phase-2 mapping below) are loaded into registers once the last chunk's
@@ -685,14 +712,15 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
     const size_t Np = (size_t)j.Np;
     const int tr = (threadIdx.x & 31) * 4;
     // native vectors: arrays of HIP's float4 struct are not promoted to registers
-    constexpr int NPF = PF ? 2 * (kT2 / CPI) : 0;
+    constexpr int NPF = PF ? 2 * (TW / CPI) : 0;
     EpiPrefetch<NPF> pf;
     pf.px = x_in;
     pf.py = j.y;
     pf.off0 = (size_t)(col0 + (threadIdx.x >> 5)) * Np + row0 + tr;
     pf.stride = CPI * Np;
-    mma_tile_dma<PREC, M, NPF, NW, staged_chunk<M>()>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds,
-                                                       pf);
+    mma_tile_dma<PREC, M, NPF, NW, CBW == 2 ? staged_chunk<M>() : 64, CBW>(j.J, phi_in, j.Np, m, row0, col0, wr, wc,
+                                                                            half, lr, acc, lds, pf);
+    if constexpr (CBW != 2) load_cfs();
 
     // Epilogue in two phases.  (1) h = sum_k coef_k(col) H_k(row, col) from the
     // accumulators (same k order as the register-tile kernel) into an LDS tile
@@ -702,8 +730,8 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
     float *hs = (float *)lds;
     __syncthreads();
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
-        const int cl = wc * 64 + c2 * 32 + lr;
+    for (int c2 = 0; c2 < CBW; ++c2) {
+        const int cl = wc * 32 * CBW + c2 * 32 + lr;
         const float *cf = cfs[c2];
 #pragma unroll
         for (int r2 = 0; r2 < RB; ++r2)
@@ -775,24 +803,24 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
     if (j.dt_alpha == 0.0f) {
         // plain SB: fully unrolled, so the prefetched registers are indexed statically
 #pragma unroll
-        for (int it = 0; it < kT2 / CPI; ++it) {
+        for (int it = 0; it < TW / CPI; ++it) {
             const int i = PF ? it : 0;
             update(it, PF ? pf.xpf[i] : load(x_in, it), PF ? pf.ypf[i] : load(j.y, it), std::false_type{});
         }
     } else {
         // noise injection (Eq. 10): the Gaussian draw makes the body too large to
         // unroll; x and y are read again here
-        for (int it = 0; it < kT2 / CPI; ++it) update(it, load(x_in, it), load(j.y, it), std::true_type{});
+        for (int it = 0; it < TW / CPI; ++it) update(it, load(x_in, it), load(j.y, it), std::true_type{});
     }
 }
 
 // the stage ring, reused after the k loop for the 128 x 132 float h tile
-template <int MT>
+template <int MT, int CBW = 2>
 constexpr size_t staged_lds_bytes() {
-    constexpr int CB = staged_chunk<MT>();
-    return (size_t)dma_stages<MT, CB>() * staged_buf_bytes<MT, CB>() > sizeof(float) * kT2 * kHsPitch
-               ? (size_t)dma_stages<MT, CB>() * staged_buf_bytes<MT, CB>()
-               : sizeof(float) * kT2 * kHsPitch;
+    constexpr int CB = CBW == 2 ? staged_chunk<MT>() : 64;
+    constexpr size_t ring = (size_t)wide_stages<MT, CB, CBW>() * (MT * kT2 + 64 * CBW) * CB;
+    constexpr size_t hsb = sizeof(float) * 64 * CBW * kHsPitch;
+    return ring > hsb ? ring : hsb;
 }
 
 // XCD-aware tile order for a single job: blocks are dealt to the eight XCDs
@@ -822,12 +850,13 @@ __device__ __forceinline__ void xcd_tile(int tiles_x, int tiles_y, int &bx, int 
     bx = slot % tiles_x;
 }
 
-template <int PREC, int M, bool DSB, int NW>
+template <int PREC, int M, bool DSB, int NW, int CBW = 2>
 __global__ __launch_bounds__(64 * NW) void dense_step_staged_kernel(DenseJob j, int t) {
-    __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<M>()];
+    __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<M, CBW>()];
     int bx, by;
-    xcd_tile(j.tiles_x, j.tiles_y, bx, by);
-    dense_step_staged_body<PREC, M, DSB, true, staged_prefetch<PREC, M, NW>(false), NW>(j, t, bx, by, lds);
+    xcd_tile(j.tiles_x / (CBW / 2), j.tiles_y, bx, by);
+    dense_step_staged_body<PREC, M, DSB, true, CBW == 2 && staged_prefetch<PREC, M, NW>(false), NW, CBW>(j, t, bx, by,
+                                                                                                     lds);
 }
 
 // XCD-aware order inside one job of a grouped launch (its first block index
@@ -1134,9 +1163,39 @@ static void step_dispatch_m(dim3 grid, hipStream_t st, const DenseJob &j, int t)
 template <int PREC>
 constexpr int staged_waves() { return PREC == QAIA_FP32 ? 4 : 8; }
 
+// BF16 single-job launches with m = 2 or 3 take the wide tile (128 x 256:
+// 37.5 % fewer operand bytes per flop for m = 3, 25 % for m = 2) when the
+// columns fill 256-column tiles and those tiles still cover every CU
+// (complete N = 2048, 4096 columns: m = 3 106.1 -> 95.3-96.0 us per step,
+// m = 2 82.6 -> 77.9-78.3; m = 1 gains nothing; at N = 1024, 2048 columns the
+// 64 wide tiles would leave most CUs idle: 42.3 against 28.5 us).
+template <int PREC, int M>
+constexpr bool staged_wide() { return PREC == QAIA_BF16 && (M == 2 || M == 3); }
+
+static int device_cus() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    QAIA_HIP(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 64) {
+        const int v = cache[dev].load(std::memory_order_relaxed);
+        if (v > 0) return v;
+    }
+    int cus = 0;
+    QAIA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (dev >= 0 && dev < 64) cache[dev].store(cus, std::memory_order_relaxed);
+    return cus;
+}
+
 template <int PREC, int M, bool DSB>
 static void staged_launch(dim3 grid, hipStream_t st, const DenseJob &j, int t) {
     constexpr int NW = staged_waves<PREC>();
+    if constexpr (staged_wide<PREC, M>()) {
+        if ((j.tiles_x % 2) == 0 && (int64_t)(j.tiles_x / 2) * j.tiles_y >= device_cus()) {
+            hipLaunchKernelGGL((dense_step_staged_kernel<PREC, M, DSB, NW, 4>), dim3(grid.x / 2, grid.y), dim3(64 * NW),
+                               0, st, j, t);
+            return;
+        }
+    }
     hipLaunchKernelGGL((dense_step_staged_kernel<PREC, M, DSB, NW>), grid, dim3(64 * NW), 0, st, j, t);
 }
 
