@@ -70,8 +70,9 @@ def valu_instructions_per_replica_step(inst, variant: str) -> int:
     """VALU instructions of the generated kernel's step loop per replica (one
     replica per lane): 2|E| + 2n FMAs, three wall operations per spin
     (compare, select, clamp) and, for discrete SB, one copysign per spin that
-    feeds a neighbour.  For the 42-node, 48-edge graph: 306 (bSB), 347 (dSB),
-    as counted in the compiled loop."""
+    feeds a neighbour.  For the 42-node, 48-edge graph: 306 (bSB), 347 (dSB);
+    the compiled loop adds a few register moves per step (6 for bSB, whose
+    loop holds two steps, and 1 for dSB)."""
     n, E = inst.n, inst.num_edges
     base = 2 * E + 5 * n
     if variant == "dsb":
@@ -669,8 +670,9 @@ def main():
                                "frac": {v: rows * T / (stage[f"{v}_ms"] * 1e-3) / dual_ceiling[v] for v in variants},
                                "model": "a SIMD issues one wave64 VALU instruction per 4 cycles, or two from "
                                         "two waves; the loop's 32-bit-encoded instructions (v_fmac_f32, "
-                                        "v_cndmask_b32) co-issue, its VOP3 ones (|x| compare, med3, copysign) "
-                                        "mostly issue alone (SQ_ACTIVE_INST_VALU2); ceiling = two instructions "
+                                        "v_cndmask_b32, bSB's wall compare) co-issue, its VOP3 ones (med3, "
+                                        "copysign, dSB's |x| compare) mostly issue alone (SQ_ACTIVE_INST_VALU2); "
+                                        "ceiling = two instructions "
                                         "in every slot: 1024 SIMDs x 2.4 GHz / 4 x 2 x 64 lanes / VALU "
                                         "instructions per replica-step"}},
         "stages_ms": stage,

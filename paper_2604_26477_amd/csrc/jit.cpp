@@ -103,7 +103,7 @@ static std::string waves_attr(int waves) {
     return ", amdgpu_waves_per_eu(" + std::to_string(waves) + ")";
 }
 
-static std::string generate(const Problem &p, int variant, bool trace, bool noise, int waves) {
+static std::string generate(const Problem &p, int variant, bool trace, bool noise, int waves, bool pair_wall) {
     const int n = p.n, m = p.m;
     const int64_t E = p.E;
     const bool dsb = variant == QAIA_DSB;
@@ -135,34 +135,66 @@ static std::string generate(const Problem &p, int variant, bool trace, bool nois
           << "  asm volatile(\"\" : \"+v\"(X" << i << "), \"+v\"(Y" << i << "));\n";
     s << "  const float* jr = jcp + w * " << E << "ll;\n";
     for (int64_t e = 0; e < E; ++e) s << "  const float J" << e << " = jr[" << e << "];\n";
-    s << "  for (int t = 0; t < T; ++t) {\n";
-    s << "    const float kt = kt_tab[t];\n";
-    if (noise) s << "    const u64 nb = (g * (u64)T + (u64)t) * " << n << "ull;\n";
-    if (dsb)
-        for (int i = 0; i < n; ++i)
-            s << "    const float S" << i << " = __builtin_copysignf(1.0f, X" << i << ");\n";
-    // y_i += kt x_i + sum_j Jc'_ij phi(x_j), every phi from the pre-step x
-    for (int i = 0; i < n; ++i) {
-        s << "    Y" << i << " = __builtin_fmaf(kt, X" << i << ", Y" << i << ");";
-        for (int q = p.rowptr[i]; q < p.rowptr[i + 1]; ++q)
-            s << " Y" << i << " = __builtin_fmaf(J" << p.eid[q] << ", " << (dsb ? "S" : "X")
-              << p.col[q] << ", Y" << i << ");";
-        if (noise) s << " Y" << i << " = __builtin_fmaf(dt_alpha, nzv(seed, nb + " << i << "ull), Y" << i << ");";
-        s << "\n";
-    }
-    // x_i += dt a0 y_i, then the inelastic wall: |x| > 1 zeroes y, clamps x
-    for (int i = 0; i < n; ++i) {
-        s << "    X" << i << " = __builtin_fmaf(dta0, Y" << i << ", X" << i << "); Y" << i
-          << " = __builtin_fabsf(X" << i << ") > 1.0f ? 0.0f : Y" << i << "; X" << i
-          << " = __builtin_fminf(__builtin_fmaxf(X" << i << ", -1.0f), 1.0f);\n";
-    }
-    if (trace) {  // test hook only: the plain kernel carries no trace code
-        s << "    if (t < trace_steps) {\n";
-        s << "      float* tr = trace + (row * trace_steps + t) * " << n << "ll;\n";
-        for (int i = 0; i < n; ++i) s << "      tr[" << i << "] = X" << i << ";\n";
+    // The step coefficient and dt a0 are copied into VGPRs (an opaque move,
+    // which the compiler cannot fold back into scalar operands): with the
+    // FMAs reading them from scalar registers dSB ran 10 % slower on the
+    // 42-node graph (bSB the same), as if such FMAs issued alone.
+    s << "  float dtv; asm(\"v_mov_b32 %0, %1\" : \"=v\"(dtv) : \"s\"(dta0));\n";
+    // One SB step at time index t.
+    auto step = [&](const std::string &tv) {
+        s << "    { const int t = " << tv << ";\n";
+        s << "    const float kts = kt_tab[t]; float kt; asm(\"v_mov_b32 %0, %1\" : \"=v\"(kt) : \"s\"(kts));\n";
+        if (noise) s << "    const u64 nb = (g * (u64)T + (u64)t) * " << n << "ull;\n";
+        if (dsb)
+            for (int i = 0; i < n; ++i)
+                s << "    const float S" << i << " = __builtin_copysignf(1.0f, X" << i << ");\n";
+        // y_i += kt x_i + sum_j Jc'_ij phi(x_j), every phi from the pre-step x
+        for (int i = 0; i < n; ++i) {
+            s << "    Y" << i << " = __builtin_fmaf(kt, X" << i << ", Y" << i << ");";
+            for (int q = p.rowptr[i]; q < p.rowptr[i + 1]; ++q)
+                s << " Y" << i << " = __builtin_fmaf(J" << p.eid[q] << ", " << (dsb ? "S" : "X") << p.col[q] << ", Y"
+                  << i << ");";
+            if (noise) s << " Y" << i << " = __builtin_fmaf(dt_alpha, nzv(seed, nb + " << i << "ull), Y" << i << ");";
+            s << "\n";
+        }
+        // x_i += dt a0 y_i, then the inelastic wall: |x| > 1 zeroes y, clamps x.
+        // pair_wall writes the test as "clamping changed x", the same for every
+        // finite x (and -0 == +0): a compare of two registers has the 32-bit
+        // encoding, which the SIMD can issue together with another wave's
+        // instruction, where |x| > 1 needs the 64-bit encoding (for the abs
+        // modifier) and issues alone.
+        for (int i = 0; i < n; ++i) {
+            s << "    X" << i << " = __builtin_fmaf(dtv, Y" << i << ", X" << i << ");";
+            if (pair_wall)
+                s << " { const float C = __builtin_fminf(__builtin_fmaxf(X" << i << ", -1.0f), 1.0f); Y" << i
+                  << " = C != X" << i << " ? 0.0f : Y" << i << "; X" << i << " = C; }\n";
+            else
+                s << " Y" << i << " = __builtin_fabsf(X" << i << ") > 1.0f ? 0.0f : Y" << i << "; X" << i
+                  << " = __builtin_fminf(__builtin_fmaxf(X" << i << ", -1.0f), 1.0f);\n";
+        }
+        if (trace) {  // test hook only: the plain kernel carries no trace code
+            s << "    if (t < trace_steps) {\n";
+            s << "      float* tr = trace + (row * trace_steps + t) * " << n << "ll;\n";
+            for (int i = 0; i < n; ++i) s << "      tr[" << i << "] = X" << i << ";\n";
+            s << "    }\n";
+        }
         s << "    }\n";
+    };
+    if (pair_wall) {
+        // two steps per loop iteration: the clamped and the unclamped x are
+        // both live at the wall test, and alternating their registers between
+        // the two copies of the step leaves no copy at the back edge
+        s << "  int t0 = 0;\n  for (; t0 + 1 < T; t0 += 2) {\n";
+        step("t0");
+        step("t0 + 1");
+        s << "  }\n  if (t0 < T) {\n";
+        step("t0");
+        s << "  }\n";
+    } else {
+        s << "  for (int t0 = 0; t0 < T; ++t0) {\n";
+        step("t0");
+        s << "  }\n";
     }
-    s << "  }\n";
     // read-out: bit i set <=> x_i < 0 (sgn 0 = +1)
     for (int wd = 0; wd < p.words; ++wd) {
         s << "  { u64 b = 0ull;";
@@ -439,17 +471,42 @@ static std::mutex g_cache_mu;
 static std::map<uint64_t, std::vector<char>> g_cache;  // source hash -> code object
 static std::set<uint64_t> g_spilling;                  // sources whose step loop spills
 
-// Three waves per SIMD (168 VGPRs) where the step loop still fits without
-// spills, which hides more of the FMA chains' latency (5-7 % on the 42-node
-// graph); otherwise two (256 VGPRs: every graph the path admits keeps its
-// state in registers there, spills land outside the loop).  The binary16
-// kernels always ask for two: their packed instructions issue one per slot
-// whatever the occupancy, and three measured 1-4 % slower.
+// Build candidates in order of preference, (waves per SIMD, paired wall
+// test): the first whose step loop the compiler keeps free of spill traffic
+// is taken, the last one regardless.  Three waves per SIMD (168 VGPRs) give
+// each issue slot more candidates than two (5-7 % on the 42-node graph); two
+// (256 VGPRs) keep every graph the path admits in registers.  The paired
+// wall test saves an issue slot per spin and step (about 8 % for bSB on the
+// 42-node graph); it is tried for plain bSB only: with dSB's signs (n more
+// live values) or the noise generator it spilled on the graphs tried.  The
+// binary16 kernels always ask for two waves: their packed instructions issue
+// one per slot whatever the occupancy, and three measured 1-4 % slower.
+// (Loading the edge coefficients once per wave into scalar registers,
+// possible when R is a multiple of 64, frees their VGPRs but made both
+// variants a third slower at every occupancy from two to four waves.)
 static JitKernel *build_kernel(const Problem &p, int variant, bool trace, bool noise, bool half = false) {
+    struct Candidate {
+        int waves;
+        bool pair_wall;
+    };
+    std::vector<Candidate> cands;
+    if (half) {
+        cands = {{2, false}};
+    } else {
+        const bool pair = variant == QAIA_BSB && !noise;
+        // three waves leave 168 VGPRs: past 160 state registers (2n + E) every
+        // build spilled
+        for (int waves = 2 * (int64_t)p.n + p.E <= 160 ? 3 : 2; waves >= 2; --waves) {
+            if (pair) cands.push_back({waves, true});
+            cands.push_back({waves, false});
+        }
+    }
     std::vector<char> code;
-    for (int waves = half ? 2 : 3; waves >= 2 && code.empty(); --waves) {
-        const std::string src =
-            half ? generate16(p, variant, trace, noise, waves) : generate(p, variant, trace, noise, waves);
+    for (size_t ci = 0; ci < cands.size() && code.empty(); ++ci) {
+        const bool last = ci + 1 == cands.size();
+        const Candidate cd = cands[ci];
+        const std::string src = half ? generate16(p, variant, trace, noise, cd.waves)
+                                     : generate(p, variant, trace, noise, cd.waves, cd.pair_wall);
         const uint64_t h = fnv1a(src);
         {
             std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -459,9 +516,9 @@ static JitKernel *build_kernel(const Problem &p, int variant, bool trace, bool n
         }
         if (!code.empty()) break;
         std::string listing;
-        std::vector<char> c = compile(src, noise, waves > 2 ? &listing : nullptr);
+        std::vector<char> c = compile(src, noise, last ? nullptr : &listing);
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        if (waves > 2 && (listing.empty() || loop_spills(listing))) {
+        if (!last && (listing.empty() || loop_spills(listing))) {
             g_spilling.insert(h);
             continue;
         }

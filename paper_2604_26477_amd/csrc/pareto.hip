@@ -31,6 +31,9 @@
 //    survivor is >= it componentwise.  Any dominator of it in an earlier
 //    chunk is itself dominated-or-equal by a survivor of that chunk, so
 //    comparing survivors with survivors is complete.  Early exit per block.
+//    Lists of at most 32768 vectors skip 5 and 6: every pair of 256-row
+//    tiles is one work item of a persistent grid that marks each vector with
+//    an earlier vector >= it componentwise.
 // 7. The kept sample indices are emitted in ascending order by a flagged
 //    compaction over 0..M-1.
 // The non-dominated ranks take steps 4-6 over every row (no merging or
@@ -51,6 +54,8 @@ constexpr int kChunk = 1024;
 constexpr int kDirs = 256;          // pivot directions
 constexpr int kSampleRows = 1 << 17;  // rows of the pivot sample (at most)
 constexpr int kCandBlocks = 128;     // blocks of the pivot search
+constexpr int64_t kPairMax = 1 << 15;  // longest list of the pair pass (128 tiles)
+constexpr int kPairBlocks = 2048;      // persistent grid of the pair pass
 
 unsigned grid_for_n(int64_t n, int per) {
     const int64_t g = (n + per - 1) / per;
@@ -410,7 +415,7 @@ __global__ __launch_bounds__(kB) void chunk_nd_kernel(const int64_t *__restrict_
     __shared__ int64_t v[kChunk][MM];
     const int64_t U = *d_U;
     const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-    if (c0 >= U) return;
+    if (U <= kPairMax || c0 >= U) return;  // short lists take the pair pass
     const int len = (int)((U - c0) < kChunk ? (U - c0) : kChunk);
     for (int p = threadIdx.x; p < len; p += kB) {
         const int64_t *y = obj + (int64_t)list[c0 + p] * MM;
@@ -460,9 +465,11 @@ __global__ __launch_bounds__(kB) void chunk_nd_kernel(const int64_t *__restrict_
 template <int MM>
 __global__ __launch_bounds__(kB) void global_nd_kernel(const int64_t *__restrict__ obj,
                                                        const int32_t *__restrict__ sidx,
+                                                       const int64_t *__restrict__ d_U,
                                                        const int64_t *__restrict__ d_S,
                                                        uint8_t *__restrict__ keep) {
     __shared__ int64_t v[kB][MM];
+    if (*d_U <= kPairMax) return;  // short lists take the pair pass
     const int64_t S = *d_S;
     const int64_t j0 = (int64_t)blockIdx.x * kB;
     if (j0 >= S) return;
@@ -497,13 +504,89 @@ __global__ __launch_bounds__(kB) void global_nd_kernel(const int64_t *__restrict
     if (alive) keep[sidx[j]] = 1;
 }
 
+// Pair pass for lists of at most kPairMax vectors (the usual case once the
+// pivots have pruned a pool): the chunk and survivor passes above leave most
+// CUs idle on a few thousand rows (one block per chunk, one per 256
+// survivors, each walking its earlier rows in sequence), so short lists are
+// instead split into 256-row tiles and every tile pair (it, jt) with
+// it <= jt is one work item of a persistent grid.  Row j of tile jt is marked
+// (dom[j] = 1) when a row i < j of tile it is >= it componentwise: in the
+// lexicographic order every dominator comes first, and the vectors are
+// distinct, so "some earlier row is >= it" is exactly "dominated".  A row
+// already marked by another pair skips its comparisons, and a pair whose rows
+// are all marked is skipped; concurrent marks all store the same byte.
+template <int MM>
+__global__ __launch_bounds__(kB) void pair_nd_kernel(const int64_t *__restrict__ obj,
+                                                     const int32_t *__restrict__ list,
+                                                     const int64_t *__restrict__ d_n, uint8_t *dom) {
+    const int64_t n = *d_n;
+    if (n > kPairMax) return;
+    const int T = (int)((n + kB - 1) / kB);
+    const int P = T * (T + 1) / 2;
+    __shared__ int64_t v[kB][MM];
+    for (int p = blockIdx.x; p < P; p += gridDim.x) {
+        // p = jt (jt + 1) / 2 + it, 0 <= it <= jt
+        int jt = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+        while (jt * (jt + 1) / 2 > p) --jt;
+        while ((jt + 1) * (jt + 2) / 2 <= p) ++jt;
+        const int it = p - jt * (jt + 1) / 2;
+        const int64_t j = (int64_t)jt * kB + threadIdx.x;
+        const bool live = j < n && dom[j] == 0;
+        if (!__syncthreads_or(live ? 1 : 0)) continue;
+        const int64_t i = (int64_t)it * kB + threadIdx.x;
+        if (i < n) {
+            const int64_t *y = obj + (int64_t)list[i] * MM;
+#pragma unroll
+            for (int k = 0; k < MM; ++k) v[threadIdx.x][k] = y[k];
+        }
+        __syncthreads();
+        if (live) {
+            int64_t yj[MM];
+            const int64_t *y = obj + (int64_t)list[j] * MM;
+#pragma unroll
+            for (int k = 0; k < MM; ++k) yj[k] = y[k];
+            // tile it < jt is full (only the last tile can be partial)
+            const int lim = it < jt ? kB : (int)threadIdx.x;
+            for (int t = 0; t < lim; ++t) {
+                bool ge = true;
+#pragma unroll
+                for (int k = 0; k < MM; ++k) ge &= v[t][k] >= yj[k];
+                if (ge) {
+                    dom[j] = 1;
+                    break;
+                }
+            }
+        }
+        __syncthreads();  // v is rewritten by the next pair
+    }
+}
+
+// keep[list[j]] = 1 for the unmarked rows of a short list.
+__global__ __launch_bounds__(kB) void pair_keep_kernel(const int32_t *__restrict__ list,
+                                                       const int64_t *__restrict__ d_n,
+                                                       const uint8_t *__restrict__ dom, uint8_t *__restrict__ keep) {
+    const int64_t n = *d_n;
+    const int64_t j = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (n <= kPairMax && j < n && dom[j] == 0) keep[list[j]] = 1;
+}
+
+// Both routes are queued; the list length, known only on the device, picks
+// the one that works (the other's launches return at once).
 template <int MM>
 void launch_nd_passes(const int64_t *obj, const int32_t *list, const int64_t *d_n, int64_t cap, uint8_t *flag,
                       int32_t *sidx, int64_t *d_s, uint32_t *cnt, uint8_t *keep, hipStream_t st) {
+    const int64_t short_cap = std::min<int64_t>(cap, kPairMax);
+    const int64_t tc = (short_cap + kB - 1) / kB;
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for_n(short_cap, kB)), dim3(kB), 0, st, flag, short_cap, (uint8_t)0);
+    hipLaunchKernelGGL(pair_nd_kernel<MM>, dim3((unsigned)std::max<int64_t>(std::min<int64_t>(tc * (tc + 1) / 2, kPairBlocks), 1)),
+                       dim3(kB), 0, st, obj, list, d_n, flag);
+    hipLaunchKernelGGL(pair_keep_kernel, dim3(grid_for_n(short_cap, kB)), dim3(kB), 0, st, list, d_n, flag, keep);
+    QAIA_HIP(hipGetLastError());
+    if (cap <= kPairMax) return;
     hipLaunchKernelGGL(chunk_nd_kernel<MM>, dim3(grid_for_n(cap, kChunk)), dim3(kB), 0, st, obj, list, d_n, flag);
     QAIA_HIP(hipGetLastError());
     select_flagged<int32_t, int32_t>(list, flag, d_n, cap, sidx, d_s, cnt, nullptr, st);
-    hipLaunchKernelGGL(global_nd_kernel<MM>, dim3(grid_for_n(cap, kB)), dim3(kB), 0, st, obj, sidx, d_s, keep);
+    hipLaunchKernelGGL(global_nd_kernel<MM>, dim3(grid_for_n(cap, kB)), dim3(kB), 0, st, obj, sidx, d_n, d_s, keep);
     QAIA_HIP(hipGetLastError());
 }
 

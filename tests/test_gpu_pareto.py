@@ -70,6 +70,22 @@ def test_filter_wide_ranges_and_ties(q):
     assert np.array_equal(_filter(q, line), np.arange(40_000))
 
 
+@pytest.mark.parametrize("n", [32_668, 32_769])
+def test_filter_pair_pass_boundary(q, n):
+    """Lists of up to 32768 sorted survivors take the tile-pair pass, longer
+    ones the chunk and survivor passes.  A front of n points (none can be
+    pruned), then 100 points each just below one front point (dominated only
+    by it, so pruned only when it is a pivot) and repeats of 50 front rows:
+    between n and n + 100 survivors, all on the tile-pair side for n = 32668
+    and all on the other for n = 32769."""
+    rng = np.random.default_rng(n)
+    a = rng.permutation(n).astype(np.int64)
+    line = np.stack([a, n - a, 2 * a], axis=1)
+    lower = line[rng.choice(n, 100, replace=False)] - np.array([1, 0, 1], np.int64)
+    obj = np.concatenate([line, lower, line[:50]])
+    assert np.array_equal(_filter(q, obj), np.arange(n))
+
+
 def test_filter_empty(q):
     assert _filter(q, np.zeros((0, 3), np.int64)).size == 0
 
