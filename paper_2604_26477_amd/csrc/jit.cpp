@@ -183,9 +183,12 @@ static std::string generate(const Problem &p, int variant, bool trace, bool nois
     if (pair_wall) {
         // two steps per loop iteration: the clamped and the unclamped x are
         // both live at the wall test, and alternating their registers between
-        // the two copies of the step leaves no copy at the back edge
+        // the two copies of the step leaves no copy at the back edge; the
+        // scheduling barrier keeps the copies apart, so that the live values
+        // stay those of one step (interleaved, dSB's spilled)
         s << "  int t0 = 0;\n  for (; t0 + 1 < T; t0 += 2) {\n";
         step("t0");
+        s << "    __builtin_amdgcn_sched_barrier(0);\n";
         step("t0 + 1");
         s << "  }\n  if (t0 < T) {\n";
         step("t0");
@@ -477,8 +480,8 @@ static std::set<uint64_t> g_spilling;                  // sources whose step loo
 // each issue slot more candidates than two (5-7 % on the 42-node graph); two
 // (256 VGPRs) keep every graph the path admits in registers.  The paired
 // wall test saves an issue slot per spin and step (about 8 % for bSB on the
-// 42-node graph); it is tried for plain bSB only: with dSB's signs (n more
-// live values) or the noise generator it spilled on the graphs tried.  The
+// 42-node graph); it is not tried with the noise generator, whose registers
+// leave no room for it.  The
 // binary16 kernels always ask for two waves: their packed instructions issue
 // one per slot whatever the occupancy, and three measured 1-4 % slower.
 // (Loading the edge coefficients once per wave into scalar registers,
@@ -493,7 +496,7 @@ static JitKernel *build_kernel(const Problem &p, int variant, bool trace, bool n
     if (half) {
         cands = {{2, false}};
     } else {
-        const bool pair = variant == QAIA_BSB && !noise;
+        const bool pair = !noise;
         // three waves leave 168 VGPRs: past 160 state registers (2n + E) every
         // build spilled
         for (int waves = 2 * (int64_t)p.n + p.E <= 160 ? 3 : 2; waves >= 2; --waves) {
