@@ -437,8 +437,8 @@ def table2_form(q, wl, torch, sizes=((25, 0.5), (25, 1.0), (100, 0.5), (100, 1.0
 
 
 def traffic_probe(q, wl, torch, kind="sparse"):
-    """For counter collection.  sparse: one bSB sampling launch of the
-    benchmark workload.  dense: one 20-step dSB call of the precision workload
+    """For counter collection.  sparse (sparse-dsb): one bSB (dSB) sampling
+    launch of the benchmark workload.  dense: one 20-step dSB call of the precision workload
     per operand format (FP32, BF16, FP8).  Then, as the counters' calibration,
     one plain device copy of 1 GiB (1 GiB read, 1 GiB written)."""
     if kind == "dense":
@@ -455,7 +455,8 @@ def traffic_probe(q, wl, torch, kind="sparse"):
         inst = wl.workload_instance(WORKLOAD)
         prob = q.problem_from_instance(inst, 0)
         c = torch.from_numpy(wl.workload_weights(WORKLOAD)).cuda()
-        s = q.make_schedule("bsb", steps=cfg["T"], dt=0.5, seed=cfg["seed"] + 3)
+        variant = "dsb" if kind == "sparse-dsb" else "bsb"
+        s = q.make_schedule(variant, steps=cfg["T"], dt=0.5, seed=cfg["seed"] + 3)
         spins, obj, ws = q.qaia_sample(prob, c, cfg["R"], s)
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -478,8 +479,8 @@ def main():
                     help="run one form measurement alone and print its JSON (for profiling)")
     ap.add_argument("--precision-steps", type=int, default=1000,
                     help="SB steps of the precision form (shorter runs for counter collection)")
-    ap.add_argument("--traffic-probe", nargs="?", const="sparse", choices=["sparse", "dense"],
-                    help="run one bSB sampling launch of the workload (sparse) or 20 dSB steps of the "
+    ap.add_argument("--traffic-probe", nargs="?", const="sparse", choices=["sparse", "sparse-dsb", "dense"],
+                    help="run one bSB (sparse) or dSB (sparse-dsb) sampling launch of the workload or 20 dSB steps of the "
                          "precision workload per operand format (dense), then one 1 GiB device copy, for "
                          "counter collection (rocprofv3 --pmc), then exit")
     ap.add_argument("--noise-form", action="store_true",
