@@ -6,8 +6,10 @@
 //
 // 1. Duplicate merging.  Every row looks its vector up in an open-addressing
 //    hash table; each distinct vector ends with one slot holding its smallest
-//    sample index (the representative).  The occupied slots are compacted
-//    into the list of distinct vectors.
+//    sample index (the representative).  Rows are first merged per chunk of
+//    1024 in an LDS table, so that only each chunk's distinct vectors reach
+//    the global one.  The occupied slots are compacted into the list of
+//    distinct vectors.
 // 2. Pivots.  On an evenly strided sample of that list, the row with the
 //    largest normalised weighted sum is taken for each of 256 fixed positive
 //    directions (a maximiser of a positive weighted sum is non-dominated, so
@@ -317,44 +319,99 @@ __global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) p[i] = v;
 }
 
-// Duplicate merging by open addressing: every row r looks its vector up in a
-// table of `mask + 1` slots (more than the row count, so a free slot always
-// exists), linear probing from a hash of the vector.  A free slot (-1) is
-// claimed with a compare-and-swap; a slot naming a row with the same vector
-// takes min(that row, r) with an atomic minimum.  Slots never change vector,
-// so every row of a vector reaches the same slot, which ends holding the
-// vector's smallest row index.
+__device__ __forceinline__ uint64_t vec_hash_step(uint64_t h, int64_t y) {
+    h = (h ^ (uint64_t)y) * 0xFF51AFD7ED558CCDull;
+    return h ^ (h >> 32);
+}
+
+template <int MM>
+__device__ __forceinline__ uint64_t vec_hash(const int64_t (&y)[MM]) {
+    uint64_t h = 0x243F6A8885A308D3ull;
+#pragma unroll
+    for (int k = 0; k < MM; ++k) h = vec_hash_step(h, y[k]);
+    h = (h ^ (h >> 29)) * 0xC4CEB9FE1A85EC53ull;
+    return h ^ (h >> 32);
+}
+
+// Open addressing in the global table of `mask + 1` slots (more than the row
+// count, so a free slot always exists), linear probing from the vector's
+// hash: a free slot (-1) is claimed with a compare-and-swap; a slot naming a
+// row with the same vector takes min(that row, me) with an atomic minimum.
+// Slots never change vector, so every row of a vector reaches the same slot,
+// which ends holding the smallest row index offered for it.
+template <int MM>
+__device__ __forceinline__ void table_insert(const int64_t *__restrict__ obj, const int64_t (&y)[MM], uint64_t h,
+                                             int32_t me, int32_t *__restrict__ table, uint64_t mask) {
+    uint64_t s = h & mask;
+    while (true) {
+        int32_t q = table[s];
+        if (q < 0) {
+            q = atomicCAS(&table[s], -1, me);
+            if (q < 0) return;  // claimed
+        }
+        bool eq = true;
+#pragma unroll
+        for (int k = 0; k < MM; ++k) eq &= obj[(int64_t)q * MM + k] == y[k];
+        if (eq) {
+            if (me < q) atomicMin(&table[s], me);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+constexpr int kDedupRows = 1024;   // rows per chunk of the in-block merge
+constexpr int kDedupSlots = 2048;  // its LDS hash slots
+
+// Duplicate merging in two levels.  A sampler's pool repeats its most
+// frequent cut vectors hundreds of thousands of times, and one global table
+// slot per vector made those rows queue on a few cache lines.  So each block
+// first merges a chunk of 1024 consecutive rows in an LDS table (the same
+// probing, on the chunk's vectors staged in LDS, keeping the smallest row of
+// the chunk per vector), and only the chunk's distinct vectors, with those
+// rows, go to the global table.  The global minimum over the chunks'
+// minima is the vector's smallest row.
 template <int MM>
 __global__ __launch_bounds__(kB) void dedupe_kernel(const int64_t *__restrict__ obj, int64_t M,
                                                     int32_t *__restrict__ table, uint64_t mask) {
-    for (int64_t r = (int64_t)blockIdx.x * kB + threadIdx.x; r < M; r += (int64_t)gridDim.x * kB) {
-        int64_t y[MM];
-        uint64_t h = 0x243F6A8885A308D3ull;
+    __shared__ int64_t v[kDedupRows][MM];
+    __shared__ int32_t loc[kDedupSlots];
+    for (int64_t c0 = (int64_t)blockIdx.x * kDedupRows; c0 < M; c0 += (int64_t)gridDim.x * kDedupRows) {
+        const int len = (int)((M - c0) < kDedupRows ? (M - c0) : kDedupRows);
+        for (int i = threadIdx.x; i < kDedupSlots; i += kB) loc[i] = -1;
+        for (int i = threadIdx.x; i < len * MM; i += kB) (&v[0][0])[i] = obj[c0 * MM + i];
+        __syncthreads();
+        for (int p = threadIdx.x; p < len; p += kB) {
+            int64_t y[MM];
 #pragma unroll
-        for (int k = 0; k < MM; ++k) {
-            y[k] = obj[r * MM + k];
-            h = (h ^ (uint64_t)y[k]) * 0xFF51AFD7ED558CCDull;
-            h ^= h >> 32;
-        }
-        h = (h ^ (h >> 29)) * 0xC4CEB9FE1A85EC53ull;
-        h ^= h >> 32;
-        uint64_t s = h & mask;
-        const int32_t me = (int32_t)r;
-        while (true) {
-            int32_t q = table[s];
-            if (q < 0) {
-                q = atomicCAS(&table[s], -1, me);
-                if (q < 0) break;  // claimed
-            }
-            bool eq = true;
+            for (int k = 0; k < MM; ++k) y[k] = v[p][k];
+            uint32_t s = (uint32_t)vec_hash<MM>(y) & (kDedupSlots - 1);
+            while (true) {
+                int32_t q = loc[s];
+                if (q < 0) {
+                    q = atomicCAS(&loc[s], -1, p);
+                    if (q < 0) break;  // claimed
+                }
+                bool eq = true;
 #pragma unroll
-            for (int k = 0; k < MM; ++k) eq &= obj[(int64_t)q * MM + k] == y[k];
-            if (eq) {
-                if (me < q) atomicMin(&table[s], me);
-                break;
+                for (int k = 0; k < MM; ++k) eq &= v[q][k] == y[k];
+                if (eq) {
+                    if (p < q) atomicMin(&loc[s], p);
+                    break;
+                }
+                s = (s + 1) & (kDedupSlots - 1);
             }
-            s = (s + 1) & mask;
         }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kDedupSlots; i += kB) {
+            const int32_t p = loc[i];
+            if (p < 0) continue;
+            int64_t y[MM];
+#pragma unroll
+            for (int k = 0; k < MM; ++k) y[k] = v[p][k];
+            table_insert<MM>(obj, y, vec_hash<MM>(y), (int32_t)(c0 + p), table, mask);
+        }
+        __syncthreads();  // v and loc are rewritten for the next chunk
     }
 }
 
@@ -833,8 +890,8 @@ void prune_and_sort(const int64_t *obj, RowList rows, int64_t cap, int32_t m, bo
 template <int MM>
 void launch_dedupe(const int64_t *obj, int64_t M, const PView &v, hipStream_t st) {
     hipLaunchKernelGGL(fill_i32_kernel, dim3(2048), dim3(kB), 0, st, v.table, (int64_t)v.table_slots, (int32_t)-1);
-    hipLaunchKernelGGL(dedupe_kernel<MM>, dim3((unsigned)std::min<int64_t>(grid_for(M), 8192)), dim3(kB), 0, st, obj,
-                       M, v.table, v.table_slots - 1);
+    hipLaunchKernelGGL(dedupe_kernel<MM>, dim3((unsigned)std::min<int64_t>(grid_for(M, kDedupRows), 2048)), dim3(kB),
+                       0, st, obj, M, v.table, v.table_slots - 1);
     QAIA_HIP(hipGetLastError());
 }
 

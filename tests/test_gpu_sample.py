@@ -364,6 +364,28 @@ def test_noise_generated_kernel_matches_generic_kernel(q, variant):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("variant", ["bsb", "dsb"])
+@pytest.mark.parametrize("steps", [1, 2, 3, 7, 301])
+def test_generated_kernel_matches_generic_kernel_any_step_count(q, variant, steps):
+    """The generated kernel's plain loop holds two SB steps (an odd count ends
+    with one more), and its wall test is written as "clamping changed x"; the
+    generic kernel runs one step per iteration with the |x| > 1 test.  Spins,
+    cuts and the traced trajectories agree bit for bit at odd and even counts."""
+    import torch
+    inst = wl.workload_instance("c1_bsb_n42_m3")
+    c = wl.workload_weights("c1_bsb_n42_m3", count=10)
+    prob = q.problem_from_instance(inst)
+    outs = []
+    for path in ("sparse_reg", "sparse_lds"):
+        s = q.make_schedule(variant, steps=steps, dt=0.5, seed=90 + steps, path=path)
+        sp, ob, _ = q.qaia_sample(prob, _dev(c), 8, s)
+        _, _, _, tr = q.qaia_sample_trace(prob, _dev(c[:2]), 8, s, min(steps, 20))
+        torch.cuda.synchronize()
+        outs.append((sp.cpu().numpy(), ob.cpu().numpy(), tr.cpu().numpy()))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("path", ["sparse_reg", "sparse_lds", "dense_staged"])
 def test_noise_injected_sampling_exact_cuts(q, path):
     inst = wl.workload_instance("c1_bsb_n42_m3")
