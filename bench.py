@@ -49,7 +49,7 @@ SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
 _KIB = 1024.0
 _FETCH_SCALE = 1048576.0 / 524322.4375
 _WRITE_SCALE = 1048576.0 / 1048579.46875
-SB_REG_TRAFFIC_BYTES = (5242.25 * _FETCH_SCALE + 203315.25 * _WRITE_SCALE) * _KIB
+SB_REG_TRAFFIC_BYTES = (5243.5 * _FETCH_SCALE + 203296.25 * _WRITE_SCALE) * _KIB
 
 
 def algorithmic_flops_per_replica_step(n: int, E: int) -> int:
