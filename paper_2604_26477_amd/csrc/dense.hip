@@ -256,8 +256,9 @@ constexpr int staged_chunk() { return MT <= 3 ? 128 : 64; }
 // one unit overlap the MFMAs of the other.  A unit is KPU consecutive k-groups
 // of the chunk (k-groups of 32 bytes for FP32 and BF16, 64 bytes for FP8);
 // when a chunk holds a single k-group (FP8 in 64-byte chunks) a unit is one
-// half of the wave's accumulators instead (its two 32-row halves, or its two
-// 32-column halves when the wave owns 32 rows).  Each accumulator receives
+// half of the wave's accumulators instead (its two 32-row halves with all
+// its column blocks, or, when the wave owns 32 rows, half of its CBW 32-column
+// blocks).  Each accumulator receives
 // the chunk's k-groups in increasing order whatever the split.  For every
 // MFMA the A and B fragments of a lane come from the same k positions (lane
 // half h, slot j), so any internal k order of the instruction pairs them.
@@ -298,14 +299,15 @@ __device__ __forceinline__ void frag_load(Frags<PREC, MT, RB, kg_per_unit<PREC, 
         };
         if constexpr (half_units<PREC, CB>()) {
             if constexpr (RB == 2) {
-                // unit u = rows r2 = u, both column halves
+                // unit u = rows r2 = u, every column block
 #pragma unroll
-                for (int c2 = 0; c2 < 2; ++c2) f.b[0][c2] = frag(L.b + c2 * 32 * CB, 0);
+                for (int c2 = 0; c2 < CBW; ++c2) f.b[0][c2] = frag(L.b + c2 * 32 * CB, 0);
 #pragma unroll
                 for (int k = 0; k < MT; ++k) f.a[0][k][0] = frag(L.a + (k * kT2 + u * 32) * CB, 0);
             } else {
-                // unit u = column half u, the wave's 32 rows
-                f.b[0][0] = frag(L.b + u * 32 * CB, 0);
+                // unit u = column blocks u CBW / 2 .. (u + 1) CBW / 2 - 1, the wave's 32 rows
+#pragma unroll
+                for (int j = 0; j < CBW / 2; ++j) f.b[0][j] = frag(L.b + (u * CBW / 2 + j) * 32 * CB, 0);
 #pragma unroll
                 for (int k = 0; k < MT; ++k) f.a[0][k][0] = frag(L.a + k * kT2 * CB, 0);
             }
@@ -358,7 +360,7 @@ __device__ __forceinline__ void mma_one(const Frags<PREC, MT, RB, KPU, CBW> &f, 
 // copy interleaving below).  MFMAs per unit with m = MT: unit_mfmas().
 template <int PREC, int MT, int RB, int CB, int CBW = 2>
 constexpr int unit_mfmas() {
-    return half_units<PREC, CB>() ? MT * RB
+    return half_units<PREC, CB>() ? MT * (RB == 2 ? CBW : CBW / 2)
                                   : kg_per_unit<PREC, CB>() * MT * RB * CBW * (PREC == QAIA_FP32 ? 4 : 1);
 }
 
@@ -374,13 +376,16 @@ __device__ __forceinline__ void unit_mma(const Frags<PREC, MT, RB, kg_per_unit<P
             if (k >= m) break;
             if constexpr (RB == 2) {
 #pragma unroll
-                for (int c2 = 0; c2 < 2; ++c2) {
+                for (int c2 = 0; c2 < CBW; ++c2) {
                     mma_one(f, acc[k][u][c2], 0, k, 0, c2, 0);
                     hook(i++);
                 }
             } else {
-                mma_one(f, acc[k][0][u], 0, k, 0, 0, 0);
-                hook(i++);
+#pragma unroll
+                for (int j = 0; j < CBW / 2; ++j) {
+                    mma_one(f, acc[k][0][u * CBW / 2 + j], 0, k, 0, j, 0);
+                    hook(i++);
+                }
             }
         }
     } else {
@@ -455,8 +460,13 @@ constexpr int dma_stages() {
 // insertion does not see an LDS-writing memory operation: with one pending it
 // treats the LDS counter as out of order and drains it completely before every
 // MFMA group, serialising the fragment reads with the MFMAs.  The copies are
-// ordered by hand (dma_wait, lds_barrier).  M0 is declared clobbered, so the
-// compiler keeps nothing it needs in M0 across the copy.
+// ordered by hand (dma_wait, lds_barrier).  M0 is listed as clobbered, but
+// it is a register the compiler reserves (it warns that such a clobber is not
+// guaranteed to be honoured): what makes the write safe is that the compiler
+// allocates no values of its own to M0, and no compiler-generated instruction
+// in these kernels reads it (in their ISA every M0 write is this copy's).
+// The compiler's own LDS-DMA builtin would manage M0 itself, but brings back
+// the waits described above.
 template <int PER>
 __device__ __forceinline__ void dma_copy(char *stage, const char *src, size_t koff, int wave, int i) {
     const uint32_t base = (uint32_t)(uintptr_t)(lds_void_t *)stage;

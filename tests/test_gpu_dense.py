@@ -210,21 +210,21 @@ def test_staged_tiles_match_register_tiles_when_exact(q, variant, prec, m):
     assert np.array_equal(outs[0][1], oracle.cut_values(inst, unpack_spins(outs[0][0], inst.n)))
 
 
-@pytest.mark.parametrize("m", [2, 3])
-def test_wide_bf16_tiles_match_register_tiles_when_exact(q, m):
+@pytest.mark.parametrize("prec,m", [("bf16", 2), ("bf16", 3), ("fp8", 2), ("fp8", 3)])
+def test_wide_tiles_match_register_tiles_when_exact(q, prec, m):
     """BF16 launches with m = 2 or 3 whose columns fill 256-column tiles, with
     at least one such tile per CU, run the 128 x 256 wide tile (eight waves on
-    32 x 128 wave tiles, one fragment set, 64-byte chunks): at 2000 spins
-    (16 row tiles, the last ragged) and 500 x 8 = 4000 replicas (16 wide
-    tiles, the last ragged) it agrees bit for bit with the register tiles
-    under exact weights."""
+    32 x 128 wave tiles, one fragment set, 64-byte chunks); FP8 launches of the
+    same shape run the 128 x 128 tile.  At 2000 spins (16 row tiles, the last
+    ragged) and 500 x 8 = 4000 replicas (the last column tile ragged) both
+    agree bit for bit with the register tiles under exact weights."""
     import torch
     inst = _small_int_instance(2000, m, seed=70 + m)
     c = wl.dirichlet_weights(500, m, 71)
     prob = q.problem_from_instance(inst)
     got = []
     for path in DENSE_PATHS:
-        s = q.make_schedule("dsb", precision="bf16", steps=60, dt=0.5, seed=72, path=path)
+        s = q.make_schedule("dsb", precision=prec, steps=60, dt=0.5, seed=72, path=path)
         sp, ob, _ = q.qaia_sample(prob, _dev(c), 8, s)
         torch.cuda.synchronize()
         got.append((sp.cpu().numpy(), ob.cpu().numpy()))
