@@ -149,7 +149,7 @@ def precision_form(q, wl, torch, T=1000):
     prob = q.problem_from_instance(inst, 0)
     c = torch.from_numpy(wl.dirichlet_weights(W, m, 3002)).cuda()
     out = {"workload": f"complete N={N}, m={m}, {W} weight vectors x {R} replicas, T={T}, dSB dense, "
-                       "LDS-staged matrix-core tiles (128 x 256 for BF16, 128 x 128 for FP32 and FP8)"}
+                       "LDS-staged matrix-core tiles (128 x 256 for BF16 and FP8, 128 x 128 for FP32)"}
     flops = 2 * m * N * N * W * R * T
     for prec in ("fp32", "bf16", "fp8"):
         s = q.make_schedule("dsb", precision=prec, steps=T, dt=0.5, seed=3003, path="dense_staged")

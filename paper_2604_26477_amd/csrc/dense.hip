@@ -1173,14 +1173,16 @@ static void step_dispatch_m(dim3 grid, hipStream_t st, const DenseJob &j, int t)
 template <int PREC>
 constexpr int staged_waves() { return PREC == QAIA_FP32 ? 4 : 8; }
 
-// BF16 single-job launches with m = 2 or 3 take the wide tile (128 x 256:
-// 37.5 % fewer operand bytes per flop for m = 3, 25 % for m = 2) when the
-// columns fill 256-column tiles and those tiles still cover every CU
-// (complete N = 2048, 4096 columns: m = 3 106.1 -> 95.3-96.0 us per step,
-// m = 2 82.6 -> 77.9-78.3; m = 1 gains nothing; at N = 1024, 2048 columns the
+// BF16 single-job launches with m = 2 or 3, and FP8 ones with m = 3, take the
+// wide tile (128 x 256: 37.5 % fewer operand bytes per flop for m = 3, 25 %
+// for m = 2) when the columns fill 256-column tiles and those tiles still
+// cover every CU (complete N = 2048, 4096 columns: BF16 m = 3 106.1 ->
+// 95.3-96.0 us per step, m = 2 82.6 -> 77.9-78.3; FP8 m = 3 63.8-64.1 ->
+// 62.5-62.7, its 64-byte chunks one k-group each, so a unit is half of the
+// wave's column blocks; m = 1 gains nothing; at N = 1024, 2048 columns the
 // 64 wide tiles would leave most CUs idle: 42.3 against 28.5 us).
 template <int PREC, int M>
-constexpr bool staged_wide() { return PREC == QAIA_BF16 && (M == 2 || M == 3); }
+constexpr bool staged_wide() { return (PREC == QAIA_BF16 && (M == 2 || M == 3)) || (PREC == QAIA_FP8 && M == 3); }
 
 static int device_cus() {
     static std::atomic<int> cache[64];

@@ -212,12 +212,14 @@ def test_staged_tiles_match_register_tiles_when_exact(q, variant, prec, m):
 
 @pytest.mark.parametrize("prec,m", [("bf16", 2), ("bf16", 3), ("fp8", 2), ("fp8", 3)])
 def test_wide_tiles_match_register_tiles_when_exact(q, prec, m):
-    """BF16 launches with m = 2 or 3 whose columns fill 256-column tiles, with
-    at least one such tile per CU, run the 128 x 256 wide tile (eight waves on
-    32 x 128 wave tiles, one fragment set, 64-byte chunks); FP8 launches of the
-    same shape run the 128 x 128 tile.  At 2000 spins (16 row tiles, the last
-    ragged) and 500 x 8 = 4000 replicas (the last column tile ragged) both
-    agree bit for bit with the register tiles under exact weights."""
+    """Launches whose columns fill 256-column tiles, with at least one such
+    tile per CU, run the 128 x 256 wide tile (eight waves on 32 x 128 wave
+    tiles, one fragment set, 64-byte chunks) in BF16 with m = 2 or 3 and in
+    FP8 with m = 3 (each chunk one k-group, so a unit is half of the wave's
+    four column blocks); FP8 with m = 2 runs the 128 x 128 tile.  At 2000
+    spins (16 row tiles, the last ragged) and 500 x 8 = 4000 replicas (the
+    last column tile ragged) every case agrees bit for bit with the register
+    tiles under exact weights."""
     import torch
     inst = _small_int_instance(2000, m, seed=70 + m)
     c = wl.dirichlet_weights(500, m, 71)
