@@ -253,7 +253,9 @@ template <int MT>
 constexpr int staged_chunk() { return MT <= 3 ? 128 : 64; }
 
 // Work on one LDS chunk is split into two units so that the fragment reads of
-// one unit overlap the MFMAs of the other.  A unit is KPU consecutive k-groups
+// one unit overlap the MFMAs of the other (with a single fragment set, wide
+// tiles, into one unit per k-group, run one after the other).  A unit is KPU
+// consecutive k-groups
 // of the chunk (k-groups of 32 bytes for FP32 and BF16, 64 bytes for FP8);
 // when a chunk holds a single k-group (FP8 in 64-byte chunks) a unit is one
 // half of the wave's accumulators instead (its two 32-row halves with all
@@ -266,8 +268,16 @@ template <int PREC, int CB>
 constexpr int kgroups_per_chunk() { return CB / (PrecInfo<PREC>::KG * (int)sizeof(typename PrecInfo<PREC>::T)); }
 template <int PREC, int CB>
 constexpr bool half_units() { return kgroups_per_chunk<PREC, CB>() == 1; }
-template <int PREC, int CB>
-constexpr int kg_per_unit() { return half_units<PREC, CB>() ? 1 : kgroups_per_chunk<PREC, CB>() / 2; }
+// k-groups per unit: half of the chunk's, or one with a single fragment set
+// (wide tiles, CBW > 2), whose loop takes the chunk's k-groups one by one
+template <int PREC, int CB, int CBW = 2>
+constexpr int kg_per_unit() {
+    return half_units<PREC, CB>() || CBW > 2 ? 1 : kgroups_per_chunk<PREC, CB>() / 2;
+}
+template <int PREC, int CB, int CBW>
+constexpr int units_per_chunk() {
+    return half_units<PREC, CB>() ? 2 : kgroups_per_chunk<PREC, CB>() / kg_per_unit<PREC, CB, CBW>();
+}
 
 template <int PREC> struct FragType;
 template <> struct FragType<QAIA_FP32> { typedef float4 V; };
@@ -289,8 +299,8 @@ __device__ __forceinline__ u32x4 lds16(const char *row, int part, int sw) {
 }
 
 template <int PREC, int MT, int RB, int CB, int CBW = 2>
-__device__ __forceinline__ void frag_load(Frags<PREC, MT, RB, kg_per_unit<PREC, CB>(), CBW> &f, const LaneLds &L, int u) {
-    constexpr int KPU = kg_per_unit<PREC, CB>();
+__device__ __forceinline__ void frag_load(Frags<PREC, MT, RB, kg_per_unit<PREC, CB, CBW>(), CBW> &f, const LaneLds &L, int u) {
+    constexpr int KPU = kg_per_unit<PREC, CB, CBW>();
     if constexpr (PREC == QAIA_FP8) {
         // lane half h holds k = 32h + 0..31 of a 64-byte k-group: parts 4g + 2h, 4g + 2h + 1
         auto frag = [&](const char *row, int g) {
@@ -361,13 +371,13 @@ __device__ __forceinline__ void mma_one(const Frags<PREC, MT, RB, KPU, CBW> &f, 
 template <int PREC, int MT, int RB, int CB, int CBW = 2>
 constexpr int unit_mfmas() {
     return half_units<PREC, CB>() ? MT * (RB == 2 ? CBW : CBW / 2)
-                                  : kg_per_unit<PREC, CB>() * MT * RB * CBW * (PREC == QAIA_FP32 ? 4 : 1);
+                                  : kg_per_unit<PREC, CB, CBW>() * MT * RB * CBW * (PREC == QAIA_FP32 ? 4 : 1);
 }
 
 template <int PREC, int MT, int RB, int CB, int CBW, typename Hook>
-__device__ __forceinline__ void unit_mma(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>(), CBW> &f, int m, int u,
+__device__ __forceinline__ void unit_mma(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB, CBW>(), CBW> &f, int m, int u,
                                          f16v (&acc)[MT][RB][CBW], Hook &&hook) {
-    constexpr int KPU = kg_per_unit<PREC, CB>();
+    constexpr int KPU = kg_per_unit<PREC, CB, CBW>();
     constexpr int NJ = PREC == QAIA_FP32 ? 4 : 1;  // fp32: four 32x32x2 steps per 16-byte fragment
     int i = 0;
     if constexpr (half_units<PREC, CB>()) {
@@ -408,7 +418,7 @@ __device__ __forceinline__ void unit_mma(const Frags<PREC, MT, RB, kg_per_unit<P
 }
 
 template <int PREC, int MT, int RB, int CB, int CBW = 2>
-__device__ __forceinline__ void frag_mma(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>(), CBW> &f, int m, int u,
+__device__ __forceinline__ void frag_mma(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB, CBW>(), CBW> &f, int m, int u,
                                          f16v (&acc)[MT][RB][CBW]) {
     unit_mma<PREC, MT, RB, CB, CBW>(f, m, u, acc, [](int) {});
 }
@@ -418,7 +428,7 @@ __device__ __forceinline__ void frag_mma(const Frags<PREC, MT, RB, kg_per_unit<P
 // waits for room in the memory queue stalls behind queued matrix work instead
 // of in front of an idle matrix pipe.  Copies not yet issued (m < MT) follow.
 template <int PREC, int MT, int RB, int CB, int NC, int CBW = 2, typename Copy>
-__device__ __forceinline__ void frag_mma_cp(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB>(), CBW> &f, int m, int u,
+__device__ __forceinline__ void frag_mma_cp(const Frags<PREC, MT, RB, kg_per_unit<PREC, CB, CBW>(), CBW> &f, int m, int u,
                                             f16v (&acc)[MT][RB][CBW], Copy &&copy) {
     constexpr int NM = unit_mfmas<PREC, MT, RB, CB, CBW>();
     int j = 0;
@@ -545,7 +555,12 @@ __device__ __forceinline__ void epi_prefetch(EpiPrefetch<NPF> &pf) {
 // leave no room for two; the second wave on each SIMD overlaps the fragment
 // reads instead).
 template <int MT, int CB, int CBW>
-constexpr int wide_stages() { return CBW == 2 ? dma_stages<MT, CB>() : 3; }
+constexpr int wide_stages() { return CBW == 2 ? dma_stages<MT, CB>() : CB == 128 ? 2 : 3; }
+// wide tiles: 128-byte chunks (two stages, all 160 KB of LDS) for BF16 with
+// m = 3 (94.4 against 96.5 ms per 1000 C3 steps with 64-byte chunks in three
+// stages); 64-byte chunks otherwise
+template <int PREC, int MT>
+constexpr int wide_chunk() { return PREC == QAIA_BF16 && MT == 3 ? 128 : 64; }
 
 template <int PREC, int MT, int NPF, int NW, int CB, int CBW = 2>
 __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, int Np_, int m, int row0, int col0,
@@ -560,7 +575,7 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
     static_assert((ROWS * GPR) % (64 * NW) == 0, "copies per wave");
     constexpr int PER = ROWS * GPR / (64 * NW);  // copies per wave per chunk
     constexpr int P0 = PER / 2, P1 = PER - P0;    // spread over the two MFMA groups
-    constexpr int KPU = kg_per_unit<PREC, CB>();
+    constexpr int KPU = kg_per_unit<PREC, CB, CBW>();
     constexpr bool SINGLE = CBW > 2;          // one fragment set (register budget)
     constexpr int D = wide_stages<MT, CB, CBW>();
     static_assert(D >= 2 && D - 2 <= 6, "stage ring depth");
@@ -632,13 +647,21 @@ __device__ __forceinline__ void mma_tile_dma(const void *Jv, const void *phiv, i
                 const LaneLds L = lane_lds(u);
                 // scheduling barriers keep each unit's reads ahead of the other unit's MFMAs
                 if constexpr (SINGLE) {
-                    frag_load<PREC, MT, RB, CB, CBW>(f0, L, 0);
-                    __builtin_amdgcn_sched_barrier(0);
-                    frag_mma_cp<PREC, MT, RB, CB, kSpread ? P0 : 0, CBW>(f0, m, 0, acc, copy0);
-                    __builtin_amdgcn_sched_barrier(0);
-                    frag_load<PREC, MT, RB, CB, CBW>(f0, L, 1);
-                    __builtin_amdgcn_sched_barrier(0);
-                    frag_mma_cp<PREC, MT, RB, CB, kSpread ? P1 : 0, CBW>(f0, m, 1, acc, copy1);
+                    // units one after the other in one fragment set; the
+                    // chunk's copies spread over them in equal groups
+                    constexpr int U = units_per_chunk<PREC, CB, CBW>();
+                    constexpr int NG = (PER + U - 1) / U;
+#pragma unroll
+                    for (int uu = 0; uu < U; ++uu) {
+                        auto copyg = [&](int i) {
+                            const int ci = uu * NG + i;
+                            if (kSpread && issue && ci < PER) dma_copy<PER>(nst, src[ci], koff, wave, ci);
+                        };
+                        frag_load<PREC, MT, RB, CB, CBW>(f0, L, uu);
+                        __builtin_amdgcn_sched_barrier(0);
+                        frag_mma_cp<PREC, MT, RB, CB, kSpread ? NG : 0, CBW>(f0, m, uu, acc, copyg);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 } else {
                 frag_load<PREC, MT, RB, CB, CBW>(f0, L, 0);
                 __builtin_amdgcn_sched_barrier(0);
@@ -728,8 +751,8 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
     pf.py = j.y;
     pf.off0 = (size_t)(col0 + (threadIdx.x >> 5)) * Np + row0 + tr;
     pf.stride = CPI * Np;
-    mma_tile_dma<PREC, M, NPF, NW, CBW == 2 ? staged_chunk<M>() : 64, CBW>(j.J, phi_in, j.Np, m, row0, col0, wr, wc,
-                                                                            half, lr, acc, lds, pf);
+    constexpr int CB = CBW == 2 ? staged_chunk<M>() : wide_chunk<PREC, M>();
+    mma_tile_dma<PREC, M, NPF, NW, CB, CBW>(j.J, phi_in, j.Np, m, row0, col0, wr, wc, half, lr, acc, lds, pf);
     if constexpr (CBW != 2) load_cfs();
 
     // Epilogue in two phases.  (1) h = sum_k coef_k(col) H_k(row, col) from the
@@ -825,9 +848,9 @@ __device__ __forceinline__ void dense_step_staged_body(const DenseJob &j, int t,
 }
 
 // the stage ring, reused after the k loop for the 128 x 132 float h tile
-template <int MT, int CBW = 2>
+template <int PREC, int MT, int CBW = 2>
 constexpr size_t staged_lds_bytes() {
-    constexpr int CB = CBW == 2 ? staged_chunk<MT>() : 64;
+    constexpr int CB = CBW == 2 ? staged_chunk<MT>() : wide_chunk<PREC, MT>();
     constexpr size_t ring = (size_t)wide_stages<MT, CB, CBW>() * (MT * kT2 + 64 * CBW) * CB;
     constexpr size_t hsb = sizeof(float) * 64 * CBW * kHsPitch;
     return ring > hsb ? ring : hsb;
@@ -862,7 +885,7 @@ __device__ __forceinline__ void xcd_tile(int tiles_x, int tiles_y, int &bx, int 
 
 template <int PREC, int M, bool DSB, int NW, int CBW = 2>
 __global__ __launch_bounds__(64 * NW) void dense_step_staged_kernel(DenseJob j, int t) {
-    __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<M, CBW>()];
+    __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<PREC, M, CBW>()];
     int bx, by;
     xcd_tile(j.tiles_x / (CBW / 2), j.tiles_y, bx, by);
     dense_step_staged_body<PREC, M, DSB, true, CBW == 2 && staged_prefetch<PREC, M, NW>(false), NW, CBW>(j, t, bx, by,
@@ -901,7 +924,7 @@ __global__ __launch_bounds__(64 * NW) void dense_batch_step_staged_kernel(const 
                                                                           int count,
                                                                           const int64_t *__restrict__ block_start,
                                                                           int t) {
-    __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<MT>()];
+    __shared__ __attribute__((aligned(16))) char lds[staged_lds_bytes<PREC, MT>()];
     const int64_t b = blockIdx.x;
     int i = 0;
     while (i + 1 < count && block_start[i + 1] <= b) ++i;
