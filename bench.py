@@ -71,8 +71,8 @@ def valu_instructions_per_replica_step(inst, variant: str) -> int:
     replica per lane): 2|E| + 2n FMAs, three wall operations per spin
     (compare, select, clamp) and, for discrete SB, one copysign per spin that
     feeds a neighbour.  For the 42-node, 48-edge graph: 306 (bSB), 347 (dSB);
-    the compiled loop adds a few register moves per step (6 for bSB, whose
-    loop holds two steps, and 1 for dSB)."""
+    the compiled loop, two steps per iteration, adds one register move per
+    step (the step coefficient into a VGPR)."""
     n, E = inst.n, inst.num_edges
     base = 2 * E + 5 * n
     if variant == "dsb":
