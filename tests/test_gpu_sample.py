@@ -386,6 +386,25 @@ def test_generated_kernel_matches_generic_kernel_any_step_count(q, variant, step
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("variant", ["bsb", "dsb"])
+@pytest.mark.parametrize("n,edges", [(50, 75), (60, 90), (77, 78)])
+def test_generated_kernel_register_budget_fallbacks(q, variant, n, edges):
+    """Larger degree-3 graphs (2n + |E| = 175, 210, 232, the last the largest
+    the register path admits) leave three waves per SIMD and, for some, the
+    paired wall test behind: the build takes the first of its candidate forms
+    whose step loop does not spill.  Whichever it takes, spins and cuts equal
+    the generic kernel's bit for bit (odd step count)."""
+    inst = wl.random_instance(n, 3, "deg3", seed=n, num_edges=edges)
+    assert 2 * inst.n + inst.num_edges == 2 * n + edges
+    c = wl.dirichlet_weights(6, 3, n + 1)
+    prob = q.problem_from_instance(inst)
+    outs = []
+    for path in ("sparse_reg", "sparse_lds"):
+        outs.append(_sample(q, prob, c, 64, variant=variant, steps=151, dt=0.5, seed=n + 2, path=path)[:2])
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
 @pytest.mark.parametrize("path", ["sparse_reg", "sparse_lds", "dense_staged"])
 def test_noise_injected_sampling_exact_cuts(q, path):
     inst = wl.workload_instance("c1_bsb_n42_m3")
